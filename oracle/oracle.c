@@ -1,0 +1,476 @@
+/*
+ * FP64 CPU oracle for bit-wise demapping of labelled constellations over AWGN.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes or
+ * calls this file; only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark load it.  It shares no code, header, table or constant
+ * generator with the GPU library.
+ *
+ * What the method computes is not written out in the paper: the paper's receiver
+ * (section "Experimental setup", DSP-chain paragraph) ends with the equaliser
+ * decisions being demapped, and its acronym glossary names the quantities used
+ * here (LLR, GMI, AIR, AWGN, BICM, BRGC) without defining them.  The oracle is
+ * therefore the textbook definition of each quantity for bit-interleaved coded
+ * modulation with a bit-metric decoder and uniform priors:
+ *
+ *   q[n][j]   = -||y_n - x_j||^2 / (2 sigma2)                 (difference form)
+ *   L[n][k]   = LSE_{j: bit_k(l_j)=0} q[n][j] - LSE_{j: bit_k(l_j)=1} q[n][j]
+ *               bit_k(l) = (l >> (m-1-k)) & 1   (column 0 is the label's MSB)
+ *               LSE(S)   = max(S) + ln sum exp(q - max(S))    (max per subset)
+ *   Lml[n][k] = max_{bit=0} q - max_{bit=1} q                 (max-log)
+ *   T_n       = sum_k softplus(-s_nk L_nk) / ln 2,  s = +1 if the sent bit is 0
+ *   GMI       = m - (1/N) sum_n T_n      bits per D-dimensional symbol
+ *   SE        = std(T_n) / sqrt(N)
+ *
+ * plus a re-implementation, from its written definition, of the counter-based
+ * AWGN generator that the library's awgn_sample follows (Philox4x32-10, Salmon et
+ * al., SC'11, then a Box-Muller transform evaluated with IEEE double +,-,*,/,
+ * fma and sqrt only), and an FP64 reference of the small MLP demapper with its
+ * analytic backward pass and an Adam step.
+ *
+ * Everything is plain double precision.  Build with -ffp-contract=off: the AWGN
+ * twin depends on every operation being the one written here.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw: "Parallel random numbers: as easy
+ * as 1, 2, 3", SC'11).  Counter c[4], key k[2]; ten rounds, each round
+ *   (hi0,lo0) = mulhilo(0xD2511F53, c0), (hi1,lo1) = mulhilo(0xCD9E8D57, c2)
+ *   c <- (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0)
+ * followed by the Weyl key bump k0 += 0x9E3779B9, k1 += 0xBB67AE85 between
+ * rounds. */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Natural log of U = K * 2^-53 for an odd 53-bit-or-shorter integer K > 0,
+ * evaluated as the generator definition fixes it:
+ *   K = f * 2^b with f in [1,2) (b = index of K's top bit), e = b - 53;
+ *   if f > sqrt(2): f = f/2, e = e+1;
+ *   s = (f-1)/(f+1), w = s*s,
+ *   P = Horner over w of 1/(2i+1), i = 9..0, with fma,
+ *   ln f = (2 s) * P,
+ *   ln U = fma(e, LN2_HI, fma(e, LN2_LO, ln f)).
+ * (ln f = 2 atanh s; LN2_HI/LN2_LO is the fdlibm split of ln 2.) */
+static double orc_gen_log_u(uint64_t K) {
+    int b = 63 - __builtin_clzll(K);
+    double f = (double)K;            /* exact: K < 2^53 */
+    f = ldexp(f, -b);                /* exact power-of-two scaling */
+    double e = (double)(b - 53);
+    const double SQRT2 = 0x1.6a09e667f3bcdp+0;
+    if (f > SQRT2) {
+        f = f * 0.5;
+        e = e + 1.0;
+    }
+    double s = (f - 1.0) / (f + 1.0);
+    double w = s * s;
+    double P = 1.0 / 19.0;
+    P = fma(P, w, 1.0 / 17.0);
+    P = fma(P, w, 1.0 / 15.0);
+    P = fma(P, w, 1.0 / 13.0);
+    P = fma(P, w, 1.0 / 11.0);
+    P = fma(P, w, 1.0 / 9.0);
+    P = fma(P, w, 1.0 / 7.0);
+    P = fma(P, w, 1.0 / 5.0);
+    P = fma(P, w, 1.0 / 3.0);
+    P = fma(P, w, 1.0);
+    double lnf = (2.0 * s) * P;
+    const double LN2_HI = 0x1.62e42feep-1;          /* 6.93147180369123816490e-01 */
+    const double LN2_LO = 0x1.a39ef35793c76p-33;    /* 1.90821492927058770002e-10 */
+    return fma(e, LN2_HI, fma(e, LN2_LO, lnf));
+}
+
+/* sin and cos of phi = t * (pi/2) for t = (2T+1) * 2^-51 in (0, 1/2], by Taylor
+ * polynomials in w = phi^2 (sin to phi^17, cos to phi^18), Horner with fma. */
+static void orc_gen_sincos_quarter(uint64_t T, double* s_out, double* c_out) {
+    const double PIO2 = 0x1.921fb54442d18p+0;
+    double t = (double)(2 * T + 1) * 0x1p-51;       /* exact */
+    double phi = t * PIO2;
+    double w = phi * phi;
+    double S = 1.0 / 355687428096000.0;              /* 1/17! */
+    S = fma(S, w, -1.0 / 1307674368000.0);           /* 1/15! */
+    S = fma(S, w, 1.0 / 6227020800.0);               /* 1/13! */
+    S = fma(S, w, -1.0 / 39916800.0);                /* 1/11! */
+    S = fma(S, w, 1.0 / 362880.0);                   /* 1/9!  */
+    S = fma(S, w, -1.0 / 5040.0);                    /* 1/7!  */
+    S = fma(S, w, 1.0 / 120.0);                      /* 1/5!  */
+    S = fma(S, w, -1.0 / 6.0);                       /* 1/3!  */
+    S = fma(S, w, 1.0);
+    double C = -1.0 / 6402373705728000.0;            /* 1/18! */
+    C = fma(C, w, 1.0 / 20922789888000.0);           /* 1/16! */
+    C = fma(C, w, -1.0 / 87178291200.0);             /* 1/14! */
+    C = fma(C, w, 1.0 / 479001600.0);                /* 1/12! */
+    C = fma(C, w, -1.0 / 3628800.0);                 /* 1/10! */
+    C = fma(C, w, 1.0 / 40320.0);                    /* 1/8!  */
+    C = fma(C, w, -1.0 / 720.0);                     /* 1/6!  */
+    C = fma(C, w, 1.0 / 24.0);                       /* 1/4!  */
+    C = fma(C, w, -1.0 / 2.0);                       /* 1/2!  */
+    C = fma(C, w, 1.0);
+    *s_out = phi * S;
+    *c_out = C;
+}
+
+/* One Box-Muller pair from the four Philox words of (symbol g, pair p, domain 2). */
+static void orc_gen_normal_pair(const uint32_t r[4], double* z0, double* z1) {
+    uint64_t J1 = ((uint64_t)(r[0] >> 6) << 26) | (uint64_t)(r[1] >> 6);   /* 52 bits */
+    uint64_t J2 = ((uint64_t)(r[2] >> 6) << 26) | (uint64_t)(r[3] >> 6);   /* 52 bits */
+    double lnU1 = orc_gen_log_u(2 * J1 + 1);                               /* U1 = (2 J1 + 1) 2^-53 */
+    double R = sqrt(-2.0 * lnU1);
+    uint64_t q = J2 >> 50;                                                  /* quadrant of 2 pi U2 */
+    uint64_t T = J2 & ((1ull << 50) - 1);                                   /* position inside it */
+    double sp, cp, c, s;
+    if (T < (1ull << 49)) {
+        orc_gen_sincos_quarter(T, &sp, &cp);
+        c = cp; s = sp;
+    } else {
+        /* phi = pi/2 - phi' with phi' = (2 T' + 1) 2^-51 pi/2 */
+        orc_gen_sincos_quarter((1ull << 50) - 1 - T, &sp, &cp);
+        c = sp; s = cp;
+    }
+    double ct, st;
+    switch ((int)q) {
+        case 0: ct = c;  st = s;  break;
+        case 1: ct = -s; st = c;  break;
+        case 2: ct = -c; st = -s; break;
+        default: ct = s; st = -c; break;
+    }
+    *z0 = R * ct;
+    *z1 = R * st;
+}
+
+/* The normal pair for four given Philox words (exported so the transform can be
+ * checked against libm's log, atan2 and hypot). */
+void orc_gen_box_muller(const uint32_t r[4], double z[2]) {
+    orc_gen_normal_pair(r, &z[0], &z[1]);
+}
+
+/* Channel: u_n uniform on {0..M-1}, z_n ~ N(0, I_D), y_n = fl32(x_{u_n} + sigma z_n).
+ * Counter (g_lo, g_hi, sub, domain) with g = offset + n, key = (seed_lo, seed_hi);
+ * domain 1 gives u_n = word0 >> (32 - m); domain 2, sub = p gives the normal pair
+ * feeding dimensions 2p and 2p+1. */
+void orc_awgn(const float* X, int M, int D, uint64_t seed, uint64_t offset, int64_t N,
+              double sigma, uint32_t* tx, float* y) {
+    int m = 0;
+    while ((1 << m) < M) ++m;
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    int npairs = (D + 1) / 2;
+    for (int64_t n = 0; n < N; ++n) {
+        uint64_t g = offset + (uint64_t)n;
+        uint32_t ctr[4] = {(uint32_t)g, (uint32_t)(g >> 32), 0u, 1u};
+        uint32_t r[4];
+        orc_philox4x32_10(ctr, key, r);
+        uint32_t u = r[0] >> (32 - m);
+        tx[n] = u;
+        for (int p = 0; p < npairs; ++p) {
+            uint32_t c2[4] = {(uint32_t)g, (uint32_t)(g >> 32), (uint32_t)p, 2u};
+            orc_philox4x32_10(c2, key, r);
+            double z0, z1;
+            orc_gen_normal_pair(r, &z0, &z1);
+            int d0 = 2 * p, d1 = 2 * p + 1;
+            y[n * D + d0] = (float)fma(sigma, z0, (double)X[(int64_t)u * D + d0]);
+            if (d1 < D) y[n * D + d1] = (float)fma(sigma, z1, (double)X[(int64_t)u * D + d1]);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+static int orc_log2_int(int M) {
+    int m = 0;
+    while ((1 << m) < M) ++m;
+    return m;
+}
+
+/* Exact bit-wise LLR (definition above), one symbol at a time; q[] is scratch of M doubles. */
+static void orc_llr_exact_one(const float* X, const uint32_t* labels, int M, int D, int m,
+                              const float* yn, double sigma2, double* q, double* out) {
+    for (int j = 0; j < M; ++j) {
+        double d2 = 0.0;
+        for (int d = 0; d < D; ++d) {
+            double diff = (double)yn[d] - (double)X[(int64_t)j * D + d];
+            d2 += diff * diff;
+        }
+        q[j] = -d2 / (2.0 * sigma2);
+    }
+    for (int k = 0; k < m; ++k) {
+        int shift = m - 1 - k;
+        double lse[2];
+        for (int b = 0; b < 2; ++b) {
+            double mx = -INFINITY;
+            for (int j = 0; j < M; ++j)
+                if ((int)((labels[j] >> shift) & 1u) == b && q[j] > mx) mx = q[j];
+            double s = 0.0;
+            for (int j = 0; j < M; ++j)
+                if ((int)((labels[j] >> shift) & 1u) == b) s += exp(q[j] - mx);
+            lse[b] = mx + log(s);
+        }
+        out[k] = lse[0] - lse[1];
+    }
+}
+
+void orc_llr_exact(const float* X, const uint32_t* labels, int M, int D, const float* y, int64_t N,
+                   double sigma2, double* llr) {
+    int m = orc_log2_int(M);
+#pragma omp parallel
+    {
+        double* q = (double*)malloc(sizeof(double) * (size_t)M);
+#pragma omp for schedule(static)
+        for (int64_t n = 0; n < N; ++n)
+            orc_llr_exact_one(X, labels, M, D, m, y + n * D, sigma2, q, llr + n * m);
+        free(q);
+    }
+}
+
+void orc_llr_maxlog(const float* X, const uint32_t* labels, int M, int D, const float* y, int64_t N,
+                    double sigma2, double* llr) {
+    int m = orc_log2_int(M);
+#pragma omp parallel
+    {
+        double* q = (double*)malloc(sizeof(double) * (size_t)M);
+#pragma omp for schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            const float* yn = y + n * D;
+            for (int j = 0; j < M; ++j) {
+                double d2 = 0.0;
+                for (int d = 0; d < D; ++d) {
+                    double diff = (double)yn[d] - (double)X[(int64_t)j * D + d];
+                    d2 += diff * diff;
+                }
+                q[j] = -d2 / (2.0 * sigma2);
+            }
+            for (int k = 0; k < m; ++k) {
+                int shift = m - 1 - k;
+                double mx[2] = {-INFINITY, -INFINITY};
+                for (int j = 0; j < M; ++j) {
+                    int b = (int)((labels[j] >> shift) & 1u);
+                    if (q[j] > mx[b]) mx[b] = q[j];
+                }
+                llr[n * m + k] = mx[0] - mx[1];
+            }
+        }
+        free(q);
+    }
+}
+
+/* Hard decision: index of the nearest constellation point (lowest index on ties). */
+void orc_hard_decision(const float* X, int M, int D, const float* y, int64_t N, uint32_t* jhat) {
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        double best = INFINITY;
+        uint32_t arg = 0;
+        for (int j = 0; j < M; ++j) {
+            double d2 = 0.0;
+            for (int d = 0; d < D; ++d) {
+                double diff = (double)y[n * D + d] - (double)X[(int64_t)j * D + d];
+                d2 += diff * diff;
+            }
+            if (d2 < best) { best = d2; arg = (uint32_t)j; }
+        }
+        jhat[n] = arg;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+static double orc_softplus(double t) {
+    return (t > 0.0 ? t : 0.0) + log1p(exp(-fabs(t)));
+}
+
+/* Neumaier-compensated running sum. */
+typedef struct { double s, c; } orc_ksum;
+static void orc_ksum_add(orc_ksum* a, double x) {
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double orc_ksum_get(const orc_ksum* a) { return a->s + a->c; }
+
+/* Per-symbol T_n = sum_k softplus(-s_nk L_nk)/ln 2 (bits lost by symbol n). */
+void orc_gmi_terms(const double* llr, int64_t N, int m, const uint32_t* tx, const uint32_t* labels,
+                   double* T, double* per_bit_terms /* N x m or NULL */) {
+    for (int64_t n = 0; n < N; ++n) {
+        uint32_t lab = labels[tx[n]];
+        double acc = 0.0;
+        for (int k = 0; k < m; ++k) {
+            int bit = (int)((lab >> (m - 1 - k)) & 1u);
+            double sgn = bit ? -1.0 : 1.0;
+            double t = orc_softplus(-sgn * llr[n * m + k]) / M_LN2;
+            if (per_bit_terms) per_bit_terms[n * m + k] = t;
+            acc += t;
+        }
+        T[n] = acc;
+    }
+}
+
+/* GMI, per-bit GMI and standard error (two-pass variance), all sums compensated. */
+void orc_gmi(const double* llr, int64_t N, int m, const uint32_t* tx, const uint32_t* labels,
+             double* gmi, double* gmi_per_bit, double* se) {
+    double* T = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    double* Tb = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N * m : 1));
+    orc_gmi_terms(llr, N, m, tx, labels, T, Tb);
+    orc_ksum tot = {0.0, 0.0};
+    for (int64_t n = 0; n < N; ++n) orc_ksum_add(&tot, T[n]);
+    double mean = orc_ksum_get(&tot) / (double)N;
+    *gmi = (double)m - mean;
+    if (gmi_per_bit) {
+        for (int k = 0; k < m; ++k) {
+            orc_ksum bk = {0.0, 0.0};
+            for (int64_t n = 0; n < N; ++n) orc_ksum_add(&bk, Tb[n * m + k]);
+            gmi_per_bit[k] = 1.0 - orc_ksum_get(&bk) / (double)N;
+        }
+    }
+    if (se) {
+        orc_ksum v = {0.0, 0.0};
+        for (int64_t n = 0; n < N; ++n) orc_ksum_add(&v, (T[n] - mean) * (T[n] - mean));
+        *se = N > 1 ? sqrt(orc_ksum_get(&v) / (double)(N - 1)) / sqrt((double)N) : 0.0;
+    }
+    free(T);
+    free(Tb);
+}
+
+/* ------------------------------------------------------------------------- */
+/* MLP demapper reference: f(y) = W3 g(W2 g(W1 y + b1) + b2) + b3 with
+ * g(a) = a Phi(a) = a (1 + erf(a / sqrt 2)) / 2 (GELU).  Weights are row-major
+ * [out][in].  Loss per sample: sum_k p_k softplus(-f_k) + (1 - p_k) softplus(f_k)
+ * with p_k = sigmoid(L_target_k), averaged over the batch. */
+static double orc_gelu(double a) { return 0.5 * a * (1.0 + erf(a / M_SQRT2)); }
+static double orc_gelu_grad(double a) {
+    return 0.5 * (1.0 + erf(a / M_SQRT2)) + a * exp(-0.5 * a * a) / sqrt(2.0 * M_PI);
+}
+static double orc_sigmoid(double t) {
+    return t >= 0.0 ? 1.0 / (1.0 + exp(-t)) : exp(t) / (1.0 + exp(t));
+}
+
+void orc_mlp_forward(int D, int H1, int H2, int m,
+                     const double* W1, const double* b1, const double* W2, const double* b2,
+                     const double* W3, const double* b3,
+                     const float* y, int64_t N, double* out) {
+#pragma omp parallel
+    {
+        double* h1 = (double*)malloc(sizeof(double) * (size_t)H1);
+        double* h2 = (double*)malloc(sizeof(double) * (size_t)H2);
+#pragma omp for schedule(static)
+        for (int64_t n = 0; n < N; ++n) {
+            for (int i = 0; i < H1; ++i) {
+                double z = b1[i];
+                for (int d = 0; d < D; ++d) z += W1[i * D + d] * (double)y[n * D + d];
+                h1[i] = orc_gelu(z);
+            }
+            for (int i = 0; i < H2; ++i) {
+                double z = b2[i];
+                for (int d = 0; d < H1; ++d) z += W2[(int64_t)i * H1 + d] * h1[d];
+                h2[i] = orc_gelu(z);
+            }
+            for (int k = 0; k < m; ++k) {
+                double z = b3[k];
+                for (int d = 0; d < H2; ++d) z += W3[(int64_t)k * H2 + d] * h2[d];
+                out[n * m + k] = z;
+            }
+        }
+        free(h1);
+        free(h2);
+    }
+}
+
+/* Mean distillation loss over the batch and its gradient with respect to every
+ * parameter (gradient arrays are overwritten). */
+double orc_mlp_loss_grad(int D, int H1, int H2, int m,
+                         const double* W1, const double* b1, const double* W2, const double* b2,
+                         const double* W3, const double* b3,
+                         const float* y, const float* target, int64_t B,
+                         double* gW1, double* gb1, double* gW2, double* gb2, double* gW3, double* gb3) {
+    memset(gW1, 0, sizeof(double) * (size_t)H1 * D);
+    memset(gb1, 0, sizeof(double) * (size_t)H1);
+    memset(gW2, 0, sizeof(double) * (size_t)H2 * H1);
+    memset(gb2, 0, sizeof(double) * (size_t)H2);
+    memset(gW3, 0, sizeof(double) * (size_t)m * H2);
+    memset(gb3, 0, sizeof(double) * (size_t)m);
+    double* z1 = (double*)malloc(sizeof(double) * (size_t)H1);
+    double* h1 = (double*)malloc(sizeof(double) * (size_t)H1);
+    double* z2 = (double*)malloc(sizeof(double) * (size_t)H2);
+    double* h2 = (double*)malloc(sizeof(double) * (size_t)H2);
+    double* dz2 = (double*)malloc(sizeof(double) * (size_t)H2);
+    double* dz1 = (double*)malloc(sizeof(double) * (size_t)H1);
+    double* f = (double*)malloc(sizeof(double) * (size_t)m);
+    double* df = (double*)malloc(sizeof(double) * (size_t)m);
+    double loss = 0.0;
+    for (int64_t n = 0; n < B; ++n) {
+        const float* yn = y + n * D;
+        for (int i = 0; i < H1; ++i) {
+            double z = b1[i];
+            for (int d = 0; d < D; ++d) z += W1[i * D + d] * (double)yn[d];
+            z1[i] = z;
+            h1[i] = orc_gelu(z);
+        }
+        for (int i = 0; i < H2; ++i) {
+            double z = b2[i];
+            for (int d = 0; d < H1; ++d) z += W2[(int64_t)i * H1 + d] * h1[d];
+            z2[i] = z;
+            h2[i] = orc_gelu(z);
+        }
+        for (int k = 0; k < m; ++k) {
+            double z = b3[k];
+            for (int d = 0; d < H2; ++d) z += W3[(int64_t)k * H2 + d] * h2[d];
+            f[k] = z;
+            double p = orc_sigmoid((double)target[n * m + k]);
+            loss += p * orc_softplus(-z) + (1.0 - p) * orc_softplus(z);
+            df[k] = (orc_sigmoid(z) - p) / (double)B;
+        }
+        for (int k = 0; k < m; ++k) {
+            gb3[k] += df[k];
+            for (int d = 0; d < H2; ++d) gW3[(int64_t)k * H2 + d] += df[k] * h2[d];
+        }
+        for (int i = 0; i < H2; ++i) {
+            double g = 0.0;
+            for (int k = 0; k < m; ++k) g += W3[(int64_t)k * H2 + i] * df[k];
+            dz2[i] = g * orc_gelu_grad(z2[i]);
+            gb2[i] += dz2[i];
+            for (int d = 0; d < H1; ++d) gW2[(int64_t)i * H1 + d] += dz2[i] * h1[d];
+        }
+        for (int i = 0; i < H1; ++i) {
+            double g = 0.0;
+            for (int k = 0; k < H2; ++k) g += W2[(int64_t)k * H1 + i] * dz2[k];
+            dz1[i] = g * orc_gelu_grad(z1[i]);
+            gb1[i] += dz1[i];
+            for (int d = 0; d < D; ++d) gW1[i * D + d] += dz1[i] * (double)yn[d];
+        }
+    }
+    free(z1); free(h1); free(z2); free(h2); free(dz2); free(dz1); free(f); free(df);
+    return loss / (double)B;
+}
+
+/* One Adam step (Kingma & Ba, 2015) on P parameters; t is the 1-based step count. */
+void orc_adam_step(double* w, const double* g, double* mom1, double* mom2, int64_t P, int t,
+                   double lr, double beta1, double beta2, double eps) {
+    double c1 = 1.0 - pow(beta1, (double)t);
+    double c2 = 1.0 - pow(beta2, (double)t);
+    for (int64_t i = 0; i < P; ++i) {
+        mom1[i] = beta1 * mom1[i] + (1.0 - beta1) * g[i];
+        mom2[i] = beta2 * mom2[i] + (1.0 - beta2) * g[i] * g[i];
+        double mh = mom1[i] / c1;
+        double vh = mom2[i] / c2;
+        w[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}

@@ -1,0 +1,82 @@
+"""Pins of the oracle's FP64 MLP demapper reference: central finite differences of the
+loss, closed-form values of GELU and of the loss at special points, and the closed
+form of Adam's first step."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+
+
+def _params(D=3, H1=5, H2=4, m=2, seed=0, scale=0.7):
+    rng = np.random.default_rng(seed)
+    return oracle.MLPParams(
+        rng.standard_normal((H1, D)) * scale, rng.standard_normal(H1) * 0.1,
+        rng.standard_normal((H2, H1)) * scale, rng.standard_normal(H2) * 0.1,
+        rng.standard_normal((m, H2)) * scale, rng.standard_normal(m) * 0.1)
+
+
+def test_gelu_closed_form_values():
+    # one hidden unit per layer with identity-like weights exposes GELU itself
+    p = oracle.MLPParams(np.array([[1.0]]), np.zeros(1), np.array([[1.0]]), np.zeros(1),
+                         np.array([[1.0]]), np.zeros(1))
+    y = np.array([[0.0], [1.0], [-1.0], [8.0]], dtype=np.float32)
+    out = oracle.mlp_forward(p, y)[:, 0]
+    phi1 = 0.8413447460685429                       # standard normal CDF at 1
+    g1 = 1.0 * phi1
+    gm1 = -1.0 * (1 - phi1)
+    expect = [0.0, g1 * 0.5 * (1 + math.erf(g1 / math.sqrt(2))),
+              gm1 * 0.5 * (1 + math.erf(gm1 / math.sqrt(2))), 8.0]
+    np.testing.assert_allclose(out, expect, rtol=1e-12, atol=1e-12)
+
+
+def test_zero_network_loss_closed_form():
+    # all-zero weights: output = b3 = 0, p = sigmoid(0) = 1/2 -> loss = m ln 2 and dL/db3 = 0
+    D, H1, H2, m = 4, 6, 5, 3
+    p = oracle.MLPParams(np.zeros((H1, D)), np.zeros(H1), np.zeros((H2, H1)), np.zeros(H2),
+                         np.zeros((m, H2)), np.zeros(m))
+    y = np.random.default_rng(1).standard_normal((10, D)).astype(np.float32)
+    loss, g = oracle.mlp_loss_grad(p, y, np.zeros((10, m), dtype=np.float32))
+    assert abs(loss - m * math.log(2)) < 1e-14
+    assert np.all(np.abs(g[5]) < 1e-15)
+    # target +inf-like: p -> 1, gradient wrt b3 = sigmoid(0) - 1 = -1/2
+    loss2, g2 = oracle.mlp_loss_grad(p, y, np.full((10, m), 60.0, dtype=np.float32))
+    np.testing.assert_allclose(g2[5], -0.5, atol=1e-12)
+    assert abs(loss2 - m * math.log(2)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradient_central_differences(seed):
+    p = _params(seed=seed)
+    rng = np.random.default_rng(10 + seed)
+    y = rng.standard_normal((7, 3)).astype(np.float32)
+    tgt = (rng.standard_normal((7, 2)) * 3).astype(np.float32)
+    _, grads = oracle.mlp_loss_grad(p, y, tgt)
+    h = 1e-6
+    for a, g in zip(p.flat(), grads):
+        flat = a.reshape(-1)
+        gflat = g.reshape(-1)
+        for i in range(flat.size):
+            old = flat[i]
+            flat[i] = old + h
+            lp, _ = oracle.mlp_loss_grad(p, y, tgt)
+            flat[i] = old - h
+            lm, _ = oracle.mlp_loss_grad(p, y, tgt)
+            flat[i] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - gflat[i]) <= 1e-7 * max(1.0, abs(fd)), (i, fd, gflat[i])
+
+
+def test_adam_first_step_closed_form():
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal(50)
+    g = rng.standard_normal(50)
+    w0 = w.copy()
+    m1 = np.zeros(50)
+    m2 = np.zeros(50)
+    oracle.adam_step(w, g, m1, m2, 1, 1e-3)
+    # bias-corrected moments equal g and g^2 on the first step
+    np.testing.assert_allclose(w, w0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-14)
+    np.testing.assert_allclose(m2, 0.001 * g * g, rtol=1e-13)
