@@ -1,0 +1,155 @@
+/*
+ * mdemap -- bit-wise soft demapping of labelled multidimensional constellations
+ * over AWGN on AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * What is computed.  The paper's GPU receiver (section "Experimental setup",
+ * DSP-chain paragraph) ends by demapping the equaliser's decisions; its acronym
+ * glossary names LLR, GMI, AIR, AWGN, BICM and BRGC but the text defines none of
+ * them.  The library computes their standard bit-interleaved-coded-modulation
+ * definitions with uniform priors.  For a constellation X (M x D, M = 2^m) with a
+ * bijective labelling l_j, received symbols y_n and noise variance sigma2 per
+ * real dimension:
+ *
+ *   q_nj  = -||y_n - x_j||^2 / (2 sigma2)
+ *   L_nk  = ln sum_{j: b_k(l_j)=0} e^{q_nj} - ln sum_{j: b_k(l_j)=1} e^{q_nj}
+ *           b_k(l) = (l >> (m-1-k)) & 1: column k of the LLR row is label bit
+ *           m-1-k (most significant bit first); the sign is ln P(b=0)/P(b=1)
+ *   GMI   = m - (1/N) sum_n sum_k log2(1 + e^{-s_nk L_nk}),  s_nk = +1 if the
+ *           transmitted label's bit k is 0, else -1     [bits per D-dim symbol]
+ *
+ * Conventions for every call
+ *   - Pointers named d_* are DEVICE memory owned by the caller; the library never
+ *     frees them.  Arrays are dense and row-major.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Every call only enqueues work on that stream and returns; results are ready
+ *     when the stream has reached them.
+ *   - Arguments are checked on the host before anything is enqueued; a negative
+ *     status is returned and last_error() describes it.  No call throws.
+ *   - The library keeps an internal device workspace per (device, stream) that it
+ *     grows on demand and frees in release_cache().  Calls on one stream are
+ *     ordered; calls that overlap on different streams use different workspaces.
+ *   - Labels are checked to be a permutation of [0, M): on the host the first time
+ *     a given label buffer is seen (a synchronous copy, skipped while the stream is
+ *     being captured into a graph), and on the device in every call (an invalid
+ *     label set turns every output of that call into NaN).
+ *   - Limits: 2 <= M <= 65536 and a power of two; 1 <= D <= 30; N >= 0.
+ */
+#ifndef MDEMAP_H
+#define MDEMAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define MD_OK            0
+#define MD_EINVAL       -1   /* bad argument (null pointer, N < 0, sigma2 <= 0 ...) */
+#define MD_ENOTPOW2     -2   /* M is not a power of two in [2, 65536] */
+#define MD_ELABEL       -3   /* labels are not a permutation of [0, M) */
+#define MD_EDIM         -4   /* D outside [1, 30] or a shape mismatch */
+#define MD_ENOMEM       -5   /* device workspace allocation failed */
+#define MD_EHIP         -6   /* a HIP runtime call failed (message in last_error) */
+#define MD_ENODEV       -7   /* no GPU visible */
+#define MD_EUNSUPPORTED -8   /* combination not implemented */
+
+/* Precision of llr_exact.
+ *   MD_PREC_FP32: scores by a three-pass split-FP16 MFMA contraction with FP32
+ *     accumulation (error about 2^-21 of sum_k |a_k b_k|), exponentials and all
+ *     subset sums in FP32.
+ *   MD_PREC_BF16: same scores; the exponentials are rounded to BF16 and the
+ *     subset sums are formed by a BF16 MFMA contraction against the label-bit
+ *     matrix with FP32 accumulation (LLR relative error about 2^-8). */
+#define MD_PREC_FP32 0
+#define MD_PREC_BF16 2
+
+/* ------------------------------------------------------------------ channel */
+/* awgn_sample -- draws N channel uses: a uniform transmitted index u_n in [0, M)
+ * and y_n = fl32(x_{u_n} + sigma z_n), z_n ~ N(0, I_D).  The AWGN of the paper's
+ * glossary; the generator is fixed bit for bit by this definition, so that any
+ * (seed, offset) window is reproducible on any launch geometry and on the CPU:
+ *
+ *   key = (seed & 0xffffffff, seed >> 32); g = offset + n (64-bit);
+ *   Philox4x32-10 (Salmon et al., SC'11) of counter (g_lo, g_hi, sub, domain).
+ *   u_n = word0 >> (32 - m) of counter (g_lo, g_hi, 0, 1).
+ *   For pair p = 0 .. ceil(D/2)-1, words r0..r3 of counter (g_lo, g_hi, p, 2):
+ *     J1 = (r0 >> 6) * 2^26 + (r1 >> 6), U1 = (2 J1 + 1) * 2^-53;
+ *     J2 = (r2 >> 6) * 2^26 + (r3 >> 6), quadrant Q = J2 >> 50,
+ *     T = J2 mod 2^50 (the angle is 2 pi (2 J2 + 1) 2^-53);
+ *     ln U1 from U1 = f 2^e, f in [1,2) (f/2 and e+1 if f > sqrt2),
+ *       s = (f-1)/(f+1), P = Horner in s^2 of 1/(2i+1), i = 9..0 (fma),
+ *       ln U1 = fma(e, LN2_HI, fma(e, LN2_LO, (2s) P)) with the fdlibm split
+ *       LN2_HI = 0x1.62e42feep-1, LN2_LO = 0x1.a39ef35793c76p-33;
+ *     R = sqrt(-2 ln U1) (IEEE correctly rounded);
+ *     if T < 2^49: phi = ((2T+1) 2^-51) * PIO2 gives (cos, sin) = (C, S)
+ *       else phi' from T' = 2^50 - 1 - T gives (cos, sin) = (S', C'),
+ *       with PIO2 = 0x1.921fb54442d18p+0, w = phi^2,
+ *       S = phi * Horner_w(+-1/(2i+1)!, i = 8..0), C = Horner_w(+-1/(2i)!, i = 9..0);
+ *     rotate by Q quarter turns: (c, s) -> (c, s), (-s, c), (-c, -s), (s, -c);
+ *     z_{2p} = R c, z_{2p+1} = R s (the latter dropped when 2p+1 = D);
+ *   y_nd = (float) fma(sigma, z_d, (double) X[u_n][d]).
+ * All arithmetic is IEEE double with round-to-nearest, no contraction beyond the
+ * fma written above.
+ *
+ *   d_X    M x D float32 constellation (row u is point u; labels are not used)
+ *   sigma  noise standard deviation per real dimension, sigma >= 0 (host FP64)
+ *   d_tx   out: N uint32 transmitted point indices (rows of X)
+ *   d_y    out: N x D float32 received symbols
+ * Returns MD_OK (N = 0 enqueues nothing), MD_EINVAL, MD_ENOTPOW2, MD_EDIM, MD_EHIP. */
+int awgn_sample(const float* d_X, int M, int D, uint64_t seed, uint64_t offset, int64_t N,
+                double sigma, uint32_t* d_tx, float* d_y, void* stream);
+
+/* ------------------------------------------------------------------ demappers */
+/* llr_exact -- exact bit-wise LLRs L_nk above (log-sum-exp over the label-0 and
+ * label-1 subsets of every bit).
+ *   d_X       M x D float32 constellation
+ *   d_labels  M uint32, a permutation of [0, M); l_j is the label of point j
+ *   d_y       N x D float32 received symbols
+ *   sigma2    noise variance per real dimension (> 0, finite)
+ *   prec      MD_PREC_FP32 or MD_PREC_BF16
+ *   d_llr     out: N x m float32
+ * Symbols whose subset sums would leave the FP32 range are recomputed by a
+ * per-subset-maximum evaluation, so every finite input gives finite LLRs.
+ * Returns MD_OK (N = 0 enqueues nothing), MD_EINVAL, MD_ENOTPOW2, MD_ELABEL,
+ * MD_EDIM, MD_ENOMEM, MD_EHIP. */
+int llr_exact(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y,
+              int64_t N, double sigma2, int prec, float* d_llr, void* stream);
+
+/* llr_maxlog -- max-log LLRs: L_nk = max_{b_k=0} q_nj - max_{b_k=1} q_nj.  Same
+ * arguments, layout and errors as llr_exact (no precision argument). */
+int llr_maxlog(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y,
+               int64_t N, double sigma2, float* d_llr, void* stream);
+
+/* ------------------------------------------------------------------ metric */
+/* gmi_reduce -- Monte-Carlo GMI (the glossary's generalised mutual information,
+ * an achievable information rate of BICM) of N LLR rows against the transmitted
+ * labels: T_n = sum_k log2(1 + e^{-s_nk L_nk}) in FP32 per symbol, compensated
+ * FP32 partial sums, FP64 final sums in a fixed order (deterministic).
+ *   d_llr          N x m float32
+ *   d_tx           N uint32 transmitted point indices
+ *   d_labels       M = 2^m uint32 labels (d_labels[d_tx[n]] is the sent label)
+ *   d_gmi          out: 1 double, bits per D-dimensional symbol
+ *   d_gmi_per_bit  out: m doubles (1 - mean loss of column k) or NULL
+ *   d_se           out: 1 double, std(T_n)/sqrt(N), or NULL
+ * N = 0 is MD_EINVAL (the GMI of an empty sample is undefined).  Non-finite LLRs
+ * give a NaN GMI. */
+int gmi_reduce(const float* d_llr, int64_t N, int m, const uint32_t* d_tx,
+               const uint32_t* d_labels, double* d_gmi, double* d_gmi_per_bit, double* d_se,
+               void* stream);
+
+/* ------------------------------------------------------------------ housekeeping */
+/* Frees every internal device workspace (synchronises the device first). */
+int release_cache(void);
+
+/* Message for the last non-OK status returned on the calling thread ("" if none). */
+const char* last_error(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int mdemap_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDEMAP_H */

@@ -57,6 +57,7 @@ def _load():
     lib.orc_mlp_loss_grad.argtypes = [I, I, I, I, P, P, P, P, P, P, P, P, I64, P, P, P, P, P, P]
     lib.orc_mlp_loss_grad.restype = Dbl
     lib.orc_adam_step.argtypes = [P, P, P, P, I64, I, Dbl, Dbl, Dbl, Dbl]
+    lib.orc_num_threads.restype = I
     _lib = lib
     return lib
 
@@ -236,3 +237,8 @@ def adam_step(w, g, m1, m2, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8)
     for a in (w, g, m1, m2):
         assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     lib.orc_adam_step(_ptr(w), _ptr(g), _ptr(m1), _ptr(m2), w.size, t, lr, beta1, beta2, eps)
+
+
+def num_threads() -> int:
+    """OpenMP threads used by the parallel oracle loops."""
+    return int(_load().orc_num_threads())

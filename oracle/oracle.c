@@ -32,6 +32,7 @@
  * twin depends on every operation being the one written here.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -474,3 +475,6 @@ void orc_adam_step(double* w, const double* g, double* mom1, double* mom2, int64
         w[i] -= lr * mh / (sqrt(vh) + eps);
     }
 }
+
+/* Number of OpenMP threads the parallel loops above use. */
+int orc_num_threads(void) { return omp_get_max_threads(); }

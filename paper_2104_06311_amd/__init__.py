@@ -1,0 +1,120 @@
+"""MI355X-native bit-wise soft demapping of labelled multidimensional constellations
+over AWGN: counter-based AWGN channel, exact and max-log LLRs, Monte-Carlo GMI.
+
+Thin Python layer over the C ABI of ``libmdemap.so`` (see ``include/mdemap.h``):
+the functions below have the names of the C entry points and only marshal
+arguments.  Inputs are CUDA/HIP torch tensors; outputs are allocated with torch on
+the same device and every call is enqueued on torch's current stream.
+"""
+from __future__ import annotations
+
+import torch
+
+from ._lib import MdemapError, PREC, check, lib
+
+__all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "gmi_reduce", "release_cache", "MdemapError",
+           "log2_exact"]
+
+
+def _stream():
+    return ctypes_void(torch.cuda.current_stream().cuda_stream)
+
+
+def ctypes_void(v):
+    import ctypes
+    return ctypes.c_void_p(v)
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _dev(t: torch.Tensor, name: str, dtype: torch.dtype, ndim: int):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def log2_exact(M: int) -> int:
+    m = int(M).bit_length() - 1
+    if M < 2 or (1 << m) != M:
+        raise ValueError(f"M={M} is not a power of two >= 2")
+    return m
+
+
+def awgn_sample(X: torch.Tensor, seed: int, offset: int, N: int, sigma: float, tx=None, y=None):
+    """(tx uint32[N] as int32 storage, y float32[N, D]) for the channel defined in mdemap.h."""
+    _dev(X, "X", torch.float32, 2)
+    M, D = X.shape
+    if tx is None:
+        tx = torch.empty(N, dtype=torch.int32, device=X.device)
+    if y is None:
+        y = torch.empty((N, D), dtype=torch.float32, device=X.device)
+    st = lib().awgn_sample(_ptr(X), M, D, seed & (2 ** 64 - 1), offset & (2 ** 64 - 1), N, float(sigma),
+                           _ptr(tx), _ptr(y), _stream())
+    check("awgn_sample", st)
+    return tx, y
+
+
+def _demap_args(X, labels, y):
+    _dev(X, "X", torch.float32, 2)
+    _dev(labels, "labels", torch.int32, 1)
+    _dev(y, "y", torch.float32, 2)
+    M, D = X.shape
+    if labels.shape[0] != M:
+        raise ValueError("labels must have M entries")
+    if y.shape[1] != D:
+        raise ValueError("y must have D columns")
+    return M, D, y.shape[0]
+
+
+def llr_exact(X, labels, y, sigma2: float, prec: str = "fp32", out=None):
+    """Exact bit-wise LLRs float32[N, m] (column k = label bit m-1-k, sign ln P0/P1)."""
+    M, D, N = _demap_args(X, labels, y)
+    m = log2_exact(M)
+    if out is None:
+        out = torch.empty((N, m), dtype=torch.float32, device=X.device)
+    st = lib().llr_exact(_ptr(X), _ptr(labels), M, D, _ptr(y), N, float(sigma2), PREC[prec], _ptr(out), _stream())
+    check("llr_exact", st)
+    return out
+
+
+def llr_maxlog(X, labels, y, sigma2: float, out=None):
+    """Max-log bit-wise LLRs float32[N, m]."""
+    M, D, N = _demap_args(X, labels, y)
+    m = log2_exact(M)
+    if out is None:
+        out = torch.empty((N, m), dtype=torch.float32, device=X.device)
+    st = lib().llr_maxlog(_ptr(X), _ptr(labels), M, D, _ptr(y), N, float(sigma2), _ptr(out), _stream())
+    check("llr_maxlog", st)
+    return out
+
+
+def gmi_reduce(llr, tx, labels, per_bit: bool = True, se: bool = True):
+    """(gmi float64[1], gmi_per_bit float64[m] or None, se float64[1] or None), device tensors."""
+    _dev(llr, "llr", torch.float32, 2)
+    _dev(tx, "tx", torch.int32, 1)
+    _dev(labels, "labels", torch.int32, 1)
+    N, m = llr.shape
+    if tx.shape[0] != N:
+        raise ValueError("tx must have N entries")
+    if labels.shape[0] != (1 << m):
+        raise ValueError("labels must have 2^m entries")
+    g = torch.empty(1, dtype=torch.float64, device=llr.device)
+    gb = torch.empty(m, dtype=torch.float64, device=llr.device) if per_bit else None
+    s = torch.empty(1, dtype=torch.float64, device=llr.device) if se else None
+    st = lib().gmi_reduce(_ptr(llr), N, m, _ptr(tx), _ptr(labels), _ptr(g), _ptr(gb), _ptr(s), _stream())
+    check("gmi_reduce", st)
+    return g, gb, s
+
+
+def release_cache():
+    check("release_cache", lib().release_cache())

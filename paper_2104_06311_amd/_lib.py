@@ -1,0 +1,67 @@
+"""ctypes binding of libmdemap.so (the C ABI declared in include/mdemap.h).
+
+Argument marshalling only: torch tensors are used for device memory and streams,
+every step of the computation runs in the library's HIP kernels.  If the shared
+library is missing the import fails loudly; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdemap.so")
+
+MD_OK = 0
+STATUS_NAMES = {
+    0: "MD_OK", -1: "MD_EINVAL", -2: "MD_ENOTPOW2", -3: "MD_ELABEL", -4: "MD_EDIM",
+    -5: "MD_ENOMEM", -6: "MD_EHIP", -7: "MD_ENODEV", -8: "MD_EUNSUPPORTED",
+}
+PREC = {"fp32": 0, "bf16": 2}
+
+# name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
+_D = ctypes.c_double
+_F = ctypes.c_float
+SIGNATURES = {
+    "awgn_sample": (_I, [_P, _I, _I, _U64, _U64, _I64, _D, _P, _P, _P]),
+    "llr_exact": (_I, [_P, _P, _I, _I, _P, _I64, _D, _I, _P, _P]),
+    "llr_maxlog": (_I, [_P, _P, _I, _I, _P, _I64, _D, _P, _P]),
+    "gmi_reduce": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P, _P]),
+    "release_cache": (_I, []),
+    "last_error": (ctypes.c_char_p, []),
+    "mdemap_version": (_I, []),
+}
+
+
+class MdemapError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2104_06311_amd.build` "
+                              "(the HIP library is required; there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(fn: str, status: int):
+    if status != MD_OK:
+        msg = lib().last_error().decode(errors="replace")
+        raise MdemapError(fn, status, msg)

@@ -1,0 +1,94 @@
+// C entry points: argument validation on the host, then prep + kernel launches on the
+// caller's stream.  Nothing here computes on the host.
+#include <cmath>
+
+#include "common.hpp"
+#include "llr_kernels.hpp"
+
+namespace {
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+int check_constellation(const void* d_X, int M, int D) {
+  if (!d_X) return md::fail(MD_EINVAL, "constellation pointer is NULL");
+  if (M < 2 || M > 65536 || !md::is_pow2(M))
+    return md::fail(MD_ENOTPOW2, "M=" + std::to_string(M) + " is not a power of two in [2, 65536]");
+  if (D < 1 || D > 30) return md::fail(MD_EDIM, "D=" + std::to_string(D) + " is outside [1, 30]");
+  return MD_OK;
+}
+
+int demap(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y, int64_t N, double sigma2,
+          int prec, bool maxlog, float* d_llr, void* stream) {
+  md::set_error("");
+  int st = check_constellation(d_X, M, D);
+  if (st != MD_OK) return st;
+  if (!d_labels) return md::fail(MD_EINVAL, "labels pointer is NULL");
+  if (N < 0) return md::fail(MD_EINVAL, "N is negative");
+  if (N > 0 && (!d_y || !d_llr)) return md::fail(MD_EINVAL, "y or llr pointer is NULL");
+  if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return md::fail(MD_EINVAL, "sigma2 must be finite and > 0");
+  if (prec != MD_PREC_FP32 && prec != MD_PREC_BF16) return md::fail(MD_EINVAL, "unknown precision");
+  int dev = 0;
+  st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  hipStream_t s = as_stream(stream);
+  st = md::check_labels_once(d_labels, M, s);
+  if (st != MD_OK) return st;
+  if (N == 0) return MD_OK;
+  char* ws = nullptr;
+  st = md::workspace(s, md::prep_bytes(M, D, N), &ws);
+  if (st != MD_OK) return st;
+  md::Prepared P;
+  float alpha = 1.0f, c_over_alpha = 1.0f;
+  md::score_scales(sigma2, &alpha, &c_over_alpha);
+  st = md::prepare(d_X, d_labels, M, D, N, alpha, c_over_alpha, ws, s, &P);
+  if (st != MD_OK) return st;
+  return md::launch_llr(P, M, D, d_y, N, sigma2, maxlog, prec == MD_PREC_BF16, d_llr, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int awgn_sample(const float* d_X, int M, int D, uint64_t seed, uint64_t offset, int64_t N, double sigma,
+                uint32_t* d_tx, float* d_y, void* stream) {
+  md::set_error("");
+  int st = check_constellation(d_X, M, D);
+  if (st != MD_OK) return st;
+  if (N < 0) return md::fail(MD_EINVAL, "N is negative");
+  if (N > 0 && (!d_tx || !d_y)) return md::fail(MD_EINVAL, "tx or y pointer is NULL");
+  if (!(sigma >= 0.0) || !std::isfinite(sigma)) return md::fail(MD_EINVAL, "sigma must be finite and >= 0");
+  int dev = 0;
+  st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  if (N == 0) return MD_OK;
+  return md::launch_awgn(d_X, M, D, seed, offset, N, sigma, d_tx, d_y, as_stream(stream));
+}
+
+int llr_exact(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y, int64_t N, double sigma2,
+              int prec, float* d_llr, void* stream) {
+  return demap(d_X, d_labels, M, D, d_y, N, sigma2, prec, false, d_llr, stream);
+}
+
+int llr_maxlog(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y, int64_t N, double sigma2,
+               float* d_llr, void* stream) {
+  return demap(d_X, d_labels, M, D, d_y, N, sigma2, MD_PREC_FP32, true, d_llr, stream);
+}
+
+int gmi_reduce(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels, double* d_gmi,
+               double* d_gmi_per_bit, double* d_se, void* stream) {
+  md::set_error("");
+  if (N <= 0) return md::fail(MD_EINVAL, "GMI needs N > 0 symbols");
+  if (m < 1 || m > 16) return md::fail(MD_EINVAL, "m=" + std::to_string(m) + " is outside [1, 16]");
+  if (!d_llr || !d_tx || !d_labels || !d_gmi) return md::fail(MD_EINVAL, "llr, tx, labels or gmi pointer is NULL");
+  int dev = 0;
+  int st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  hipStream_t s = as_stream(stream);
+  char* ws = nullptr;
+  // calls on one stream run in order, so the partials may reuse the demappers' workspace
+  st = md::workspace(s, md::gmi_workspace_bytes(N, m), &ws);
+  if (st != MD_OK) return st;
+  return md::launch_gmi(d_llr, N, m, d_tx, d_labels, d_gmi, d_gmi_per_bit, d_se, ws, s);
+}
+
+}  // extern "C"

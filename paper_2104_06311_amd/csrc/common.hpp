@@ -1,0 +1,84 @@
+// Internal definitions shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/mdemap.h"
+
+namespace md {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+int fail(int status, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define MD_HIP_TRY(expr)                                  \
+  do {                                                    \
+    hipError_t md_e_ = (expr);                            \
+    if (md_e_ != hipSuccess) return md::hip_fail(md_e_, #expr); \
+  } while (0)
+
+// Checks that a launch was accepted (grid/block/LDS limits).
+#define MD_LAUNCH_CHECK(name)                                          \
+  do {                                                                 \
+    hipError_t md_e_ = hipGetLastError();                              \
+    if (md_e_ != hipSuccess) return md::hip_fail(md_e_, name);         \
+  } while (0)
+
+inline int ilog2_pow2(int M) {
+  int m = 0;
+  while ((1 << m) < M) ++m;
+  return m;
+}
+inline bool is_pow2(int M) { return M >= 2 && (M & (M - 1)) == 0; }
+
+// ---------------------------------------------------------------- workspace
+// One growable device buffer per (device, stream); sub-buffers are carved from it
+// with 256-byte alignment.
+struct Carver {
+  char* base;
+  size_t off;
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+inline size_t carve_size(size_t bytes) { return ((bytes + 255) & ~size_t(255)); }
+
+// Returns a device buffer of at least `bytes` bytes private to (current device, stream).
+int workspace(hipStream_t stream, size_t bytes, char** out);
+
+// Host-side label check cache: returns MD_OK if the labels at d_labels (M entries)
+// form a permutation; checks on the host the first time (pointer, M) is seen.
+int check_labels_once(const uint32_t* d_labels, int M, hipStream_t stream);
+
+int current_device(int* dev);
+
+// ---------------------------------------------------------------- prepared constellation
+// Device-side view of a prepared constellation (label order).
+struct Prepared {
+  const float* xl;          // M x D float32, row s = point with label s
+  const uint4* frag;        // MFMA A-operand fragments (see prep.hip)
+  int* flags;               // [0] labels invalid, [1] fallback count, [2] range overflow
+  unsigned* fb_list;        // fallback symbol indices (capacity N)
+  int ks;                   // number of 16-slot K steps of the fragment
+  float alpha;              // power-of-two operand balance a
+  float c_over_alpha;       // c / a, c = log2(e) / (2 sigma2)
+};
+
+// Builds the label-ordered copy, fragments and flags for one call.  `ws` must point
+// at a workspace of at least prep_bytes(M, D, N) bytes.
+size_t prep_bytes(int M, int D, int64_t N);
+int prepare(const float* d_X, const uint32_t* d_labels, int M, int D, int64_t N, float alpha,
+            float c_over_alpha, char* ws, hipStream_t stream, Prepared* out);
+
+int frag_ksteps(int D);    // ceil((3 D + 4) / 16) steps of 16 K slots
+
+}  // namespace md

@@ -1,0 +1,137 @@
+// gmi_reduce: Monte-Carlo GMI of bit-metric decoding from LLRs and transmitted labels.
+//   T_n = sum_k log2(1 + exp(-s_nk L_nk))  (FP32 per symbol; s = +1 for a sent 0 bit)
+//   GMI = m - (1/N) sum_n T_n,  GMI_k = 1 - (1/N) sum_n t_nk,  SE = std(T_n) / sqrt(N)
+// Each thread keeps Neumaier-compensated FP32 sums over a grid-stride range of symbols;
+// blocks reduce those in FP64 in a fixed order, and one final block adds the block
+// partials in FP64.  The grid depends only on N, so results are deterministic.
+#include <cmath>
+
+#include "common.hpp"
+#include "llr_kernels.hpp"
+
+namespace md {
+namespace {
+
+constexpr int kMaxM = 16;
+constexpr int kBlock = 256;
+constexpr int kMaxBlocks = 1024;
+
+struct Kahan {
+  float s, c;
+  __device__ void add(float x) {
+    const float t = s + x;
+    if (fabsf(s) >= fabsf(x)) c += (s - t) + x;
+    else c += (x - t) + s;
+    s = t;
+  }
+  __device__ double get() const { return static_cast<double>(s) + static_cast<double>(c); }
+};
+
+__device__ __forceinline__ float softplus_bits(float x) {
+  // log2(1 + e^x) = (max(x, 0) + log1p(e^-|x|)) / ln 2
+  return (fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)))) * 1.4426950408889634f;
+}
+
+__device__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kBlock / 2; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// partials: per block, [sum T, sum T^2, sum t_0 .. sum t_{m-1}]
+__global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __restrict__ llr, int64_t N, int m,
+                                                             const uint32_t* __restrict__ tx,
+                                                             const uint32_t* __restrict__ labels,
+                                                             double* __restrict__ partials) {
+  __shared__ double sh[kBlock];
+  Kahan sT{0.f, 0.f}, sT2{0.f, 0.f};
+  Kahan sb[kMaxM];
+#pragma unroll
+  for (int k = 0; k < kMaxM; ++k) sb[k] = Kahan{0.f, 0.f};
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t n = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; n < N; n += stride) {
+    const uint32_t u = tx[n];
+    const bool ok = u < (1u << m);                       // an index outside the labels gives NaN
+    const uint32_t lab = ok ? labels[u] : 0u;
+    float T = ok ? 0.0f : __builtin_nanf("");
+#pragma unroll
+    for (int k = 0; k < kMaxM; ++k) {
+      if (k < m) {
+        const float L = llr[n * m + k];
+        const float s = ((lab >> (m - 1 - k)) & 1u) ? 1.0f : -1.0f;   // -s_nk
+        const float t = softplus_bits(s * L);
+        sb[k].add(t);
+        T += t;
+      }
+    }
+    sT.add(T);
+    sT2.add(T * T);
+  }
+  const int nout = m + 2;
+  double v = block_sum(sT.get(), sh);
+  if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * nout + 0] = v;
+  v = block_sum(sT2.get(), sh);
+  if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * nout + 1] = v;
+  for (int k = 0; k < m; ++k) {
+    v = block_sum(sb[k].get(), sh);
+    if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * nout + 2 + k] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) gmi_final_kernel(const double* __restrict__ partials, int nblocks,
+                                                           int64_t N, int m, double* __restrict__ gmi,
+                                                           double* __restrict__ gmi_per_bit,
+                                                           double* __restrict__ se) {
+  __shared__ double sh[kBlock];
+  const int nout = m + 2;
+  double tot[kMaxM + 2];
+  for (int c = 0; c < nout; ++c) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) a += partials[static_cast<int64_t>(b) * nout + c];
+    tot[c] = block_sum(a, sh);
+  }
+  if (threadIdx.x == 0) {
+    const double Nd = static_cast<double>(N);
+    const double mean = tot[0] / Nd;
+    gmi[0] = static_cast<double>(m) - mean;
+    if (gmi_per_bit)
+      for (int k = 0; k < m; ++k) gmi_per_bit[k] = 1.0 - tot[2 + k] / Nd;
+    if (se) {
+      const double var = N > 1 ? (tot[1] - tot[0] * mean) / (Nd - 1.0) : 0.0;
+      se[0] = var > 0.0 ? sqrt(var) / sqrt(Nd) : 0.0;
+    }
+  }
+}
+
+int gmi_blocks(int64_t N) {
+  int64_t b = (N + kBlock - 1) / kBlock;
+  if (b > kMaxBlocks) b = kMaxBlocks;
+  if (b < 1) b = 1;
+  return static_cast<int>(b);
+}
+
+}  // namespace
+
+size_t gmi_workspace_bytes(int64_t N, int m) {
+  return carve_size(sizeof(double) * static_cast<size_t>(gmi_blocks(N)) * (m + 2));
+}
+
+int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels, double* d_gmi,
+               double* d_gmi_per_bit, double* d_se, char* ws, hipStream_t stream) {
+  const int nb = gmi_blocks(N);
+  double* partials = reinterpret_cast<double*>(ws);
+  hipLaunchKernelGGL(gmi_partial_kernel, dim3(nb), dim3(kBlock), 0, stream, d_llr, N, m, d_tx, d_labels, partials);
+  MD_LAUNCH_CHECK("gmi_partial_kernel launch");
+  hipLaunchKernelGGL(gmi_final_kernel, dim3(1), dim3(kBlock), 0, stream, partials, nb, N, m, d_gmi, d_gmi_per_bit,
+                     d_se);
+  MD_LAUNCH_CHECK("gmi_final_kernel launch");
+  return MD_OK;
+}
+
+}  // namespace md

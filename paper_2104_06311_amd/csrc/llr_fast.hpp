@@ -1,0 +1,681 @@
+// Fast MFMA kernel of the exact and max-log demappers (template shared by the two
+// translation units that instantiate it).  See llr.hip for the method.
+#pragma once
+
+#include <cmath>
+#include <cstdlib>
+
+#include "common.hpp"
+
+namespace md {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+namespace fastk {
+
+constexpr float kLn2 = 0.69314718055994530942f;
+
+__device__ __forceinline__ half8 as_half8(uint4 v) {
+  half8 h;
+  __builtin_memcpy(&h, &v, 16);
+  return h;
+}
+
+// ------------------------------------------------------------------ fast kernel
+// e = 2^(t + kExpBias): with t <= 0 (up to rounding) every partial sum stays below
+// 2^(16 + 1 + kExpBias) < 2^128, and a subset only loses FP32 range (sum < 2^-96, the
+// fallback trigger) when its best point is more than 196 base-2 units below -c||y||^2.
+constexpr float kExpBias = 100.0f;
+
+template <int MB>
+struct Geo {
+  static constexpr int LOG2G = MB - 5 < 3 ? MB - 5 : 3;   // tile-index bits handled inside a group
+  static constexpr int G = 1 << LOG2G;
+  static constexpr int NH = MB - 5 - LOG2G;               // tile-index bits routed through H0/H1
+  static constexpr int NHA = NH > 0 ? NH : 1;
+};
+
+template <int MB>
+struct SymAcc {
+  float E[16], Tg[Geo<MB>::G], H0[Geo<MB>::NHA], H1[Geo<MB>::NHA], GT;
+};
+
+// Bytes of LDS used to assemble the symbol-side (B) operand of one 32-symbol block.
+template <int KS>
+constexpr int bstage_bytes() { return 32 * 16 * KS * 2; }
+
+// Symbol (B) operand of the score contraction for the wavefront's symbol n (lane % 32):
+// the row of K slots [ w_hi (D), w_hi (D), w_lo (D), a, a, r_hi, r_lo, 0 ... ] with
+// w = (2c/a) y and r = (bias - c ||y||^2)/a is assembled in the wave's LDS staging row
+// (lane half 0 writes), then every lane reads its 8-slot fragments.  Returns true when
+// an operand leaves the FP16 split range (the symbol then takes the fallback path).
+template <int KS>
+__device__ __forceinline__ bool build_symbol_operand(_Float16* row, const float* __restrict__ y, int64_t n,
+                                                     bool live, int D, float cb, float cn, float alpha,
+                                                     float bias, half8 (&bf)[KS]) {
+  constexpr int S = 16 * KS;
+  const int h = (threadIdx.x & 63) >> 5;
+  float ysq = 0.0f;
+  bool bad = false;
+  for (int d = 0; d < D; ++d) {
+    const float yd = live ? y[n * D + d] : 0.0f;
+    ysq = fmaf(yd, yd, ysq);
+    const float w = cb * yd;
+    bad |= !(fabsf(w) <= 30000.0f);
+    const _Float16 hi = static_cast<_Float16>(w);
+    const _Float16 lo = static_cast<_Float16>(w - static_cast<float>(hi));
+    if (h == 0) {
+      row[d] = hi;
+      row[D + d] = hi;
+      row[2 * D + d] = lo;
+    }
+  }
+  const float r = bias / alpha - cn * ysq;
+  bad |= !(fabsf(r) <= 30000.0f);
+  const _Float16 rhi = static_cast<_Float16>(r);
+  const _Float16 rlo = static_cast<_Float16>(r - static_cast<float>(rhi));
+  if (h == 0) {
+    const _Float16 a16 = static_cast<_Float16>(alpha);
+    row[3 * D] = a16;
+    row[3 * D + 1] = a16;
+    row[3 * D + 2] = rhi;
+    row[3 * D + 3] = rlo;
+    for (int k = 3 * D + 4; k < S; ++k) row[k] = static_cast<_Float16>(0.0f);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const uint4 v = *reinterpret_cast<const uint4*>(row + 16 * ks + 8 * h);
+    __builtin_memcpy(&bf[ks], &v, 16);
+  }
+  return bad;
+}
+
+// Tiles are visited in groups of G = 2^LOG2G consecutive tiles so that the low LOG2G
+// bits of the tile index (label bits 5 .. 4+LOG2G) are compile-time inside a group:
+// their tile sums go to Tg[i]; only the group sum is routed by the remaining label
+// bits into H0/H1.  Each wavefront carries SB blocks of 32 symbols and reads the A
+// fragments of a tile once for all blocks.  The MFMAs of tile t+1 are issued before the
+// exponentials of tile t (hard scheduling fences keep that order), so a wavefront's
+// matrix work runs underneath its own VALU work.
+template <int KS, int WAVES, int MB, int SB, bool MAXLOG>
+__global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __restrict__ frag, int ntiles,
+                                                              int chunk_tiles, int D,
+                                                              const float* __restrict__ y, int64_t N, float cb,
+                                                              float cn, float alpha, float* __restrict__ llr,
+                                                              int* __restrict__ flags,
+                                                              unsigned* __restrict__ fb_list) {
+  constexpr int m = MB;
+  constexpr int LOG2G = Geo<MB>::LOG2G;
+  constexpr int G = Geo<MB>::G;
+  constexpr int nh = Geo<MB>::NH;
+  constexpr int NHMAX = Geo<MB>::NHA;
+  constexpr int S = 16 * KS;                 // K slots per symbol
+  extern __shared__ uint4 lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const bool invalid = flags[0] != 0;
+  const bool range_bad = flags[2] != 0;
+  const int64_t per_group = static_cast<int64_t>(WAVES) * 32 * SB;
+  const int64_t ngroups = (N + per_group - 1) / per_group;
+  const int nchunks = (ntiles + chunk_tiles - 1) / chunk_tiles;
+  const int frag_per_tile = KS * 64;
+  const float ident = MAXLOG ? -INFINITY : 0.0f;
+  // per-wave staging rows for the B operand, after the fragment chunk
+  _Float16* bst = reinterpret_cast<_Float16*>(lds + chunk_tiles * frag_per_tile) + wave * SB * 32 * S;
+  bool staged = false;
+
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    half8 bf[SB][KS];
+    SymAcc<MB> ac[SB];
+    bool bad[SB];
+    int64_t nsym[SB];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const int64_t n = g * per_group + (static_cast<int64_t>(wave) * SB + sb) * 32 + (lane & 31);
+      nsym[sb] = n;
+      const bool live = n < N;
+      const bool b = build_symbol_operand<KS>(bst + (sb * 32 + (lane & 31)) * S, y, n, live, D, cb, cn, alpha,
+                                              MAXLOG ? 0.0f : kExpBias, bf[sb]);
+      bad[sb] = b || range_bad;
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) ac[sb].E[rr] = ident;
+#pragma unroll
+      for (int i = 0; i < G; ++i) ac[sb].Tg[i] = ident;
+#pragma unroll
+      for (int q = 0; q < NHMAX; ++q) {
+        ac[sb].H0[q] = ident;
+        ac[sb].H1[q] = ident;
+      }
+    }
+
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const int t0 = ch * chunk_tiles;
+      const int tn = min(chunk_tiles, ntiles - t0);     // a multiple of G
+      if (nchunks > 1 || !staged) {
+        __syncthreads();
+        const int total = tn * frag_per_tile;
+        const uint4* src = frag + static_cast<int64_t>(t0) * frag_per_tile;
+        for (int i = threadIdx.x; i < total; i += WAVES * 64) lds[i] = src[i];
+        __syncthreads();
+        staged = true;
+      }
+      // prologue: score block of the chunk's first tile
+      floatx16 cur[SB];
+      {
+        half8 ah[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[ks * 64 + lane]);
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) {
+#pragma unroll
+          for (int rr = 0; rr < 16; ++rr) cur[sb][rr] = 0.0f;
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks)
+            cur[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], cur[sb], 0, 0, 0);
+        }
+      }
+      for (int tg = 0; tg < tn; tg += G) {
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          // issue the next tile's score blocks (the chunk's last tile recomputes itself)
+          const int tnext = min(tg + i + 1, tn - 1);
+          floatx16 nxt[SB];
+          half8 ah[KS];
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[(tnext * KS + ks) * 64 + lane]);
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) {
+#pragma unroll
+            for (int rr = 0; rr < 16; ++rr) nxt[sb][rr] = 0.0f;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+              nxt[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], nxt[sb], 0, 0, 0);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) {
+            SymAcc<MB>& A = ac[sb];
+            float v[16];
+            if (MAXLOG) {
+#pragma unroll
+              for (int rr = 0; rr < 16; ++rr) {
+                v[rr] = cur[sb][rr];
+                A.E[rr] = fmaxf(A.E[rr], v[rr]);
+              }
+#pragma unroll
+              for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+                for (int rr = 0; rr < w; ++rr) v[rr] = fmaxf(v[rr], v[rr + w]);
+              A.Tg[i] = fmaxf(A.Tg[i], v[0]);
+              A.GT = (i == 0) ? v[0] : fmaxf(A.GT, v[0]);
+            } else {
+#pragma unroll
+              for (int rr = 0; rr < 16; ++rr) {
+                v[rr] = __builtin_amdgcn_exp2f(cur[sb][rr]);
+                A.E[rr] += v[rr];
+              }
+#pragma unroll
+              for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+                for (int rr = 0; rr < w; ++rr) v[rr] += v[rr + w];
+              A.Tg[i] += v[0];
+              A.GT = (i == 0) ? v[0] : A.GT + v[0];
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) cur[sb] = nxt[sb];
+        }
+        // route the group sums by the label bits above the group
+        const int grp = (t0 + tg) >> LOG2G;
+#pragma unroll
+        for (int q = 0; q < nh; ++q) {
+          const bool bit = (grp >> q) & 1;
+#pragma unroll
+          for (int sb = 0; sb < SB; ++sb) {
+            SymAcc<MB>& A = ac[sb];
+            if (MAXLOG) {
+              A.H1[q] = bit ? fmaxf(A.H1[q], A.GT) : A.H1[q];
+              A.H0[q] = bit ? A.H0[q] : fmaxf(A.H0[q], A.GT);
+            } else {
+              const float a = bit ? A.GT : 0.0f;
+              A.H1[q] += a;
+              A.H0[q] += A.GT - a;
+            }
+          }
+        }
+      }
+    }
+
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const SymAcc<MB>& A = ac[sb];
+      const int64_t n = nsym[sb];
+      const bool live = n < N;
+      // subset sums per label bit.  bits 0..3: positions inside the lane; bit 4: lane
+      // half; bits 5..4+LOG2G: Tg; bits 5+LOG2G ..: H0/H1.
+      float L0[4 + LOG2G], L1[4 + LOG2G];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        float a0 = ident, a1 = ident;
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) {
+          if ((rr >> b) & 1) a1 = MAXLOG ? fmaxf(a1, A.E[rr]) : a1 + A.E[rr];
+          else a0 = MAXLOG ? fmaxf(a0, A.E[rr]) : a0 + A.E[rr];
+        }
+        L0[b] = a0;
+        L1[b] = a1;
+      }
+#pragma unroll
+      for (int b = 0; b < LOG2G; ++b) {
+        float a0 = ident, a1 = ident;
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+          if ((i >> b) & 1) a1 = MAXLOG ? fmaxf(a1, A.Tg[i]) : a1 + A.Tg[i];
+          else a0 = MAXLOG ? fmaxf(a0, A.Tg[i]) : a0 + A.Tg[i];
+        }
+        L0[4 + b] = a0;
+        L1[4 + b] = a1;
+      }
+      const float Th = MAXLOG ? fmaxf(L0[0], L1[0]) : L0[0] + L1[0];
+      float pL0[4 + LOG2G], pL1[4 + LOG2G], pH0[NHMAX], pH1[NHMAX];
+#pragma unroll
+      for (int b = 0; b < 4 + LOG2G; ++b) {
+        pL0[b] = __shfl_xor(L0[b], 32, 64);
+        pL1[b] = __shfl_xor(L1[b], 32, 64);
+      }
+      const float pTh = __shfl_xor(Th, 32, 64);
+#pragma unroll
+      for (int q = 0; q < NHMAX; ++q) {
+        pH0[q] = __shfl_xor(A.H0[q], 32, 64);
+        pH1[q] = __shfl_xor(A.H1[q], 32, 64);
+      }
+      const bool badp = __shfl_xor(static_cast<int>(bad[sb]), 32, 64) != 0;
+      if (h == 0 && live) {
+        if (invalid) {
+          for (int k = 0; k < m; ++k) llr[n * m + k] = __builtin_nanf("");
+        } else {
+          float S0[m], S1[m];
+          float smin = INFINITY, smax = 0.0f;
+#pragma unroll
+          for (int b = 0; b < m; ++b) {
+            float a0, a1;
+            if (b < 4) {
+              a0 = MAXLOG ? fmaxf(L0[b], pL0[b]) : L0[b] + pL0[b];
+              a1 = MAXLOG ? fmaxf(L1[b], pL1[b]) : L1[b] + pL1[b];
+            } else if (b == 4) {
+              a0 = Th;
+              a1 = pTh;
+            } else if (b < 5 + LOG2G) {
+              a0 = MAXLOG ? fmaxf(L0[b - 1], pL0[b - 1]) : L0[b - 1] + pL0[b - 1];
+              a1 = MAXLOG ? fmaxf(L1[b - 1], pL1[b - 1]) : L1[b - 1] + pL1[b - 1];
+            } else {
+              const int q = b - 5 - LOG2G;
+              a0 = MAXLOG ? fmaxf(A.H0[q], pH0[q]) : A.H0[q] + pH0[q];
+              a1 = MAXLOG ? fmaxf(A.H1[q], pH1[q]) : A.H1[q] + pH1[q];
+            }
+            S0[b] = a0;
+            S1[b] = a1;
+            smin = fminf(smin, fminf(a0, a1));
+            smax = fmaxf(smax, fmaxf(a0, a1));
+          }
+          const bool range_lost = MAXLOG ? false : !(smin >= 0x1p-96f && smax <= 0x1p+126f);
+          if (bad[sb] || badp || range_lost) {
+            const int idx = atomicAdd(&flags[1], 1);
+            fb_list[idx] = static_cast<unsigned>(n);
+          } else {
+#pragma unroll
+            for (int k = 0; k < m; ++k) {
+              const int b = m - 1 - k;
+              llr[n * m + k] = MAXLOG ? kLn2 * (S0[b] - S1[b]) : kLn2 * (log2f(S0[b]) - log2f(S1[b]));
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int KS, int WAVES, int MB, int SB, bool MAXLOG>
+int launch_fast_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
+                  hipStream_t stream) {
+  const int ntiles = M / 32;
+  const int frag_tile_bytes = KS * 64 * 16;
+  const int bstage = WAVES * SB * bstage_bytes<KS>();
+  const int max_lds = 160 * 1024 - bstage;
+  int chunk_tiles = max_lds / frag_tile_bytes;
+  constexpr int G = Geo<MB>::G;
+  chunk_tiles -= chunk_tiles % G;
+  if (chunk_tiles > ntiles) chunk_tiles = ntiles;
+  if (chunk_tiles < G) return fail(MD_EUNSUPPORTED, "constellation fragments do not fit in LDS");
+  const size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
+  auto kern = llr_fast_kernel<KS, WAVES, MB, SB, MAXLOG>;
+  static bool attr_done = false;
+  if (!attr_done) {
+    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr_done = true;
+  }
+  int dev = 0, ncu = 0, occ = 0;
+  MD_HIP_TRY(hipGetDevice(&dev));
+  MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  MD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kern), WAVES * 64,
+                                                           lds_bytes));
+  if (occ < 1) occ = 1;
+  const int64_t per_group = static_cast<int64_t>(WAVES) * 32 * SB;
+  const int64_t ngroups = (N + per_group - 1) / per_group;
+  int64_t grid = static_cast<int64_t>(ncu) * occ;
+  if (grid > ngroups) grid = ngroups;
+  const double c = P.c_over_alpha * static_cast<double>(P.alpha);
+  const float cb = static_cast<float>(2.0 * c / P.alpha);
+  const float cn = P.c_over_alpha;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(WAVES * 64), lds_bytes, stream, P.frag, ntiles,
+                     chunk_tiles, D, d_y, N, cb, cn, P.alpha, d_llr, P.flags, P.fb_list);
+  MD_LAUNCH_CHECK("llr_fast_kernel launch");
+  return MD_OK;
+}
+
+template <int KS, int W, int SBV, bool MAXLOG>
+int launch_fast_m(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
+                  hipStream_t stream) {
+  switch (ilog2_pow2(M)) {
+    case 5: return launch_fast_t<KS, W, 5, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 6: return launch_fast_t<KS, W, 6, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 7: return launch_fast_t<KS, W, 7, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 8: return launch_fast_t<KS, W, 8, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 9: return launch_fast_t<KS, W, 9, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 10: return launch_fast_t<KS, W, 10, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 11: return launch_fast_t<KS, W, 11, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 12: return launch_fast_t<KS, W, 12, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 13: return launch_fast_t<KS, W, 13, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 14: return launch_fast_t<KS, W, 14, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 15: return launch_fast_t<KS, W, 15, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    default: return launch_fast_t<KS, W, 16, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+  }
+}
+
+// Launch shapes of the fast kernel: (wavefronts per block, 32-symbol blocks per wavefront)
+// for one or two K steps: 0: (8, 2)  2: (16, 1).  More K steps use (8, 1).
+inline int fast_variant() {
+  static int g_fast_variant = -1;
+  if (g_fast_variant < 0) {
+    const char* e = std::getenv("MDEMAP_FAST_VARIANT");
+    g_fast_variant = e ? std::atoi(e) : 0;
+    if (g_fast_variant < 0 || g_fast_variant > 2) g_fast_variant = 0;
+  }
+  return g_fast_variant;
+}
+
+template <bool MAXLOG>
+int launch_fast(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
+                hipStream_t stream) {
+  const int v = fast_variant();
+  switch (P.ks) {
+    case 1:
+      if (v == 2) return launch_fast_m<1, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+      return launch_fast_m<1, 8, 2, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 2:
+      if (v == 2) return launch_fast_m<2, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+      return launch_fast_m<2, 8, 2, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 3: return launch_fast_m<3, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 4: return launch_fast_m<4, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 5: return launch_fast_m<5, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    default: return launch_fast_m<6, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+  }
+}
+
+
+// ------------------------------------------------------------------ BF16 subset-sum kernel
+// Same scores as llr_fast_kernel; the exponentials are rounded to BF16 and the 2m subset
+// sums are a second MFMA contraction, e (32 points x 32 symbols) against the 0/1 matrix
+// R (32 rows x 32 points): row b < 16 selects the points whose label has bit b set, row
+// 16 + b those with bit b clear.  Two v_mfma_f32_32x32x16_bf16 per tile accumulate the
+// sums in FP32 over all tiles, so each pair costs one exponential and half a conversion
+// instruction on the VALU.  R's columns follow the B-operand layout of the exponentials:
+// K slot k of reduction step q is the point at tile offset 16 (k / 8) + 8 q + k % 8.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <int KS, int WAVES, int MB, int SB>
+__global__ void __launch_bounds__(WAVES * 64) llr_bf16_kernel(const uint4* __restrict__ frag, int ntiles,
+                                                              int chunk_tiles, int D,
+                                                              const float* __restrict__ y, int64_t N, float cb,
+                                                              float cn, float alpha, float* __restrict__ llr,
+                                                              int* __restrict__ flags,
+                                                              unsigned* __restrict__ fb_list) {
+  constexpr int m = MB;
+  constexpr int S = 16 * KS;
+  extern __shared__ uint4 lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const bool invalid = flags[0] != 0;
+  const bool range_bad = flags[2] != 0;
+  const int64_t per_group = static_cast<int64_t>(WAVES) * 32 * SB;
+  const int64_t ngroups = (N + per_group - 1) / per_group;
+  const int nchunks = (ntiles + chunk_tiles - 1) / chunk_tiles;
+  const int frag_per_tile = KS * 64;
+  _Float16* bst = reinterpret_cast<_Float16*>(lds + chunk_tiles * frag_per_tile) + wave * SB * 32 * S;
+  // this lane's row of R: label bit rb, selecting label bit value want
+  const int rrow = lane & 31;
+  const int rb = rrow & 15;
+  const uint32_t want = rrow < 16 ? 1u : 0u;
+  const bool r_low = rb < 5 && rb < m;       // decided by the offset inside the tile
+  const bool r_high = rb >= 5 && rb < m;     // decided by the tile index
+  constexpr uint32_t kOne = 0x3F80u;         // BF16 1.0
+  uint32_t lowA[2][4];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      uint32_t word = 0;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const uint32_t off = 16u * h + 8u * q + 2u * w + e;
+        const bool sel = r_low && (((off >> rb) & 1u) == want);
+        word |= (sel ? kOne : 0u) << (16 * e);
+      }
+      lowA[q][w] = word;
+    }
+  bool staged = false;
+
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    half8 bf[SB][KS];
+    floatx16 R[SB];
+    bool bad[SB];
+    int64_t nsym[SB];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const int64_t n = g * per_group + (static_cast<int64_t>(wave) * SB + sb) * 32 + (lane & 31);
+      nsym[sb] = n;
+      const bool b = build_symbol_operand<KS>(bst + (sb * 32 + (lane & 31)) * S, y, n, n < N, D, cb, cn, alpha,
+                                              kExpBias, bf[sb]);
+      bad[sb] = b || range_bad;
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) R[sb][rr] = 0.0f;
+    }
+
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const int t0 = ch * chunk_tiles;
+      const int tn = min(chunk_tiles, ntiles - t0);
+      if (nchunks > 1 || !staged) {
+        __syncthreads();
+        const int total = tn * frag_per_tile;
+        const uint4* src = frag + static_cast<int64_t>(t0) * frag_per_tile;
+        for (int i = threadIdx.x; i < total; i += WAVES * 64) lds[i] = src[i];
+        __syncthreads();
+        staged = true;
+      }
+      floatx16 cur[SB];
+      {
+        half8 ah[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[ks * 64 + lane]);
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) {
+#pragma unroll
+          for (int rr = 0; rr < 16; ++rr) cur[sb][rr] = 0.0f;
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks)
+            cur[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], cur[sb], 0, 0, 0);
+        }
+      }
+      for (int t = 0; t < tn; ++t) {
+        const int tnext = min(t + 1, tn - 1);
+        floatx16 nxt[SB];
+        half8 ah[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[(tnext * KS + ks) * 64 + lane]);
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) {
+#pragma unroll
+          for (int rr = 0; rr < 16; ++rr) nxt[sb][rr] = 0.0f;
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks)
+            nxt[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], nxt[sb], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // reduction matrix of this tile
+        const uint32_t tau = static_cast<uint32_t>(t0 + t);
+        const uint32_t hv = (r_high && (((tau >> (rb - 5)) & 1u) == want)) ? (kOne | (kOne << 16)) : 0u;
+        bf16x8 A[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          uint32_t wv[4];
+#pragma unroll
+          for (int w = 0; w < 4; ++w) wv[w] = r_high ? hv : lowA[q][w];
+          __builtin_memcpy(&A[q], wv, 16);
+        }
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) {
+          bf16x8 B[2];
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int v = 0; v < 8; ++v) B[q][v] = static_cast<__bf16>(__builtin_amdgcn_exp2f(cur[sb][8 * q + v]));
+          R[sb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0], B[0], R[sb], 0, 0, 0);
+          R[sb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[1], B[1], R[sb], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int sb = 0; sb < SB; ++sb) cur[sb] = nxt[sb];
+      }
+    }
+
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const int64_t n = nsym[sb];
+      // lane half h holds result rows 8 (r / 4) + 4 h + r % 4; gather all 32 rows in half 0
+      float P[16];
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) P[rr] = __shfl_xor(R[sb][rr], 32, 64);
+      const bool badp = __shfl_xor(static_cast<int>(bad[sb]), 32, 64) != 0;
+      if (h == 0 && n < N) {
+        if (invalid) {
+          for (int k = 0; k < m; ++k) llr[n * m + k] = __builtin_nanf("");
+        } else {
+          float rowv[32];
+#pragma unroll
+          for (int rr = 0; rr < 16; ++rr) {
+            rowv[8 * (rr / 4) + (rr % 4)] = R[sb][rr];
+            rowv[8 * (rr / 4) + 4 + (rr % 4)] = P[rr];
+          }
+          float smin = INFINITY, smax = 0.0f;
+#pragma unroll
+          for (int b = 0; b < m; ++b) {
+            smin = fminf(smin, fminf(rowv[b], rowv[16 + b]));
+            smax = fmaxf(smax, fmaxf(rowv[b], rowv[16 + b]));
+          }
+          const bool range_lost = !(smin >= 0x1p-96f && smax <= 0x1p+126f);
+          if (bad[sb] || badp || range_lost) {
+            const int idx = atomicAdd(&flags[1], 1);
+            fb_list[idx] = static_cast<unsigned>(n);
+          } else {
+#pragma unroll
+            for (int k = 0; k < m; ++k) {
+              const int b = m - 1 - k;
+              llr[n * m + k] = kLn2 * (log2f(rowv[16 + b]) - log2f(rowv[b]));
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int KS, int WAVES, int MB, int SB>
+int launch_bf16_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr, hipStream_t stream) {
+  const int ntiles = M / 32;
+  const int frag_tile_bytes = KS * 64 * 16;
+  const int bstage = WAVES * SB * bstage_bytes<KS>();
+  int chunk_tiles = (160 * 1024 - bstage) / frag_tile_bytes;
+  if (chunk_tiles > ntiles) chunk_tiles = ntiles;
+  if (chunk_tiles < 1) return fail(MD_EUNSUPPORTED, "constellation fragments do not fit in LDS");
+  const size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
+  auto kern = llr_bf16_kernel<KS, WAVES, MB, SB>;
+  static bool attr_done = false;
+  if (!attr_done) {
+    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr_done = true;
+  }
+  int dev = 0, ncu = 0, occ = 0;
+  MD_HIP_TRY(hipGetDevice(&dev));
+  MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  MD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kern), WAVES * 64,
+                                                           lds_bytes));
+  if (occ < 1) occ = 1;
+  const int64_t per_group = static_cast<int64_t>(WAVES) * 32 * SB;
+  const int64_t ngroups = (N + per_group - 1) / per_group;
+  int64_t grid = static_cast<int64_t>(ncu) * occ;
+  if (grid > ngroups) grid = ngroups;
+  const double c = P.c_over_alpha * static_cast<double>(P.alpha);
+  const float cb = static_cast<float>(2.0 * c / P.alpha);
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(WAVES * 64), lds_bytes, stream, P.frag, ntiles,
+                     chunk_tiles, D, d_y, N, cb, P.c_over_alpha, P.alpha, d_llr, P.flags, P.fb_list);
+  MD_LAUNCH_CHECK("llr_bf16_kernel launch");
+  return MD_OK;
+}
+
+template <int KS, int W, int SB>
+int launch_bf16_m(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr, hipStream_t stream) {
+  switch (ilog2_pow2(M)) {
+    case 5: return launch_bf16_t<KS, W, 5, SB>(P, M, D, d_y, N, d_llr, stream);
+    case 6: return launch_bf16_t<KS, W, 6, SB>(P, M, D, d_y, N, d_llr, stream);
+    case 7: return launch_bf16_t<KS, W, 7, SB>(P, M, D, d_y, N, d_llr, stream);
+    case 8: return launch_bf16_t<KS, W, 8, SB>(P, M, D, d_y, N, d_llr, stream);
+    case 9: return launch_bf16_t<KS, W, 9, SB>(P, M, D, d_y, N, d_llr, stream);
+    case 10: return launch_bf16_t<KS, W, 10, SB>(P, M, D, d_y, N, d_llr, stream);
+    case 11: return launch_bf16_t<KS, W, 11, SB>(P, M, D, d_y, N, d_llr, stream);
+    case 12: return launch_bf16_t<KS, W, 12, SB>(P, M, D, d_y, N, d_llr, stream);
+    case 13: return launch_bf16_t<KS, W, 13, SB>(P, M, D, d_y, N, d_llr, stream);
+    case 14: return launch_bf16_t<KS, W, 14, SB>(P, M, D, d_y, N, d_llr, stream);
+    case 15: return launch_bf16_t<KS, W, 15, SB>(P, M, D, d_y, N, d_llr, stream);
+    default: return launch_bf16_t<KS, W, 16, SB>(P, M, D, d_y, N, d_llr, stream);
+  }
+}
+
+inline int launch_bf16(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr,
+                       hipStream_t stream) {
+  const int v = fast_variant();
+  switch (P.ks) {
+    case 1:
+      if (v == 2) return launch_bf16_m<1, 16, 1>(P, M, D, d_y, N, d_llr, stream);
+      return launch_bf16_m<1, 8, 2>(P, M, D, d_y, N, d_llr, stream);
+    case 2:
+      if (v == 2) return launch_bf16_m<2, 16, 1>(P, M, D, d_y, N, d_llr, stream);
+      return launch_bf16_m<2, 8, 2>(P, M, D, d_y, N, d_llr, stream);
+    case 3: return launch_bf16_m<3, 8, 1>(P, M, D, d_y, N, d_llr, stream);
+    case 4: return launch_bf16_m<4, 8, 1>(P, M, D, d_y, N, d_llr, stream);
+    case 5: return launch_bf16_m<5, 8, 1>(P, M, D, d_y, N, d_llr, stream);
+    default: return launch_bf16_m<6, 8, 1>(P, M, D, d_y, N, d_llr, stream);
+  }
+}
+
+}  // namespace fastk
+
+}  // namespace md

@@ -1,0 +1,32 @@
+// Launchers implemented by the kernel translation units.
+#pragma once
+
+#include "common.hpp"
+
+namespace md {
+
+int launch_awgn(const float* d_X, int M, int D, uint64_t seed, uint64_t offset, int64_t N, double sigma,
+                uint32_t* d_tx, float* d_y, hipStream_t stream);
+
+// Power-of-two scale a that balances the two operands of the split-FP16 score
+// contraction, and c / a with c = log2(e) / (2 sigma2).
+void score_scales(double sigma2, float* alpha, float* c_over_alpha);
+
+// Fast MFMA path (M >= 32) followed by the careful kernel on the fallback list, or the
+// careful kernel on every symbol (M < 32).
+int launch_llr(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, bool maxlog,
+               bool bf16, float* d_llr, hipStream_t stream);
+int launch_fast_exact(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
+                      hipStream_t stream);
+int launch_fast_maxlog(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2,
+                       float* d_llr, hipStream_t stream);
+int launch_fast_bf16(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr,
+                     hipStream_t stream);
+int launch_llr_careful_all(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2,
+                           bool maxlog, float* d_llr, hipStream_t stream);
+
+size_t gmi_workspace_bytes(int64_t N, int m);
+int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels, double* d_gmi,
+               double* d_gmi_per_bit, double* d_se, char* ws, hipStream_t stream);
+
+}  // namespace md

@@ -1,0 +1,136 @@
+// Host runtime of the library: error strings, per-(device, stream) workspaces and the
+// host-side label check cache.
+#include <map>
+#include <mutex>
+#include <set>
+#include <utility>
+#include <vector>
+
+#include "common.hpp"
+
+namespace md {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int status, const std::string& msg) {
+  g_last_error = msg;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory) return MD_ENOMEM;
+  if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return MD_ENODEV;
+  return MD_EHIP;
+}
+
+int current_device(int* dev) {
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n == 0) return fail(MD_ENODEV, "no GPU visible");
+  MD_HIP_TRY(hipGetDevice(dev));
+  return MD_OK;
+}
+
+namespace {
+struct WsEntry {
+  char* ptr = nullptr;
+  size_t cap = 0;
+};
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, WsEntry> g_ws;
+
+std::mutex g_lab_mu;
+std::set<std::tuple<int, const uint32_t*, int>> g_lab_ok;
+}  // namespace
+
+int workspace(hipStream_t stream, size_t bytes, char** out) {
+  int dev = 0;
+  int st = current_device(&dev);
+  if (st != MD_OK) return st;
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  WsEntry& w = g_ws[{dev, stream}];
+  if (w.cap < bytes) {
+    size_t cap = bytes + bytes / 4 + (1 << 20);
+    if (w.ptr) {
+      // the old buffer may still be in use by work queued on this stream
+      MD_HIP_TRY(hipStreamSynchronize(stream));
+      MD_HIP_TRY(hipFree(w.ptr));
+      w.ptr = nullptr;
+      w.cap = 0;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, cap);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MD_ENOMEM, "workspace allocation of " + std::to_string(cap) + " bytes failed");
+    }
+    w.ptr = static_cast<char*>(p);
+    w.cap = cap;
+  }
+  *out = w.ptr;
+  return MD_OK;
+}
+
+int check_labels_once(const uint32_t* d_labels, int M, hipStream_t stream) {
+  int dev = 0;
+  int st = current_device(&dev);
+  if (st != MD_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_lab_mu);
+    if (g_lab_ok.count({dev, d_labels, M})) return MD_OK;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  MD_HIP_TRY(hipStreamIsCapturing(stream, &cap));
+  if (cap != hipStreamCaptureStatusNone) return MD_OK;   // the device-side check still applies
+  std::vector<uint32_t> h(static_cast<size_t>(M));
+  MD_HIP_TRY(hipMemcpyAsync(h.data(), d_labels, sizeof(uint32_t) * M, hipMemcpyDeviceToHost, stream));
+  MD_HIP_TRY(hipStreamSynchronize(stream));
+  std::vector<char> seen(static_cast<size_t>(M), 0);
+  for (int j = 0; j < M; ++j) {
+    if (h[j] >= static_cast<uint32_t>(M))
+      return fail(MD_ELABEL, "label " + std::to_string(h[j]) + " of point " + std::to_string(j) +
+                                 " is outside [0, M)");
+    if (seen[h[j]]) return fail(MD_ELABEL, "label " + std::to_string(h[j]) + " is used twice");
+    seen[h[j]] = 1;
+  }
+  std::lock_guard<std::mutex> lk(g_lab_mu);
+  g_lab_ok.insert({dev, d_labels, M});
+  return MD_OK;
+}
+
+int release_workspaces() {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (!g_ws.empty()) MD_HIP_TRY(hipDeviceSynchronize());
+  for (auto& kv : g_ws) {
+    if (kv.second.ptr) {
+      int cur = 0;
+      MD_HIP_TRY(hipGetDevice(&cur));
+      MD_HIP_TRY(hipSetDevice(kv.first.first));
+      hipError_t e = hipFree(kv.second.ptr);
+      MD_HIP_TRY(hipSetDevice(cur));
+      if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
+    }
+  }
+  g_ws.clear();
+  std::lock_guard<std::mutex> lk2(g_lab_mu);
+  g_lab_ok.clear();
+  return MD_OK;
+}
+
+}  // namespace md
+
+extern "C" {
+
+int release_cache(void) {
+  md::set_error("");
+  return md::release_workspaces();
+}
+
+const char* last_error(void) { return md::g_last_error.c_str(); }
+
+int mdemap_version(void) { return 100; }
+
+}  // extern "C"

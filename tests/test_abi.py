@@ -1,0 +1,82 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function that
+include/mdemap.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mdemap.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("awgn_sample", "llr_exact", "llr_maxlog", "gmi_reduce",
+                     "release_cache", "last_error"):
+        assert required in names, required
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2104_06311_amd import _lib
+    L = _lib.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), f"libmdemap.so does not export {name}"
+    # and the binding describes every declared function
+    for name in declared_functions():
+        assert name in _lib.SIGNATURES, f"binding has no signature for {name}"
+
+
+
+def test_argument_validation_before_device_work():
+    from paper_2104_06311_amd._lib import lib
+    L = lib()
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: validation fails first
+    # M not a power of two
+    assert L.llr_exact(fake, fake, 48, 4, fake, 10, 0.1, 0, fake, None) == -2
+    assert L.llr_exact(fake, fake, 1, 4, fake, 10, 0.1, 0, fake, None) == -2
+    assert L.llr_exact(fake, fake, 131072, 4, fake, 10, 0.1, 0, fake, None) == -2
+    # D out of range
+    assert L.llr_exact(fake, fake, 64, 0, fake, 10, 0.1, 0, fake, None) == -4
+    assert L.llr_exact(fake, fake, 64, 31, fake, 10, 0.1, 0, fake, None) == -4
+    # sigma2 <= 0, NaN, inf
+    for s2 in (0.0, -1.0, float("nan"), float("inf")):
+        assert L.llr_exact(fake, fake, 64, 4, fake, 10, s2, 0, fake, None) == -1
+    # negative N, null pointers, unknown precision
+    assert L.llr_exact(fake, fake, 64, 4, fake, -1, 0.1, 0, fake, None) == -1
+    assert L.llr_exact(None, fake, 64, 4, fake, 10, 0.1, 0, fake, None) == -1
+    assert L.llr_exact(fake, None, 64, 4, fake, 10, 0.1, 0, fake, None) == -1
+    assert L.llr_exact(fake, fake, 64, 4, None, 10, 0.1, 0, fake, None) == -1
+    assert L.llr_exact(fake, fake, 64, 4, fake, 10, 0.1, 7, fake, None) == -1
+    assert L.llr_maxlog(fake, fake, 64, 4, fake, 10, -0.1, fake, None) == -1
+    assert b"sigma2" in L.last_error()
+    # awgn_sample
+    assert L.awgn_sample(fake, 6, 2, 1, 0, 10, 0.1, fake, fake, None) == -2
+    assert L.awgn_sample(fake, 8, 2, 1, 0, 10, -0.1, fake, fake, None) == -1
+    assert L.awgn_sample(fake, 8, 2, 1, 0, 10, 0.1, None, fake, None) == -1
+    # gmi_reduce: N = 0 undefined, m out of range
+    assert L.gmi_reduce(fake, 0, 4, fake, fake, fake, None, None, None) == -1
+    assert L.gmi_reduce(fake, 10, 17, fake, fake, fake, None, None, None) == -1
+    assert L.gmi_reduce(fake, 10, 4, fake, fake, None, None, None, None) == -1
+
+
+def test_no_device_is_reported_not_crashed():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_2104_06311_amd._lib import lib
+    L = lib()
+    fake = ctypes.c_void_p(0x1000)
+    assert L.llr_exact(fake, fake, 64, 4, fake, 10, 0.1, 0, fake, None) == -7
+    assert L.awgn_sample(fake, 8, 2, 1, 0, 10, 0.1, fake, fake, None) == -7
+    assert L.gmi_reduce(fake, 10, 4, fake, fake, fake, None, None, None) == -7
+    assert L.release_cache() == 0
+    assert L.mdemap_version() >= 100

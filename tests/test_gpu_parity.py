@@ -1,0 +1,272 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle on the
+same seeded inputs.
+
+Tolerances (derivation in the design notes):
+  * awgn_sample: bit-exact (tx indices and float32 bit patterns).
+  * LLRs, FP32 precision: |dL| <= 2e-3 + 2e-4 |L|.  The score contraction is a
+    three-pass split-FP16 MFMA product whose dropped lo*lo term and FP32
+    accumulation leave an error of a few 2^-22 of sum_k |a_k b_k| (up to ~1e3 in
+    base-2 exponent units at 14 dB) on each exponent, so ~3e-4 nat per score.
+  * max-log LLRs: same bound.
+  * LLRs, BF16 precision: the exponentials are rounded to BF16 (relative error
+    <= 2^-9 per term), so each subset sum is within 2^-9 and the LLR within
+    2 * 2^-9 ~ 3.9e-3 nat, plus the score error: |dL| <= 6e-3 + 2e-4 |L|.
+  * GMI: |dGMI| <= 1e-4 bit (the target), measured on the same y and tx.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+ATOL = 2e-3
+RTOL = 2e-4
+
+
+def md():
+    import paper_2104_06311_amd as m
+    return m
+
+
+def to_dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def labels_dev(labels):
+    return to_dev(labels.astype(np.int64).astype(np.int32))
+
+
+def channel(X, labels, snr_db, N, seed, offset=0):
+    """Draw the channel on the GPU; return host copies too."""
+    s2 = synth.sigma2_from_snr_db(X, snr_db)
+    Xd = to_dev(X)
+    tx, y = md().awgn_sample(Xd, seed, offset, N, math.sqrt(s2))
+    torch.cuda.synchronize()
+    return s2, Xd, tx, y, tx.cpu().numpy().astype(np.uint32), y.cpu().numpy()
+
+
+def assert_llr_close(got, ref, atol=ATOL, rtol=RTOL, what=""):
+    err = np.abs(got.astype(np.float64) - ref)
+    bound = atol + rtol * np.abs(ref)
+    worst = np.argmax(err - bound)
+    assert np.all(np.isfinite(got)), what + ": non-finite LLR"
+    assert np.all(err <= bound), (f"{what}: max |dL| {err.max():.3e}, worst at {np.unravel_index(worst, err.shape)} "
+                                  f"got {got.flat[worst]} ref {ref.flat[worst]}")
+    return float(err.max())
+
+
+# ----------------------------------------------------------------------------- AWGN
+@pytest.mark.parametrize("M,D,seed,offset,N", [
+    (64, 4, 2104, 0, 100_003),
+    (2048, 8, 2105, 3, 20_000),
+    (2, 1, 1, 0, 5000),
+    (8, 3, 77, (1 << 32) - 100, 4097),     # offset crosses the 32-bit counter word
+    (65536, 16, 2108, 123456789012, 3000),
+    (16, 30, 9, 0, 1000),
+])
+def test_awgn_bit_exact_against_cpu_twin(M, D, seed, offset, N):
+    X, _ = synth.gaussian_constellation(M, D, seed)
+    sigma = 0.37
+    txd, yd = md().awgn_sample(to_dev(X), seed, offset, N, sigma)
+    tx_ref, y_ref = oracle.awgn(X, seed, offset, N, sigma)
+    assert np.array_equal(txd.cpu().numpy().astype(np.uint32), tx_ref)
+    assert np.array_equal(yd.cpu().numpy().view(np.uint32), y_ref.view(np.uint32))
+
+
+def test_awgn_window_consistency():
+    X, _ = synth.gaussian_constellation(256, 4, 3)
+    Xd = to_dev(X)
+    tx, y = md().awgn_sample(Xd, 5, 1000, 50_000, 0.2)
+    tx2, y2 = md().awgn_sample(Xd, 5, 1000 + 12_345, 1000, 0.2)
+    assert torch.equal(tx[12_345:13_345], tx2) and torch.equal(y[12_345:13_345], y2)
+
+
+# ----------------------------------------------------------------------------- exact LLR + GMI
+def _parity(X, labels, snr_db, N, seed, maxlog=False, prec="fp32"):
+    s2, Xd, tx, y, txh, yh = channel(X, labels, snr_db, N, seed)
+    ld = labels_dev(labels)
+    if maxlog:
+        L = md().llr_maxlog(Xd, ld, y, s2)
+        ref = oracle.llr_maxlog(X, labels, yh, s2)
+    else:
+        L = md().llr_exact(Xd, ld, y, s2, prec=prec)
+        ref = oracle.llr_exact(X, labels, yh, s2)
+    Lh = L.cpu().numpy()
+    atol = ATOL if prec == "fp32" else 6e-3
+    err = assert_llr_close(Lh, ref, atol=atol, what=f"M={X.shape[0]} D={X.shape[1]} snr={snr_db} {prec}")
+    g, gb, se = md().gmi_reduce(L, tx, ld)
+    g_ref, gb_ref, se_ref = oracle.gmi(ref, txh, labels)
+    g = float(g.item())
+    assert abs(g - g_ref) <= 1e-4, (g, g_ref)
+    # the reduction alone: GPU gmi_reduce vs FP64 GMI of the very same float32 LLRs
+    g_same, gb_same, se_same = oracle.gmi(Lh.astype(np.float64), txh, labels)
+    assert abs(g - g_same) <= 1e-6 * max(1.0, abs(g_same))
+    np.testing.assert_allclose(gb.cpu().numpy(), gb_same, atol=1e-6)
+    assert abs(float(se.item()) - se_same) <= 1e-6 + 1e-3 * se_same
+    return err, g, g_ref
+
+
+def test_parity_4d_64_8psk_product_full():
+    """4D M=64 (two 8-PSK, BRGC, 6 bits) at 8 dB, N = 1e5 seeded symbols, in full."""
+    X, labels = synth.product_4d_8psk()
+    err, g, g_ref = _parity(X, labels, 8.0, 100_000, 2104)
+    assert 4.6 < g < 4.9
+
+
+@pytest.mark.parametrize("snr_db", [4.0, 9.0, 14.0])
+def test_parity_8d_2048_subset(snr_db):
+    """8D M=2048 Gaussian constellation: a 20,000-symbol window of the sweep."""
+    X, labels = synth.gaussian_constellation(2048, 8, synth.SEED_BASE + 1)
+    _parity(X, labels, snr_db, 20_000, synth.SEED_BASE + 1)
+
+
+@pytest.mark.parametrize("M,D,N,snr,perm", [
+    (2, 1, 1000, 3.0, False), (4, 2, 777, 8.0, True), (16, 3, 2049, 10.0, True),
+    (32, 2, 5000, 12.0, True), (64, 4, 4099, 6.0, True), (256, 8, 3333, 11.0, True),
+    (1024, 13, 1500, 9.0, True), (128, 14, 999, 7.0, True), (512, 16, 700, 12.0, True),
+    (64, 30, 300, 20.0, True), (4096, 2, 1200, 16.0, True), (64, 5, 1, 8.0, True),
+])
+def test_parity_random_problems(M, D, N, snr, perm):
+    X, labels = synth.gaussian_constellation(M, D, 1000 + M + D)
+    if perm:
+        labels = synth.random_labels(M, M * 7 + D)
+    _parity(X, labels, snr, N, 31 + M)
+
+
+@pytest.mark.parametrize("M,D,N,snr", [(2048, 8, 20_000, 4.0), (2048, 8, 20_000, 14.0), (64, 4, 30_001, 8.0),
+                                       (32, 2, 3000, 10.0), (4096, 8, 2000, 12.0), (256, 16, 1500, 9.0),
+                                       (128, 30, 700, 15.0)])
+def test_parity_bf16_subset_sums(M, D, N, snr):
+    if M == 64 and D == 4:
+        X, labels = synth.product_4d_8psk()
+    else:
+        X, labels = synth.gaussian_constellation(M, D, 77 + M + D)
+        labels = synth.random_labels(M, D)
+    _parity(X, labels, snr, N, 41, prec="bf16")
+
+
+@pytest.mark.parametrize("M,D,snr", [(64, 4, 8.0), (2048, 8, 14.0), (2, 1, 0.0), (4, 2, 8.0), (256, 16, 12.0)])
+def test_parity_maxlog(M, D, snr):
+    if M == 64 and D == 4:
+        X, labels = synth.product_4d_8psk()
+    elif M == 2:
+        X, labels = synth.bpsk()
+    elif M == 4:
+        X, labels = synth.gray_qpsk()
+    else:
+        X, labels = synth.gaussian_constellation(M, D, 5 + M)
+    _parity(X, labels, snr, 5000, 7, maxlog=True)
+
+
+def test_maxlog_equals_exact_for_gray_qpsk():
+    X, labels = synth.gray_qpsk()
+    s2, Xd, tx, y, txh, yh = channel(X, labels, 8.0, 10_000, 3)
+    ld = labels_dev(labels)
+    a = float(X[0, 0])
+    closed = np.stack([2 * a * yh[:, 1] / s2, 2 * a * yh[:, 0] / s2], axis=1)
+    assert_llr_close(md().llr_exact(Xd, ld, y, s2).cpu().numpy(), closed)
+    assert_llr_close(md().llr_maxlog(Xd, ld, y, s2).cpu().numpy(), closed)
+
+
+# ----------------------------------------------------------------------------- edge cases
+def test_far_symbols_take_the_careful_path():
+    X, labels = synth.gaussian_constellation(256, 4, 1)
+    rng = np.random.default_rng(0)
+    y = (rng.standard_normal((600, 4)) * 30).astype(np.float32)     # far from every point
+    y[:300] = X[rng.integers(0, 256, 300)] + 0.05 * rng.standard_normal((300, 4)).astype(np.float32)
+    s2 = 0.004
+    L = md().llr_exact(to_dev(X), labels_dev(labels), to_dev(y), s2).cpu().numpy()
+    ref = oracle.llr_exact(X, labels, y, s2)
+    assert_llr_close(L, ref, atol=ATOL, rtol=RTOL, what="far symbols")
+
+
+def test_extreme_snr_range_fallback():
+    # sigma2 so small that the split-FP16 operands overflow: every symbol must still be exact
+    X, labels = synth.gaussian_constellation(64, 4, 2)
+    rng = np.random.default_rng(1)
+    y = (X[rng.integers(0, 64, 500)] + 1e-4 * rng.standard_normal((500, 4))).astype(np.float32)
+    s2 = 1e-9
+    L = md().llr_exact(to_dev(X), labels_dev(labels), to_dev(y), s2).cpu().numpy()
+    ref = oracle.llr_exact(X, labels, y, s2)
+    assert_llr_close(L, ref, atol=ATOL, rtol=RTOL, what="extreme snr")
+
+
+def test_empty_input_is_a_no_op_and_gmi_rejects_it():
+    X, labels = synth.gaussian_constellation(64, 4, 2)
+    Xd, ld = to_dev(X), labels_dev(labels)
+    y = torch.empty((0, 4), dtype=torch.float32, device="cuda")
+    assert md().llr_exact(Xd, ld, y, 0.1).shape == (0, 6)
+    assert md().llr_maxlog(Xd, ld, y, 0.1).shape == (0, 6)
+    tx, y0 = md().awgn_sample(Xd, 1, 0, 0, 0.1)
+    assert tx.numel() == 0
+    with pytest.raises(md().MdemapError):
+        md().gmi_reduce(torch.empty((0, 6), dtype=torch.float32, device="cuda"),
+                        torch.empty(0, dtype=torch.int32, device="cuda"), ld)
+
+
+def test_invalid_labels_are_rejected():
+    X, _ = synth.gaussian_constellation(64, 4, 2)
+    bad = np.arange(64, dtype=np.uint32)
+    bad[5] = 7                           # duplicate
+    y = to_dev(np.zeros((10, 4), dtype=np.float32))
+    with pytest.raises(md().MdemapError) as e:
+        md().llr_exact(to_dev(X), labels_dev(bad), y, 0.1)
+    assert e.value.status == -3
+    bad2 = np.arange(64, dtype=np.uint32)
+    bad2[0] = 64                         # out of range
+    with pytest.raises(md().MdemapError):
+        md().llr_maxlog(to_dev(X), labels_dev(bad2), y, 0.1)
+
+
+def test_results_do_not_depend_on_label_storage_order():
+    X, labels = synth.gaussian_constellation(512, 8, 4)
+    labels = synth.random_labels(512, 3)
+    s2, Xd, tx, y, txh, yh = channel(X, labels, 10.0, 3000, 5)
+    L1 = md().llr_exact(Xd, labels_dev(labels), y, s2)
+    perm = np.random.default_rng(2).permutation(512)
+    L2 = md().llr_exact(to_dev(X[perm]), labels_dev(labels[perm]), y, s2)
+    assert torch.equal(L1, L2)          # the prep puts points in label order: identical bits
+
+
+def test_deterministic_gmi():
+    X, labels = synth.gaussian_constellation(1024, 8, 6)
+    s2, Xd, tx, y, txh, yh = channel(X, labels, 9.0, 200_000, 8)
+    ld = labels_dev(labels)
+    L = md().llr_exact(Xd, ld, y, s2)
+    g1 = md().gmi_reduce(L, tx, ld)[0].item()
+    g2 = md().gmi_reduce(L, tx, ld)[0].item()
+    assert g1 == g2
+
+
+# ----------------------------------------------------------------------------- full size
+def test_full_size_8d_2048_sampled_rows():
+    """The benchmark's configuration (N = 1e7 per SNR, 8D M = 2048): sampled rows against
+    the oracle, GMI bounds and monotonicity across the SNR sweep ends."""
+    X, labels = synth.gaussian_constellation(2048, 8, synth.SEED_BASE + 1)
+    Xd, ld = to_dev(X), labels_dev(labels)
+    N = 10_000_000
+    rng = np.random.default_rng(9)
+    rows = np.sort(rng.choice(N, 1500, replace=False))
+    prev = -1.0
+    for snr in (4.0, 14.0):
+        s2 = synth.sigma2_from_snr_db(X, snr)
+        tx, y = md().awgn_sample(Xd, synth.SEED_BASE + 1, 0, N, math.sqrt(s2))
+        L = md().llr_exact(Xd, ld, y, s2)
+        g, _, se = md().gmi_reduce(L, tx, ld)
+        g = g.item()
+        assert 0.0 <= g <= 11.0 and g > prev
+        prev = g
+        idx = torch.from_numpy(rows).cuda()
+        ys = y[idx].cpu().numpy()
+        Ls = L[idx].cpu().numpy()
+        assert_llr_close(Ls, oracle.llr_exact(X, labels, ys, s2), what=f"full-size rows snr={snr}")
+        del tx, y, L
+        torch.cuda.empty_cache()
