@@ -138,6 +138,56 @@ int gmi_reduce(const float* d_llr, int64_t N, int m, const uint32_t* d_tx,
                const uint32_t* d_labels, double* d_gmi, double* d_gmi_per_bit, double* d_se,
                void* stream);
 
+/* ------------------------------------------------------------------ learned demapper */
+/* A small network f: R^D -> R^m approximating the exact LLRs, trained on the GPU by the
+ * library's own kernels on (y, exact-LLR) pairs that llr_exact produces; the exact path
+ * stays the reference that judges it (through gmi_reduce).  The glossary's ML entry is
+ * the only mention of learning in the paper; the network and its training are this
+ * library's design:
+ *   f(y) = W3 g(W2 g(W1 y + b1) + b2) + b3,  hidden width H in both layers,
+ *   g(a) = a (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3))) / 2   (GELU, tanh form),
+ *   loss = mean_b sum_k p_bk softplus(-f_bk) + (1 - p_bk) softplus(f_bk),
+ *          p_bk = sigmoid(L_target_bk)   (distillation of the exact bit posteriors),
+ *   Adam (beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master weights.
+ * Every product runs as a BF16 MFMA with FP32 accumulation.  Parameters form one FP32
+ * vector in the order W1 (H x D), b1 (H), W2 (H x H), b2 (H), W3 (m x H), b3 (m), row-major
+ * [out][in]; initial values are uniform in +-1/sqrt(fan_in) from Philox4x32-10 (key =
+ * seed, counter = (index_lo, index_hi, 0, 3)).  A handle is bound to the device that was
+ * current at mlp_create and must be used on that device.  Handles are not thread-safe. */
+
+/* Creates a network (1 <= D <= 30, 1 <= hidden <= 4096, 1 <= m <= 16).  *out receives the
+ * handle; release it with mlp_destroy. */
+int mlp_create(int D, int hidden, int m, uint64_t seed, void** out);
+int mlp_destroy(void* mlp);
+/* Number of parameters P, or -1 for a NULL handle. */
+int64_t mlp_num_params(const void* mlp);
+int mlp_info(const void* mlp, int* D, int* hidden, int* m, int64_t* step);
+/* Copies P floats between host memory and the handle (synchronises the device).
+ * which: 0 parameters, 1 last gradient, 2 Adam first moment, 3 Adam second moment. */
+int mlp_get(const void* mlp, int which, float* h_out);
+int mlp_set(void* mlp, int which, const float* h_in);
+/* Forward + backward on a batch: d_y B x D, d_target B x m (exact LLRs); gradients are
+ * kept in the handle, the mean loss goes to d_loss (1 double, device) unless NULL. */
+int mlp_grad(void* mlp, const float* d_y, const float* d_target, int64_t B, double* d_loss, void* stream);
+/* One Adam update with the last gradient. */
+int mlp_adam_step(void* mlp, float lr, void* stream);
+/* mlp_grad followed by mlp_adam_step. */
+int mlp_train_step(void* mlp, const float* d_y, const float* d_target, int64_t B, float lr, double* d_loss,
+                   void* stream);
+/* `steps` training steps on batches of B rows drawn with replacement from the N pairs
+ * (a hash of (shuffle_seed, step, row) picks the rows), learning rate on a cosine
+ * schedule from lr_max to lr_min; d_loss_trace receives `steps` doubles or is NULL.
+ * Allocates its batch buffers and returns after the stream has drained. */
+int mlp_fit(void* mlp, const float* d_y, const float* d_target, int64_t N, int64_t steps, int64_t B,
+            float lr_max, float lr_min, uint64_t shuffle_seed, double* d_loss_trace, void* stream);
+/* llr_learned -- network LLRs for N symbols: d_y N x D float32 -> d_llr N x m float32,
+ * same column order and sign as llr_exact.  N = 0 enqueues nothing. */
+int llr_learned(const void* mlp, const float* d_y, int64_t N, float* d_llr, void* stream);
+/* Checkpoint: parameters, Adam moments and step count, with a CRC-32 over the data.
+ * mlp_load creates a new handle on the current device; a corrupt file is MD_EINVAL. */
+int mlp_save(const void* mlp, const char* path);
+int mlp_load(const char* path, void** out);
+
 /* ------------------------------------------------------------------ housekeeping */
 /* Frees every internal device workspace (synchronises the device first). */
 int release_cache(void);

@@ -352,13 +352,20 @@ void orc_gmi(const double* llr, int64_t N, int m, const uint32_t* tx, const uint
 }
 
 /* ------------------------------------------------------------------------- */
-/* MLP demapper reference: f(y) = W3 g(W2 g(W1 y + b1) + b2) + b3 with
- * g(a) = a Phi(a) = a (1 + erf(a / sqrt 2)) / 2 (GELU).  Weights are row-major
- * [out][in].  Loss per sample: sum_k p_k softplus(-f_k) + (1 - p_k) softplus(f_k)
- * with p_k = sigmoid(L_target_k), averaged over the batch. */
-static double orc_gelu(double a) { return 0.5 * a * (1.0 + erf(a / M_SQRT2)); }
+/* MLP demapper reference: f(y) = W3 g(W2 g(W1 y + b1) + b2) + b3 with the GELU
+ * activation in its tanh form (Hendrycks & Gimpel):
+ *   g(a) = a (1 + tanh(k (a + 0.044715 a^3))) / 2,  k = sqrt(2 / pi).
+ * Weights are row-major [out][in].  Loss per sample:
+ * sum_k p_k softplus(-f_k) + (1 - p_k) softplus(f_k) with p_k = sigmoid(L_target_k),
+ * averaged over the batch. */
+static double orc_gelu(double a) {
+    const double k = sqrt(2.0 / M_PI);
+    return 0.5 * a * (1.0 + tanh(k * (a + 0.044715 * a * a * a)));
+}
 static double orc_gelu_grad(double a) {
-    return 0.5 * (1.0 + erf(a / M_SQRT2)) + a * exp(-0.5 * a * a) / sqrt(2.0 * M_PI);
+    const double k = sqrt(2.0 / M_PI);
+    double th = tanh(k * (a + 0.044715 * a * a * a));
+    return 0.5 * (1.0 + th) + 0.5 * a * (1.0 - th * th) * k * (1.0 + 3.0 * 0.044715 * a * a);
 }
 static double orc_sigmoid(double t) {
     return t >= 0.0 ? 1.0 / (1.0 + exp(-t)) : exp(t) / (1.0 + exp(t));

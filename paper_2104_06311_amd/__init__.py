@@ -12,7 +12,7 @@ import torch
 
 from ._lib import MdemapError, PREC, check, lib
 
-__all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "gmi_reduce", "release_cache", "MdemapError",
+__all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "gmi_reduce", "llr_learned", "MLP", "release_cache", "MdemapError",
            "log2_exact"]
 
 
@@ -118,3 +118,109 @@ def gmi_reduce(llr, tx, labels, per_bit: bool = True, se: bool = True):
 
 def release_cache():
     check("release_cache", lib().release_cache())
+
+
+# ----------------------------------------------------------------------------- learned demapper
+class MLP:
+    """Handle of a learned demapper D -> hidden -> hidden -> m (see mlp_* in mdemap.h)."""
+
+    def __init__(self, D: int = 0, hidden: int = 0, m: int = 0, seed: int = 0, _handle=None):
+        import ctypes
+        if _handle is None:
+            h = ctypes.c_void_p()
+            check("mlp_create", lib().mlp_create(D, hidden, m, seed & (2 ** 64 - 1), ctypes.byref(h)))
+            _handle = h
+        self._h = _handle
+        d, hh, mm, st = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        check("mlp_info", lib().mlp_info(self._h, ctypes.byref(d), ctypes.byref(hh), ctypes.byref(mm),
+                                         ctypes.byref(st)))
+        self.D, self.hidden, self.m = d.value, hh.value, mm.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def num_params(self) -> int:
+        return int(lib().mlp_num_params(self._h))
+
+    @property
+    def step(self) -> int:
+        import ctypes
+        st = ctypes.c_int64()
+        check("mlp_info", lib().mlp_info(self._h, None, None, None, ctypes.byref(st)))
+        return st.value
+
+    def close(self):
+        if self._h is not None:
+            check("mlp_destroy", lib().mlp_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if self._h is not None:
+                lib().mlp_destroy(self._h)
+        except Exception:
+            pass
+
+    def get(self, which: int = 0):
+        import numpy as np
+        out = np.zeros(self.num_params, dtype=np.float32)
+        check("mlp_get", lib().mlp_get(self._h, which, out.ctypes.data))
+        return out
+
+    def set(self, values, which: int = 0):
+        import numpy as np
+        v = np.ascontiguousarray(values, dtype=np.float32)
+        if v.size != self.num_params:
+            raise ValueError("wrong number of parameters")
+        check("mlp_set", lib().mlp_set(self._h, which, v.ctypes.data))
+
+    def grad(self, y, target):
+        _dev(y, "y", torch.float32, 2)
+        _dev(target, "target", torch.float32, 2)
+        loss = torch.empty(1, dtype=torch.float64, device=y.device)
+        check("mlp_grad", lib().mlp_grad(self._h, _ptr(y), _ptr(target), y.shape[0], _ptr(loss), _stream()))
+        return loss
+
+    def adam_step(self, lr: float):
+        check("mlp_adam_step", lib().mlp_adam_step(self._h, float(lr), _stream()))
+
+    def train_step(self, y, target, lr: float):
+        _dev(y, "y", torch.float32, 2)
+        _dev(target, "target", torch.float32, 2)
+        loss = torch.empty(1, dtype=torch.float64, device=y.device)
+        check("mlp_train_step", lib().mlp_train_step(self._h, _ptr(y), _ptr(target), y.shape[0], float(lr),
+                                                     _ptr(loss), _stream()))
+        return loss
+
+    def fit(self, y, target, steps: int, batch: int = 4096, lr_max: float = 1e-3, lr_min: float = 1e-5,
+            seed: int = 0, trace: bool = True):
+        _dev(y, "y", torch.float32, 2)
+        _dev(target, "target", torch.float32, 2)
+        tr = torch.empty(max(steps, 1), dtype=torch.float64, device=y.device) if trace else None
+        check("mlp_fit", lib().mlp_fit(self._h, _ptr(y), _ptr(target), y.shape[0], steps, batch, float(lr_max),
+                                       float(lr_min), seed & (2 ** 64 - 1), _ptr(tr), _stream()))
+        return tr
+
+    def save(self, path: str):
+        check("mlp_save", lib().mlp_save(self._h, path.encode()))
+
+    @classmethod
+    def load(cls, path: str) -> "MLP":
+        import ctypes
+        h = ctypes.c_void_p()
+        check("mlp_load", lib().mlp_load(path.encode(), ctypes.byref(h)))
+        return cls(_handle=h)
+
+
+def llr_learned(mlp: MLP, y, out=None):
+    """Network LLRs float32[N, m] for received symbols y float32[N, D]."""
+    _dev(y, "y", torch.float32, 2)
+    if y.shape[1] != mlp.D:
+        raise ValueError("y must have D columns")
+    N = y.shape[0]
+    if out is None:
+        out = torch.empty((N, mlp.m), dtype=torch.float32, device=y.device)
+    check("llr_learned", lib().llr_learned(mlp.handle, _ptr(y), N, _ptr(out), _stream()))
+    return out

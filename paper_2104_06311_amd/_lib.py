@@ -31,6 +31,19 @@ SIGNATURES = {
     "llr_exact": (_I, [_P, _P, _I, _I, _P, _I64, _D, _I, _P, _P]),
     "llr_maxlog": (_I, [_P, _P, _I, _I, _P, _I64, _D, _P, _P]),
     "gmi_reduce": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P, _P]),
+    "mlp_create": (_I, [_I, _I, _I, _U64, ctypes.POINTER(ctypes.c_void_p)]),
+    "mlp_destroy": (_I, [_P]),
+    "mlp_num_params": (_I64, [_P]),
+    "mlp_info": (_I, [_P, _P, _P, _P, _P]),
+    "mlp_get": (_I, [_P, _I, _P]),
+    "mlp_set": (_I, [_P, _I, _P]),
+    "mlp_grad": (_I, [_P, _P, _P, _I64, _P, _P]),
+    "mlp_adam_step": (_I, [_P, _F, _P]),
+    "mlp_train_step": (_I, [_P, _P, _P, _I64, _F, _P, _P]),
+    "mlp_fit": (_I, [_P, _P, _P, _I64, _I64, _I64, _F, _F, _U64, _P, _P]),
+    "llr_learned": (_I, [_P, _P, _I64, _P, _P]),
+    "mlp_save": (_I, [_P, ctypes.c_char_p]),
+    "mlp_load": (_I, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
     "release_cache": (_I, []),
     "last_error": (ctypes.c_char_p, []),
     "mdemap_version": (_I, []),

@@ -1,0 +1,879 @@
+// Learned demapper: a D -> H -> H -> m GELU network trained on (y, exact LLR) pairs by
+// the library's own BF16 MFMA kernels, and its inference.
+//
+//   f(y) = W3 g(W2 g(W1 y + b1) + b2) + b3,  g(a) = a sigmoid(2k (a + 0.044715 a^3)),
+//   k = sqrt(2/pi)  (the tanh form of GELU: a (1 + tanh(k (a + 0.044715 a^3))) / 2).
+//   loss = mean over the batch of sum_k p_k softplus(-f_k) + (1 - p_k) softplus(f_k),
+//   p_k = sigmoid(L_exact_k), so that dloss/df = (sigmoid(f) - p) / B.
+//
+// Parameters live on the device as one FP32 vector (W1, b1, W2, b2, W3, b3, row-major
+// [out][in]) with FP32 Adam moments.  Every product is a BF16 MFMA with FP32
+// accumulation: operands are rounded to BF16 when they are staged into LDS.
+//
+// Training: a tiled GEMM (64x64 block tile, v_mfma_f32_32x32x16_bf16) with fused
+// epilogues (bias + GELU storing pre- and post-activation; multiplication by GELU'),
+// a loss kernel that also forms dloss/df, column sums for the bias gradients, and
+// an elementwise Adam kernel.  Inference (llr_learned) for H <= 256: one fused kernel
+// holds all weights in LDS as BF16 MFMA fragments; each wavefront pushes 32 symbols
+// through the three layers, and the hidden units of each layer are ordered so that
+// the MFMA result registers of one layer are directly the B operand of the next.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+#include "llr_kernels.hpp"
+
+namespace md {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+namespace {
+
+constexpr float kGeluK2 = 1.5957691216057308f;    // 2 sqrt(2/pi)
+constexpr float kGeluC = 0.044715f;
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ __forceinline__ float sigmoidf_fast(float v) {
+  // 1 / (1 + 2^(-v log2 e)); exact limits 0 and 1 for large |v|
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-v * kLog2e));
+}
+__device__ __forceinline__ float gelu(float a) {
+  const float v = kGeluK2 * fmaf(kGeluC * a * a, a, a);
+  return a * sigmoidf_fast(v);
+}
+__device__ __forceinline__ float gelu_grad(float a) {
+  const float v = kGeluK2 * fmaf(kGeluC * a * a, a, a);
+  const float s = sigmoidf_fast(v);
+  const float dv = kGeluK2 * fmaf(3.0f * kGeluC, a * a, 1.0f);
+  return s + a * s * (1.0f - s) * dv;
+}
+__device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+__device__ __forceinline__ float sigmoidf_acc(float t) {
+  return t >= 0.0f ? 1.0f / (1.0f + expf(-t)) : expf(t) / (1.0f + expf(t));
+}
+
+// ------------------------------------------------------------------ generic GEMM
+// C[i][j] = sum_k A(i,k) B(k,j), A(i,k) = A[i*sar + k*sac], B(k,j) = B[k*sbr + j*sbc]
+// (FP32 in memory, BF16 in the MFMA), C row-major with leading dimension ldc.
+enum { EPI_STORE = 0, EPI_BIAS_GELU = 1, EPI_GELU_GRAD = 2 };
+
+template <int EPI>
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(const float* __restrict__ A, int64_t sar, int64_t sac,
+                                                        const float* __restrict__ B, int64_t sbr, int64_t sbc,
+                                                        int M, int N, int K, float* __restrict__ C, int64_t ldc,
+                                                        const float* __restrict__ bias, float* __restrict__ C2,
+                                                        const float* __restrict__ Z) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[64][16];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[64][16];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  floatx16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    // stage a 64x16 A tile and a 16x64 B tile (B stored transposed: row j, column k)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid * 4 + e;        // 0..1023
+      const int r = idx >> 4, kk = idx & 15;
+      const int gi = i0 + r, gk = k0 + kk, gj = j0 + r;
+      const float av = (gi < M && gk < K) ? A[gi * sar + gk * sac] : 0.0f;
+      const float bv = (gj < N && gk < K) ? B[gk * sbr + gj * sbc] : 0.0f;
+      As[r][kk] = static_cast<__bf16>(av);
+      Bs[r][kk] = static_cast<__bf16>(bv);
+    }
+    __syncthreads();
+    bf16x8 a, b;
+    __builtin_memcpy(&a, &As[wi + (lane & 31)][8 * h], 16);
+    __builtin_memcpy(&b, &Bs[wj + (lane & 31)][8 * h], 16);
+    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    __syncthreads();
+  }
+  const int j = j0 + wj + (lane & 31);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = i0 + wi + 8 * (r >> 2) + 4 * h + (r & 3);
+    if (i < M && j < N) {
+      float v = acc[r];
+      const int64_t o = static_cast<int64_t>(i) * ldc + j;
+      if (EPI == EPI_STORE) {
+        if (bias) v += bias[j];
+        C[o] = v;
+      } else if (EPI == EPI_BIAS_GELU) {
+        v += bias[j];
+        C[o] = v;
+        C2[o] = gelu(v);
+      } else {
+        C[o] = v * gelu_grad(Z[o]);
+      }
+    }
+  }
+}
+
+template <int EPI>
+int gemm(const float* A, int64_t sar, int64_t sac, const float* B, int64_t sbr, int64_t sbc, int M, int N, int K,
+         float* C, int64_t ldc, const float* bias, float* C2, const float* Z, hipStream_t s) {
+  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  hipLaunchKernelGGL(gemm_bf16_kernel<EPI>, grid, dim3(256), 0, s, A, sar, sac, B, sbr, sbc, M, N, K, C, ldc, bias,
+                     C2, Z);
+  MD_LAUNCH_CHECK("gemm_bf16_kernel launch");
+  return MD_OK;
+}
+
+// ------------------------------------------------------------------ loss, bias grads, Adam
+// One thread per sample: loss terms and dloss/df = (sigmoid(f) - sigmoid(L)) / B.
+// partials[block] = sum of the block's per-sample losses (FP64, fixed order).
+__global__ void __launch_bounds__(256) loss_grad_kernel(const float* __restrict__ f, const float* __restrict__ tgt,
+                                                        int64_t B, int m, float* __restrict__ df,
+                                                        double* __restrict__ partials) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  const int64_t b = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (b < B) {
+    const float invB = 1.0f / static_cast<float>(B);
+    for (int k = 0; k < m; ++k) {
+      const float z = f[b * m + k];
+      const float p = sigmoidf_acc(tgt[b * m + k]);
+      acc += static_cast<double>(p * softplusf(-z) + (1.0f - p) * softplusf(z));
+      df[b * m + k] = (sigmoidf_acc(z) - p) * invB;
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sh[0];
+}
+
+__global__ void loss_final_kernel(const double* __restrict__ partials, int nb, int64_t B, double* __restrict__ loss) {
+  __shared__ double sh[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) a += partials[i];
+  sh[threadIdx.x] = a;
+  __syncthreads();
+  for (int w = 128; w >= 1; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[0] = sh[0] / static_cast<double>(B);
+}
+
+// out[j] = sum_b G[b][j] (column sums; one thread per column, fixed order)
+__global__ void colsum_kernel(const float* __restrict__ G, int64_t B, int n, float* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  float s = 0.0f, c = 0.0f;
+  for (int64_t b = 0; b < B; ++b) {
+    const float x = G[b * n + j];
+    const float t = s + x;
+    c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  out[j] = s + c;
+}
+
+// Adam (Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; w -= lr m^ / (sqrt(v^) + eps)
+__global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m1,
+                            float* __restrict__ m2, int64_t P, float lr, float b1, float b2, float eps, float c1,
+                            float c2) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.0f - b1) * gi;
+  const float v = b2 * m2[i] + (1.0f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = v;
+  w[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// Gathers the rows idx[b] of y (D columns) and t (m columns) into contiguous batches.
+__global__ void gather_kernel(const float* __restrict__ y, const float* __restrict__ t, int D, int m, int64_t N,
+                              uint64_t seed, uint64_t step, int64_t B, float* __restrict__ yb,
+                              float* __restrict__ tb) {
+  const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  // index = floor(u * N / 2^32) from a 64-bit mix of (seed, step, b): uniform up to N / 2^32
+  uint64_t x = seed ^ (step * 0x9E3779B97F4A7C15ull) ^ (static_cast<uint64_t>(b) * 0xD1B54A32D192ED03ull);
+  x ^= x >> 31;
+  x *= 0xBF58476D1CE4E5B9ull;
+  x ^= x >> 29;
+  x *= 0x94D049BB133111EBull;
+  x ^= x >> 32;
+  const int64_t idx = static_cast<int64_t>(((x & 0xFFFFFFFFull) * static_cast<uint64_t>(N)) >> 32);
+  for (int d = 0; d < D; ++d) yb[b * D + d] = y[idx * D + d];
+  for (int k = 0; k < m; ++k) tb[b * m + k] = t[idx * m + k];
+}
+
+// ------------------------------------------------------------------ fused inference
+// LDS image (BF16 fragments, built by pack_infer_kernel from the FP32 master weights):
+//   f1[rb][lane]           layer 1, hidden rows 32 rb + lane % 32, K slots 8 (lane/32) .. +7
+//                          of [y (D), 1 (bias), 0 ...]
+//   f2[ob][rb][q][lane]    layer 2: output rows 32 ob + lane % 32, input units of K step
+//                          (rb, q) in the order of the layer-1 result registers
+//   f3[rb][q][lane]        layer 3, output rows lane % 32 (rows >= m are zero)
+//   b2[H], b3[32]          FP32 biases
+// The K slot kk = 8 h + v of step (rb, q) is hidden unit 32 rb + 8 (2q + v/4) + 4h + v%4,
+// exactly the unit that lane half h holds in register 8q + v of block rb.
+__device__ __forceinline__ int unit_of_slot(int rb, int q, int kk) {
+  const int hh = kk >> 3, v = kk & 7;
+  return 32 * rb + 8 * (2 * q + (v >> 2)) + 4 * hh + (v & 3);
+}
+
+struct InferLayout {
+  int H, nrb;
+  size_t f1, f2, f3, b2, b3, bytes;    // byte offsets
+};
+
+inline InferLayout infer_layout(int H) {
+  InferLayout L;
+  L.H = H;
+  L.nrb = H / 32;
+  size_t o = 0;
+  L.f1 = o;
+  o += static_cast<size_t>(L.nrb) * 64 * 16;
+  L.f2 = o;
+  o += static_cast<size_t>(L.nrb) * L.nrb * 2 * 64 * 16;
+  L.f3 = o;
+  o += static_cast<size_t>(L.nrb) * 2 * 64 * 16;
+  L.b2 = o;
+  o += static_cast<size_t>(H) * 4;
+  L.b3 = o;
+  o += 32 * 4;
+  L.bytes = o;
+  return L;
+}
+
+__global__ void pack_infer_kernel(const float* __restrict__ w, int D, int H, int m, InferLayout L,
+                                  char* __restrict__ img) {
+  const int nrb = L.nrb;
+  const float* W1 = w;
+  const float* b1 = W1 + static_cast<int64_t>(H) * D;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + static_cast<int64_t>(H) * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + static_cast<int64_t>(m) * H;
+  const int64_t n1 = static_cast<int64_t>(nrb) * 64;
+  const int64_t n2 = static_cast<int64_t>(nrb) * nrb * 2 * 64;
+  const int64_t n3 = static_cast<int64_t>(nrb) * 2 * 64;
+  const int64_t total = n1 + n2 + n3 + H + 32;
+  for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (t < n1) {
+      const int rb = static_cast<int>(t / 64), lane = static_cast<int>(t % 64);
+      const int row = 32 * rb + (lane & 31), hh = lane >> 5;
+      __bf16 v8[8];
+      for (int v = 0; v < 8; ++v) {
+        const int k = 8 * hh + v;
+        const float x = k < D ? W1[static_cast<int64_t>(row) * D + k] : (k == D ? b1[row] : 0.0f);
+        v8[v] = static_cast<__bf16>(x);
+      }
+      __builtin_memcpy(img + L.f1 + t * 16, v8, 16);
+    } else if (t < n1 + n2) {
+      const int64_t u = t - n1;
+      const int lane = static_cast<int>(u % 64);
+      const int q = static_cast<int>((u / 64) % 2);
+      const int rb = static_cast<int>((u / 128) % nrb);
+      const int ob = static_cast<int>(u / (128 * nrb));
+      const int row = 32 * ob + (lane & 31), hh = lane >> 5;
+      __bf16 v8[8];
+      for (int v = 0; v < 8; ++v)
+        v8[v] = static_cast<__bf16>(W2[static_cast<int64_t>(row) * H + unit_of_slot(rb, q, 8 * hh + v)]);
+      __builtin_memcpy(img + L.f2 + u * 16, v8, 16);
+    } else if (t < n1 + n2 + n3) {
+      const int64_t u = t - n1 - n2;
+      const int lane = static_cast<int>(u % 64);
+      const int q = static_cast<int>((u / 64) % 2);
+      const int rb = static_cast<int>(u / 128);
+      const int row = lane & 31, hh = lane >> 5;
+      __bf16 v8[8];
+      for (int v = 0; v < 8; ++v)
+        v8[v] = static_cast<__bf16>(row < m ? W3[static_cast<int64_t>(row) * H + unit_of_slot(rb, q, 8 * hh + v)]
+                                            : 0.0f);
+      __builtin_memcpy(img + L.f3 + u * 16, v8, 16);
+    } else if (t < n1 + n2 + n3 + H) {
+      const int64_t i = t - n1 - n2 - n3;
+      reinterpret_cast<float*>(img + L.b2)[i] = b2[i];
+    } else {
+      const int64_t i = t - n1 - n2 - n3 - H;
+      reinterpret_cast<float*>(img + L.b3)[i] = i < m ? b3[i] : 0.0f;
+    }
+  }
+}
+
+template <int NRB>
+__global__ void __launch_bounds__(512) mlp_infer_kernel(const char* __restrict__ img, InferLayout L, int D, int m,
+                                                        const float* __restrict__ y, int64_t N,
+                                                        float* __restrict__ llr) {
+  extern __shared__ uint4 smem[];
+  char* lds = reinterpret_cast<char*>(smem);
+  for (size_t i = threadIdx.x; i < L.bytes / 16; i += blockDim.x)
+    smem[i] = reinterpret_cast<const uint4*>(img)[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int h = lane >> 5;
+  const uint4* f1 = reinterpret_cast<const uint4*>(lds + L.f1);
+  const uint4* f2 = reinterpret_cast<const uint4*>(lds + L.f2);
+  const uint4* f3 = reinterpret_cast<const uint4*>(lds + L.f3);
+  const float* b2 = reinterpret_cast<const float*>(lds + L.b2);
+  const float* b3 = reinterpret_cast<const float*>(lds + L.b3);
+  const int64_t ntile = (N + 31) / 32;
+  for (int64_t tile = static_cast<int64_t>(blockIdx.x) * nw + wave; tile < ntile;
+       tile += static_cast<int64_t>(gridDim.x) * nw) {
+    const int64_t n = tile * 32 + (lane & 31);
+    const bool live = n < N;
+    // layer-1 B operand: [y (D), 1, 0 ...], lane half h holds K slots 8h .. 8h+7
+    bf16x8 yb;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int k = 8 * h + v;
+      const float x = (k < D) ? (live ? y[n * D + k] : 0.0f) : (k == D ? 1.0f : 0.0f);
+      yb[v] = static_cast<__bf16>(x);
+    }
+    bf16x8 act[NRB][2];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) {
+      floatx16 acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+      bf16x8 a;
+      __builtin_memcpy(&a, &f1[rb * 64 + lane], 16);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, yb, acc, 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) act[rb][q][v] = static_cast<__bf16>(gelu(acc[8 * q + v]));
+    }
+    // layer 2, one block of 32 output units at a time; each block's activations feed the
+    // two layer-3 K steps of that block right away, so only layer 1's activations stay live
+    floatx16 out;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[r] = b3[8 * (r >> 2) + 4 * h + (r & 3)];
+#pragma unroll 1
+    for (int ob = 0; ob < NRB; ++ob) {
+      floatx16 acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = b2[32 * ob + 8 * (r >> 2) + 4 * h + (r & 3)];
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          bf16x8 a;
+          __builtin_memcpy(&a, &f2[((ob * NRB + rb) * 2 + q) * 64 + lane], 16);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, act[rb][q], acc, 0, 0, 0);
+        }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        bf16x8 act2;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) act2[v] = static_cast<__bf16>(gelu(acc[8 * q + v]));
+        bf16x8 a;
+        __builtin_memcpy(&a, &f3[(ob * 2 + q) * 64 + lane], 16);
+        out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, act2, out, 0, 0, 0);
+      }
+    }
+    if (live) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int k = 8 * (r >> 2) + 4 * h + (r & 3);
+        if (k < m) llr[n * m + k] = out[r];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ initialisation
+// Philox4x32-10 on the host for the initial weights (uniform in +-1/sqrt(fan_in)).
+void philox_host(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1, uint32_t out[4]) {
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = 0xD2511F53ull * c0, p1 = 0xCD9E8D57ull * c2;
+    const uint32_t n0 = static_cast<uint32_t>(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = static_cast<uint32_t>(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0;
+    c1 = static_cast<uint32_t>(p1);
+    c2 = n2;
+    c3 = static_cast<uint32_t>(p0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+struct Mlp {
+  int D = 0, H = 0, m = 0;
+  int64_t P = 0;
+  int device = 0;
+  int64_t step = 0;
+  uint64_t seed = 0;
+  float* w = nullptr;     // FP32 parameters
+  float* g = nullptr;     // gradients
+  float* m1 = nullptr;    // Adam first moment
+  float* m2 = nullptr;    // Adam second moment
+  char* img = nullptr;    // inference image
+  int64_t img_version = -1;
+  int64_t version = 0;    // bumped whenever w changes
+  float* scratch = nullptr;
+  size_t scratch_cap = 0;
+};
+
+namespace {
+
+int64_t param_count(int D, int H, int m) {
+  return static_cast<int64_t>(H) * D + H + static_cast<int64_t>(H) * H + H + static_cast<int64_t>(m) * H + m;
+}
+
+int check_handle(const Mlp* p) {
+  if (!p) return fail(MD_EINVAL, "MLP handle is NULL");
+  return MD_OK;
+}
+
+int ensure_scratch(Mlp* p, size_t floats) {
+  if (p->scratch_cap >= floats) return MD_OK;
+  if (p->scratch) {
+    MD_HIP_TRY(hipDeviceSynchronize());
+    MD_HIP_TRY(hipFree(p->scratch));
+    p->scratch = nullptr;
+    p->scratch_cap = 0;
+  }
+  void* q = nullptr;
+  if (hipMalloc(&q, floats * sizeof(float)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MD_ENOMEM, "MLP scratch allocation failed");
+  }
+  p->scratch = static_cast<float*>(q);
+  p->scratch_cap = floats;
+  return MD_OK;
+}
+
+void init_params(int D, int H, int m, uint64_t seed, std::vector<float>* out) {
+  out->resize(static_cast<size_t>(param_count(D, H, m)));
+  const uint32_t k0 = static_cast<uint32_t>(seed), k1 = static_cast<uint32_t>(seed >> 32);
+  int64_t idx = 0;
+  auto fill = [&](int64_t count, int fan_in) {
+    const float bound = 1.0f / std::sqrt(static_cast<float>(fan_in));
+    for (int64_t i = 0; i < count; ++i, ++idx) {
+      uint32_t r[4];
+      philox_host(static_cast<uint32_t>(idx), static_cast<uint32_t>(idx >> 32), 0u, 3u, k0, k1, r);
+      const float u = (static_cast<float>(r[0] >> 8) + 0.5f) * (1.0f / 16777216.0f);   // (0, 1)
+      (*out)[static_cast<size_t>(idx)] = (2.0f * u - 1.0f) * bound;
+    }
+  };
+  fill(static_cast<int64_t>(H) * D, D);
+  fill(H, D);
+  fill(static_cast<int64_t>(H) * H, H);
+  fill(H, H);
+  fill(static_cast<int64_t>(m) * H, H);
+  fill(m, H);
+}
+
+// forward (saving activations) + loss + backward into p->g.  Scratch layout for a batch B:
+// Z1, A1, Z2, A2 (B x H each), F, dF (B x m), dZ2, dZ1 (B x H), loss partials.
+int forward_backward(Mlp* p, const float* d_y, const float* d_t, int64_t B, double* d_loss, hipStream_t s) {
+  const int D = p->D, H = p->H, m = p->m;
+  const size_t BH = static_cast<size_t>(B) * H, Bm = static_cast<size_t>(B) * m;
+  const int nb = static_cast<int>((B + 255) / 256);
+  int st = ensure_scratch(p, 6 * BH + 2 * Bm + 2 * static_cast<size_t>(nb) + 64);
+  if (st != MD_OK) return st;
+  float* Z1 = p->scratch;
+  float* A1 = Z1 + BH;
+  float* Z2 = A1 + BH;
+  float* A2 = Z2 + BH;
+  float* F = A2 + BH;
+  float* dF = F + Bm;
+  float* dZ2 = dF + Bm;
+  float* dZ1 = dZ2 + BH;
+  double* part = reinterpret_cast<double*>(dZ1 + BH);     // 6 BH + 2 Bm floats: 8-byte aligned
+  const float* W1 = p->w;
+  const float* b1 = W1 + static_cast<int64_t>(H) * D;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + static_cast<int64_t>(H) * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + static_cast<int64_t>(m) * H;
+  float* gW1 = p->g;
+  float* gb1 = gW1 + static_cast<int64_t>(H) * D;
+  float* gW2 = gb1 + H;
+  float* gb2 = gW2 + static_cast<int64_t>(H) * H;
+  float* gW3 = gb2 + H;
+  float* gb3 = gW3 + static_cast<int64_t>(m) * H;
+  const int Bi = static_cast<int>(B);
+  // forward: Z1 = Y W1^T + b1, A1 = g(Z1); Z2 = A1 W2^T + b2, A2 = g(Z2); F = A2 W3^T + b3
+  if ((st = gemm<EPI_BIAS_GELU>(d_y, D, 1, W1, 1, D, Bi, H, D, Z1, H, b1, A1, nullptr, s))) return st;
+  if ((st = gemm<EPI_BIAS_GELU>(A1, H, 1, W2, 1, H, Bi, H, H, Z2, H, b2, A2, nullptr, s))) return st;
+  if ((st = gemm<EPI_STORE>(A2, H, 1, W3, 1, H, Bi, m, H, F, m, b3, nullptr, nullptr, s))) return st;
+  hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(256), 0, s, F, d_t, B, m, dF, part);
+  MD_LAUNCH_CHECK("loss_grad_kernel launch");
+  if (d_loss) {
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, s, part, nb, B, d_loss);
+    MD_LAUNCH_CHECK("loss_final_kernel launch");
+  }
+  // backward
+  // gW3 = dF^T A2 (m x H); gb3 = colsum dF
+  if ((st = gemm<EPI_STORE>(dF, 1, m, A2, H, 1, m, H, Bi, gW3, H, nullptr, nullptr, nullptr, s))) return st;
+  hipLaunchKernelGGL(colsum_kernel, dim3((m + 63) / 64), dim3(64), 0, s, dF, B, m, gb3);
+  MD_LAUNCH_CHECK("colsum_kernel launch");
+  // dZ2 = (dF W3) * g'(Z2)   (B x H)
+  if ((st = gemm<EPI_GELU_GRAD>(dF, m, 1, W3, H, 1, Bi, H, m, dZ2, H, nullptr, nullptr, Z2, s))) return st;
+  // gW2 = dZ2^T A1 (H x H); gb2 = colsum dZ2
+  if ((st = gemm<EPI_STORE>(dZ2, 1, H, A1, H, 1, H, H, Bi, gW2, H, nullptr, nullptr, nullptr, s))) return st;
+  hipLaunchKernelGGL(colsum_kernel, dim3((H + 63) / 64), dim3(64), 0, s, dZ2, B, H, gb2);
+  MD_LAUNCH_CHECK("colsum_kernel launch");
+  // dZ1 = (dZ2 W2) * g'(Z1)
+  if ((st = gemm<EPI_GELU_GRAD>(dZ2, H, 1, W2, H, 1, Bi, H, H, dZ1, H, nullptr, nullptr, Z1, s))) return st;
+  // gW1 = dZ1^T Y (H x D); gb1 = colsum dZ1
+  if ((st = gemm<EPI_STORE>(dZ1, 1, H, d_y, D, 1, H, D, Bi, gW1, D, nullptr, nullptr, nullptr, s))) return st;
+  hipLaunchKernelGGL(colsum_kernel, dim3((H + 63) / 64), dim3(64), 0, s, dZ1, B, H, gb1);
+  MD_LAUNCH_CHECK("colsum_kernel launch");
+  return MD_OK;
+}
+
+int adam(Mlp* p, float lr, hipStream_t s) {
+  p->step += 1;
+  const double b1 = 0.9, b2 = 0.999;
+  const float c1 = static_cast<float>(1.0 - std::pow(b1, static_cast<double>(p->step)));
+  const float c2 = static_cast<float>(1.0 - std::pow(b2, static_cast<double>(p->step)));
+  hipLaunchKernelGGL(adam_kernel, dim3(static_cast<unsigned>((p->P + 255) / 256)), dim3(256), 0, s, p->w, p->g,
+                     p->m1, p->m2, p->P, lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+  MD_LAUNCH_CHECK("adam_kernel launch");
+  p->version += 1;
+  return MD_OK;
+}
+
+// Generic-GEMM inference (any H): the forward pass of training without the loss.
+int infer_gemm(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s) {
+  const int D = p->D, H = p->H, m = p->m;
+  const int64_t chunk = 1 << 16;
+  int st = ensure_scratch(p, static_cast<size_t>(4 * chunk * H));
+  if (st != MD_OK) return st;
+  const float* W1 = p->w;
+  const float* b1 = W1 + static_cast<int64_t>(H) * D;
+  const float* W2 = b1 + H;
+  const float* b2 = W2 + static_cast<int64_t>(H) * H;
+  const float* W3 = b2 + H;
+  const float* b3 = W3 + static_cast<int64_t>(m) * H;
+  float* Z = p->scratch;
+  float* A1 = Z + chunk * H;
+  float* A2 = A1 + chunk * H;
+  for (int64_t n0 = 0; n0 < N; n0 += chunk) {
+    const int nb = static_cast<int>(N - n0 < chunk ? N - n0 : chunk);
+    if ((st = gemm<EPI_BIAS_GELU>(d_y + n0 * D, D, 1, W1, 1, D, nb, H, D, Z, H, b1, A1, nullptr, s))) return st;
+    if ((st = gemm<EPI_BIAS_GELU>(A1, H, 1, W2, 1, H, nb, H, H, Z, H, b2, A2, nullptr, s))) return st;
+    if ((st = gemm<EPI_STORE>(A2, H, 1, W3, 1, H, nb, m, H, d_llr + n0 * m, m, b3, nullptr, nullptr, s))) return st;
+  }
+  return MD_OK;
+}
+
+template <int NRB>
+int infer_fused_t(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s) {
+  const InferLayout L = infer_layout(p->H);
+  auto kern = mlp_infer_kernel<NRB>;
+  static bool attr_done = false;
+  if (!attr_done) {
+    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
+    attr_done = true;
+  }
+  int dev = 0, ncu = 0;
+  MD_HIP_TRY(hipGetDevice(&dev));
+  MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int block = 512;
+  int64_t grid = ncu;
+  const int64_t tiles = (N + 31) / 32;
+  if (grid > (tiles + 7) / 8) grid = (tiles + 7) / 8;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(block), L.bytes, s, p->img, L, p->D, p->m, d_y, N,
+                     d_llr);
+  MD_LAUNCH_CHECK("mlp_infer_kernel launch");
+  return MD_OK;
+}
+
+int infer(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s) {
+  const bool fused = p->H % 32 == 0 && p->H <= 256 && p->D <= 15 && p->m <= 32 &&
+                     infer_layout(p->H).bytes <= 160 * 1024;
+  if (!fused) return infer_gemm(p, d_y, N, d_llr, s);
+  const InferLayout L = infer_layout(p->H);
+  if (!p->img) {
+    void* q = nullptr;
+    if (hipMalloc(&q, L.bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MD_ENOMEM, "MLP inference image allocation failed");
+    }
+    p->img = static_cast<char*>(q);
+  }
+  if (p->img_version != p->version) {
+    hipLaunchKernelGGL(pack_infer_kernel, dim3(256), dim3(256), 0, s, p->w, p->D, p->H, p->m, L, p->img);
+    MD_LAUNCH_CHECK("pack_infer_kernel launch");
+    p->img_version = p->version;
+  }
+  switch (L.nrb) {
+    case 1: return infer_fused_t<1>(p, d_y, N, d_llr, s);
+    case 2: return infer_fused_t<2>(p, d_y, N, d_llr, s);
+    case 3: return infer_fused_t<3>(p, d_y, N, d_llr, s);
+    case 4: return infer_fused_t<4>(p, d_y, N, d_llr, s);
+    case 5: return infer_fused_t<5>(p, d_y, N, d_llr, s);
+    case 6: return infer_fused_t<6>(p, d_y, N, d_llr, s);
+    case 7: return infer_fused_t<7>(p, d_y, N, d_llr, s);
+    default: return infer_fused_t<8>(p, d_y, N, d_llr, s);
+  }
+}
+
+uint32_t crc32(const void* data, size_t n, uint32_t crc = 0) {
+  crc = ~crc;
+  const unsigned char* b = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) {
+    crc ^= b[i];
+    for (int k = 0; k < 8; ++k) crc = (crc >> 1) ^ (0xEDB88320u & (0u - (crc & 1u)));
+  }
+  return ~crc;
+}
+
+struct CkptHeader {
+  char magic[8];          // "MDMLP\0\0\1"
+  int32_t D, H, m, pad;
+  int64_t P, step;
+  uint64_t seed;
+  uint32_t crc, pad2;
+};
+
+}  // namespace
+}  // namespace md
+
+extern "C" {
+
+int mlp_create(int D, int hidden, int m, uint64_t seed, void** out) {
+  md::set_error("");
+  if (!out) return md::fail(MD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (D < 1 || D > 30) return md::fail(MD_EDIM, "D outside [1, 30]");
+  if (hidden < 1 || hidden > 4096) return md::fail(MD_EINVAL, "hidden outside [1, 4096]");
+  if (m < 1 || m > 16) return md::fail(MD_EINVAL, "m outside [1, 16]");
+  int dev = 0;
+  int st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  md::Mlp* p = new md::Mlp();
+  p->D = D;
+  p->H = hidden;
+  p->m = m;
+  p->P = md::param_count(D, hidden, m);
+  p->device = dev;
+  p->seed = seed;
+  void* q = nullptr;
+  if (hipMalloc(&q, sizeof(float) * 4 * static_cast<size_t>(p->P)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete p;
+    return md::fail(MD_ENOMEM, "MLP parameter allocation failed");
+  }
+  p->w = static_cast<float*>(q);
+  p->g = p->w + p->P;
+  p->m1 = p->g + p->P;
+  p->m2 = p->m1 + p->P;
+  std::vector<float> init;
+  md::init_params(D, hidden, m, seed, &init);
+  std::vector<float> zeros(static_cast<size_t>(3 * p->P), 0.0f);
+  if (hipMemcpy(p->w, init.data(), sizeof(float) * p->P, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->g, zeros.data(), sizeof(float) * 3 * p->P, hipMemcpyHostToDevice) != hipSuccess) {
+    hipError_t e = hipGetLastError();
+    (void)hipFree(p->w);
+    delete p;
+    return md::hip_fail(e, "MLP parameter upload");
+  }
+  *out = p;
+  return MD_OK;
+}
+
+int mlp_destroy(void* mlp) {
+  md::set_error("");
+  md::Mlp* p = static_cast<md::Mlp*>(mlp);
+  if (!p) return MD_OK;
+  MD_HIP_TRY(hipDeviceSynchronize());
+  if (p->w) MD_HIP_TRY(hipFree(p->w));
+  if (p->img) MD_HIP_TRY(hipFree(p->img));
+  if (p->scratch) MD_HIP_TRY(hipFree(p->scratch));
+  delete p;
+  return MD_OK;
+}
+
+int64_t mlp_num_params(const void* mlp) {
+  const md::Mlp* p = static_cast<const md::Mlp*>(mlp);
+  return p ? p->P : -1;
+}
+
+int mlp_get(const void* mlp, int which, float* h_out) {
+  md::set_error("");
+  const md::Mlp* p = static_cast<const md::Mlp*>(mlp);
+  int st = md::check_handle(p);
+  if (st != MD_OK) return st;
+  if (!h_out || which < 0 || which > 3) return md::fail(MD_EINVAL, "bad buffer or selector");
+  MD_HIP_TRY(hipDeviceSynchronize());
+  MD_HIP_TRY(hipMemcpy(h_out, p->w + which * p->P, sizeof(float) * p->P, hipMemcpyDeviceToHost));
+  return MD_OK;
+}
+
+int mlp_set(void* mlp, int which, const float* h_in) {
+  md::set_error("");
+  md::Mlp* p = static_cast<md::Mlp*>(mlp);
+  int st = md::check_handle(p);
+  if (st != MD_OK) return st;
+  if (!h_in || which < 0 || which > 3) return md::fail(MD_EINVAL, "bad buffer or selector");
+  MD_HIP_TRY(hipDeviceSynchronize());
+  MD_HIP_TRY(hipMemcpy(p->w + which * p->P, h_in, sizeof(float) * p->P, hipMemcpyHostToDevice));
+  if (which == 0) p->version += 1;
+  return MD_OK;
+}
+
+int mlp_grad(void* mlp, const float* d_y, const float* d_target, int64_t B, double* d_loss, void* stream) {
+  md::set_error("");
+  md::Mlp* p = static_cast<md::Mlp*>(mlp);
+  int st = md::check_handle(p);
+  if (st != MD_OK) return st;
+  if (B < 1 || B > (1 << 24)) return md::fail(MD_EINVAL, "batch size outside [1, 2^24]");
+  if (!d_y || !d_target) return md::fail(MD_EINVAL, "y or target is NULL");
+  return md::forward_backward(p, d_y, d_target, B, d_loss, reinterpret_cast<hipStream_t>(stream));
+}
+
+int mlp_adam_step(void* mlp, float lr, void* stream) {
+  md::set_error("");
+  md::Mlp* p = static_cast<md::Mlp*>(mlp);
+  int st = md::check_handle(p);
+  if (st != MD_OK) return st;
+  if (!(lr >= 0.0f)) return md::fail(MD_EINVAL, "learning rate must be >= 0");
+  return md::adam(p, lr, reinterpret_cast<hipStream_t>(stream));
+}
+
+int mlp_train_step(void* mlp, const float* d_y, const float* d_target, int64_t B, float lr, double* d_loss,
+                   void* stream) {
+  int st = mlp_grad(mlp, d_y, d_target, B, d_loss, stream);
+  if (st != MD_OK) return st;
+  return mlp_adam_step(mlp, lr, stream);
+}
+
+int mlp_fit(void* mlp, const float* d_y, const float* d_target, int64_t N, int64_t steps, int64_t B, float lr_max,
+            float lr_min, uint64_t shuffle_seed, double* d_loss_trace, void* stream) {
+  md::set_error("");
+  md::Mlp* p = static_cast<md::Mlp*>(mlp);
+  int st = md::check_handle(p);
+  if (st != MD_OK) return st;
+  if (N < 1 || N >= (int64_t(1) << 32) || steps < 0 || B < 1 || B > (1 << 20))
+    return md::fail(MD_EINVAL, "bad N, steps or batch size");
+  if (!d_y || !d_target) return md::fail(MD_EINVAL, "y or target is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  void* q = nullptr;
+  // the batch buffers are private to this call (freed after the stream drains)
+  if (hipMalloc(&q, sizeof(float) * static_cast<size_t>(B) * (p->D + p->m)) != hipSuccess) {
+    (void)hipGetLastError();
+    return md::fail(MD_ENOMEM, "batch allocation failed");
+  }
+  float* yb = static_cast<float*>(q);
+  float* tb = yb + B * p->D;
+  const int64_t start = p->step;
+  for (int64_t i = 0; i < steps && st == MD_OK; ++i) {
+    const double frac = steps > 1 ? static_cast<double>(i) / static_cast<double>(steps - 1) : 0.0;
+    const float lr = static_cast<float>(lr_min + 0.5 * (lr_max - lr_min) * (1.0 + std::cos(M_PI * frac)));
+    hipLaunchKernelGGL(md::gather_kernel, dim3(static_cast<unsigned>((B + 255) / 256)), dim3(256), 0, s, d_y,
+                       d_target, p->D, p->m, N, shuffle_seed, static_cast<uint64_t>(start + i), B, yb, tb);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      st = md::hip_fail(e, "gather_kernel launch");
+      break;
+    }
+    st = md::forward_backward(p, yb, tb, B, d_loss_trace ? d_loss_trace + i : nullptr, s);
+    if (st == MD_OK) st = md::adam(p, lr, s);
+  }
+  hipError_t e1 = hipStreamSynchronize(s);
+  hipError_t e2 = hipFree(yb);
+  if (st != MD_OK) return st;
+  if (e1 != hipSuccess) return md::hip_fail(e1, "hipStreamSynchronize");
+  if (e2 != hipSuccess) return md::hip_fail(e2, "hipFree");
+  return MD_OK;
+}
+
+int llr_learned(const void* mlp, const float* d_y, int64_t N, float* d_llr, void* stream) {
+  md::set_error("");
+  md::Mlp* p = const_cast<md::Mlp*>(static_cast<const md::Mlp*>(mlp));
+  int st = md::check_handle(p);
+  if (st != MD_OK) return st;
+  if (N < 0) return md::fail(MD_EINVAL, "N is negative");
+  if (N == 0) return MD_OK;
+  if (!d_y || !d_llr) return md::fail(MD_EINVAL, "y or llr is NULL");
+  return md::infer(p, d_y, N, d_llr, reinterpret_cast<hipStream_t>(stream));
+}
+
+int mlp_save(const void* mlp, const char* path) {
+  md::set_error("");
+  const md::Mlp* p = static_cast<const md::Mlp*>(mlp);
+  int st = md::check_handle(p);
+  if (st != MD_OK) return st;
+  if (!path) return md::fail(MD_EINVAL, "path is NULL");
+  std::vector<float> buf(static_cast<size_t>(3 * p->P));
+  MD_HIP_TRY(hipDeviceSynchronize());
+  MD_HIP_TRY(hipMemcpy(buf.data(), p->w, sizeof(float) * p->P, hipMemcpyDeviceToHost));
+  MD_HIP_TRY(hipMemcpy(buf.data() + p->P, p->m1, sizeof(float) * 2 * p->P, hipMemcpyDeviceToHost));
+  md::CkptHeader hd;
+  std::memset(&hd, 0, sizeof(hd));
+  std::memcpy(hd.magic, "MDMLP\0\0\1", 8);
+  hd.D = p->D;
+  hd.H = p->H;
+  hd.m = p->m;
+  hd.P = p->P;
+  hd.step = p->step;
+  hd.seed = p->seed;
+  hd.crc = md::crc32(buf.data(), buf.size() * sizeof(float));
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return md::fail(MD_EINVAL, std::string("cannot open ") + path);
+  const bool ok = std::fwrite(&hd, sizeof(hd), 1, f) == 1 &&
+                  std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  std::fclose(f);
+  return ok ? MD_OK : md::fail(MD_EINVAL, "short write");
+}
+
+int mlp_load(const char* path, void** out) {
+  md::set_error("");
+  if (!path || !out) return md::fail(MD_EINVAL, "path or out is NULL");
+  *out = nullptr;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return md::fail(MD_EINVAL, std::string("cannot open ") + path);
+  md::CkptHeader hd;
+  if (std::fread(&hd, sizeof(hd), 1, f) != 1 || std::memcmp(hd.magic, "MDMLP\0\0\1", 8) != 0 ||
+      hd.P != md::param_count(hd.D, hd.H, hd.m)) {
+    std::fclose(f);
+    return md::fail(MD_EINVAL, "not an MLP checkpoint of this version");
+  }
+  std::vector<float> buf(static_cast<size_t>(3 * hd.P));
+  const bool ok = std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  std::fclose(f);
+  if (!ok || md::crc32(buf.data(), buf.size() * sizeof(float)) != hd.crc)
+    return md::fail(MD_EINVAL, "checkpoint is truncated or corrupt (CRC mismatch)");
+  void* h = nullptr;
+  int st = mlp_create(hd.D, hd.H, hd.m, hd.seed, &h);
+  if (st != MD_OK) return st;
+  md::Mlp* p = static_cast<md::Mlp*>(h);
+  MD_HIP_TRY(hipMemcpy(p->w, buf.data(), sizeof(float) * p->P, hipMemcpyHostToDevice));
+  MD_HIP_TRY(hipMemcpy(p->m1, buf.data() + p->P, sizeof(float) * 2 * p->P, hipMemcpyHostToDevice));
+  p->step = hd.step;
+  p->version += 1;
+  *out = p;
+  return MD_OK;
+}
+
+int mlp_info(const void* mlp, int* D, int* hidden, int* m, int64_t* step) {
+  const md::Mlp* p = static_cast<const md::Mlp*>(mlp);
+  if (!p) return md::fail(MD_EINVAL, "MLP handle is NULL");
+  if (D) *D = p->D;
+  if (hidden) *hidden = p->H;
+  if (m) *m = p->m;
+  if (step) *step = p->step;
+  return MD_OK;
+}
+
+}  // extern "C"

@@ -20,7 +20,7 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ("awgn_sample", "llr_exact", "llr_maxlog", "gmi_reduce",
+    for required in ("awgn_sample", "llr_exact", "llr_maxlog", "gmi_reduce", "llr_learned",
                      "release_cache", "last_error"):
         assert required in names, required
 

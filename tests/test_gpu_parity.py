@@ -8,9 +8,10 @@ Tolerances (derivation in the design notes):
     accumulation leave an error of a few 2^-22 of sum_k |a_k b_k| (up to ~1e3 in
     base-2 exponent units at 14 dB) on each exponent, so ~3e-4 nat per score.
   * max-log LLRs: same bound.
-  * LLRs, BF16 precision: the exponentials are rounded to BF16 (relative error
-    <= 2^-9 per term), so each subset sum is within 2^-9 and the LLR within
-    2 * 2^-9 ~ 3.9e-3 nat, plus the score error: |dL| <= 6e-3 + 2e-4 |L|.
+  * LLRs, BF16 precision: the exponentials are converted to BF16 (relative error
+    <= 2^-8 per term for any rounding of the 8-bit mantissa), so each subset sum is
+    within 2^-8 and the LLR within 2 * 2^-8 ~ 7.8e-3 nat, plus the FP32 bound above
+    for the scores: |dL| <= 1e-2 + 2e-4 |L|.
   * GMI: |dGMI| <= 1e-4 bit (the target), measured on the same y and tx.
 """
 import math
@@ -100,7 +101,7 @@ def _parity(X, labels, snr_db, N, seed, maxlog=False, prec="fp32"):
         L = md().llr_exact(Xd, ld, y, s2, prec=prec)
         ref = oracle.llr_exact(X, labels, yh, s2)
     Lh = L.cpu().numpy()
-    atol = ATOL if prec == "fp32" else 6e-3
+    atol = ATOL if prec == "fp32" else 1e-2
     err = assert_llr_close(Lh, ref, atol=atol, what=f"M={X.shape[0]} D={X.shape[1]} snr={snr_db} {prec}")
     g, gb, se = md().gmi_reduce(L, tx, ld)
     g_ref, gb_ref, se_ref = oracle.gmi(ref, txh, labels)

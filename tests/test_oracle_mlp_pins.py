@@ -17,18 +17,27 @@ def _params(D=3, H1=5, H2=4, m=2, seed=0, scale=0.7):
         rng.standard_normal((m, H2)) * scale, rng.standard_normal(m) * 0.1)
 
 
-def test_gelu_closed_form_values():
-    # one hidden unit per layer with identity-like weights exposes GELU itself
+def _gelu_tanh_ref(a):
+    return 0.5 * a * (1.0 + math.tanh(math.sqrt(2.0 / math.pi) * (a + 0.044715 * a ** 3)))
+
+
+def test_gelu_values_and_closeness_to_the_erf_form():
+    # one hidden unit per layer with identity weights exposes the activation itself
     p = oracle.MLPParams(np.array([[1.0]]), np.zeros(1), np.array([[1.0]]), np.zeros(1),
                          np.array([[1.0]]), np.zeros(1))
-    y = np.array([[0.0], [1.0], [-1.0], [8.0]], dtype=np.float32)
-    out = oracle.mlp_forward(p, y)[:, 0]
-    phi1 = 0.8413447460685429                       # standard normal CDF at 1
-    g1 = 1.0 * phi1
-    gm1 = -1.0 * (1 - phi1)
-    expect = [0.0, g1 * 0.5 * (1 + math.erf(g1 / math.sqrt(2))),
-              gm1 * 0.5 * (1 + math.erf(gm1 / math.sqrt(2))), 8.0]
-    np.testing.assert_allclose(out, expect, rtol=1e-12, atol=1e-12)
+    a = np.linspace(-6, 6, 241)
+    out = oracle.mlp_forward(p, a[:, None].astype(np.float32))[:, 0]
+    a32 = a.astype(np.float32).astype(np.float64)
+    # exact special values: g(0) = 0, g(a) -> a for large a, g(-a) -> 0
+    assert out[120] == 0.0
+    # the tanh form stays within 2e-3 of the erf form a * Phi(a) (Hendrycks & Gimpel)
+    phi = np.array([0.5 * (1 + math.erf(v / math.sqrt(2))) for v in a32])
+    g1 = a32 * phi
+    g_erf = g1 * 0.5 * (1 + np.array([math.erf(v / math.sqrt(2)) for v in g1]))
+    assert np.max(np.abs(out - g_erf)) < 2e-3
+    # and the composition is the activation applied twice
+    g_once = np.array([_gelu_tanh_ref(v) for v in a32])
+    np.testing.assert_allclose(out, [_gelu_tanh_ref(v) for v in g_once], rtol=1e-12, atol=1e-15)
 
 
 def test_zero_network_loss_closed_form():
