@@ -29,7 +29,8 @@ if ROOT not in sys.path:
 
 METRIC = "received symbols/s for exact LLR+GMI (8D, M=2048) and learned-vs-exact at ≤0.01b"
 # Transcendental issue rate: 256 CUs x 2.4 GHz x 32 exp lanes per clock per CU
-# (a quarter of the 128 FP32 VALU lanes per clock per CU).
+# (half of the 64 non-packed FP32 VALU lanes per clock per CU: a wave64 v_exp_f32
+# occupies its SIMD for 8 cycles, a plain FP32 op for 4).
 EXP_PEAK = 256 * 2.4e9 * 32
 
 
@@ -44,6 +45,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline sweep (no BF16 / max-log / learned / batched objects)")
+    ap.add_argument("--learn-steps", type=int, default=3000, help="training steps per learned network")
+    ap.add_argument("--learn-pairs", type=int, default=1 << 24, help="training pairs per SNR point")
+    ap.add_argument("--batch-insts", type=int, default=64, help="instances in the batched-sweep object")
     return ap.parse_args()
 
 
@@ -67,6 +73,131 @@ def cpu_baseline(X, labels, snr_db, seconds):
     return {"value": n / dt, "unit": "symbols/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"{n} symbols of the 8D M=2048 workload at {snr_db:g} dB (exact LLR + GMI, FP64, "
                       f"{dt:.1f} s)"}
+
+
+def timed(fn, reps=3):
+    """Median device time (ms) of fn() over reps runs, after one warm-up, on the current stream."""
+    import torch
+    fn()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return sorted(ts)[len(ts) // 2]
+
+
+def extra_precisions(md, wl, X, labels, N, tx, y, llr):
+    """BF16 subset-sum variant and max-log on the same channel draws, at 4, 9 and 14 dB."""
+    import math
+    out = {"bf16": {}, "maxlog": {}}
+    for snr in (4.0, 9.0, 14.0):
+        s2 = wl.sigma2(snr)
+        md.awgn_sample(X, wl.seed, 0, N, math.sqrt(s2), tx=tx, y=y)
+        md.llr_exact(X, labels, y, s2, out=llr)
+        g32 = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
+        t16 = timed(lambda: md.llr_exact(X, labels, y, s2, prec="bf16", out=llr))
+        g16 = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
+        tml = timed(lambda: md.llr_maxlog(X, labels, y, s2, out=llr))
+        gml = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
+        out["bf16"][f"{snr:g}"] = {"llr_ms": t16, "symbols_per_s": N / (t16 * 1e-3),
+                                   "exp_frac": N * wl.M / (t16 * 1e-3) / EXP_PEAK, "gmi": g16,
+                                   "gmi_minus_fp32": g16 - g32}
+        out["maxlog"][f"{snr:g}"] = {"llr_ms": tml, "symbols_per_s": N / (tml * 1e-3), "gmi": gml,
+                                     "gmi_minus_exact": gml - g32}
+    return out
+
+
+def extra_learned(md, wl, X, labels, N, tx, y, llr, steps, pairs):
+    """Learned 8 -> 256 -> 256 -> 11 demapper, one network per SNR (6, 10, 14 dB), trained on
+    `pairs` (y, exact LLR) pairs of the same constellation; judged by the exact GMI on N
+    fresh symbols; inference time against the exact kernel."""
+    import math
+    import time
+    import torch
+    res = {}
+    for snr in (6.0, 10.0, 14.0):
+        s2 = wl.sigma2(snr)
+        ty = torch.empty((pairs, wl.D), dtype=torch.float32, device="cuda")
+        tt = torch.empty(pairs, dtype=torch.int32, device="cuda")
+        tl = torch.empty((pairs, wl.m), dtype=torch.float32, device="cuda")
+        md.awgn_sample(X, wl.seed + 77, 0, pairs, math.sqrt(s2), tx=tt, y=ty)
+        md.llr_exact(X, labels, ty, s2, out=tl)
+        net = md.MLP(wl.D, 256, wl.m, seed=int(snr))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        trace = net.fit(ty, tl, steps=steps, batch=4096, lr_max=2e-3, lr_min=2e-5, seed=int(snr) + 5)
+        train_s = time.perf_counter() - t0
+        del ty, tt, tl
+        md.awgn_sample(X, wl.seed + 99, 0, N, math.sqrt(s2), tx=tx, y=y)
+        t_ex = timed(lambda: md.llr_exact(X, labels, y, s2, out=llr))
+        g_ex = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
+        md.llr_maxlog(X, labels, y, s2, out=llr)
+        g_ml = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
+        t_ml = timed(lambda: md.llr_learned(net, y, out=llr))
+        g_ln = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
+        res[f"{snr:g}"] = {"gmi_exact": g_ex, "gmi_learned": g_ln, "gap_bits": g_ex - g_ln,
+                           "gmi_maxlog": g_ml, "learned_minus_maxlog": g_ln - g_ml,
+                           "exact_ms": t_ex, "learned_ms": t_ml, "speedup_vs_exact": t_ex / t_ml,
+                           "learned_symbols_per_s": N / (t_ml * 1e-3), "train_steps": steps,
+                           "train_pairs": pairs, "train_s": train_s,
+                           "final_loss": float(trace[-50:].mean().item())}
+        net.close()
+    return res
+
+
+def extra_batched(md, n_inst):
+    """Batched sweep: n_inst Gaussian constellations of mixed M and D, N_i uniform in
+    [1e5, 4e6], 11 SNR points 2..12 dB: one captured-graph launch vs the per-instance loop."""
+    import math
+    import time
+    import numpy as np
+    import torch
+    import synth
+    insts = synth.batched_instances(n_inst)
+    specs, s2 = [], []
+    for w in insts:
+        specs.append((torch.from_numpy(w.X).cuda(), torch.from_numpy(w.labels.astype(np.int32)).cuda(), w.N,
+                      w.seed))
+        s2.append([w.sigma2(s) for s in w.snr_db])
+    s2 = np.array(s2)
+    t0 = time.perf_counter()
+    plan = md.SweepPlan(specs, s2, variant=-1)
+    plan_s = time.perf_counter() - t0
+    g = plan.run()
+    t_graph = timed(lambda: plan.run(out=g), reps=3)
+    nmax = max(w.N for w in insts)
+    dmax = max(w.D for w in insts)
+    tx = torch.empty(nmax, dtype=torch.int32, device="cuda")
+    y = torch.empty((nmax, dmax), dtype=torch.float32, device="cuda")
+    llr = torch.empty((nmax, 12), dtype=torch.float32, device="cuda")
+    ref = torch.empty_like(g)
+
+    def loop():
+        for i, (Xd, ld, N, seed) in enumerate(specs):
+            D = Xd.shape[1]
+            m = int(Xd.shape[0]).bit_length() - 1
+            yv = y.view(-1)[:N * D].view(N, D)
+            lv = llr.view(-1)[:N * m].view(N, m)
+            for s in range(s2.shape[1]):
+                md.awgn_sample(Xd, seed, s * N, N, math.sqrt(s2[i, s]), tx=tx[:N], y=yv)
+                md.llr_exact(Xd, ld, yv, s2[i, s], out=lv)
+                ref[i, s:s + 1].copy_(md.gmi_reduce(lv, tx[:N], ld, per_bit=False, se=False)[0])
+
+    t_loop = timed(loop, reps=1)
+    total = int(sum(w.N for w in insts)) * s2.shape[1]
+    pairs = float(sum(w.N * w.M for w in insts)) * s2.shape[1]
+    diff = float((g - ref).abs().max().item())
+    return {"instances": n_inst, "snr_points": int(s2.shape[1]), "symbols": total, "pairs": pairs,
+            "graph_ms": t_graph, "per_instance_ms": t_loop, "speedup": t_loop / t_graph,
+            "graph_symbols_per_s": total / (t_graph * 1e-3), "graph_exp_frac": pairs / (t_graph * 1e-3) / EXP_PEAK,
+            "launch_shape": list(plan.shape), "work_items": plan.n_items, "plan_create_s": plan_s,
+            "max_abs_gmi_diff_vs_per_instance": diff,
+            "M_mix": sorted({int(w.M) for w in insts}), "D_mix": sorted({int(w.D) for w in insts})}
 
 
 def main():
@@ -148,6 +279,13 @@ def main():
         "detail": {"gmi_bits": {f"{s:g}": round(float(g), 6) for s, g in zip(snrs, gmis.cpu().tolist())},
                    "llr_symbols_per_s": N / (llr_avg_ms * 1e-3)},
     }
+    if not args.no_extras:
+        out["detail"].update(extra_precisions(md, wl, X, labels, N, tx, y, llr))
+        out["detail"]["learned"] = extra_learned(md, wl, X, labels, N, tx, y, llr, args.learn_steps,
+                                                 args.learn_pairs)
+        del tx, y, llr
+        torch.cuda.empty_cache()
+        out["detail"]["batched"] = extra_batched(md, args.batch_insts)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl.X, wl.labels, 9.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

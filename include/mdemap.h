@@ -55,8 +55,9 @@ extern "C" {
 #define MD_EUNSUPPORTED -8   /* combination not implemented */
 
 /* Precision of llr_exact.
- *   MD_PREC_FP32: scores by a three-pass split-FP16 MFMA contraction with FP32
- *     accumulation (error about 2^-21 of sum_k |a_k b_k|), exponentials and all
+ *   MD_PREC_FP32: scores by one split-FP16 MFMA contraction whose K dimension holds
+ *     the hi*hi, hi*lo and lo*hi partial products side by side (3D+4 slots, FP32
+ *     accumulation, error about 2^-21 of sum_k |a_k b_k|); exponentials and all
  *     subset sums in FP32.
  *   MD_PREC_BF16: same scores; the exponentials are rounded to BF16 and the
  *     subset sums are formed by a BF16 MFMA contraction against the label-bit
@@ -187,6 +188,36 @@ int llr_learned(const void* mlp, const float* d_y, int64_t N, float* d_llr, void
  * mlp_load creates a new handle on the current device; a corrupt file is MD_EINVAL. */
 int mlp_save(const void* mlp, const char* path);
 int mlp_load(const char* path, void** out);
+
+/* ------------------------------------------------------------------ batched sweep */
+/* Many constellations (uneven M and D) at many noise levels in one persistent kernel
+ * captured in a hipGraph: for every (instance i, noise level s) the channel of
+ * awgn_sample (seed_i, offset = s * N_i, N_i uses), the exact LLRs and their GMI, without
+ * storing received symbols or LLRs.  The GMI equals gmi_reduce(llr_exact(...)) of the
+ * same channel draw up to FP32 rounding.  The launch shape (wavefronts per block,
+ * 32-symbol blocks per wavefront, symbol groups per work item) is measured on the plan's
+ * own workload when variant = -1, else fixed: 0 (8, 2, 1), 1 (8, 2, 4), 2 (16, 1, 1),
+ * 3 (16, 1, 4).  The plan snapshots the constellations' fragments at creation; d_X and
+ * d_labels must stay valid and unchanged while the plan lives (the channel reads d_X).
+ * Limits: M in {16 .. 8192}, 1 <= D <= 8, instances x noise levels <= 2^20; more than
+ * 2^20 symbols of one run needing the FP64 fallback makes that run's GMIs NaN. */
+typedef struct {
+  const float* d_X;           /* M x D float32 constellation (device) */
+  const uint32_t* d_labels;   /* M uint32 labels, a permutation of [0, M) (device) */
+  int M, D;
+  int64_t N;                  /* channel uses per noise level */
+  uint64_t seed;              /* channel seed */
+} md_sweep_instance;
+
+/* sigma2: host array n_inst x n_snr (row i = instance i).  Synchronous. */
+int sweep_plan_create(const md_sweep_instance* inst, int n_inst, const double* sigma2, int n_snr, int variant,
+                      void** out);
+/* The chosen launch shape and the number of work items. */
+int sweep_plan_info(const void* plan, int* waves, int* blocks_per_wave, int* groups_per_item, int* n_items);
+/* Runs the sweep (use_graph = 1: one launch of the captured graph; 0: the same kernels
+ * enqueued directly) and copies the n_inst x n_snr GMIs (bits per symbol) to d_gmi. */
+int sweep_run(void* plan, double* d_gmi, int use_graph, void* stream);
+int sweep_plan_destroy(void* plan);
 
 /* ------------------------------------------------------------------ housekeeping */
 /* Frees every internal device workspace (synchronises the device first). */

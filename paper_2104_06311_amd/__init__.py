@@ -12,7 +12,8 @@ import torch
 
 from ._lib import MdemapError, PREC, check, lib
 
-__all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "gmi_reduce", "llr_learned", "MLP", "release_cache", "MdemapError",
+__all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "gmi_reduce", "llr_learned", "MLP", "SweepPlan", "release_cache",
+           "MdemapError",
            "log2_exact"]
 
 
@@ -224,3 +225,55 @@ def llr_learned(mlp: MLP, y, out=None):
         out = torch.empty((N, mlp.m), dtype=torch.float32, device=y.device)
     check("llr_learned", lib().llr_learned(mlp.handle, _ptr(y), N, _ptr(out), _stream()))
     return out
+
+
+# ----------------------------------------------------------------------------- batched sweep
+class SweepPlan:
+    """Batched channel + exact-LLR + GMI sweep over many constellations and noise levels
+    (sweep_* in mdemap.h).  instances: list of (X, labels, N, seed) with X float32 [M, D]
+    and labels int32 [M] on the GPU (kept alive by the plan); sigma2: [n_inst, n_snr]."""
+
+    def __init__(self, instances, sigma2, variant: int = -1):
+        import ctypes
+        import numpy as np
+        from ._lib import SweepInstance
+        self._keep = []
+        arr = (SweepInstance * len(instances))()
+        for i, (X, labels, N, seed) in enumerate(instances):
+            _dev(X, "X", torch.float32, 2)
+            _dev(labels, "labels", torch.int32, 1)
+            self._keep += [X, labels]
+            arr[i] = SweepInstance(X.data_ptr(), labels.data_ptr(), X.shape[0], X.shape[1], int(N),
+                                   int(seed) & (2 ** 64 - 1))
+        s2 = np.ascontiguousarray(sigma2, dtype=np.float64)
+        if s2.shape[0] != len(instances):
+            raise ValueError("sigma2 must have one row per instance")
+        self.n_inst, self.n_snr = s2.shape
+        h = ctypes.c_void_p()
+        check("sweep_plan_create", lib().sweep_plan_create(ctypes.cast(arr, ctypes.c_void_p), len(instances),
+                                                           s2.ctypes.data, self.n_snr, variant, ctypes.byref(h)))
+        self._h = h
+        w, sb, gpi, ni = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        check("sweep_plan_info", lib().sweep_plan_info(self._h, ctypes.byref(w), ctypes.byref(sb), ctypes.byref(gpi),
+                                                       ctypes.byref(ni)))
+        self.shape = (w.value, sb.value, gpi.value)
+        self.n_items = ni.value
+
+    def run(self, out=None, use_graph: bool = True):
+        """GMI float64 [n_inst, n_snr] (device tensor)."""
+        if out is None:
+            out = torch.empty((self.n_inst, self.n_snr), dtype=torch.float64, device="cuda")
+        check("sweep_run", lib().sweep_run(self._h, _ptr(out), 1 if use_graph else 0, _stream()))
+        return out
+
+    def close(self):
+        if self._h is not None:
+            check("sweep_plan_destroy", lib().sweep_plan_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) is not None:
+                lib().sweep_plan_destroy(self._h)
+        except Exception:
+            pass

@@ -44,10 +44,20 @@ SIGNATURES = {
     "llr_learned": (_I, [_P, _P, _I64, _P, _P]),
     "mlp_save": (_I, [_P, ctypes.c_char_p]),
     "mlp_load": (_I, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "sweep_plan_create": (_I, [_P, _I, _P, _I, _I, ctypes.POINTER(ctypes.c_void_p)]),
+    "sweep_plan_info": (_I, [_P, _P, _P, _P, _P]),
+    "sweep_run": (_I, [_P, _P, _I, _P]),
+    "sweep_plan_destroy": (_I, [_P]),
     "release_cache": (_I, []),
     "last_error": (ctypes.c_char_p, []),
     "mdemap_version": (_I, []),
 }
+
+
+class SweepInstance(ctypes.Structure):
+    """md_sweep_instance of mdemap.h."""
+    _fields_ = [("d_X", ctypes.c_void_p), ("d_labels", ctypes.c_void_p), ("M", ctypes.c_int), ("D", ctypes.c_int),
+                ("N", ctypes.c_int64), ("seed", ctypes.c_uint64)]
 
 
 class MdemapError(RuntimeError):

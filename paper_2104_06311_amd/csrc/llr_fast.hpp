@@ -101,6 +101,201 @@ __device__ __forceinline__ bool build_symbol_operand(_Float16* row, const float*
 // fragments of a tile once for all blocks.  The MFMAs of tile t+1 are issued before the
 // exponentials of tile t (hard scheduling fences keep that order), so a wavefront's
 // matrix work runs underneath its own VALU work.
+template <int MB, int SB, bool MAXLOG>
+__device__ __forceinline__ void acc_init(SymAcc<MB> (&ac)[SB]) {
+  const float ident = MAXLOG ? -INFINITY : 0.0f;
+#pragma unroll
+  for (int sb = 0; sb < SB; ++sb) {
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) ac[sb].E[rr] = ident;
+#pragma unroll
+    for (int i = 0; i < Geo<MB>::G; ++i) ac[sb].Tg[i] = ident;
+#pragma unroll
+    for (int q = 0; q < Geo<MB>::NHA; ++q) {
+      ac[sb].H0[q] = ident;
+      ac[sb].H1[q] = ident;
+    }
+  }
+}
+
+// Accumulates the tiles [t0, t0 + tn) of one LDS-resident chunk (tile t of the chunk is at
+// lds[t * KS * 64 ...]; tn is a multiple of G) into the SB symbol blocks' partial sums.
+template <int KS, int MB, int SB, bool MAXLOG>
+__device__ __forceinline__ void tile_loop(const uint4* __restrict__ lds, int t0, int tn, int lane,
+                                          const half8 (&bf)[SB][KS], SymAcc<MB> (&ac)[SB]) {
+  constexpr int LOG2G = Geo<MB>::LOG2G;
+  constexpr int G = Geo<MB>::G;
+  constexpr int nh = Geo<MB>::NH;
+  // prologue: score block of the chunk's first tile
+  floatx16 cur[SB];
+  {
+    half8 ah[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[ks * 64 + lane]);
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) cur[sb][rr] = 0.0f;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        cur[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], cur[sb], 0, 0, 0);
+    }
+  }
+  for (int tg = 0; tg < tn; tg += G) {
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      // issue the next tile's score blocks (the chunk's last tile recomputes itself)
+      const int tnext = min(tg + i + 1, tn - 1);
+      floatx16 nxt[SB];
+      half8 ah[KS];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[(tnext * KS + ks) * 64 + lane]);
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) {
+#pragma unroll
+        for (int rr = 0; rr < 16; ++rr) nxt[sb][rr] = 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+          nxt[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], nxt[sb], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) {
+        SymAcc<MB>& A = ac[sb];
+        float v[16];
+        if (MAXLOG) {
+#pragma unroll
+          for (int rr = 0; rr < 16; ++rr) {
+            v[rr] = cur[sb][rr];
+            A.E[rr] = fmaxf(A.E[rr], v[rr]);
+          }
+#pragma unroll
+          for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+            for (int rr = 0; rr < w; ++rr) v[rr] = fmaxf(v[rr], v[rr + w]);
+          A.Tg[i] = fmaxf(A.Tg[i], v[0]);
+          A.GT = (i == 0) ? v[0] : fmaxf(A.GT, v[0]);
+        } else {
+#pragma unroll
+          for (int rr = 0; rr < 16; ++rr) {
+            v[rr] = __builtin_amdgcn_exp2f(cur[sb][rr]);
+            A.E[rr] += v[rr];
+          }
+#pragma unroll
+          for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+            for (int rr = 0; rr < w; ++rr) v[rr] += v[rr + w];
+          A.Tg[i] += v[0];
+          A.GT = (i == 0) ? v[0] : A.GT + v[0];
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) cur[sb] = nxt[sb];
+    }
+    // route the group sums by the label bits above the group
+    const int grp = (t0 + tg) >> LOG2G;
+#pragma unroll
+    for (int q = 0; q < nh; ++q) {
+      const bool bit = (grp >> q) & 1;
+#pragma unroll
+      for (int sb = 0; sb < SB; ++sb) {
+        SymAcc<MB>& A = ac[sb];
+        if (MAXLOG) {
+          A.H1[q] = bit ? fmaxf(A.H1[q], A.GT) : A.H1[q];
+          A.H0[q] = bit ? A.H0[q] : fmaxf(A.H0[q], A.GT);
+        } else {
+          const float a = bit ? A.GT : 0.0f;
+          A.H1[q] += a;
+          A.H0[q] += A.GT - a;
+        }
+      }
+    }
+  }
+}
+
+// Label-0 / label-1 subset sums (or maxima) of every label bit from one symbol block's
+// partial sums: bits 0..3 are positions inside the lane, bit 4 the lane half, bits
+// 5..4+LOG2G the in-group tile sums, higher bits the routed group sums.  Every lane of
+// the wavefront must call it (cross-half shuffles); the result is valid in lane half 0.
+// With half_tile (M = 16) the lane half 1 holds no labels and is ignored.
+template <int MB, bool MAXLOG>
+__device__ __forceinline__ void combine_subsets(const SymAcc<MB>& A, bool half_tile, float (&S0)[MB],
+                                                float (&S1)[MB]) {
+  constexpr int LOG2G = Geo<MB>::LOG2G;
+  constexpr int G = Geo<MB>::G;
+  constexpr int NHMAX = Geo<MB>::NHA;
+  const float ident = MAXLOG ? -INFINITY : 0.0f;
+  float L0[4 + LOG2G], L1[4 + LOG2G];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    float a0 = ident, a1 = ident;
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+      if ((rr >> b) & 1) a1 = MAXLOG ? fmaxf(a1, A.E[rr]) : a1 + A.E[rr];
+      else a0 = MAXLOG ? fmaxf(a0, A.E[rr]) : a0 + A.E[rr];
+    }
+    L0[b] = a0;
+    L1[b] = a1;
+  }
+#pragma unroll
+  for (int b = 0; b < LOG2G; ++b) {
+    float a0 = ident, a1 = ident;
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+      if ((i >> b) & 1) a1 = MAXLOG ? fmaxf(a1, A.Tg[i]) : a1 + A.Tg[i];
+      else a0 = MAXLOG ? fmaxf(a0, A.Tg[i]) : a0 + A.Tg[i];
+    }
+    L0[4 + b] = a0;
+    L1[4 + b] = a1;
+  }
+  const float Th = MAXLOG ? fmaxf(L0[0], L1[0]) : L0[0] + L1[0];
+  float pL0[4 + LOG2G], pL1[4 + LOG2G], pH0[NHMAX], pH1[NHMAX];
+#pragma unroll
+  for (int b = 0; b < 4 + LOG2G; ++b) {
+    pL0[b] = half_tile ? ident : __shfl_xor(L0[b], 32, 64);
+    pL1[b] = half_tile ? ident : __shfl_xor(L1[b], 32, 64);
+  }
+  const float pTh = __shfl_xor(Th, 32, 64);
+#pragma unroll
+  for (int q = 0; q < NHMAX; ++q) {
+    pH0[q] = __shfl_xor(A.H0[q], 32, 64);
+    pH1[q] = __shfl_xor(A.H1[q], 32, 64);
+  }
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    float a0, a1;
+    if (b < 4) {
+      a0 = MAXLOG ? fmaxf(L0[b], pL0[b]) : L0[b] + pL0[b];
+      a1 = MAXLOG ? fmaxf(L1[b], pL1[b]) : L1[b] + pL1[b];
+    } else if (b == 4) {
+      a0 = Th;
+      a1 = pTh;
+    } else if (b < 5 + LOG2G) {
+      a0 = MAXLOG ? fmaxf(L0[b - 1], pL0[b - 1]) : L0[b - 1] + pL0[b - 1];
+      a1 = MAXLOG ? fmaxf(L1[b - 1], pL1[b - 1]) : L1[b - 1] + pL1[b - 1];
+    } else {
+      const int q = b - 5 - LOG2G;
+      a0 = MAXLOG ? fmaxf(A.H0[q], pH0[q]) : A.H0[q] + pH0[q];
+      a1 = MAXLOG ? fmaxf(A.H1[q], pH1[q]) : A.H1[q] + pH1[q];
+    }
+    S0[b] = a0;
+    S1[b] = a1;
+  }
+}
+
+// Whether the FP32 subset sums of a symbol kept their range (exact path).
+template <int MB>
+__device__ __forceinline__ bool sums_in_range(const float (&S0)[MB], const float (&S1)[MB]) {
+  float smin = INFINITY, smax = 0.0f;
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    smin = fminf(smin, fminf(S0[b], S1[b]));
+    smax = fmaxf(smax, fmaxf(S0[b], S1[b]));
+  }
+  return smin >= 0x1p-96f && smax <= 0x1p+126f;
+}
+
 template <int KS, int WAVES, int MB, int SB, bool MAXLOG>
 __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __restrict__ frag, int ntiles,
                                                               int chunk_tiles, int D,
@@ -109,10 +304,6 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
                                                               int* __restrict__ flags,
                                                               unsigned* __restrict__ fb_list) {
   constexpr int m = MB;
-  constexpr int LOG2G = Geo<MB>::LOG2G;
-  constexpr int G = Geo<MB>::G;
-  constexpr int nh = Geo<MB>::NH;
-  constexpr int NHMAX = Geo<MB>::NHA;
   constexpr int S = 16 * KS;                 // K slots per symbol
   extern __shared__ uint4 lds[];
   const int lane = threadIdx.x & 63;
@@ -124,7 +315,6 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
   const int64_t ngroups = (N + per_group - 1) / per_group;
   const int nchunks = (ntiles + chunk_tiles - 1) / chunk_tiles;
   const int frag_per_tile = KS * 64;
-  const float ident = MAXLOG ? -INFINITY : 0.0f;
   // per-wave staging rows for the B operand, after the fragment chunk
   _Float16* bst = reinterpret_cast<_Float16*>(lds + chunk_tiles * frag_per_tile) + wave * SB * 32 * S;
   bool staged = false;
@@ -138,21 +328,11 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
     for (int sb = 0; sb < SB; ++sb) {
       const int64_t n = g * per_group + (static_cast<int64_t>(wave) * SB + sb) * 32 + (lane & 31);
       nsym[sb] = n;
-      const bool live = n < N;
-      const bool b = build_symbol_operand<KS>(bst + (sb * 32 + (lane & 31)) * S, y, n, live, D, cb, cn, alpha,
+      const bool b = build_symbol_operand<KS>(bst + (sb * 32 + (lane & 31)) * S, y, n, n < N, D, cb, cn, alpha,
                                               MAXLOG ? 0.0f : kExpBias, bf[sb]);
       bad[sb] = b || range_bad;
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) ac[sb].E[rr] = ident;
-#pragma unroll
-      for (int i = 0; i < G; ++i) ac[sb].Tg[i] = ident;
-#pragma unroll
-      for (int q = 0; q < NHMAX; ++q) {
-        ac[sb].H0[q] = ident;
-        ac[sb].H1[q] = ident;
-      }
     }
-
+    acc_init<MB, SB, MAXLOG>(ac);
     for (int ch = 0; ch < nchunks; ++ch) {
       const int t0 = ch * chunk_tiles;
       const int tn = min(chunk_tiles, ntiles - t0);     // a multiple of G
@@ -164,176 +344,25 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
         __syncthreads();
         staged = true;
       }
-      // prologue: score block of the chunk's first tile
-      floatx16 cur[SB];
-      {
-        half8 ah[KS];
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[ks * 64 + lane]);
-#pragma unroll
-        for (int sb = 0; sb < SB; ++sb) {
-#pragma unroll
-          for (int rr = 0; rr < 16; ++rr) cur[sb][rr] = 0.0f;
-#pragma unroll
-          for (int ks = 0; ks < KS; ++ks)
-            cur[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], cur[sb], 0, 0, 0);
-        }
-      }
-      for (int tg = 0; tg < tn; tg += G) {
-#pragma unroll
-        for (int i = 0; i < G; ++i) {
-          // issue the next tile's score blocks (the chunk's last tile recomputes itself)
-          const int tnext = min(tg + i + 1, tn - 1);
-          floatx16 nxt[SB];
-          half8 ah[KS];
-#pragma unroll
-          for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[(tnext * KS + ks) * 64 + lane]);
-#pragma unroll
-          for (int sb = 0; sb < SB; ++sb) {
-#pragma unroll
-            for (int rr = 0; rr < 16; ++rr) nxt[sb][rr] = 0.0f;
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks)
-              nxt[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], nxt[sb], 0, 0, 0);
-          }
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int sb = 0; sb < SB; ++sb) {
-            SymAcc<MB>& A = ac[sb];
-            float v[16];
-            if (MAXLOG) {
-#pragma unroll
-              for (int rr = 0; rr < 16; ++rr) {
-                v[rr] = cur[sb][rr];
-                A.E[rr] = fmaxf(A.E[rr], v[rr]);
-              }
-#pragma unroll
-              for (int w = 8; w >= 1; w >>= 1)
-#pragma unroll
-                for (int rr = 0; rr < w; ++rr) v[rr] = fmaxf(v[rr], v[rr + w]);
-              A.Tg[i] = fmaxf(A.Tg[i], v[0]);
-              A.GT = (i == 0) ? v[0] : fmaxf(A.GT, v[0]);
-            } else {
-#pragma unroll
-              for (int rr = 0; rr < 16; ++rr) {
-                v[rr] = __builtin_amdgcn_exp2f(cur[sb][rr]);
-                A.E[rr] += v[rr];
-              }
-#pragma unroll
-              for (int w = 8; w >= 1; w >>= 1)
-#pragma unroll
-                for (int rr = 0; rr < w; ++rr) v[rr] += v[rr + w];
-              A.Tg[i] += v[0];
-              A.GT = (i == 0) ? v[0] : A.GT + v[0];
-            }
-          }
-          __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-          for (int sb = 0; sb < SB; ++sb) cur[sb] = nxt[sb];
-        }
-        // route the group sums by the label bits above the group
-        const int grp = (t0 + tg) >> LOG2G;
-#pragma unroll
-        for (int q = 0; q < nh; ++q) {
-          const bool bit = (grp >> q) & 1;
-#pragma unroll
-          for (int sb = 0; sb < SB; ++sb) {
-            SymAcc<MB>& A = ac[sb];
-            if (MAXLOG) {
-              A.H1[q] = bit ? fmaxf(A.H1[q], A.GT) : A.H1[q];
-              A.H0[q] = bit ? A.H0[q] : fmaxf(A.H0[q], A.GT);
-            } else {
-              const float a = bit ? A.GT : 0.0f;
-              A.H1[q] += a;
-              A.H0[q] += A.GT - a;
-            }
-          }
-        }
-      }
+      tile_loop<KS, MB, SB, MAXLOG>(lds, t0, tn, lane, bf, ac);
     }
-
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) {
-      const SymAcc<MB>& A = ac[sb];
       const int64_t n = nsym[sb];
-      const bool live = n < N;
-      // subset sums per label bit.  bits 0..3: positions inside the lane; bit 4: lane
-      // half; bits 5..4+LOG2G: Tg; bits 5+LOG2G ..: H0/H1.
-      float L0[4 + LOG2G], L1[4 + LOG2G];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        float a0 = ident, a1 = ident;
-#pragma unroll
-        for (int rr = 0; rr < 16; ++rr) {
-          if ((rr >> b) & 1) a1 = MAXLOG ? fmaxf(a1, A.E[rr]) : a1 + A.E[rr];
-          else a0 = MAXLOG ? fmaxf(a0, A.E[rr]) : a0 + A.E[rr];
-        }
-        L0[b] = a0;
-        L1[b] = a1;
-      }
-#pragma unroll
-      for (int b = 0; b < LOG2G; ++b) {
-        float a0 = ident, a1 = ident;
-#pragma unroll
-        for (int i = 0; i < G; ++i) {
-          if ((i >> b) & 1) a1 = MAXLOG ? fmaxf(a1, A.Tg[i]) : a1 + A.Tg[i];
-          else a0 = MAXLOG ? fmaxf(a0, A.Tg[i]) : a0 + A.Tg[i];
-        }
-        L0[4 + b] = a0;
-        L1[4 + b] = a1;
-      }
-      const float Th = MAXLOG ? fmaxf(L0[0], L1[0]) : L0[0] + L1[0];
-      float pL0[4 + LOG2G], pL1[4 + LOG2G], pH0[NHMAX], pH1[NHMAX];
-#pragma unroll
-      for (int b = 0; b < 4 + LOG2G; ++b) {
-        pL0[b] = __shfl_xor(L0[b], 32, 64);
-        pL1[b] = __shfl_xor(L1[b], 32, 64);
-      }
-      const float pTh = __shfl_xor(Th, 32, 64);
-#pragma unroll
-      for (int q = 0; q < NHMAX; ++q) {
-        pH0[q] = __shfl_xor(A.H0[q], 32, 64);
-        pH1[q] = __shfl_xor(A.H1[q], 32, 64);
-      }
+      float S0[MB], S1[MB];
+      combine_subsets<MB, MAXLOG>(ac[sb], false, S0, S1);
       const bool badp = __shfl_xor(static_cast<int>(bad[sb]), 32, 64) != 0;
-      if (h == 0 && live) {
+      if (h == 0 && n < N) {
         if (invalid) {
           for (int k = 0; k < m; ++k) llr[n * m + k] = __builtin_nanf("");
+        } else if (bad[sb] || badp || (!MAXLOG && !sums_in_range<MB>(S0, S1))) {
+          const int idx = atomicAdd(&flags[1], 1);
+          fb_list[idx] = static_cast<unsigned>(n);
         } else {
-          float S0[m], S1[m];
-          float smin = INFINITY, smax = 0.0f;
 #pragma unroll
-          for (int b = 0; b < m; ++b) {
-            float a0, a1;
-            if (b < 4) {
-              a0 = MAXLOG ? fmaxf(L0[b], pL0[b]) : L0[b] + pL0[b];
-              a1 = MAXLOG ? fmaxf(L1[b], pL1[b]) : L1[b] + pL1[b];
-            } else if (b == 4) {
-              a0 = Th;
-              a1 = pTh;
-            } else if (b < 5 + LOG2G) {
-              a0 = MAXLOG ? fmaxf(L0[b - 1], pL0[b - 1]) : L0[b - 1] + pL0[b - 1];
-              a1 = MAXLOG ? fmaxf(L1[b - 1], pL1[b - 1]) : L1[b - 1] + pL1[b - 1];
-            } else {
-              const int q = b - 5 - LOG2G;
-              a0 = MAXLOG ? fmaxf(A.H0[q], pH0[q]) : A.H0[q] + pH0[q];
-              a1 = MAXLOG ? fmaxf(A.H1[q], pH1[q]) : A.H1[q] + pH1[q];
-            }
-            S0[b] = a0;
-            S1[b] = a1;
-            smin = fminf(smin, fminf(a0, a1));
-            smax = fmaxf(smax, fmaxf(a0, a1));
-          }
-          const bool range_lost = MAXLOG ? false : !(smin >= 0x1p-96f && smax <= 0x1p+126f);
-          if (bad[sb] || badp || range_lost) {
-            const int idx = atomicAdd(&flags[1], 1);
-            fb_list[idx] = static_cast<unsigned>(n);
-          } else {
-#pragma unroll
-            for (int k = 0; k < m; ++k) {
-              const int b = m - 1 - k;
-              llr[n * m + k] = MAXLOG ? kLn2 * (S0[b] - S1[b]) : kLn2 * (log2f(S0[b]) - log2f(S1[b]));
-            }
+          for (int k = 0; k < m; ++k) {
+            const int b = m - 1 - k;
+            llr[n * m + k] = MAXLOG ? kLn2 * (S0[b] - S1[b]) : kLn2 * (log2f(S0[b]) - log2f(S1[b]));
           }
         }
       }
@@ -659,8 +688,8 @@ int launch_bf16_m(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
   }
 }
 
-inline int launch_bf16(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr,
-                       hipStream_t stream) {
+template <int UNUSED = 0>
+int launch_bf16(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr, hipStream_t stream) {
   const int v = fast_variant();
   switch (P.ks) {
     case 1:

@@ -6,7 +6,7 @@ namespace md {
 
 int launch_fast_bf16(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr,
                      hipStream_t stream) {
-  return fastk::launch_bf16(P, M, D, d_y, N, d_llr, stream);
+  return fastk::launch_bf16<>(P, M, D, d_y, N, d_llr, stream);
 }
 
 }  // namespace md

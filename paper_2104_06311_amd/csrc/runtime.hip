@@ -20,6 +20,7 @@ int fail(int status, const std::string& msg) {
 }
 
 int hip_fail(hipError_t e, const char* what) {
+  (void)hipGetLastError();   // consume the error so that later checks do not report it again
   g_last_error = std::string(what) + ": " + hipGetErrorString(e);
   if (e == hipErrorOutOfMemory) return MD_ENOMEM;
   if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return MD_ENODEV;
@@ -27,6 +28,7 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 int current_device(int* dev) {
+  (void)hipGetLastError();   // a stale error of earlier, unrelated work must not be reported here
   int n = 0;
   hipError_t e = hipGetDeviceCount(&n);
   if (e != hipSuccess || n == 0) return fail(MD_ENODEV, "no GPU visible");

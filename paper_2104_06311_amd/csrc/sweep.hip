@@ -1,0 +1,700 @@
+// Batched sweep: channel draw, exact LLRs and GMI for many constellations (uneven M and
+// D) at many noise levels, in one persistent kernel launched from a captured hipGraph.
+//
+// A plan holds one "problem" per (instance, noise level): its label-ordered constellation,
+// its MFMA fragments (which depend on the noise level through the score scales), the
+// channel stream and N.  Each problem is cut into work items of a fixed number of
+// symbol groups; items are ordered by cost (M times K steps, largest first) so that the
+// dynamically scheduled persistent blocks finish together.  For every item a block draws
+// the channel uses itself (the awgn_sample definition at offset = noise index * N), forms
+// the scores and subset sums with the same tile loop as llr_exact, and adds the item's
+// GMI loss sum_n sum_k log2(1 + S_other / S_sent) to a per-item FP64 slot -- LLRs and
+// received symbols never touch HBM.  Symbols whose subset sums leave FP32 range are
+// queued with their received vector and label and re-evaluated in FP64 by a second kernel,
+// which adds its losses as 2^-40 fixed-point integers (order independent).  A final kernel
+// adds the item slots of each problem in a fixed order: the result is deterministic.
+// The graph: reset -> persistent sweep -> fallback -> final (no memset nodes).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "llr_fast.hpp"
+#include "llr_kernels.hpp"
+#include "rng.hpp"
+
+namespace md {
+namespace {
+
+using fastk::Geo;
+using fastk::SymAcc;
+
+constexpr int kMaxKS = 2;          // D <= 8
+constexpr int kFbCap = 1 << 20;    // fallback records per run
+constexpr int kDynLds = 159 * 1024;  // dynamic LDS of the persistent kernel
+
+struct Problem {
+  const uint4* frag;
+  const float* xl;         // label order
+  const float* X;          // index order (for the channel)
+  const uint32_t* labels;  // label of each index
+  int M, m, D, ks, ntiles, chunk_tiles;
+  float cb, cn, alpha;
+  double sigma;
+  uint32_t k0, k1;
+  uint64_t offset;
+  int64_t N;
+  int item_begin, item_end;
+};
+
+struct Item {
+  int prob;
+  int count;       // symbols in this item
+  int64_t start;   // first symbol
+};
+
+struct FbRecord {
+  int prob;
+  uint32_t label;
+  float y[8];
+};
+
+// Every symbol of a group: lane half h of wave w owns symbol (w * SB + h) * 32 + lane % 32
+// of the group when SB = 2 (with SB = 1 only half 0 owns symbols).
+// Writes the symbol's K-slot row (see prep.hip); returns true when an operand leaves the
+// FP16 split range.
+template <int KS>
+__device__ __forceinline__ bool write_symbol_row(_Float16* row, const float (&yv)[8], int D, float cb, float cn,
+                                                 float alpha, float bias) {
+  constexpr int S = 16 * KS;
+  float ysq = 0.0f;
+  bool bad = false;
+#pragma unroll
+  for (int d = 0; d < 8; ++d) {
+    if (d < D) {
+      ysq = fmaf(yv[d], yv[d], ysq);
+      const float w = cb * yv[d];
+      bad |= !(fabsf(w) <= 30000.0f);
+      const _Float16 hi = static_cast<_Float16>(w);
+      const _Float16 lo = static_cast<_Float16>(w - static_cast<float>(hi));
+      row[d] = hi;
+      row[D + d] = hi;
+      row[2 * D + d] = lo;
+    }
+  }
+  const float r = bias / alpha - cn * ysq;
+  bad |= !(fabsf(r) <= 30000.0f);
+  const _Float16 rhi = static_cast<_Float16>(r);
+  const _Float16 rlo = static_cast<_Float16>(r - static_cast<float>(rhi));
+  const _Float16 a16 = static_cast<_Float16>(alpha);
+  row[3 * D] = a16;
+  row[3 * D + 1] = a16;
+  row[3 * D + 2] = rhi;
+  row[3 * D + 3] = rlo;
+  for (int k = 3 * D + 4; k < S; ++k) row[k] = static_cast<_Float16>(0.0f);
+  return bad;
+}
+
+template <int WAVES, int SB, int KS, int MB>
+__device__ void process_item(const Problem& P, const Item& I, int it, uint4* lds, int& staged_prob,
+                             double* __restrict__ item_sum, FbRecord* __restrict__ fb, int* __restrict__ counters,
+                             float* __restrict__ wsum) {
+  constexpr int S = 16 * KS;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5;
+  const int frag_per_tile = KS * 64;
+  const int per_group = WAVES * 32 * SB;
+  const int ngroups = (I.count + per_group - 1) / per_group;
+  const int nchunks = (P.ntiles + P.chunk_tiles - 1) / P.chunk_tiles;
+  _Float16* bst = reinterpret_cast<_Float16*>(lds + P.chunk_tiles * frag_per_tile) + wave * SB * 32 * S;
+  const bool half_tile = P.M < 32;
+  float acc_loss = 0.0f;
+  for (int gi = 0; gi < ngroups; ++gi) {
+    // ---- channel draw by the owning lanes, symbol rows into LDS
+    const int owner_sb = (SB == 2) ? h : 0;
+    const bool owner = (SB == 2) || h == 0;
+    const int64_t local = static_cast<int64_t>(gi) * per_group + (wave * SB + owner_sb) * 32 + (lane & 31);
+    const bool live_own = owner && local < I.count;
+    uint32_t lab_own = 0;
+    bool bad_own = false;
+    float yv_own[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) yv_own[d] = 0.0f;
+    if (owner) {
+      float (&yv)[8] = yv_own;
+      if (live_own) {
+        const uint64_t g = P.offset + static_cast<uint64_t>(I.start + local);
+        const uint32_t u = rng::channel_symbol(P.X, P.m, P.D, P.k0, P.k1, g, P.sigma, yv);
+        lab_own = P.labels[u];
+      }
+      _Float16* row = bst + (owner_sb * 32 + (lane & 31)) * S;
+      bad_own = write_symbol_row<KS>(row, yv, P.D, P.cb, P.cn, P.alpha, fastk::kExpBias);
+      if (live_own && bad_own) {
+        // operands outside the FP16 split range: straight to the FP64 fallback
+        const int idx = atomicAdd(&counters[1], 1);
+        if (idx < kFbCap) {
+          FbRecord& r = fb[idx];
+          r.prob = I.prob;
+          r.label = lab_own;
+#pragma unroll
+          for (int d = 0; d < 8; ++d) r.y[d] = yv[d];
+        } else {
+          atomicOr(&counters[2], 1);
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    half8 bf[SB][KS];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const uint4 v = *reinterpret_cast<const uint4*>(bst + (sb * 32 + (lane & 31)) * S + 16 * ks + 8 * h);
+        __builtin_memcpy(&bf[sb][ks], &v, 16);
+      }
+    // the rows are consumed: the owners park their received vectors there (8 floats <= 32 KS
+    // bytes) for the rare symbol that needs the FP64 fallback after the tile loop
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (owner) {
+      float* yrow = reinterpret_cast<float*>(bst + (owner_sb * 32 + (lane & 31)) * S);
+#pragma unroll
+      for (int d = 0; d < 8; ++d) yrow[d] = yv_own[d];
+    }
+    SymAcc<MB> ac[SB];
+    fastk::acc_init<MB, SB, false>(ac);
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const int t0 = ch * P.chunk_tiles;
+      const int tn = min(P.chunk_tiles, P.ntiles - t0);
+      if (nchunks > 1 || staged_prob != I.prob) {
+        __syncthreads();
+        const int total = tn * frag_per_tile;
+        const uint4* src = P.frag + static_cast<int64_t>(t0) * frag_per_tile;
+        for (int i = threadIdx.x; i < total; i += WAVES * 64) lds[i] = src[i];
+        __syncthreads();
+        staged_prob = (nchunks > 1) ? -1 : I.prob;
+      }
+      fastk::tile_loop<KS, MB, SB, false>(lds, t0, tn, lane, bf, ac);
+    }
+    // ---- GMI loss of every symbol: sum_k log2(S0_k + S1_k) - log2(S_sent,k)
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      float S0[MB], S1[MB];
+      fastk::combine_subsets<MB, false>(ac[sb], half_tile, S0, S1);
+      // the owner of block sb is lane half sb (SB = 2) or half 0 (SB = 1)
+      const int src = (SB == 2 && sb == 1) ? 32 : 0;
+      const uint32_t lab = __shfl(lab_own, src + (lane & 31), 64);
+      const bool live = __shfl(static_cast<int>(live_own), src + (lane & 31), 64) != 0;
+      const bool bad = __shfl(static_cast<int>(bad_own), src + (lane & 31), 64) != 0;
+      if (h == 0 && live && !bad) {
+        const int m = P.m;
+        float smin = INFINITY, smax = 0.0f;
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+          if (b < m) {
+            smin = fminf(smin, fminf(S0[b], S1[b]));
+            smax = fmaxf(smax, fmaxf(S0[b], S1[b]));
+          }
+        if (smin >= 0x1p-96f && smax <= 0x1p+126f) {
+          float T = 0.0f;
+#pragma unroll
+          for (int b = 0; b < MB; ++b)
+            if (b < m) {
+              const float sent = ((lab >> b) & 1u) ? S1[b] : S0[b];
+              T += log2f(S0[b] + S1[b]) - log2f(sent);
+            }
+          acc_loss += T;
+        } else {
+          // the owner parked the received vector in the symbol's staging row
+          const float* yrow = reinterpret_cast<const float*>(bst + (sb * 32 + (lane & 31)) * S);
+          float yv[8];
+#pragma unroll
+          for (int d = 0; d < 8; ++d) yv[d] = yrow[d];
+          const int idx = atomicAdd(&counters[1], 1);
+          if (idx < kFbCap) {
+            FbRecord& r = fb[idx];
+            r.prob = I.prob;
+            r.label = lab;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) r.y[d] = yv[d];
+          } else {
+            atomicOr(&counters[2], 1);
+          }
+        }
+      }
+    }
+  }
+  // ---- item sum: wave sums, then the block's waves in a fixed order
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) acc_loss += __shfl_xor(acc_loss, o, 64);
+  __syncthreads();
+  if (lane == 0) wsum[wave] = acc_loss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < WAVES; ++w) s += static_cast<double>(wsum[w]);
+    item_sum[it] = s;
+  }
+}
+
+template <int WAVES, int SB>
+__global__ void __launch_bounds__(WAVES * 64) sweep_kernel(const Problem* __restrict__ probs,
+                                                           const Item* __restrict__ items, int n_items,
+                                                           int* __restrict__ counters, double* __restrict__ item_sum,
+                                                           FbRecord* __restrict__ fb) {
+  extern __shared__ uint4 lds[];
+  __shared__ int next;
+  __shared__ float wsum[WAVES];
+  int staged_prob = -1;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(&counters[0], 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(next);     // uniform: scalar loads below
+    __syncthreads();
+    if (it >= n_items) break;
+    const Item I = items[it];
+    const Problem P = probs[I.prob];
+    const int key = (P.ks - 1) * 16 + P.m;
+    switch (key) {
+#define MD_SWEEP_CASE(KS_, MB_, MBK_)                                                                    \
+  case (KS_ - 1) * 16 + MB_:                                                                         \
+    process_item<WAVES, SB, KS_, MBK_>(P, I, it, lds, staged_prob, item_sum, fb, counters, wsum);     \
+    break;
+      MD_SWEEP_CASE(1, 4, 5) MD_SWEEP_CASE(1, 5, 5) MD_SWEEP_CASE(1, 6, 6) MD_SWEEP_CASE(1, 7, 7)
+      MD_SWEEP_CASE(1, 8, 8) MD_SWEEP_CASE(1, 9, 9) MD_SWEEP_CASE(1, 10, 10) MD_SWEEP_CASE(1, 11, 11)
+      MD_SWEEP_CASE(1, 12, 12) MD_SWEEP_CASE(1, 13, 13)
+      MD_SWEEP_CASE(2, 4, 5) MD_SWEEP_CASE(2, 5, 5) MD_SWEEP_CASE(2, 6, 6) MD_SWEEP_CASE(2, 7, 7)
+      MD_SWEEP_CASE(2, 8, 8) MD_SWEEP_CASE(2, 9, 9) MD_SWEEP_CASE(2, 10, 10) MD_SWEEP_CASE(2, 11, 11)
+      MD_SWEEP_CASE(2, 12, 12) MD_SWEEP_CASE(2, 13, 13)
+#undef MD_SWEEP_CASE
+      default:
+        break;
+    }
+  }
+}
+
+// Re-evaluates queued symbols in FP64 (one wavefront per record): per-subset maxima and
+// log-sum-exp, then the loss sum_k log2(1 + e^{L_other - L_sent}) added to the problem's
+// fixed-point accumulator.
+__global__ void __launch_bounds__(256) sweep_fallback_kernel(const Problem* __restrict__ probs,
+                                                             const FbRecord* __restrict__ fb,
+                                                             const int* __restrict__ counters,
+                                                             unsigned long long* __restrict__ fb_acc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave_id = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+  const int64_t count = min(counters[1], kFbCap);
+  for (int64_t r = wave_id; r < count; r += nwaves) {
+    const FbRecord R = fb[r];
+    const Problem P = probs[R.prob];
+    const double cnat = static_cast<double>(P.cn) * static_cast<double>(P.alpha) / 1.4426950408889634;
+    double mx0[16], mx1[16];
+    for (int k = 0; k < 16; ++k) {
+      mx0[k] = -INFINITY;
+      mx1[k] = -INFINITY;
+    }
+    for (int j = lane; j < P.M; j += 64) {
+      double d2 = 0.0;
+      for (int d = 0; d < P.D; ++d) {
+        const double df = static_cast<double>(R.y[d]) - static_cast<double>(P.xl[static_cast<int64_t>(j) * P.D + d]);
+        d2 = fma(df, df, d2);
+      }
+      const double q = -cnat * d2;
+      for (int b = 0; b < P.m; ++b) {
+        if ((j >> b) & 1) mx1[b] = fmax(mx1[b], q);
+        else mx0[b] = fmax(mx0[b], q);
+      }
+    }
+    for (int b = 0; b < P.m; ++b)
+      for (int o = 32; o >= 1; o >>= 1) {
+        mx0[b] = fmax(mx0[b], __shfl_xor(mx0[b], o, 64));
+        mx1[b] = fmax(mx1[b], __shfl_xor(mx1[b], o, 64));
+      }
+    double s0[16], s1[16];
+    for (int k = 0; k < 16; ++k) {
+      s0[k] = 0.0;
+      s1[k] = 0.0;
+    }
+    for (int j = lane; j < P.M; j += 64) {
+      double d2 = 0.0;
+      for (int d = 0; d < P.D; ++d) {
+        const double df = static_cast<double>(R.y[d]) - static_cast<double>(P.xl[static_cast<int64_t>(j) * P.D + d]);
+        d2 = fma(df, df, d2);
+      }
+      const double q = -cnat * d2;
+      for (int b = 0; b < P.m; ++b) {
+        if ((j >> b) & 1) s1[b] += exp(q - mx1[b]);
+        else s0[b] += exp(q - mx0[b]);
+      }
+    }
+    double T = 0.0;
+    for (int b = 0; b < P.m; ++b) {
+      double a0 = s0[b], a1 = s1[b];
+      for (int o = 32; o >= 1; o >>= 1) {
+        a0 += __shfl_xor(a0, o, 64);
+        a1 += __shfl_xor(a1, o, 64);
+      }
+      const double l0 = mx0[b] + log(a0), l1 = mx1[b] + log(a1);
+      const bool one = (R.label >> b) & 1u;
+      const double diff = one ? l0 - l1 : l1 - l0;          // other minus sent
+      T += (fmax(diff, 0.0) + log1p(exp(-fabs(diff)))) / 0.69314718055994530942;
+    }
+    if (lane == 0) atomicAdd(&fb_acc[R.prob], static_cast<unsigned long long>(llround(T * 1099511627776.0)));
+  }
+}
+
+__global__ void sweep_reset_kernel(int* __restrict__ counters, unsigned long long* __restrict__ fb_acc, int nprob) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 4) counters[i] = 0;
+  if (i < nprob) fb_acc[i] = 0ull;
+}
+
+__global__ void sweep_final_kernel(const Problem* __restrict__ probs, int nprob, const double* __restrict__ item_sum,
+                                   const unsigned long long* __restrict__ fb_acc, const int* __restrict__ counters,
+                                   double* __restrict__ gmi) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  const Problem P = probs[p];
+  double s = 0.0;
+  for (int i = P.item_begin; i < P.item_end; ++i) s += item_sum[i];
+  s += static_cast<double>(fb_acc[p]) * (1.0 / 1099511627776.0);
+  const bool overflow = counters[2] != 0;
+  gmi[p] = overflow ? __builtin_nan("") : static_cast<double>(P.m) - s / static_cast<double>(P.N);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan
+struct SweepPlan {
+  int n_inst = 0, n_snr = 0, nprob = 0, n_items = 0;
+  int waves = 8, sb = 2, gpi = 1;
+  int device = 0;
+  std::vector<void*> allocs;
+  Problem* d_probs = nullptr;
+  Item* d_items = nullptr;
+  int* d_counters = nullptr;
+  double* d_item_sum = nullptr;
+  FbRecord* d_fb = nullptr;
+  unsigned long long* d_fb_acc = nullptr;
+  double* d_gmi = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<Problem> h_probs;
+  std::vector<int*> h_flags;
+  size_t lds_bytes = 0;
+};
+
+namespace {
+
+int dev_alloc(SweepPlan* p, size_t bytes, void** out) {
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes > 0 ? bytes : 16) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(MD_ENOMEM, "sweep plan allocation failed");
+  }
+  p->allocs.push_back(q);
+  *out = q;
+  return MD_OK;
+}
+
+void free_plan(SweepPlan* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (void* q : p->allocs) (void)hipFree(q);
+  delete p;
+}
+
+template <int WAVES, int SB>
+int enqueue_sweep(SweepPlan* p, hipStream_t s) {
+  auto kern = sweep_kernel<WAVES, SB>;
+  static bool attr_done = false;
+  if (!attr_done) {
+    // the kernel's static LDS (< 1 KiB) and the dynamic part share the 160 KiB of a CU
+    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   kDynLds));
+    attr_done = true;
+  }
+  int ncu = 0, occ = 0;
+  MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
+  MD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kern), WAVES * 64,
+                                                           p->lds_bytes));
+  if (occ < 1) occ = 1;
+  hipLaunchKernelGGL(sweep_reset_kernel, dim3((std::max(p->nprob, 4) + 255) / 256), dim3(256), 0, s, p->d_counters,
+                     p->d_fb_acc, p->nprob);
+  MD_LAUNCH_CHECK("sweep_reset_kernel launch");
+  hipLaunchKernelGGL(kern, dim3(ncu * occ), dim3(WAVES * 64), p->lds_bytes, s, p->d_probs, p->d_items, p->n_items,
+                     p->d_counters, p->d_item_sum, p->d_fb);
+  MD_LAUNCH_CHECK("sweep_kernel launch");
+  hipLaunchKernelGGL(sweep_fallback_kernel, dim3(ncu * 4), dim3(256), 0, s, p->d_probs, p->d_fb, p->d_counters,
+                     p->d_fb_acc);
+  MD_LAUNCH_CHECK("sweep_fallback_kernel launch");
+  hipLaunchKernelGGL(sweep_final_kernel, dim3((p->nprob + 255) / 256), dim3(256), 0, s, p->d_probs, p->nprob,
+                     p->d_item_sum, p->d_fb_acc, p->d_counters, p->d_gmi);
+  MD_LAUNCH_CHECK("sweep_final_kernel launch");
+  return MD_OK;
+}
+
+int enqueue(SweepPlan* p, hipStream_t s) {
+  if (p->waves == 16) return enqueue_sweep<16, 1>(p, s);
+  return enqueue_sweep<8, 2>(p, s);
+}
+
+// Builds the item list for the plan's launch shape (groups per item gpi).
+int build_items(SweepPlan* p) {
+  const int per_group = p->waves * 32 * p->sb;
+  const int per_item = per_group * p->gpi;
+  std::vector<int> order(static_cast<size_t>(p->nprob));
+  for (int i = 0; i < p->nprob; ++i) order[static_cast<size_t>(i)] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const Problem& A = p->h_probs[static_cast<size_t>(a)];
+    const Problem& B = p->h_probs[static_cast<size_t>(b)];
+    return static_cast<int64_t>(A.M) * A.ks > static_cast<int64_t>(B.M) * B.ks;
+  });
+  std::vector<Item> items;
+  for (int pi : order) {
+    Problem& P = p->h_probs[static_cast<size_t>(pi)];
+    P.item_begin = static_cast<int>(items.size());
+    for (int64_t s0 = 0; s0 < P.N; s0 += per_item) {
+      Item it;
+      it.prob = pi;
+      it.start = s0;
+      it.count = static_cast<int>(std::min<int64_t>(per_item, P.N - s0));
+      items.push_back(it);
+    }
+    P.item_end = static_cast<int>(items.size());
+  }
+  if (items.size() > static_cast<size_t>(1) << 30) return fail(MD_EINVAL, "too many work items");
+  p->n_items = static_cast<int>(items.size());
+  void* q = nullptr;
+  int st = dev_alloc(p, sizeof(Item) * items.size(), &q);
+  if (st != MD_OK) return st;
+  p->d_items = static_cast<Item*>(q);
+  st = dev_alloc(p, sizeof(double) * items.size(), &q);
+  if (st != MD_OK) return st;
+  p->d_item_sum = static_cast<double*>(q);
+  MD_HIP_TRY(hipMemcpy(p->d_items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice));
+  MD_HIP_TRY(hipMemcpy(p->d_probs, p->h_probs.data(), sizeof(Problem) * p->h_probs.size(), hipMemcpyHostToDevice));
+  return MD_OK;
+}
+
+int capture(SweepPlan* p) {
+  if (p->exec) {
+    MD_HIP_TRY(hipGraphExecDestroy(p->exec));
+    p->exec = nullptr;
+  }
+  if (p->graph) {
+    MD_HIP_TRY(hipGraphDestroy(p->graph));
+    p->graph = nullptr;
+  }
+  MD_HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+  int st = enqueue(p, p->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+  if (st != MD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  p->graph = g;
+  MD_HIP_TRY(hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0));
+  return MD_OK;
+}
+
+}  // namespace
+}  // namespace md
+
+extern "C" {
+
+int sweep_plan_create(const md_sweep_instance* inst, int n_inst, const double* sigma2, int n_snr, int variant,
+                      void** out) {
+  md::set_error("");
+  if (!out || !inst || !sigma2) return md::fail(MD_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n_inst < 1 || n_snr < 1 || static_cast<int64_t>(n_inst) * n_snr > (1 << 20))
+    return md::fail(MD_EINVAL, "need 1 <= instances x noise levels <= 2^20");
+  if (variant < -1 || variant > 3) return md::fail(MD_EINVAL, "variant outside [-1, 3]");
+  int dev = 0;
+  int st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  for (int i = 0; i < n_inst; ++i) {
+    const md_sweep_instance& I = inst[i];
+    if (!I.d_X || !I.d_labels) return md::fail(MD_EINVAL, "instance " + std::to_string(i) + ": NULL pointer");
+    if (I.M < 16 || I.M > 8192 || !md::is_pow2(I.M))
+      return md::fail(MD_EUNSUPPORTED, "instance " + std::to_string(i) + ": the sweep takes M in {16 .. 8192}");
+    if (I.D < 1 || I.D > 8)
+      return md::fail(MD_EUNSUPPORTED, "instance " + std::to_string(i) + ": the sweep takes D in [1, 8]");
+    if (I.N < 1) return md::fail(MD_EINVAL, "instance " + std::to_string(i) + ": N must be >= 1");
+    st = md::check_labels_once(I.d_labels, I.M, nullptr);
+    if (st != MD_OK) return st;
+    for (int s = 0; s < n_snr; ++s) {
+      const double v = sigma2[static_cast<size_t>(i) * n_snr + s];
+      if (!(v > 0.0) || !std::isfinite(v)) return md::fail(MD_EINVAL, "sigma2 must be finite and > 0");
+    }
+  }
+  md::SweepPlan* p = new md::SweepPlan();
+  p->n_inst = n_inst;
+  p->n_snr = n_snr;
+  p->nprob = n_inst * n_snr;
+  p->device = dev;
+  auto bail = [&](int code) {
+    md::free_plan(p);
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(md::hip_fail(hipGetLastError(), "hipStreamCreate"));
+  void* q = nullptr;
+  if ((st = md::dev_alloc(p, sizeof(md::Problem) * p->nprob, &q))) return bail(st);
+  p->d_probs = static_cast<md::Problem*>(q);
+  if ((st = md::dev_alloc(p, sizeof(int) * 4, &q))) return bail(st);
+  p->d_counters = static_cast<int*>(q);
+  if ((st = md::dev_alloc(p, sizeof(md::FbRecord) * md::kFbCap, &q))) return bail(st);
+  p->d_fb = static_cast<md::FbRecord*>(q);
+  if ((st = md::dev_alloc(p, sizeof(unsigned long long) * p->nprob, &q))) return bail(st);
+  p->d_fb_acc = static_cast<unsigned long long*>(q);
+  if ((st = md::dev_alloc(p, sizeof(double) * p->nprob, &q))) return bail(st);
+  p->d_gmi = static_cast<double*>(q);
+  // per (instance, noise level): label-order copy + fragments (prep kernels on cap_stream)
+  int max_frag_bytes = 0;
+  p->h_probs.resize(static_cast<size_t>(p->nprob));
+  p->h_flags.resize(static_cast<size_t>(p->nprob));
+  for (int i = 0; i < n_inst; ++i) {
+    const md_sweep_instance& I = inst[i];
+    const int ks = md::frag_ksteps(I.D);
+    const int mpad = I.M < 32 ? 32 : I.M;
+    max_frag_bytes = std::max(max_frag_bytes, mpad / 32 * ks * 64 * 16);
+    for (int s = 0; s < n_snr; ++s) {
+      const int pi = i * n_snr + s;
+      const double s2 = sigma2[static_cast<size_t>(i) * n_snr + s];
+      char* ws = nullptr;
+      if ((st = md::dev_alloc(p, md::prep_bytes(I.M, I.D, 1), &q))) return bail(st);
+      ws = static_cast<char*>(q);
+      float alpha = 1.0f, c_over_alpha = 1.0f;
+      md::score_scales(s2, &alpha, &c_over_alpha);
+      md::Prepared prep;
+      if ((st = md::prepare(I.d_X, I.d_labels, I.M, I.D, 1, alpha, c_over_alpha, ws, p->cap_stream, &prep)))
+        return bail(st);
+      p->h_flags[static_cast<size_t>(pi)] = prep.flags;
+      md::Problem& P = p->h_probs[static_cast<size_t>(pi)];
+      P.frag = prep.frag;
+      P.xl = prep.xl;
+      P.X = I.d_X;
+      P.labels = I.d_labels;
+      P.M = I.M;
+      P.m = md::ilog2_pow2(I.M);
+      P.D = I.D;
+      P.ks = ks;
+      P.ntiles = mpad / 32;
+      const double c = static_cast<double>(c_over_alpha) * alpha;
+      P.cb = static_cast<float>(2.0 * c / alpha);
+      P.cn = c_over_alpha;
+      P.alpha = alpha;
+      P.sigma = std::sqrt(s2);
+      P.k0 = static_cast<uint32_t>(I.seed);
+      P.k1 = static_cast<uint32_t>(I.seed >> 32);
+      P.offset = static_cast<uint64_t>(s) * static_cast<uint64_t>(I.N);
+      P.N = I.N;
+    }
+  }
+  if (hipStreamSynchronize(p->cap_stream) != hipSuccess) return bail(md::hip_fail(hipGetLastError(), "prep"));
+  for (int pi = 0; pi < p->nprob; ++pi) {
+    // the prep flags sit right after the fragments' inverse-label table: read them back
+    int fl[4] = {0, 0, 0, 0};
+    if (hipMemcpy(fl, p->h_flags[static_cast<size_t>(pi)], sizeof(fl), hipMemcpyDeviceToHost) != hipSuccess)
+      return bail(md::hip_fail(hipGetLastError(), "prep flags"));
+    if (fl[0]) return bail(md::fail(MD_ELABEL, "labels of problem " + std::to_string(pi) + " are invalid"));
+    if (fl[2])
+      return bail(md::fail(MD_EUNSUPPORTED, "problem " + std::to_string(pi) +
+                                                ": constellation outside the FP16 split range at this noise level"));
+  }
+  // launch shape: autotuned when variant < 0
+  const int shapes[4][3] = {{8, 2, 1}, {8, 2, 4}, {16, 1, 1}, {16, 1, 4}};
+  auto configure = [&](int v) -> int {
+    p->waves = shapes[v][0];
+    p->sb = shapes[v][1];
+    p->gpi = shapes[v][2];
+    // dynamic LDS: fragment chunk, then the symbol staging rows (static LDS < 1 KiB)
+    const int dyn = md::kDynLds;
+    const int bstage = p->waves * p->sb * md::fastk::bstage_bytes<md::kMaxKS>();
+    for (auto& P : p->h_probs) {
+      const int tile_bytes = P.ks * 64 * 16;
+      int ct = (dyn - bstage) / tile_bytes;
+      ct -= ct % 8;
+      P.chunk_tiles = std::min(ct, P.ntiles);
+    }
+    p->lds_bytes = static_cast<size_t>(dyn);
+    return md::build_items(p);
+  };
+  int chosen = variant;
+  if (variant < 0) {
+    // time every launch shape on this plan and keep the fastest
+    float best = 1e30f;
+    for (int v = 0; v < 4; ++v) {
+      if ((st = configure(v))) return bail(st);
+      if ((st = md::enqueue(p, p->cap_stream))) return bail(st);
+      hipEvent_t a, b;
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      (void)hipEventRecord(a, p->cap_stream);
+      st = md::enqueue(p, p->cap_stream);
+      (void)hipEventRecord(b, p->cap_stream);
+      if (hipEventSynchronize(b) != hipSuccess) st = md::hip_fail(hipGetLastError(), "autotune");
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      if (st) return bail(st);
+      if (ms < best) {
+        best = ms;
+        chosen = v;
+      }
+    }
+  }
+  if ((st = configure(chosen))) return bail(st);
+  if ((st = md::capture(p))) return bail(st);
+  *out = p;
+  return MD_OK;
+}
+
+int sweep_plan_info(const void* plan, int* variant_waves, int* variant_sb, int* groups_per_item, int* n_items) {
+  const md::SweepPlan* p = static_cast<const md::SweepPlan*>(plan);
+  if (!p) return md::fail(MD_EINVAL, "plan is NULL");
+  if (variant_waves) *variant_waves = p->waves;
+  if (variant_sb) *variant_sb = p->sb;
+  if (groups_per_item) *groups_per_item = p->gpi;
+  if (n_items) *n_items = p->n_items;
+  return MD_OK;
+}
+
+int sweep_run(void* plan, double* d_gmi, int use_graph, void* stream) {
+  md::set_error("");
+  md::SweepPlan* p = static_cast<md::SweepPlan*>(plan);
+  if (!p || !d_gmi) return md::fail(MD_EINVAL, "plan or gmi is NULL");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (use_graph) {
+    MD_HIP_TRY(hipGraphLaunch(p->exec, s));
+  } else {
+    const int st = md::enqueue(p, s);
+    if (st != MD_OK) return st;
+  }
+  MD_HIP_TRY(hipMemcpyAsync(d_gmi, p->d_gmi, sizeof(double) * p->nprob, hipMemcpyDeviceToDevice, s));
+  return MD_OK;
+}
+
+int sweep_plan_destroy(void* plan) {
+  md::set_error("");
+  md::SweepPlan* p = static_cast<md::SweepPlan*>(plan);
+  if (!p) return MD_OK;
+  MD_HIP_TRY(hipDeviceSynchronize());
+  md::free_plan(p);
+  return MD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+"""GPU checks of the batched sweep (one persistent kernel in a captured hipGraph).
+
+The sweep draws the same channel as awgn_sample (seed_i, offset = s * N_i) and computes
+the GMI loss from the subset sums directly (log2(S0 + S1) - log2(S_sent) per bit, the
+same quantity as softplus of the LLR); compared with the per-instance path
+awgn_sample -> llr_exact -> gmi_reduce the difference is FP32 rounding only:
+|dGMI| <= 2e-5 bit.  Against the FP64 oracle: |dGMI| <= 1e-4 bit.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def md():
+    import paper_2104_06311_amd as m
+    return m
+
+
+def make_instances(specs, seed=5):
+    inst, host = [], []
+    for k, (M, D, N) in enumerate(specs):
+        X, labels = synth.gaussian_constellation(M, D, seed * 100 + k)
+        labels = synth.random_labels(M, seed + k)
+        Xd = torch.from_numpy(X).cuda()
+        ld = torch.from_numpy(labels.astype(np.int32)).cuda()
+        inst.append((Xd, ld, N, 1000 + k))
+        host.append((X, labels))
+    return inst, host
+
+
+def per_instance_gmi(inst, sigma2):
+    out = np.zeros(sigma2.shape)
+    for i, (Xd, ld, N, seed) in enumerate(inst):
+        for s in range(sigma2.shape[1]):
+            tx, y = md().awgn_sample(Xd, seed, s * N, N, math.sqrt(sigma2[i, s]))
+            L = md().llr_exact(Xd, ld, y, sigma2[i, s])
+            out[i, s] = md().gmi_reduce(L, tx, ld)[0].item()
+    return out
+
+
+SPECS = [(16, 2, 3001), (64, 4, 5000), (256, 8, 4000), (1024, 2, 2500), (4096, 8, 1200), (32, 8, 777),
+         (128, 4, 1), (2048, 8, 3000)]
+
+
+def sigma2_grid(host, snrs):
+    return np.array([[synth.sigma2_from_snr_db(X, s) for s in snrs] for X, _ in host])
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_sweep_matches_per_instance_path(variant):
+    inst, host = make_instances(SPECS)
+    s2 = sigma2_grid(host, [2.0, 7.0, 12.0])
+    plan = md().SweepPlan(inst, s2, variant=variant)
+    g = plan.run().cpu().numpy()
+    ref = per_instance_gmi(inst, s2)
+    assert np.all(np.isfinite(g))
+    np.testing.assert_allclose(g, ref, atol=2e-5, rtol=0)
+    plan.close()
+
+
+def test_sweep_against_oracle():
+    inst, host = make_instances([(64, 4, 20000), (256, 2, 8000)], seed=9)
+    s2 = sigma2_grid(host, [4.0, 10.0])
+    plan = md().SweepPlan(inst, s2, variant=0)
+    g = plan.run().cpu().numpy()
+    for i, (X, labels) in enumerate(host):
+        for s in range(2):
+            N, seed = inst[i][2], inst[i][3]
+            tx, y = oracle.awgn(X, seed, s * N, N, math.sqrt(s2[i, s]))
+            gr, _, _ = oracle.gmi(oracle.llr_exact(X, labels, y, s2[i, s]), tx, labels)
+            assert abs(g[i, s] - gr) <= 1e-4, (i, s, g[i, s], gr)
+
+
+def test_graph_replays_equal_eager_and_are_deterministic():
+    inst, host = make_instances(SPECS[:5], seed=3)
+    s2 = sigma2_grid(host, [3.0, 9.0])
+    plan = md().SweepPlan(inst, s2, variant=1)
+    eager = plan.run(use_graph=False).cpu().numpy()
+    for _ in range(3):
+        # unrelated eager work between replays
+        md().llr_exact(inst[1][0], inst[1][1], torch.zeros((100, 4), device="cuda"), 0.3)
+        torch.cuda.synchronize()
+        g = plan.run(use_graph=True).cpu().numpy()
+        assert np.array_equal(g, eager)
+
+
+def test_autotuned_plan_and_limits():
+    inst, host = make_instances(SPECS[:4], seed=4)
+    s2 = sigma2_grid(host, [5.0])
+    plan = md().SweepPlan(inst, s2, variant=-1)
+    assert plan.shape in [(8, 2, 1), (8, 2, 4), (16, 1, 1), (16, 1, 4)]
+    ref = per_instance_gmi(inst, s2)
+    np.testing.assert_allclose(plan.run().cpu().numpy(), ref, atol=2e-5, rtol=0)
+    X, labels = synth.gaussian_constellation(8, 2, 1)
+    bad = [(torch.from_numpy(X).cuda(), torch.from_numpy(labels.astype(np.int32)).cuda(), 100, 1)]
+    with pytest.raises(md().MdemapError) as e:
+        md().SweepPlan(bad, np.array([[0.1]]))
+    assert e.value.status == -8
+    X, labels = synth.gaussian_constellation(64, 12, 1)
+    bad = [(torch.from_numpy(X).cuda(), torch.from_numpy(labels.astype(np.int32)).cuda(), 100, 1)]
+    with pytest.raises(md().MdemapError):
+        md().SweepPlan(bad, np.array([[0.1]]))
