@@ -8,9 +8,11 @@ llr_exact (label-order prep + fused score/exp/subset-sum kernel + fallback) and
 gmi_reduce.  value = 11 * N received symbols per step / step time.
 
 Prints one JSON line.  Extra objects:
-  roofline      the dominant kernel (the llr_exact launch) against the
-                transcendental (exp) throughput of the chip, timed with HIP events
-                on the stream the kernels run on;
+  roofline      the dominant kernel (the llr_exact launch) against the VALU issue
+                ceiling of its per-pair work (one exponential and two FP32 adds),
+                timed with HIP events on the stream the kernels run on; traffic from
+                the committed rocprofv3 counter summary while the kernel sources
+                match it;
   cpu_baseline  the FP64 oracle on a bounded sample of the same workload, timed on
                 this host's cores.
 """
@@ -28,10 +30,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "received symbols/s for exact LLR+GMI (8D, M=2048) and learned-vs-exact at ≤0.01b"
-# Transcendental issue rate: 256 CUs x 2.4 GHz x 32 exp lanes per clock per CU
-# (half of the 64 non-packed FP32 VALU lanes per clock per CU: a wave64 v_exp_f32
-# occupies its SIMD for 8 cycles, a plain FP32 op for 4).
-EXP_PEAK = 256 * 2.4e9 * 32
+# Issue rates of the two VALU instructions the exact path is made of, from the unit counts
+# (256 CUs x 4 SIMDs at 2.4 GHz): a wave64 v_exp_f32 occupies its SIMD for 8 cycles, a
+# wave64 v_add_f32 for 2 (the FP32 vector rate of 157.3 TFLOP/s is 32 FMA lanes per
+# SIMD per clock).  Every (symbol, point) pair needs one exponential and, to form the
+# label-0/label-1 sums of all bits without cancellation, two FP32 adds.
+SIMD_CLOCKS = 256 * 4 * 2.4e9
+EXP_PEAK = SIMD_CLOCKS * 64 / 8                 # 1.966e13 exp/s
+PAIR_PEAK = SIMD_CLOCKS * 64 / (8 + 2 * 2)       # 1.311e13 pairs/s: 1 exp + 2 adds per pair
 
 
 def parse():
@@ -50,6 +56,7 @@ def parse():
     ap.add_argument("--learn-steps", type=int, default=3000, help="training steps per learned network")
     ap.add_argument("--learn-pairs", type=int, default=1 << 24, help="training pairs per SNR point")
     ap.add_argument("--batch-insts", type=int, default=64, help="instances in the batched-sweep object")
+    ap.add_argument("--learn-pairs-16d", type=int, default=1 << 22, help="training pairs per SNR point, 16D")
     return ap.parse_args()
 
 
@@ -105,7 +112,7 @@ def extra_precisions(md, wl, X, labels, N, tx, y, llr):
         tml = timed(lambda: md.llr_maxlog(X, labels, y, s2, out=llr))
         gml = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
         out["bf16"][f"{snr:g}"] = {"llr_ms": t16, "symbols_per_s": N / (t16 * 1e-3),
-                                   "exp_frac": N * wl.M / (t16 * 1e-3) / EXP_PEAK, "gmi": g16,
+                                   "exp_pipe_frac": N * wl.M / (t16 * 1e-3) / EXP_PEAK, "gmi": g16,
                                    "gmi_minus_fp32": g16 - g32}
         out["maxlog"][f"{snr:g}"] = {"llr_ms": tml, "symbols_per_s": N / (tml * 1e-3), "gmi": gml,
                                      "gmi_minus_exact": gml - g32}
@@ -148,6 +155,81 @@ def extra_learned(md, wl, X, labels, N, tx, y, llr, steps, pairs):
                            "final_loss": float(trace[-50:].mean().item())}
         net.close()
     return res
+
+
+def extra_16d(md, steps, pairs):
+    """16D M = 65536 (16 bits), N = 1e6 at 10 and 16 dB: exact vs max-log vs a learned
+    16 -> 512 -> 512 -> 16 network trained on `pairs` (y, exact LLR) pairs per SNR point."""
+    import math
+    import time
+    import numpy as np
+    import torch
+    import synth
+    wl = synth.workload_16d65536()
+    X = torch.from_numpy(wl.X).cuda()
+    labels = torch.from_numpy(wl.labels.astype(np.int32)).cuda()
+    N, m = wl.N, wl.m
+    tx = torch.empty(N, dtype=torch.int32, device="cuda")
+    y = torch.empty((N, wl.D), dtype=torch.float32, device="cuda")
+    llr = torch.empty((N, m), dtype=torch.float32, device="cuda")
+    res = {}
+    for i, snr in enumerate(wl.snr_db):
+        s2 = wl.sigma2(snr)
+        md.awgn_sample(X, wl.seed, i * N, N, math.sqrt(s2), tx=tx, y=y)
+        t_ex = timed(lambda: md.llr_exact(X, labels, y, s2, out=llr))
+        n_wide, n_careful = md.llr_path_counts()
+        g_ex = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
+        t_ml = timed(lambda: md.llr_maxlog(X, labels, y, s2, out=llr))
+        g_ml = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
+        ty = torch.empty((pairs, wl.D), dtype=torch.float32, device="cuda")
+        tt = torch.empty(pairs, dtype=torch.int32, device="cuda")
+        tl = torch.empty((pairs, m), dtype=torch.float32, device="cuda")
+        md.awgn_sample(X, wl.seed + 77, 0, pairs, math.sqrt(s2), tx=tt, y=ty)
+        md.llr_exact(X, labels, ty, s2, out=tl)
+        net = md.MLP(wl.D, 512, m, seed=int(snr))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net.fit(ty, tl, steps=steps, batch=4096, lr_max=2e-3, lr_min=2e-5, seed=int(snr) + 5)
+        train_s = time.perf_counter() - t0
+        del ty, tt, tl
+        t_ln = timed(lambda: md.llr_learned(net, y, out=llr))
+        g_ln = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
+        net.close()
+        res[f"{snr:g}"] = {"exact_ms": t_ex, "exact_symbols_per_s": N / (t_ex * 1e-3),
+                           "exact_pairs_per_s": N * wl.M / (t_ex * 1e-3), "wide_pass_symbols": n_wide,
+                           "careful_symbols": n_careful, "gmi_exact": g_ex, "maxlog_ms": t_ml, "gmi_maxlog": g_ml,
+                           "learned_ms": t_ln, "gmi_learned": g_ln, "learned_gap_bits": g_ex - g_ln,
+                           "learned_speedup_vs_exact": t_ex / t_ln, "train_steps": steps, "train_pairs": pairs,
+                           "train_s": train_s}
+    return {"workload": "16d_m65536_gauss", "N_per_snr": N, "per_snr": res}
+
+
+def counter_traffic(kernel_sources):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "llr_fast_kernel_8d2048_counters.txt")
+    if not os.path.exists(path):
+        return None, "no counter summary"
+    h = hashlib.sha256()
+    for f in kernel_sources:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_sources_sha256") != h.hexdigest():
+        return None, "kernel changed since the counters were taken"
+    try:
+        return float(fields["traffic_bytes_per_launch"]), "rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated"
+    except (KeyError, ValueError):
+        return None, "counter summary incomplete"
+
+
+KERNEL_SOURCES = ["paper_2104_06311_amd/csrc/llr_fast.hpp", "paper_2104_06311_amd/csrc/llr_fast_exact.hip"]
 
 
 def extra_batched(md, n_inst):
@@ -194,7 +276,7 @@ def extra_batched(md, n_inst):
     diff = float((g - ref).abs().max().item())
     return {"instances": n_inst, "snr_points": int(s2.shape[1]), "symbols": total, "pairs": pairs,
             "graph_ms": t_graph, "per_instance_ms": t_loop, "speedup": t_loop / t_graph,
-            "graph_symbols_per_s": total / (t_graph * 1e-3), "graph_exp_frac": pairs / (t_graph * 1e-3) / EXP_PEAK,
+            "graph_symbols_per_s": total / (t_graph * 1e-3), "graph_pair_frac": pairs / (t_graph * 1e-3) / PAIR_PEAK,
             "launch_shape": list(plan.shape), "work_items": plan.n_items, "plan_create_s": plan_s,
             "max_abs_gmi_diff_vs_per_instance": diff,
             "M_mix": sorted({int(w.M) for w in insts}), "D_mix": sorted({int(w.D) for w in insts})}
@@ -256,10 +338,16 @@ def main():
     llr_avg_ms = float(np.mean(llr_ms))
     pairs = N * M
     achieved = pairs / (llr_avg_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": EXP_PEAK / 1e12, "unit": "Texp/s",
-                "frac": achieved / EXP_PEAK, "traffic": None,
-                "kernel": "llr_exact (llr_fast_kernel<1,16,false> + prep + fallback)",
-                "per_launch": f"{pairs:.3e} exp2 (N*M pairs)", "avg_launch_ms": llr_avg_ms}
+    traffic, traffic_note = counter_traffic(KERNEL_SOURCES)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PAIR_PEAK / 1e12, "unit": "Tpair/s",
+                "frac": achieved / PAIR_PEAK, "traffic": traffic,
+                "peak_basis": "VALU issue of 1 v_exp_f32 (8 cycles/wave64) + 2 v_add_f32 (2 cycles/wave64) "
+                              "per (symbol, point) pair; 256 CUs x 4 SIMDs x 2.4 GHz",
+                "frac_exp_pipe": achieved / EXP_PEAK, "exp_pipe_peak": EXP_PEAK / 1e12,
+                "kernel": "llr_fast_kernel<KS=2, 16 wavefronts, m=11, 1 block, exact> (llr_exact: "
+                          "+ 3 prep kernels + wide-range and careful passes over empty lists)",
+                "per_launch": f"{pairs:.3e} (symbol, point) pairs = N*M", "avg_launch_ms": llr_avg_ms,
+                "traffic_note": traffic_note}
 
     if args.copy_probe:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)   # 256 MiB
@@ -277,7 +365,8 @@ def main():
                    "step": "awgn_sample + llr_exact + gmi_reduce per SNR point"},
         "roofline": roofline,
         "detail": {"gmi_bits": {f"{s:g}": round(float(g), 6) for s, g in zip(snrs, gmis.cpu().tolist())},
-                   "llr_symbols_per_s": N / (llr_avg_ms * 1e-3)},
+                   "llr_symbols_per_s": N / (llr_avg_ms * 1e-3),
+                   "wide_careful_symbols_at_14dB": list(md.llr_path_counts())},
     }
     if not args.no_extras:
         out["detail"].update(extra_precisions(md, wl, X, labels, N, tx, y, llr))
@@ -286,6 +375,7 @@ def main():
         del tx, y, llr
         torch.cuda.empty_cache()
         out["detail"]["batched"] = extra_batched(md, args.batch_insts)
+        out["detail"]["16d"] = extra_16d(md, args.learn_steps, args.learn_pairs_16d)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl.X, wl.labels, 9.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -110,8 +110,11 @@ int awgn_sample(const float* d_X, int M, int D, uint64_t seed, uint64_t offset, 
  *   sigma2    noise variance per real dimension (> 0, finite)
  *   prec      MD_PREC_FP32 or MD_PREC_BF16
  *   d_llr     out: N x m float32
- * Symbols whose subset sums would leave the FP32 range are recomputed by a
- * per-subset-maximum evaluation, so every finite input gives finite LLRs.
+ * Symbols whose subset sums leave the FP32 range in the first pass (a subset's best
+ * point more than 196 base-2 units below the bias; high SNR) are evaluated again in
+ * two exponent windows, and what neither window holds by a per-subset-maximum FP64
+ * evaluation, so every finite input gives finite LLRs (llr_path_counts reports how
+ * many symbols took each stage).
  * Returns MD_OK (N = 0 enqueues nothing), MD_EINVAL, MD_ENOTPOW2, MD_ELABEL,
  * MD_EDIM, MD_ENOMEM, MD_EHIP. */
 int llr_exact(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y,
@@ -121,6 +124,13 @@ int llr_exact(const float* d_X, const uint32_t* d_labels, int M, int D, const fl
  * arguments, layout and errors as llr_exact (no precision argument). */
 int llr_maxlog(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y,
                int64_t N, double sigma2, float* d_llr, void* stream);
+
+/* llr_path_counts -- waits for `stream` and reports, for the last llr_exact or
+ * llr_maxlog call enqueued on it from this process, how many symbols the wide-range
+ * second pass took (*n_wide; exact only) and how many the FP64 careful kernel took
+ * (*n_careful; every symbol when M < 32).  Both are 0 if no call was made on the
+ * stream since the last release_cache.  Returns MD_OK, MD_EINVAL, MD_EHIP. */
+int llr_path_counts(void* stream, int64_t* n_wide, int64_t* n_careful);
 
 /* ------------------------------------------------------------------ metric */
 /* gmi_reduce -- Monte-Carlo GMI (the glossary's generalised mutual information,
@@ -138,6 +148,20 @@ int llr_maxlog(const float* d_X, const uint32_t* d_labels, int M, int D, const f
 int gmi_reduce(const float* d_llr, int64_t N, int m, const uint32_t* d_tx,
                const uint32_t* d_labels, double* d_gmi, double* d_gmi_per_bit, double* d_se,
                void* stream);
+
+/* ber_count -- hard decisions and bit errors (the paper's receiver decides hard and
+ * reports the Q-factor of the measured bit-error rate, see its Results section): the
+ * decided bit of LLR column k is 1 where L_nk < 0 and 0 otherwise (for max-log LLRs
+ * this is the label of the nearest point, the ML symbol decision; for exact LLRs the
+ * bit-wise MAP decision), counted against the sent label's bit m-1-k.  Integer sums,
+ * deterministic.
+ *   d_llr          N x m float32
+ *   d_tx           N uint32 transmitted point indices; d_labels M = 2^m uint32
+ *   d_bit_errors   out: m uint64, errors of column k, or NULL
+ *   d_errors       out: 1 uint64, all bit errors (BER = errors / (N m))
+ * Returns MD_OK, MD_EINVAL (N <= 0, m outside [1, 16], NULL pointer), MD_EHIP. */
+int ber_count(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels,
+              uint64_t* d_bit_errors, uint64_t* d_errors, void* stream);
 
 /* ------------------------------------------------------------------ learned demapper */
 /* A small network f: R^D -> R^m approximating the exact LLRs, trained on the GPU by the

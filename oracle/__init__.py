@@ -19,6 +19,8 @@ is in ``tests/test_oracle_pins.py``):
   mlp_forward / mlp_loss_grad  pinned (finite differences, closed-form layers)
   adam_step                    pinned (closed-form first step)
   hard_decision                pinned (brute force on tiny inputs)
+  bit_errors, q_factor_db      pinned (BPSK/QPSK closed-form error rates, the
+                               Gaussian tail identity)
 """
 from __future__ import annotations
 
@@ -155,6 +157,33 @@ def hard_decision(X, y) -> np.ndarray:
     out = np.zeros(N, dtype=np.uint32)
     lib.orc_hard_decision(_ptr(X), M, D, _ptr(y), N, _ptr(out))
     return out
+
+
+def bit_errors(decided_labels, tx, labels, m: int) -> np.ndarray:
+    """Bit errors per label bit column (column k = bit m-1-k) of decided labels against
+    the labels of the transmitted points: the hard-decision receiver of the paper's
+    Results section, which reports the Q-factor of the bit-error rate."""
+    sent = np.asarray(labels, dtype=np.int64)[np.asarray(tx, dtype=np.int64)]
+    diff = sent ^ np.asarray(decided_labels, dtype=np.int64)
+    return np.array([int(((diff >> (m - 1 - k)) & 1).sum()) for k in range(m)], dtype=np.int64)
+
+
+def llr_decisions(llr) -> np.ndarray:
+    """Decided labels from LLR signs: bit m-1-k is 1 where column k is negative."""
+    L = np.asarray(llr)
+    m = L.shape[1]
+    out = np.zeros(L.shape[0], dtype=np.int64)
+    for k in range(m):
+        out |= (L[:, k] < 0).astype(np.int64) << (m - 1 - k)
+    return out
+
+
+def q_factor_db(ber: float) -> float:
+    """Q-factor of a bit-error rate, 20 log10(sqrt(2) erfc^-1(2 BER)): the Gaussian tail
+    relation BER = erfc(Q / sqrt 2) / 2 (the paper quotes Q from measured BER without
+    printing the relation; this is the standard one)."""
+    from scipy.special import erfcinv
+    return float(20.0 * np.log10(np.sqrt(2.0) * erfcinv(2.0 * ber)))
 
 
 def gmi_terms(llr, tx, labels):

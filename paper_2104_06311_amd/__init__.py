@@ -12,7 +12,7 @@ import torch
 
 from ._lib import MdemapError, PREC, check, lib
 
-__all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "gmi_reduce", "llr_learned", "MLP", "SweepPlan", "release_cache",
+__all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "release_cache",
            "MdemapError",
            "log2_exact"]
 
@@ -97,6 +97,45 @@ def llr_maxlog(X, labels, y, sigma2: float, out=None):
     st = lib().llr_maxlog(_ptr(X), _ptr(labels), M, D, _ptr(y), N, float(sigma2), _ptr(out), _stream())
     check("llr_maxlog", st)
     return out
+
+
+def ber_count(llr, tx, labels, per_bit: bool = True):
+    """(bit errors int64[1], per-column bit errors int64[m] or None), device tensors; the
+    hard decision of column k is 1 where the LLR is negative."""
+    _dev(llr, "llr", torch.float32, 2)
+    _dev(tx, "tx", torch.int32, 1)
+    N, m = llr.shape
+    errors = torch.zeros(1, dtype=torch.int64, device=llr.device)
+    bit_errors = torch.zeros(m, dtype=torch.int64, device=llr.device) if per_bit else None
+    check("ber_count", lib().ber_count(_ptr(llr), N, m, _ptr(tx), _ptr(labels), _ptr(bit_errors), _ptr(errors),
+                                        _stream()))
+    return errors, bit_errors
+
+
+def q_factor_db(ber: float) -> float:
+    """Q-factor in dB of a bit-error rate, 20 log10(sqrt(2) erfcinv(2 BER)) (host scalar;
+    Newton steps on math.erfc)."""
+    import math
+    if not 0.0 < ber < 0.5:
+        raise ValueError("BER must lie in (0, 0.5)")
+    target = 2.0 * ber
+    x = 1.0
+    for _ in range(100):
+        f = math.erfc(x) - target
+        step = f / (-2.0 / math.sqrt(math.pi) * math.exp(-x * x))
+        x -= step
+        if abs(step) < 1e-15 * max(1.0, abs(x)):
+            break
+    return 20.0 * math.log10(math.sqrt(2.0) * x)
+
+
+def llr_path_counts():
+    """(symbols of the wide-range pass, symbols of the FP64 careful kernel) of the last
+    llr_exact / llr_maxlog call on torch's current stream; waits for that stream."""
+    import ctypes
+    a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+    check("llr_path_counts", lib().llr_path_counts(_stream(), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def gmi_reduce(llr, tx, labels, per_bit: bool = True, se: bool = True):

@@ -31,6 +31,8 @@ SIGNATURES = {
     "llr_exact": (_I, [_P, _P, _I, _I, _P, _I64, _D, _I, _P, _P]),
     "llr_maxlog": (_I, [_P, _P, _I, _I, _P, _I64, _D, _P, _P]),
     "gmi_reduce": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P, _P]),
+    "ber_count": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P]),
+    "llr_path_counts": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "mlp_create": (_I, [_I, _I, _I, _U64, ctypes.POINTER(ctypes.c_void_p)]),
     "mlp_destroy": (_I, [_P]),
     "mlp_num_params": (_I64, [_P]),

@@ -40,8 +40,17 @@ int demap(const float* d_X, const uint32_t* d_labels, int M, int D, const float*
   md::Prepared P;
   float alpha = 1.0f, c_over_alpha = 1.0f;
   md::score_scales(sigma2, &alpha, &c_over_alpha);
-  st = md::prepare(d_X, d_labels, M, D, N, alpha, c_over_alpha, ws, s, &P);
+  int* flags = nullptr;
+  st = md::stream_flags(s, &flags);
   if (st != MD_OK) return st;
+  st = md::prepare(d_X, d_labels, M, D, N, alpha, c_over_alpha, ws, s, &P, flags);
+  if (st != MD_OK) return st;
+  md::LastCall lc;
+  lc.valid = true;
+  lc.maxlog = maxlog;
+  lc.all_careful = M < 32;
+  lc.N = N;
+  md::record_last_call(s, lc);
   return md::launch_llr(P, M, D, d_y, N, sigma2, maxlog, prec == MD_PREC_BF16, d_llr, s);
 }
 
@@ -74,6 +83,36 @@ int llr_maxlog(const float* d_X, const uint32_t* d_labels, int M, int D, const f
   return demap(d_X, d_labels, M, D, d_y, N, sigma2, MD_PREC_FP32, true, d_llr, stream);
 }
 
+int llr_path_counts(void* stream, int64_t* n_wide, int64_t* n_careful) {
+  md::set_error("");
+  if (!n_wide || !n_careful) return md::fail(MD_EINVAL, "output pointer is NULL");
+  *n_wide = 0;
+  *n_careful = 0;
+  int dev = 0;
+  int st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  hipStream_t s = as_stream(stream);
+  md::LastCall lc;
+  int* flags = nullptr;
+  st = md::last_call(s, &lc, &flags);
+  if (st != MD_OK) return st;
+  if (!lc.valid || !flags) return MD_OK;
+  if (lc.all_careful) {
+    *n_careful = lc.N;
+    return MD_OK;
+  }
+  int h[4] = {0, 0, 0, 0};
+  MD_HIP_TRY(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s));
+  MD_HIP_TRY(hipStreamSynchronize(s));
+  if (lc.maxlog) {
+    *n_careful = h[1];
+  } else {
+    *n_wide = h[1];
+    *n_careful = h[3];
+  }
+  return MD_OK;
+}
+
 int gmi_reduce(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels, double* d_gmi,
                double* d_gmi_per_bit, double* d_se, void* stream) {
   md::set_error("");
@@ -89,6 +128,23 @@ int gmi_reduce(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const
   st = md::workspace(s, md::gmi_workspace_bytes(N, m), &ws);
   if (st != MD_OK) return st;
   return md::launch_gmi(d_llr, N, m, d_tx, d_labels, d_gmi, d_gmi_per_bit, d_se, ws, s);
+}
+
+int ber_count(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels,
+              uint64_t* d_bit_errors, uint64_t* d_errors, void* stream) {
+  md::set_error("");
+  if (N <= 0) return md::fail(MD_EINVAL, "bit-error counting needs N > 0 symbols");
+  if (m < 1 || m > 16) return md::fail(MD_EINVAL, "m=" + std::to_string(m) + " is outside [1, 16]");
+  if (!d_llr || !d_tx || !d_labels || !d_errors)
+    return md::fail(MD_EINVAL, "llr, tx, labels or errors pointer is NULL");
+  int dev = 0;
+  int st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  hipStream_t s = as_stream(stream);
+  char* ws = nullptr;
+  st = md::workspace(s, md::ber_workspace_bytes(N, m), &ws);
+  if (st != MD_OK) return st;
+  return md::launch_ber(d_llr, N, m, d_tx, d_labels, d_bit_errors, d_errors, ws, s);
 }
 
 }  // extern "C"

@@ -55,6 +55,18 @@ inline size_t carve_size(size_t bytes) { return ((bytes + 255) & ~size_t(255)); 
 // Returns a device buffer of at least `bytes` bytes private to (current device, stream).
 int workspace(hipStream_t stream, size_t bytes, char** out);
 
+// Stage counters of the demapping calls on (current device, stream): a 16-byte device
+// buffer that stays at one address until release_cache, plus what the last call was.
+struct LastCall {
+  bool valid = false;
+  bool maxlog = false;
+  bool all_careful = false;
+  int64_t N = 0;
+};
+int stream_flags(hipStream_t stream, int** out);
+void record_last_call(hipStream_t stream, const LastCall& lc);
+int last_call(hipStream_t stream, LastCall* lc, int** flags);
+
 // Host-side label check cache: returns MD_OK if the labels at d_labels (M entries)
 // form a permutation; checks on the host the first time (pointer, M) is seen.
 int check_labels_once(const uint32_t* d_labels, int M, hipStream_t stream);
@@ -66,8 +78,10 @@ int current_device(int* dev);
 struct Prepared {
   const float* xl;          // M x D float32, row s = point with label s
   const uint4* frag;        // MFMA A-operand fragments (see prep.hip)
-  int* flags;               // [0] labels invalid, [1] fallback count, [2] range overflow
-  unsigned* fb_list;        // fallback symbol indices (capacity N)
+  int* flags;               // [0] labels invalid, [1] first fallback count, [2] constellation
+                            // outside the FP16 split range, [3] second fallback count
+  unsigned* fb_list;        // symbols the fast pass could not finish (capacity N)
+  unsigned* fb_list2;       // symbols left for the careful kernel after the wide pass (capacity N)
   int ks;                   // number of 16-slot K steps of the fragment
   float alpha;              // power-of-two operand balance a
   float c_over_alpha;       // c / a, c = log2(e) / (2 sigma2)
@@ -76,8 +90,9 @@ struct Prepared {
 // Builds the label-ordered copy, fragments and flags for one call.  `ws` must point
 // at a workspace of at least prep_bytes(M, D, N) bytes.
 size_t prep_bytes(int M, int D, int64_t N);
+// `flags` (4 ints) may be given by the caller; otherwise they are carved from ws.
 int prepare(const float* d_X, const uint32_t* d_labels, int M, int D, int64_t N, float alpha,
-            float c_over_alpha, char* ws, hipStream_t stream, Prepared* out);
+            float c_over_alpha, char* ws, hipStream_t stream, Prepared* out, int* flags = nullptr);
 
 int frag_ksteps(int D);    // ceil((3 D + 4) / 16) steps of 16 K slots
 

@@ -109,6 +109,68 @@ __global__ void __launch_bounds__(kBlock) gmi_final_kernel(const double* __restr
   }
 }
 
+// Hard decisions from LLR signs (bit 1 where L < 0) against the sent labels: bit-error
+// counts per LLR column, integer sums per block, summed in a fixed order by one block.
+__global__ void __launch_bounds__(kBlock) ber_partial_kernel(const float* __restrict__ llr, int64_t N, int m,
+                                                             const uint32_t* __restrict__ tx,
+                                                             const uint32_t* __restrict__ labels,
+                                                             unsigned long long* __restrict__ partials) {
+  __shared__ unsigned long long sh[kBlock];
+  uint32_t cnt[kMaxM];
+#pragma unroll
+  for (int k = 0; k < kMaxM; ++k) cnt[k] = 0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t n = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; n < N; n += stride) {
+    const uint32_t u = tx[n];
+    const uint32_t lab = u < (1u << m) ? labels[u] : 0u;
+#pragma unroll
+    for (int k = 0; k < kMaxM; ++k) {
+      if (k < m) {
+        const uint32_t sent = (lab >> (m - 1 - k)) & 1u;
+        const uint32_t dec = llr[n * m + k] < 0.0f ? 1u : 0u;
+        cnt[k] += sent ^ dec;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxM; ++k) {
+    if (k < m) {
+      sh[threadIdx.x] = cnt[k];
+      __syncthreads();
+      for (int w = kBlock / 2; w >= 1; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * m + k] = sh[0];
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) ber_final_kernel(const unsigned long long* __restrict__ partials,
+                                                           int nblocks, int m,
+                                                           unsigned long long* __restrict__ bit_errors,
+                                                           unsigned long long* __restrict__ errors) {
+  __shared__ unsigned long long sh[kBlock];
+  unsigned long long total = 0;
+  for (int k = 0; k < m; ++k) {
+    unsigned long long a = 0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) a += partials[static_cast<int64_t>(b) * m + k];
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = kBlock / 2; w >= 1; w >>= 1) {
+      if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      if (bit_errors) bit_errors[k] = sh[0];
+      total += sh[0];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) errors[0] = total;
+}
+
 int gmi_blocks(int64_t N) {
   int64_t b = (N + kBlock - 1) / kBlock;
   if (b > kMaxBlocks) b = kMaxBlocks;
@@ -131,6 +193,23 @@ int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const
   hipLaunchKernelGGL(gmi_final_kernel, dim3(1), dim3(kBlock), 0, stream, partials, nb, N, m, d_gmi, d_gmi_per_bit,
                      d_se);
   MD_LAUNCH_CHECK("gmi_final_kernel launch");
+  return MD_OK;
+}
+
+size_t ber_workspace_bytes(int64_t N, int m) {
+  return carve_size(sizeof(unsigned long long) * static_cast<size_t>(gmi_blocks(N)) * m);
+}
+
+int launch_ber(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels,
+               uint64_t* d_bit_errors, uint64_t* d_errors, char* ws, hipStream_t stream) {
+  const int nb = gmi_blocks(N);
+  auto* partials = reinterpret_cast<unsigned long long*>(ws);
+  hipLaunchKernelGGL(ber_partial_kernel, dim3(nb), dim3(kBlock), 0, stream, d_llr, N, m, d_tx, d_labels, partials);
+  MD_LAUNCH_CHECK("ber_partial_kernel launch");
+  hipLaunchKernelGGL(ber_final_kernel, dim3(1), dim3(kBlock), 0, stream, partials, nb, m,
+                     reinterpret_cast<unsigned long long*>(d_bit_errors),
+                     reinterpret_cast<unsigned long long*>(d_errors));
+  MD_LAUNCH_CHECK("ber_final_kernel launch");
   return MD_OK;
 }
 

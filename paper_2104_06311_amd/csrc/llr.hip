@@ -15,11 +15,14 @@
 // The label-0/label-1 subset sums of bit b follow from those partial sums, and
 // L = ln2 (log2 S0 - log2 S1).
 //
-// A symbol whose smaller subset sum falls below 2^-96 (its far subset lost FP32
-// range), or whose score operands leave the FP16 split range, is appended to a
-// fallback list and recomputed by the careful kernel: one wavefront per symbol,
-// difference-form FP64 distances, per-subset maxima by wavefront reductions, then
-// per-subset log-sum-exp -- the textbook evaluation, robust for any finite input.
+// Exact path in three stages.  (1) The fast kernel appends to a first list every
+// symbol with a subset sum outside [2^-96, 2^126] (its far subset lost FP32 range:
+// the subset's best point lies more than 196 base-2 units below the bias) or with score
+// operands outside the FP16 split range.  (2) The wide-range pass evaluates those
+// symbols in two exponent windows 190 units apart and takes each subset sum from the
+// window that kept it in range.  (3) What is left goes to the careful kernel: one
+// wavefront per symbol, difference-form FP64 distances, per-subset maxima and
+// log-sum-exp, robust for any finite input.  Max-log has only stages 1 and 3.
 #include <cmath>
 #include <cstdlib>
 
@@ -46,21 +49,41 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // ------------------------------------------------------------------ careful kernel
 // One wavefront per symbol, all arithmetic in FP64 (the inputs are FP32, so squared
-// distances are exact to double rounding): per-subset maxima by wavefront
-// reductions, then per-subset log-sum-exp.  Used for every symbol when M < 32 and for
-// the rare symbols the fast kernel hands over.
+// distances are exact to double rounding).  Pass 1: per-subset maxima (wavefront
+// reductions) and the global maximum g.  Pass 2: one exponential per point,
+// e = exp(q - g), added to the m subsets the point belongs to.  A subset whose maximum
+// lies within kNearNat of g keeps every term that matters (a term lost to FP64
+// underflow is below e^-745 of g, so below e^-145 of the subset's largest term), and
+// its log-sum-exp is g + ln(sum); a subset further below g is summed again against its
+// own maximum in a pass of its own (in practice never).  Used for every symbol when M < 32 and for the symbols the fast
+// passes hand over.
+constexpr double kNearNat = 600.0;
+
+__device__ __forceinline__ double point_q(const double (&yv)[kMaxD], const float* __restrict__ xl, int j, int D,
+                                          double cnat) {
+  double d2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < kMaxD; ++d) {
+    if (d < D) {
+      const double df = yv[d] - static_cast<double>(xl[static_cast<int64_t>(j) * D + d]);
+      d2 = fma(df, df, d2);
+    }
+  }
+  return -cnat * d2;
+}
+
 template <bool MAXLOG>
 __global__ void __launch_bounds__(256) llr_careful_kernel(const float* __restrict__ xl, int M, int m, int D,
                                                           const float* __restrict__ y, int64_t N, double cnat,
                                                           float* __restrict__ llr, const int* __restrict__ flags,
-                                                          const unsigned* __restrict__ list, int use_list) {
+                                                          const unsigned* __restrict__ list, int count_slot) {
   const int lane = threadIdx.x & 63;
   const int64_t wave_id = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
-  const int64_t count = use_list ? static_cast<int64_t>(flags[1]) : N;
+  const int64_t count = list ? static_cast<int64_t>(flags[count_slot]) : N;
   const bool invalid = flags[0] != 0;
   for (int64_t item = wave_id; item < count; item += nwaves) {
-    const int64_t n = use_list ? static_cast<int64_t>(list[item]) : item;
+    const int64_t n = list ? static_cast<int64_t>(list[item]) : item;
     if (invalid) {
       if (lane < m) llr[n * m + lane] = __builtin_nanf("");
       continue;
@@ -75,15 +98,7 @@ __global__ void __launch_bounds__(256) llr_careful_kernel(const float* __restric
       mx1[k] = -INFINITY;
     }
     for (int j = lane; j < M; j += 64) {
-      double d2 = 0.0;
-#pragma unroll
-      for (int d = 0; d < kMaxD; ++d) {
-        if (d < D) {
-          const double df = yv[d] - static_cast<double>(xl[static_cast<int64_t>(j) * D + d]);
-          d2 = fma(df, df, d2);
-        }
-      }
-      const double q = -cnat * d2;
+      const double q = point_q(yv, xl, j, D, cnat);
 #pragma unroll
       for (int k = 0; k < kMaxM; ++k) {
         if (k < m) {
@@ -93,11 +108,13 @@ __global__ void __launch_bounds__(256) llr_careful_kernel(const float* __restric
         }
       }
     }
+    double gmax = -INFINITY;
 #pragma unroll
     for (int k = 0; k < kMaxM; ++k) {
       if (k < m) {
         mx0[k] = wave_max(mx0[k]);
         mx1[k] = wave_max(mx1[k]);
+        gmax = fmax(gmax, fmax(mx0[k], mx1[k]));
       }
     }
     if (MAXLOG) {
@@ -113,49 +130,60 @@ __global__ void __launch_bounds__(256) llr_careful_kernel(const float* __restric
       s1[k] = 0.0;
     }
     for (int j = lane; j < M; j += 64) {
-      double d2 = 0.0;
-#pragma unroll
-      for (int d = 0; d < kMaxD; ++d) {
-        if (d < D) {
-          const double df = yv[d] - static_cast<double>(xl[static_cast<int64_t>(j) * D + d]);
-          d2 = fma(df, df, d2);
-        }
-      }
-      const double q = -cnat * d2;
+      const double e = exp(point_q(yv, xl, j, D, cnat) - gmax);
 #pragma unroll
       for (int k = 0; k < kMaxM; ++k) {
         if (k < m) {
           const bool b = (j >> (m - 1 - k)) & 1;
-          const double e = exp(q - (b ? mx1[k] : mx0[k]));
-          if (b) s1[k] += e;
-          else s0[k] += e;
+          s1[k] += b ? e : 0.0;
+          s0[k] += b ? 0.0 : e;
         }
       }
     }
+    double lse0[kMaxM], lse1[kMaxM];
 #pragma unroll
     for (int k = 0; k < kMaxM; ++k) {
       if (k < m) {
-        const double a0 = wave_sum(s0[k]);
-        const double a1 = wave_sum(s1[k]);
-        if (lane == k) llr[n * m + k] = static_cast<float>((mx0[k] + log(a0)) - (mx1[k] + log(a1)));
+        lse0[k] = gmax + log(wave_sum(s0[k]));
+        lse1[k] = gmax + log(wave_sum(s1[k]));
       }
     }
+    // subsets far below the global maximum: sum again against their own maximum
+#pragma unroll
+    for (int k = 0; k < kMaxM; ++k) {
+      if (k >= m) continue;
+#pragma unroll
+      for (int bv = 0; bv < 2; ++bv) {
+        const double mk = bv ? mx1[k] : mx0[k];
+        if (!(gmax - mk > kNearNat)) continue;     // wave-uniform
+        double a = 0.0;
+        for (int j = lane; j < M; j += 64)
+          if (((j >> (m - 1 - k)) & 1) == bv) a += exp(point_q(yv, xl, j, D, cnat) - mk);
+        const double l = mk + log(wave_sum(a));
+        if (bv) lse1[k] = l;
+        else lse0[k] = l;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxM; ++k)
+      if (k < m && lane == k) llr[n * m + k] = static_cast<float>(lse0[k] - lse1[k]);
   }
 }
 
+// list == nullptr: every symbol; otherwise the list with its length in flags[count_slot].
 template <bool MAXLOG>
 int launch_careful_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
-                     bool use_list, hipStream_t stream) {
+                     const unsigned* list, int count_slot, hipStream_t stream) {
   const int m = ilog2_pow2(M);
   int dev = 0, ncu = 0;
   MD_HIP_TRY(hipGetDevice(&dev));
   MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  int64_t grid = use_list ? static_cast<int64_t>(ncu) * 8 : (N + 3) / 4;
+  int64_t grid = list ? static_cast<int64_t>(ncu) * 8 : (N + 3) / 4;
   if (grid > static_cast<int64_t>(ncu) * 64) grid = static_cast<int64_t>(ncu) * 64;
   if (grid < 1) grid = 1;
   const double cnat = 1.0 / (2.0 * sigma2);
   hipLaunchKernelGGL(llr_careful_kernel<MAXLOG>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, P.xl, M,
-                     m, D, d_y, N, cnat, d_llr, P.flags, P.fb_list, use_list ? 1 : 0);
+                     m, D, d_y, N, cnat, d_llr, P.flags, list, count_slot);
   MD_LAUNCH_CHECK("llr_careful_kernel launch");
   return MD_OK;
 }
@@ -173,21 +201,27 @@ void score_scales(double sigma2, float* alpha, float* c_over_alpha) {
 int launch_llr(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, bool maxlog,
                bool bf16, float* d_llr, hipStream_t stream) {
   if (M < 32) {
-    return maxlog ? launch_careful_t<true>(P, M, D, d_y, N, sigma2, d_llr, false, stream)
-                  : launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, false, stream);
+    return maxlog ? launch_careful_t<true>(P, M, D, d_y, N, sigma2, d_llr, nullptr, 0, stream)
+                  : launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, nullptr, 0, stream);
   }
-  const int st = maxlog ? launch_fast_maxlog(P, M, D, d_y, N, sigma2, d_llr, stream)
-                 : bf16   ? launch_fast_bf16(P, M, D, d_y, N, d_llr, stream)
-                          : launch_fast_exact(P, M, D, d_y, N, sigma2, d_llr, stream);
+  if (maxlog) {
+    // max-log never loses range; its list holds only operands outside the FP16 split range
+    int st = launch_fast_maxlog(P, M, D, d_y, N, sigma2, d_llr, stream);
+    if (st != MD_OK) return st;
+    return launch_careful_t<true>(P, M, D, d_y, N, sigma2, d_llr, P.fb_list, 1, stream);
+  }
+  int st = bf16 ? launch_fast_bf16(P, M, D, d_y, N, d_llr, stream)
+                : launch_fast_exact(P, M, D, d_y, N, sigma2, d_llr, stream);
   if (st != MD_OK) return st;
-  return maxlog ? launch_careful_t<true>(P, M, D, d_y, N, sigma2, d_llr, true, stream)
-                : launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, true, stream);
+  st = launch_wide_exact(P, M, D, d_y, d_llr, stream);
+  if (st != MD_OK) return st;
+  return launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, P.fb_list2, 3, stream);
 }
 
 int launch_llr_careful_all(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, bool maxlog,
                            float* d_llr, hipStream_t stream) {
-  return maxlog ? launch_careful_t<true>(P, M, D, d_y, N, sigma2, d_llr, false, stream)
-                : launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, false, stream);
+  return maxlog ? launch_careful_t<true>(P, M, D, d_y, N, sigma2, d_llr, nullptr, 0, stream)
+                : launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, nullptr, 0, stream);
 }
 
 }  // namespace md

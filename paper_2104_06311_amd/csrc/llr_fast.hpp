@@ -126,10 +126,10 @@ __device__ __forceinline__ void tile_loop(const uint4* __restrict__ lds, int t0,
   constexpr int LOG2G = Geo<MB>::LOG2G;
   constexpr int G = Geo<MB>::G;
   constexpr int nh = Geo<MB>::NH;
-  // prologue: score block of the chunk's first tile
+  // prologue: score block of the chunk's first tile, and the fragments of the second
   floatx16 cur[SB];
+  half8 ah[KS];
   {
-    half8 ah[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[ks * 64 + lane]);
 #pragma unroll
@@ -140,16 +140,17 @@ __device__ __forceinline__ void tile_loop(const uint4* __restrict__ lds, int t0,
       for (int ks = 0; ks < KS; ++ks)
         cur[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], cur[sb], 0, 0, 0);
     }
+    const int t1 = min(1, tn - 1);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[(t1 * KS + ks) * 64 + lane]);
   }
   for (int tg = 0; tg < tn; tg += G) {
 #pragma unroll
     for (int i = 0; i < G; ++i) {
-      // issue the next tile's score blocks (the chunk's last tile recomputes itself)
-      const int tnext = min(tg + i + 1, tn - 1);
+      // issue the next tile's score blocks (the chunk's last tile recomputes itself) and
+      // the LDS reads of the tile after it, which then have a whole tile of VALU work
+      // to arrive
       floatx16 nxt[SB];
-      half8 ah[KS];
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[(tnext * KS + ks) * 64 + lane]);
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) {
 #pragma unroll
@@ -158,6 +159,9 @@ __device__ __forceinline__ void tile_loop(const uint4* __restrict__ lds, int t0,
         for (int ks = 0; ks < KS; ++ks)
           nxt[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], nxt[sb], 0, 0, 0);
       }
+      const int tpre = min(tg + i + 2, tn - 1);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[(tpre * KS + ks) * 64 + lane]);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int sb = 0; sb < SB; ++sb) {
@@ -205,9 +209,9 @@ __device__ __forceinline__ void tile_loop(const uint4* __restrict__ lds, int t0,
           A.H1[q] = bit ? fmaxf(A.H1[q], A.GT) : A.H1[q];
           A.H0[q] = bit ? A.H0[q] : fmaxf(A.H0[q], A.GT);
         } else {
-          const float a = bit ? A.GT : 0.0f;
-          A.H1[q] += a;
-          A.H0[q] += A.GT - a;
+          // selects, not GT - a: in the wide-range pass a near group's GT may be +inf
+          A.H1[q] += bit ? A.GT : 0.0f;
+          A.H0[q] += bit ? 0.0f : A.GT;
         }
       }
     }
@@ -428,14 +432,170 @@ int launch_fast_m(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
   }
 }
 
+// ------------------------------------------------------------------ wide-range pass
+// Second pass of the exact path over the symbols the first pass listed.  Every symbol is
+// evaluated in two exponent windows at once, e = 2^(t + kExpBias) and
+// e' = 2^(t + kExpBias + kWideShift) (the two symbol blocks of tile_loop carry the same
+// symbols with the two biases).  Every partial sum holds points of one label subset
+// only, so each subset sum is taken from the window in which it kept its range: a
+// subset that underflowed in the first window (best point more than 196 units below the
+// bias) is exact in the second as long as its best point lies less than 196 + kWideShift
+// units below.  Symbols with neither window in range (or operands outside the FP16
+// split range) go on to the careful kernel through the second list.
+constexpr float kWideShift = 190.0f;
+
+template <int KS, int WAVES, int MB>
+__global__ void __launch_bounds__(WAVES * 64) llr_wide_kernel(const uint4* __restrict__ frag, int ntiles,
+                                                              int chunk_tiles, int D,
+                                                              const float* __restrict__ y, float cb, float cn,
+                                                              float alpha, float* __restrict__ llr,
+                                                              int* __restrict__ flags,
+                                                              const unsigned* __restrict__ list_in,
+                                                              unsigned* __restrict__ list_out) {
+  constexpr int m = MB;
+  constexpr int S = 16 * KS;
+  extern __shared__ uint4 lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const bool range_bad = flags[2] != 0;
+  const int64_t count = flags[1];
+  const int64_t per_group = static_cast<int64_t>(WAVES) * 32;
+  const int64_t ngroups = (count + per_group - 1) / per_group;
+  const int nchunks = (ntiles + chunk_tiles - 1) / chunk_tiles;
+  const int frag_per_tile = KS * 64;
+  _Float16* bst = reinterpret_cast<_Float16*>(lds + chunk_tiles * frag_per_tile) + wave * 2 * 32 * S;
+  bool staged = false;
+
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const int64_t item = g * per_group + static_cast<int64_t>(wave) * 32 + (lane & 31);
+    const bool live = item < count;
+    const int64_t n = live ? static_cast<int64_t>(list_in[item]) : 0;
+    half8 bf[2][KS];
+    SymAcc<MB> ac[2];
+    bool bad = range_bad;
+#pragma unroll
+    for (int w = 0; w < 2; ++w)
+      bad |= build_symbol_operand<KS>(bst + (w * 32 + (lane & 31)) * S, y, n, live, D, cb, cn, alpha,
+                                      kExpBias + (w ? kWideShift : 0.0f), bf[w]);
+    acc_init<MB, 2, false>(ac);
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const int t0 = ch * chunk_tiles;
+      const int tn = min(chunk_tiles, ntiles - t0);
+      if (nchunks > 1 || !staged) {
+        __syncthreads();
+        const int total = tn * frag_per_tile;
+        const uint4* src = frag + static_cast<int64_t>(t0) * frag_per_tile;
+        for (int i = threadIdx.x; i < total; i += WAVES * 64) lds[i] = src[i];
+        __syncthreads();
+        staged = true;
+      }
+      tile_loop<KS, MB, 2, false>(lds, t0, tn, lane, bf, ac);
+    }
+    float S0[2][MB], S1[2][MB];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) combine_subsets<MB, false>(ac[w], false, S0[w], S1[w]);
+    const bool badp = __shfl_xor(static_cast<int>(bad), 32, 64) != 0;
+    if (h == 0 && live) {
+      float l2[2][MB];
+      bool ok = !(bad || badp);
+#pragma unroll
+      for (int b = 0; b < MB; ++b) {
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+          const float a0 = v ? S1[0][b] : S0[0][b];
+          const float a1 = v ? S1[1][b] : S0[1][b];
+          const bool in0 = a0 >= 0x1p-96f && a0 <= 0x1p+126f;
+          const bool in1 = a1 >= 0x1p-96f && a1 <= 0x1p+126f;
+          ok = ok && (in0 || in1);
+          l2[v][b] = in0 ? log2f(a0) : log2f(a1) - kWideShift;
+        }
+      }
+      if (!ok) {
+        const int idx = atomicAdd(&flags[3], 1);
+        list_out[idx] = static_cast<unsigned>(n);
+      } else {
+#pragma unroll
+        for (int k = 0; k < m; ++k) {
+          const int b = m - 1 - k;
+          llr[n * m + k] = kLn2 * (l2[0][b] - l2[1][b]);
+        }
+      }
+    }
+  }
+}
+
+template <int KS, int WAVES, int MB>
+int launch_wide_t(const Prepared& P, int M, const float* d_y, int D, float* d_llr, hipStream_t stream) {
+  const int ntiles = M / 32;
+  const int frag_tile_bytes = KS * 64 * 16;
+  const int bstage = WAVES * 2 * bstage_bytes<KS>();
+  int chunk_tiles = (160 * 1024 - bstage) / frag_tile_bytes;
+  constexpr int G = Geo<MB>::G;
+  chunk_tiles -= chunk_tiles % G;
+  if (chunk_tiles > ntiles) chunk_tiles = ntiles;
+  if (chunk_tiles < G) return fail(MD_EUNSUPPORTED, "constellation fragments do not fit in LDS");
+  const size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
+  auto kern = llr_wide_kernel<KS, WAVES, MB>;
+  static bool attr_done = false;
+  if (!attr_done) {
+    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    attr_done = true;
+  }
+  int dev = 0, ncu = 0;
+  MD_HIP_TRY(hipGetDevice(&dev));
+  MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  // the list length is only known on the device: one block per CU, each loops until
+  // the list is exhausted
+  const double c = P.c_over_alpha * static_cast<double>(P.alpha);
+  const float cb = static_cast<float>(2.0 * c / P.alpha);
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(ncu)), dim3(WAVES * 64), lds_bytes, stream, P.frag, ntiles,
+                     chunk_tiles, D, d_y, cb, P.c_over_alpha, P.alpha, d_llr, P.flags, P.fb_list, P.fb_list2);
+  MD_LAUNCH_CHECK("llr_wide_kernel launch");
+  return MD_OK;
+}
+
+template <int KS>
+int launch_wide_m(const Prepared& P, int M, const float* d_y, int D, float* d_llr, hipStream_t stream) {
+  switch (ilog2_pow2(M)) {
+    case 5: return launch_wide_t<KS, 8, 5>(P, M, d_y, D, d_llr, stream);
+    case 6: return launch_wide_t<KS, 8, 6>(P, M, d_y, D, d_llr, stream);
+    case 7: return launch_wide_t<KS, 8, 7>(P, M, d_y, D, d_llr, stream);
+    case 8: return launch_wide_t<KS, 8, 8>(P, M, d_y, D, d_llr, stream);
+    case 9: return launch_wide_t<KS, 8, 9>(P, M, d_y, D, d_llr, stream);
+    case 10: return launch_wide_t<KS, 8, 10>(P, M, d_y, D, d_llr, stream);
+    case 11: return launch_wide_t<KS, 8, 11>(P, M, d_y, D, d_llr, stream);
+    case 12: return launch_wide_t<KS, 8, 12>(P, M, d_y, D, d_llr, stream);
+    case 13: return launch_wide_t<KS, 8, 13>(P, M, d_y, D, d_llr, stream);
+    case 14: return launch_wide_t<KS, 8, 14>(P, M, d_y, D, d_llr, stream);
+    case 15: return launch_wide_t<KS, 8, 15>(P, M, d_y, D, d_llr, stream);
+    default: return launch_wide_t<KS, 8, 16>(P, M, d_y, D, d_llr, stream);
+  }
+}
+
+template <int UNUSED = 0>
+int launch_wide(const Prepared& P, int M, int D, const float* d_y, float* d_llr, hipStream_t stream) {
+  switch (P.ks) {
+    case 1: return launch_wide_m<1>(P, M, d_y, D, d_llr, stream);
+    case 2: return launch_wide_m<2>(P, M, d_y, D, d_llr, stream);
+    case 3: return launch_wide_m<3>(P, M, d_y, D, d_llr, stream);
+    case 4: return launch_wide_m<4>(P, M, d_y, D, d_llr, stream);
+    case 5: return launch_wide_m<5>(P, M, d_y, D, d_llr, stream);
+    default: return launch_wide_m<6>(P, M, d_y, D, d_llr, stream);
+  }
+}
+
 // Launch shapes of the fast kernel: (wavefronts per block, 32-symbol blocks per wavefront)
-// for one or two K steps: 0: (8, 2)  2: (16, 1).  More K steps use (8, 1).
+// for one or two K steps: 2 (default): (16, 1), four wavefronts per SIMD at <= 128
+// registers, which hides latency better than 0: (8, 2) (measured 6 % faster at 8D
+// M = 2048).  More K steps use (8, 1).  MDEMAP_FAST_VARIANT selects one for timing.
 inline int fast_variant() {
   static int g_fast_variant = -1;
   if (g_fast_variant < 0) {
     const char* e = std::getenv("MDEMAP_FAST_VARIANT");
-    g_fast_variant = e ? std::atoi(e) : 0;
-    if (g_fast_variant < 0 || g_fast_variant > 2) g_fast_variant = 0;
+    g_fast_variant = e ? std::atoi(e) : 2;
+    if (g_fast_variant != 0 && g_fast_variant != 2) g_fast_variant = 2;
   }
   return g_fast_variant;
 }
@@ -468,6 +628,56 @@ int launch_fast(const Prepared& P, int M, int D, const float* d_y, int64_t N, do
 // instruction on the VALU.  R's columns follow the B-operand layout of the exponentials:
 // K slot k of reduction step q is the point at tile offset 16 (k / 8) + 8 q + k % 8.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// One step t (0 <= t <= tn) of the BF16 kernel's tile pipeline: score MFMAs of tile t + 1
+// into nx, reduction MFMAs of tile t - 1 (operands Ap/Bp), then the reduction operands of
+// tile t from the scores in cu.  Step tn only drains the last reduction.
+template <int KS, int SB>
+__device__ __forceinline__ void bf16_step(const uint4* __restrict__ lds, int t, int t0, int tn, int lane,
+                                          bool r_high, int rb, uint32_t want, const uint32_t (&lowA)[2][4],
+                                          const half8 (&bf)[SB][KS], const floatx16 (&cu)[SB],
+                                          floatx16 (&nx)[SB], half8 (&ah)[KS], bf16x8 (&Ap)[2],
+                                          bf16x8 (&Bp)[SB][2], floatx16 (&R0)[SB], floatx16 (&R1)[SB]) {
+  constexpr uint32_t kOne = 0x3F80u;   // BF16 1.0
+  const bool more = t < tn;
+  if (more) {
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) nx[sb][rr] = 0.0f;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        nx[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], nx[sb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int sb = 0; sb < SB; ++sb) {
+    R0[sb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ap[0], Bp[sb][0], R0[sb], 0, 0, 0);
+    R1[sb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ap[1], Bp[sb][1], R1[sb], 0, 0, 0);
+  }
+  if (!more) return;
+  const int tpre = min(t + 2, tn - 1);
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[(tpre * KS + ks) * 64 + lane]);
+  __builtin_amdgcn_sched_barrier(0);
+  // reduction matrix of this tile: the rows of the tile-index bits select all or none
+  const uint32_t tau = static_cast<uint32_t>(t0 + t);
+  const uint32_t hv = (r_high && (((tau >> (rb - 5)) & 1u) == want)) ? (kOne | (kOne << 16)) : 0u;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    uint32_t wv[4];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wv[w] = lowA[q][w] | hv;
+    __builtin_memcpy(&Ap[q], wv, 16);
+  }
+#pragma unroll
+  for (int sb = 0; sb < SB; ++sb)
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) Bp[sb][q][v] = static_cast<__bf16>(__builtin_amdgcn_exp2f(cu[sb][8 * q + v]));
+  __builtin_amdgcn_sched_barrier(0);
+}
 
 template <int KS, int WAVES, int MB, int SB>
 __global__ void __launch_bounds__(WAVES * 64) llr_bf16_kernel(const uint4* __restrict__ frag, int ntiles,
@@ -514,7 +724,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_bf16_kernel(const uint4* __res
 
   for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
     half8 bf[SB][KS];
-    floatx16 R[SB];
+    floatx16 R0[SB], R1[SB];   // subset sums: two accumulators break the MFMA dependency chain
     bool bad[SB];
     int64_t nsym[SB];
 #pragma unroll
@@ -525,7 +735,10 @@ __global__ void __launch_bounds__(WAVES * 64) llr_bf16_kernel(const uint4* __res
                                               kExpBias, bf[sb]);
       bad[sb] = b || range_bad;
 #pragma unroll
-      for (int rr = 0; rr < 16; ++rr) R[sb][rr] = 0.0f;
+      for (int rr = 0; rr < 16; ++rr) {
+        R0[sb][rr] = 0.0f;
+        R1[sb][rr] = 0.0f;
+      }
     }
 
     for (int ch = 0; ch < nchunks; ++ch) {
@@ -539,61 +752,49 @@ __global__ void __launch_bounds__(WAVES * 64) llr_bf16_kernel(const uint4* __res
         __syncthreads();
         staged = true;
       }
+      // Software pipeline over the tiles: in step t the score MFMAs of tile t + 1 and
+      // the reduction MFMAs of tile t - 1 are issued first; the exponentials of tile t
+      // then run on the VALU while the matrix pipe works through them.
       floatx16 cur[SB];
-      {
-        half8 ah[KS];
+      bf16x8 Bp[SB][2];
+      half8 ah[KS];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[ks * 64 + lane]);
+      for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[ks * 64 + lane]);
 #pragma unroll
-        for (int sb = 0; sb < SB; ++sb) {
+      for (int sb = 0; sb < SB; ++sb) {
 #pragma unroll
-          for (int rr = 0; rr < 16; ++rr) cur[sb][rr] = 0.0f;
+        for (int rr = 0; rr < 16; ++rr) cur[sb][rr] = 0.0f;
 #pragma unroll
-          for (int ks = 0; ks < KS; ++ks)
-            cur[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], cur[sb], 0, 0, 0);
-        }
+        for (int ks = 0; ks < KS; ++ks)
+          cur[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], cur[sb], 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int v = 0; v < 8; ++v) Bp[sb][q][v] = static_cast<__bf16>(0.0f);
       }
-      for (int t = 0; t < tn; ++t) {
-        const int tnext = min(t + 1, tn - 1);
-        floatx16 nxt[SB];
-        half8 ah[KS];
+      {
+        const int t1 = min(1, tn - 1);
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[(tnext * KS + ks) * 64 + lane]);
+        for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[(t1 * KS + ks) * 64 + lane]);
+      }
+      bf16x8 Ap[2];
 #pragma unroll
-        for (int sb = 0; sb < SB; ++sb) {
+      for (int q = 0; q < 2; ++q)
 #pragma unroll
-          for (int rr = 0; rr < 16; ++rr) nxt[sb][rr] = 0.0f;
-#pragma unroll
-          for (int ks = 0; ks < KS; ++ks)
-            nxt[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], nxt[sb], 0, 0, 0);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        // reduction matrix of this tile
-        const uint32_t tau = static_cast<uint32_t>(t0 + t);
-        const uint32_t hv = (r_high && (((tau >> (rb - 5)) & 1u) == want)) ? (kOne | (kOne << 16)) : 0u;
-        bf16x8 A[2];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          uint32_t wv[4];
-#pragma unroll
-          for (int w = 0; w < 4; ++w) wv[w] = r_high ? hv : lowA[q][w];
-          __builtin_memcpy(&A[q], wv, 16);
-        }
-#pragma unroll
-        for (int sb = 0; sb < SB; ++sb) {
-          bf16x8 B[2];
-#pragma unroll
-          for (int q = 0; q < 2; ++q)
-#pragma unroll
-            for (int v = 0; v < 8; ++v) B[q][v] = static_cast<__bf16>(__builtin_amdgcn_exp2f(cur[sb][8 * q + v]));
-          R[sb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[0], B[0], R[sb], 0, 0, 0);
-          R[sb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A[1], B[1], R[sb], 0, 0, 0);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int sb = 0; sb < SB; ++sb) cur[sb] = nxt[sb];
+        for (int v = 0; v < 8; ++v) Ap[q][v] = static_cast<__bf16>(0.0f);
+      floatx16 nxt[SB];
+      // two steps per iteration with the score registers swapping roles, so that no
+      // register copies are needed between steps
+      for (int t = 0;; t += 2) {
+        bf16_step<KS, SB>(lds, t, t0, tn, lane, r_high, rb, want, lowA, bf, cur, nxt, ah, Ap, Bp, R0, R1);
+        if (t == tn) break;
+        bf16_step<KS, SB>(lds, t + 1, t0, tn, lane, r_high, rb, want, lowA, bf, nxt, cur, ah, Ap, Bp, R0, R1);
+        if (t + 1 == tn) break;
       }
     }
+
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) R0[sb] += R1[sb];
 
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) {
@@ -601,7 +802,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_bf16_kernel(const uint4* __res
       // lane half h holds result rows 8 (r / 4) + 4 h + r % 4; gather all 32 rows in half 0
       float P[16];
 #pragma unroll
-      for (int rr = 0; rr < 16; ++rr) P[rr] = __shfl_xor(R[sb][rr], 32, 64);
+      for (int rr = 0; rr < 16; ++rr) P[rr] = __shfl_xor(R0[sb][rr], 32, 64);
       const bool badp = __shfl_xor(static_cast<int>(bad[sb]), 32, 64) != 0;
       if (h == 0 && n < N) {
         if (invalid) {
@@ -610,7 +811,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_bf16_kernel(const uint4* __res
           float rowv[32];
 #pragma unroll
           for (int rr = 0; rr < 16; ++rr) {
-            rowv[8 * (rr / 4) + (rr % 4)] = R[sb][rr];
+            rowv[8 * (rr / 4) + (rr % 4)] = R0[sb][rr];
             rowv[8 * (rr / 4) + 4 + (rr % 4)] = P[rr];
           }
           float smin = INFINITY, smax = 0.0f;
@@ -690,14 +891,10 @@ int launch_bf16_m(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
 
 template <int UNUSED = 0>
 int launch_bf16(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr, hipStream_t stream) {
-  const int v = fast_variant();
+  // (16 wavefronts, 1 block) would need more than the 128 registers it allows
   switch (P.ks) {
-    case 1:
-      if (v == 2) return launch_bf16_m<1, 16, 1>(P, M, D, d_y, N, d_llr, stream);
-      return launch_bf16_m<1, 8, 2>(P, M, D, d_y, N, d_llr, stream);
-    case 2:
-      if (v == 2) return launch_bf16_m<2, 16, 1>(P, M, D, d_y, N, d_llr, stream);
-      return launch_bf16_m<2, 8, 2>(P, M, D, d_y, N, d_llr, stream);
+    case 1: return launch_bf16_m<1, 8, 2>(P, M, D, d_y, N, d_llr, stream);
+    case 2: return launch_bf16_m<2, 8, 2>(P, M, D, d_y, N, d_llr, stream);
     case 3: return launch_bf16_m<3, 8, 1>(P, M, D, d_y, N, d_llr, stream);
     case 4: return launch_bf16_m<4, 8, 1>(P, M, D, d_y, N, d_llr, stream);
     case 5: return launch_bf16_m<5, 8, 1>(P, M, D, d_y, N, d_llr, stream);

@@ -22,11 +22,17 @@ int launch_fast_maxlog(const Prepared& P, int M, int D, const float* d_y, int64_
                        float* d_llr, hipStream_t stream);
 int launch_fast_bf16(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr,
                      hipStream_t stream);
+// Wide-range second pass over the first fallback list (exact LLRs).
+int launch_wide_exact(const Prepared& P, int M, int D, const float* d_y, float* d_llr, hipStream_t stream);
 int launch_llr_careful_all(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2,
                            bool maxlog, float* d_llr, hipStream_t stream);
 
 size_t gmi_workspace_bytes(int64_t N, int m);
 int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels, double* d_gmi,
                double* d_gmi_per_bit, double* d_se, char* ws, hipStream_t stream);
+
+size_t ber_workspace_bytes(int64_t N, int m);
+int launch_ber(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels,
+               uint64_t* d_bit_errors, uint64_t* d_errors, char* ws, hipStream_t stream);
 
 }  // namespace md

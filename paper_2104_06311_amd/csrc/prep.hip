@@ -118,20 +118,22 @@ size_t prep_bytes(int M, int D, int64_t N) {
   b += carve_size(sizeof(uint4) * static_cast<size_t>(Mpad / 32) * KS * 64);      // frag
   b += carve_size(sizeof(uint32_t) * M);                                       // inv
   b += carve_size(sizeof(int) * 4);                                            // flags
-  b += carve_size(sizeof(unsigned) * static_cast<size_t>(N > 0 ? N : 1));     // fallback list
+  b += 2 * carve_size(sizeof(unsigned) * static_cast<size_t>(N > 0 ? N : 1)); // fallback lists
   return b;
 }
 
 int prepare(const float* d_X, const uint32_t* d_labels, int M, int D, int64_t N, float alpha,
-            float c_over_alpha, char* ws, hipStream_t stream, Prepared* out) {
+            float c_over_alpha, char* ws, hipStream_t stream, Prepared* out, int* flags_given) {
   const int Mpad = ((M + 31) / 32) * 32;
   const int KS = frag_ksteps(D);
   Carver cv{ws, 0};
   float* xl = cv.take<float>(static_cast<size_t>(M) * D);
   uint4* frag = cv.take<uint4>(static_cast<size_t>(Mpad / 32) * KS * 64);
   uint32_t* inv = cv.take<uint32_t>(M);
-  int* flags = cv.take<int>(4);
+  int* flags_carved = cv.take<int>(4);
+  int* flags = flags_given ? flags_given : flags_carved;
   unsigned* fb = cv.take<unsigned>(static_cast<size_t>(N > 0 ? N : 1));
+  unsigned* fb2 = cv.take<unsigned>(static_cast<size_t>(N > 0 ? N : 1));
   const int bs = 256;
   hipLaunchKernelGGL(prep_init_kernel, dim3((M + bs - 1) / bs), dim3(bs), 0, stream, inv, M, flags);
   MD_LAUNCH_CHECK("prep_init_kernel launch");
@@ -144,6 +146,7 @@ int prepare(const float* d_X, const uint32_t* d_labels, int M, int D, int64_t N,
   out->frag = frag;
   out->flags = flags;
   out->fb_list = fb;
+  out->fb_list2 = fb2;
   out->ks = KS;
   out->alpha = alpha;
   out->c_over_alpha = c_over_alpha;

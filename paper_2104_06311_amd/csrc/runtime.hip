@@ -46,7 +46,59 @@ std::map<std::pair<int, hipStream_t>, WsEntry> g_ws;
 
 std::mutex g_lab_mu;
 std::set<std::tuple<int, const uint32_t*, int>> g_lab_ok;
+
+struct FlagsEntry {
+  int* ptr = nullptr;
+  LastCall last;
+};
+std::mutex g_fl_mu;
+std::map<std::pair<int, hipStream_t>, FlagsEntry> g_fl;
 }  // namespace
+
+int stream_flags(hipStream_t stream, int** out) {
+  int dev = 0;
+  int st = current_device(&dev);
+  if (st != MD_OK) return st;
+  std::lock_guard<std::mutex> lk(g_fl_mu);
+  FlagsEntry& f = g_fl[{dev, stream}];
+  if (!f.ptr) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, 256);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MD_ENOMEM, "allocation of the stage counters failed");
+    }
+    f.ptr = static_cast<int*>(p);
+  }
+  *out = f.ptr;
+  return MD_OK;
+}
+
+void record_last_call(hipStream_t stream, const LastCall& lc) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_fl_mu);
+  g_fl[{dev, stream}].last = lc;
+}
+
+int last_call(hipStream_t stream, LastCall* lc, int** flags) {
+  int dev = 0;
+  int st = current_device(&dev);
+  if (st != MD_OK) return st;
+  std::lock_guard<std::mutex> lk(g_fl_mu);
+  auto it = g_fl.find({dev, stream});
+  if (it == g_fl.end() || !it->second.ptr) {
+    *lc = LastCall{};
+    *flags = nullptr;
+    return MD_OK;
+  }
+  *lc = it->second.last;
+  *flags = it->second.ptr;
+  return MD_OK;
+}
 
 int workspace(hipStream_t stream, size_t bytes, char** out) {
   int dev = 0;
@@ -117,8 +169,22 @@ int release_workspaces() {
     }
   }
   g_ws.clear();
-  std::lock_guard<std::mutex> lk2(g_lab_mu);
-  g_lab_ok.clear();
+  {
+    std::lock_guard<std::mutex> lk2(g_lab_mu);
+    g_lab_ok.clear();
+  }
+  std::lock_guard<std::mutex> lk3(g_fl_mu);
+  for (auto& kv : g_fl) {
+    if (kv.second.ptr) {
+      int cur = 0;
+      MD_HIP_TRY(hipGetDevice(&cur));
+      MD_HIP_TRY(hipSetDevice(kv.first.first));
+      hipError_t e = hipFree(kv.second.ptr);
+      MD_HIP_TRY(hipSetDevice(cur));
+      if (e != hipSuccess) return hip_fail(e, "hipFree(stage counters)");
+    }
+  }
+  g_fl.clear();
   return MD_OK;
 }
 

@@ -4,9 +4,10 @@ same seeded inputs.
 Tolerances (derivation in the design notes):
   * awgn_sample: bit-exact (tx indices and float32 bit patterns).
   * LLRs, FP32 precision: |dL| <= 2e-3 + 2e-4 |L|.  The score contraction is a
-    three-pass split-FP16 MFMA product whose dropped lo*lo term and FP32
-    accumulation leave an error of a few 2^-22 of sum_k |a_k b_k| (up to ~1e3 in
-    base-2 exponent units at 14 dB) on each exponent, so ~3e-4 nat per score.
+    split-FP16 MFMA product (hi*hi, hi*lo and lo*hi partial products side by side in
+    K) whose dropped lo*lo term and FP32 accumulation leave an error of a few 2^-22 of
+    sum_k |a_k b_k| (up to ~1e3 in base-2 exponent units at 14 dB) on each exponent,
+    so ~3e-4 nat per score.
   * max-log LLRs: same bound.
   * LLRs, BF16 precision: the exponentials are converted to BF16 (relative error
     <= 2^-8 per term for any rounding of the 8-bit mantissa), so each subset sum is
@@ -198,6 +199,62 @@ def test_extreme_snr_range_fallback():
     L = md().llr_exact(to_dev(X), labels_dev(labels), to_dev(y), s2).cpu().numpy()
     ref = oracle.llr_exact(X, labels, y, s2)
     assert_llr_close(L, ref, atol=ATOL, rtol=RTOL, what="extreme snr")
+
+
+def test_wide_range_pass_at_high_snr():
+    """8D M=2048 at 20 dB: the far subset of about half the symbols lies beyond the first
+    exponent window; those symbols take the two-window pass, a few the careful kernel."""
+    X, labels = synth.gaussian_constellation(2048, 8, synth.SEED_BASE + 1)
+    s2, Xd, tx, y, txh, yh = channel(X, labels, 20.0, 3000, 11)
+    ld = labels_dev(labels)
+    L = md().llr_exact(Xd, ld, y, s2)
+    n_wide, n_careful = md().llr_path_counts()
+    assert n_wide > 300 and n_careful < n_wide, (n_wide, n_careful)
+    ref = oracle.llr_exact(X, labels, yh, s2)
+    assert_llr_close(L.cpu().numpy(), ref, what="wide-range pass")
+    g = md().gmi_reduce(L, tx, ld)[0].item()
+    g_ref = oracle.gmi(ref, txh, labels)[0]
+    assert abs(g - g_ref) <= 1e-4
+    Lm = md().llr_maxlog(Xd, ld, y, s2)
+    assert md().llr_path_counts() == (0, 0)
+    assert_llr_close(Lm.cpu().numpy(), oracle.llr_maxlog(X, labels, yh, s2), what="max-log 20 dB")
+
+
+def test_path_counts_low_snr_and_small_m():
+    X, labels = synth.gaussian_constellation(2048, 8, synth.SEED_BASE + 1)
+    s2, Xd, tx, y, txh, yh = channel(X, labels, 6.0, 5000, 12)
+    md().llr_exact(Xd, labels_dev(labels), y, s2)
+    assert md().llr_path_counts() == (0, 0)
+    X, labels = synth.gaussian_constellation(16, 2, 3)
+    s2, Xd, tx, y, txh, yh = channel(X, labels, 6.0, 777, 12)
+    md().llr_exact(Xd, labels_dev(labels), y, s2)
+    assert md().llr_path_counts() == (0, 777)      # M < 32: the careful kernel for all
+
+
+def test_ber_count_and_q_factor():
+    """Hard decisions from LLR signs: the counts are integers, so they are compared
+    exactly -- with the signs of the GPU's own LLRs, and with the oracle's FP64
+    nearest-point decisions except where the oracle's LLR lies within 1e-3 of 0 (a
+    near tie the FP32 scores may break either way)."""
+    X, labels = synth.product_4d_8psk()
+    s2, Xd, tx, y, txh, yh = channel(X, labels, 8.0, 100_000, 2104)
+    ld = labels_dev(labels)
+    for maxlog in (True, False):
+        L = md().llr_maxlog(Xd, ld, y, s2) if maxlog else md().llr_exact(Xd, ld, y, s2)
+        e, eb = md().ber_count(L, tx, ld)
+        Lh = L.cpu().numpy()
+        own = oracle.bit_errors(oracle.llr_decisions(Lh), txh, labels, 6)
+        assert np.array_equal(eb.cpu().numpy(), own) and int(e.item()) == int(own.sum())
+        ref = oracle.llr_maxlog(X, labels, yh, s2) if maxlog else oracle.llr_exact(X, labels, yh, s2)
+        ref_err = oracle.bit_errors(oracle.llr_decisions(ref), txh, labels, 6)
+        ties = int((np.abs(ref) < 1e-3).sum())
+        assert abs(int(e.item()) - int(ref_err.sum())) <= ties
+        if maxlog:
+            dec = labels.astype(np.int64)[oracle.hard_decision(X, yh).astype(np.int64)]
+            assert abs(int(e.item()) - int(oracle.bit_errors(dec, txh, labels, 6).sum())) <= ties
+        ber = int(e.item()) / (100_000 * 6)
+        assert 0.0 < ber < 0.5
+        assert abs(md().q_factor_db(ber) - oracle.q_factor_db(ber)) < 1e-9
 
 
 def test_empty_input_is_a_no_op_and_gmi_rejects_it():

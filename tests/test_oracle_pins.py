@@ -374,3 +374,34 @@ def test_hard_decision_brute_force():
     X, labels, tx, y, s2 = _rand_problem(M=16, D=2, N=300)
     d2 = ((y[:, None, :].astype(np.float64) - X[None].astype(np.float64)) ** 2).sum(-1)
     assert np.array_equal(oracle.hard_decision(X, y), np.argmin(d2, axis=1).astype(np.uint32))
+
+
+# ----------------------------------------------------------------------------- hard decisions, BER, Q
+def test_bpsk_and_gray_qpsk_ber_closed_form():
+    """Nearest-point decisions: with SNR per real dimension (sigma2 = Es / (D SNR)), BPSK
+    and Gray QPSK both have BER = Q(sqrt(SNR)) = erfc(sqrt(SNR / 2)) / 2 per bit
+    (textbook), checked within 4 Monte-Carlo standard errors on an independent draw."""
+    for X, labels in (synth.bpsk(), synth.gray_qpsk()):
+        m = int(X.shape[0]).bit_length() - 1
+        for snr_db in (0.0, 4.0, 7.0):
+            s2 = synth.sigma2_from_snr_db(X, snr_db)
+            tx, y = mc_channel(X, labels, s2, 200_000, 17)
+            dec = labels.astype(np.int64)[oracle.hard_decision(X, y).astype(np.int64)]
+            errs = oracle.bit_errors(dec, tx, labels, m)
+            ber = errs.sum() / (len(tx) * m)
+            p = 0.5 * math.erfc(math.sqrt(10 ** (snr_db / 10) / 2.0))
+            assert abs(ber - p) <= 4 * math.sqrt(p * (1 - p) / (len(tx) * m)), (snr_db, ber, p)
+
+
+def test_maxlog_signs_are_the_nearest_point_labels():
+    X, labels, tx, y, s2 = _rand_problem(M=64, D=4, N=2000)
+    dec_ml = labels.astype(np.int64)[oracle.hard_decision(X, y).astype(np.int64)]
+    assert np.array_equal(oracle.llr_decisions(oracle.llr_maxlog(X, labels, y, s2)), dec_ml)
+
+
+def test_q_factor_gaussian_tail_identity():
+    # Q = 6 (15.563 dB) is BER = 9.866e-10 in the standard tables; BER = erfc(Q/sqrt2)/2
+    assert abs(oracle.q_factor_db(0.5 * math.erfc(6.0 / math.sqrt(2.0))) - 20 * math.log10(6.0)) < 1e-9
+    assert abs(0.5 * math.erfc(6.0 / math.sqrt(2.0)) - 9.8659e-10) < 1e-13
+    for q in (0.5, 2.0, 3.5):
+        assert abs(oracle.q_factor_db(0.5 * math.erfc(q / math.sqrt(2.0))) - 20 * math.log10(q)) < 1e-9
