@@ -27,9 +27,16 @@ struct Kahan {
   __device__ double get() const { return static_cast<double>(s) + static_cast<double>(c); }
 };
 
+// log2(1 + e^x) = max(x, 0) log2(e) + log2(1 + u), u = 2^(-|x| log2 e) in (0, 1], with
+// the hardware base-2 exponential and logarithm.  log2(1 + u) is evaluated as
+// log2(w) u / (w - 1), w = fl(1 + u), which cancels the rounding of w (the classic
+// accurate log1p construction), so small terms keep their relative accuracy.
 __device__ __forceinline__ float softplus_bits(float x) {
-  // log2(1 + e^x) = (max(x, 0) + log1p(e^-|x|)) / ln 2
-  return (fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x)))) * 1.4426950408889634f;
+  constexpr float kLog2e = 1.4426950408889634f;
+  const float u = __builtin_amdgcn_exp2f(-fabsf(x) * kLog2e);
+  const float w = 1.0f + u;
+  const float l1p = (w == 1.0f) ? u * kLog2e : __builtin_amdgcn_logf(w) * (u * __builtin_amdgcn_rcpf(w - 1.0f));
+  return fmaxf(x, 0.0f) * kLog2e + l1p;
 }
 
 __device__ double block_sum(double v, double* sh) {
@@ -78,9 +85,14 @@ __global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __rest
   if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * nout + 0] = v;
   v = block_sum(sT2.get(), sh);
   if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * nout + 1] = v;
-  for (int k = 0; k < m; ++k) {
-    v = block_sum(sb[k].get(), sh);
-    if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * nout + 2 + k] = v;
+  // unrolled with a guard: a loop bounded by the runtime m would index sb dynamically and
+  // put the accumulators in scratch memory
+#pragma unroll
+  for (int k = 0; k < kMaxM; ++k) {
+    if (k < m) {
+      v = block_sum(sb[k].get(), sh);
+      if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * nout + 2 + k] = v;
+    }
   }
 }
 
@@ -91,17 +103,24 @@ __global__ void __launch_bounds__(kBlock) gmi_final_kernel(const double* __restr
   __shared__ double sh[kBlock];
   const int nout = m + 2;
   double tot[kMaxM + 2];
-  for (int c = 0; c < nout; ++c) {
-    double a = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock) a += partials[static_cast<int64_t>(b) * nout + c];
-    tot[c] = block_sum(a, sh);
+#pragma unroll
+  for (int c = 0; c < kMaxM + 2; ++c) {
+    tot[c] = 0.0;
+    if (c < nout) {
+      double a = 0.0;
+      for (int b = threadIdx.x; b < nblocks; b += kBlock) a += partials[static_cast<int64_t>(b) * nout + c];
+      tot[c] = block_sum(a, sh);
+    }
   }
   if (threadIdx.x == 0) {
     const double Nd = static_cast<double>(N);
     const double mean = tot[0] / Nd;
     gmi[0] = static_cast<double>(m) - mean;
-    if (gmi_per_bit)
-      for (int k = 0; k < m; ++k) gmi_per_bit[k] = 1.0 - tot[2 + k] / Nd;
+    if (gmi_per_bit) {
+#pragma unroll
+      for (int k = 0; k < kMaxM; ++k)
+        if (k < m) gmi_per_bit[k] = 1.0 - tot[2 + k] / Nd;
+    }
     if (se) {
       const double var = N > 1 ? (tot[1] - tot[0] * mean) / (Nd - 1.0) : 0.0;
       se[0] = var > 0.0 ? sqrt(var) / sqrt(Nd) : 0.0;
