@@ -2,8 +2,9 @@
 //   T_n = sum_k log2(1 + exp(-s_nk L_nk))  (FP32 per symbol; s = +1 for a sent 0 bit)
 //   GMI = m - (1/N) sum_n T_n,  GMI_k = 1 - (1/N) sum_n t_nk,  SE = std(T_n) / sqrt(N)
 // Each thread keeps Neumaier-compensated FP32 sums over a grid-stride range of symbols;
-// blocks reduce those in FP64 in a fixed order, and one final block adds the block
-// partials in FP64.  The grid depends only on N, so results are deterministic.
+// blocks reduce those in FP64 in a fixed order, one block per column adds the block
+// partials in FP64, and one thread forms the outputs.  The grid depends only on N, so
+// results are deterministic.
 #include <cmath>
 
 #include "common.hpp"
@@ -14,7 +15,7 @@ namespace {
 
 constexpr int kMaxM = 16;
 constexpr int kBlock = 256;
-constexpr int kMaxBlocks = 1024;
+constexpr int kMaxBlocks = 4096;
 
 struct Kahan {
   float s, c;
@@ -80,47 +81,42 @@ __global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __rest
     sT.add(T);
     sT2.add(T * T);
   }
-  const int nout = m + 2;
+  // column-major partials: column c of block b at partials[c * gridDim.x + b]
+  const int64_t nb = gridDim.x;
   double v = block_sum(sT.get(), sh);
-  if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * nout + 0] = v;
+  if (threadIdx.x == 0) partials[0 * nb + blockIdx.x] = v;
   v = block_sum(sT2.get(), sh);
-  if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * nout + 1] = v;
+  if (threadIdx.x == 0) partials[1 * nb + blockIdx.x] = v;
   // unrolled with a guard: a loop bounded by the runtime m would index sb dynamically and
   // put the accumulators in scratch memory
 #pragma unroll
   for (int k = 0; k < kMaxM; ++k) {
     if (k < m) {
       v = block_sum(sb[k].get(), sh);
-      if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * nout + 2 + k] = v;
+      if (threadIdx.x == 0) partials[(2 + k) * nb + blockIdx.x] = v;
     }
   }
 }
 
-__global__ void __launch_bounds__(kBlock) gmi_final_kernel(const double* __restrict__ partials, int nblocks,
-                                                           int64_t N, int m, double* __restrict__ gmi,
-                                                           double* __restrict__ gmi_per_bit,
-                                                           double* __restrict__ se) {
+// One block per column: the block partials of column c summed in a fixed order.
+__global__ void __launch_bounds__(kBlock) gmi_column_kernel(const double* __restrict__ partials, int nblocks,
+                                                            double* __restrict__ totals) {
   __shared__ double sh[kBlock];
-  const int nout = m + 2;
-  double tot[kMaxM + 2];
-#pragma unroll
-  for (int c = 0; c < kMaxM + 2; ++c) {
-    tot[c] = 0.0;
-    if (c < nout) {
-      double a = 0.0;
-      for (int b = threadIdx.x; b < nblocks; b += kBlock) a += partials[static_cast<int64_t>(b) * nout + c];
-      tot[c] = block_sum(a, sh);
-    }
-  }
-  if (threadIdx.x == 0) {
-    const double Nd = static_cast<double>(N);
+  const int c = blockIdx.x;
+  double a = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) a += partials[static_cast<int64_t>(c) * nblocks + b];
+  const double t = block_sum(a, sh);
+  if (threadIdx.x == 0) totals[c] = t;
+}
+
+__global__ void gmi_output_kernel(const double* __restrict__ tot, int64_t N, int m, double* __restrict__ gmi,
+                                  double* __restrict__ gmi_per_bit, double* __restrict__ se) {
+  const int k = threadIdx.x;
+  const double Nd = static_cast<double>(N);
+  if (gmi_per_bit && k < m) gmi_per_bit[k] = 1.0 - tot[2 + k] / Nd;
+  if (k == 0) {
     const double mean = tot[0] / Nd;
     gmi[0] = static_cast<double>(m) - mean;
-    if (gmi_per_bit) {
-#pragma unroll
-      for (int k = 0; k < kMaxM; ++k)
-        if (k < m) gmi_per_bit[k] = 1.0 - tot[2 + k] / Nd;
-    }
     if (se) {
       const double var = N > 1 ? (tot[1] - tot[0] * mean) / (Nd - 1.0) : 0.0;
       se[0] = var > 0.0 ? sqrt(var) / sqrt(Nd) : 0.0;
@@ -200,7 +196,8 @@ int gmi_blocks(int64_t N) {
 }  // namespace
 
 size_t gmi_workspace_bytes(int64_t N, int m) {
-  return carve_size(sizeof(double) * static_cast<size_t>(gmi_blocks(N)) * (m + 2));
+  return carve_size(sizeof(double) * static_cast<size_t>(gmi_blocks(N)) * (m + 2)) +
+         carve_size(sizeof(double) * (m + 2));
 }
 
 int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels, double* d_gmi,
@@ -209,9 +206,11 @@ int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const
   double* partials = reinterpret_cast<double*>(ws);
   hipLaunchKernelGGL(gmi_partial_kernel, dim3(nb), dim3(kBlock), 0, stream, d_llr, N, m, d_tx, d_labels, partials);
   MD_LAUNCH_CHECK("gmi_partial_kernel launch");
-  hipLaunchKernelGGL(gmi_final_kernel, dim3(1), dim3(kBlock), 0, stream, partials, nb, N, m, d_gmi, d_gmi_per_bit,
-                     d_se);
-  MD_LAUNCH_CHECK("gmi_final_kernel launch");
+  double* totals = partials + carve_size(sizeof(double) * static_cast<size_t>(nb) * (m + 2)) / sizeof(double);
+  hipLaunchKernelGGL(gmi_column_kernel, dim3(m + 2), dim3(kBlock), 0, stream, partials, nb, totals);
+  MD_LAUNCH_CHECK("gmi_column_kernel launch");
+  hipLaunchKernelGGL(gmi_output_kernel, dim3(1), dim3(64), 0, stream, totals, N, m, d_gmi, d_gmi_per_bit, d_se);
+  MD_LAUNCH_CHECK("gmi_output_kernel launch");
   return MD_OK;
 }
 

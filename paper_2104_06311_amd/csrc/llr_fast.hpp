@@ -611,8 +611,12 @@ int launch_fast(const Prepared& P, int M, int D, const float* d_y, int64_t N, do
     case 2:
       if (v == 2) return launch_fast_m<2, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
       return launch_fast_m<2, 8, 2, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 3: return launch_fast_m<3, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 4: return launch_fast_m<4, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 3:
+      if (v == 2) return launch_fast_m<3, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+      return launch_fast_m<3, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 4:
+      if (v == 2) return launch_fast_m<4, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+      return launch_fast_m<4, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
     case 5: return launch_fast_m<5, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
     default: return launch_fast_m<6, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
   }

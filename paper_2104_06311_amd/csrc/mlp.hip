@@ -73,18 +73,23 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(const float* __restrict_
   const int h = lane >> 5;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  // split K: slice z of gridDim.z covers [kb, ke) and writes its own partial product
+  const int kper = ((K + 15) / 16 + gridDim.z - 1) / gridDim.z * 16;
+  const int kb = blockIdx.z * kper;
+  const int ke = min(K, kb + kper);
+  C += static_cast<int64_t>(blockIdx.z) * M * ldc;
   floatx16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kb; k0 < ke; k0 += 16) {
     // stage a 64x16 A tile and a 16x64 B tile (B stored transposed: row j, column k)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int idx = tid * 4 + e;        // 0..1023
       const int r = idx >> 4, kk = idx & 15;
       const int gi = i0 + r, gk = k0 + kk, gj = j0 + r;
-      const float av = (gi < M && gk < K) ? A[gi * sar + gk * sac] : 0.0f;
-      const float bv = (gj < N && gk < K) ? B[gk * sbr + gj * sbc] : 0.0f;
+      const float av = (gi < M && gk < ke) ? A[gi * sar + gk * sac] : 0.0f;
+      const float bv = (gj < N && gk < ke) ? B[gk * sbr + gj * sbc] : 0.0f;
       As[r][kk] = static_cast<__bf16>(av);
       Bs[r][kk] = static_cast<__bf16>(bv);
     }
@@ -119,10 +124,37 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(const float* __restrict_
 template <int EPI>
 int gemm(const float* A, int64_t sar, int64_t sac, const float* B, int64_t sbr, int64_t sbc, int M, int N, int K,
          float* C, int64_t ldc, const float* bias, float* C2, const float* Z, hipStream_t s) {
-  dim3 grid((N + 63) / 64, (M + 63) / 64);
+  dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
   hipLaunchKernelGGL(gemm_bf16_kernel<EPI>, grid, dim3(256), 0, s, A, sar, sac, B, sbr, sbc, M, N, K, C, ldc, bias,
                      C2, Z);
   MD_LAUNCH_CHECK("gemm_bf16_kernel launch");
+  return MD_OK;
+}
+
+// Sums the `slices` partial products of a split-K GEMM in a fixed order.
+__global__ void __launch_bounds__(256) splitk_reduce_kernel(const float* __restrict__ part, int slices, int64_t n,
+                                                            float* __restrict__ out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.0f;
+  for (int z = 0; z < slices; ++z) acc += part[z * n + i];
+  out[i] = acc;
+}
+
+constexpr int kSplitK = 16;
+
+// Weight-gradient products (small M x N, K = batch): K split over kSplitK slices so
+// that the grid covers the chip, partials in `part` (kSplitK * M * N floats).
+int gemm_splitk(const float* A, int64_t sar, int64_t sac, const float* B, int64_t sbr, int64_t sbc, int M, int N,
+                int K, float* C, float* part, hipStream_t s) {
+  dim3 grid((N + 63) / 64, (M + 63) / 64, kSplitK);
+  hipLaunchKernelGGL(gemm_bf16_kernel<EPI_STORE>, grid, dim3(256), 0, s, A, sar, sac, B, sbr, sbc, M, N, K, part,
+                     static_cast<int64_t>(N), nullptr, nullptr, nullptr);
+  MD_LAUNCH_CHECK("gemm_bf16_kernel (split K) launch");
+  const int64_t n = static_cast<int64_t>(M) * N;
+  hipLaunchKernelGGL(splitk_reduce_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, part,
+                     kSplitK, n, C);
+  MD_LAUNCH_CHECK("splitk_reduce_kernel launch");
   return MD_OK;
 }
 
@@ -166,18 +198,46 @@ __global__ void loss_final_kernel(const double* __restrict__ partials, int nb, i
   if (threadIdx.x == 0) loss[0] = sh[0] / static_cast<double>(B);
 }
 
-// out[j] = sum_b G[b][j] (column sums; one thread per column, fixed order)
-__global__ void colsum_kernel(const float* __restrict__ G, int64_t B, int n, float* __restrict__ out) {
+// Column sums out[j] = sum_b G[b][j] in two deterministic stages: block (x, slice) sums the
+// rows of one slice for 64 columns (4 row lanes of compensated sums, combined in a fixed
+// order), then one thread per column adds the slice partials in order.
+constexpr int kColSlices = 32;
+
+__global__ void __launch_bounds__(256) colsum_partial_kernel(const float* __restrict__ G, int64_t B, int n,
+                                                             float* __restrict__ partial) {
+  __shared__ float sh[4][64];
+  const int c = threadIdx.x & 63, r = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
+  const int64_t per = (B + kColSlices - 1) / kColSlices;
+  const int64_t b0 = static_cast<int64_t>(blockIdx.y) * per;
+  const int64_t b1 = min(B, b0 + per);
+  float s = 0.0f, comp = 0.0f;
+  if (j < n) {
+    for (int64_t b = b0 + r; b < b1; b += 4) {
+      const float x = G[b * n + j];
+      const float t = s + x;
+      comp += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+      s = t;
+    }
+  }
+  sh[r][c] = s + comp;
+  __syncthreads();
+  if (r == 0 && j < n)
+    partial[static_cast<int64_t>(blockIdx.y) * n + j] = (sh[0][c] + sh[1][c]) + (sh[2][c] + sh[3][c]);
+}
+
+__global__ void __launch_bounds__(256) colsum_final_kernel(const float* __restrict__ partial, int n,
+                                                           float* __restrict__ out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  float s = 0.0f, c = 0.0f;
-  for (int64_t b = 0; b < B; ++b) {
-    const float x = G[b * n + j];
+  float s = 0.0f, comp = 0.0f;
+  for (int q = 0; q < kColSlices; ++q) {
+    const float x = partial[static_cast<int64_t>(q) * n + j];
     const float t = s + x;
-    c += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
+    comp += fabsf(s) >= fabsf(x) ? (s - t) + x : (x - t) + s;
     s = t;
   }
-  out[j] = s + c;
+  out[j] = s + comp;
 }
 
 // Adam (Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; w -= lr m^ / (sqrt(v^) + eps)
@@ -479,13 +539,23 @@ void init_params(int D, int H, int m, uint64_t seed, std::vector<float>* out) {
   fill(m, H);
 }
 
+int colsum(const float* G, int64_t B, int n, float* partial, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(colsum_partial_kernel, dim3((n + 63) / 64, kColSlices), dim3(256), 0, s, G, B, n, partial);
+  MD_LAUNCH_CHECK("colsum_partial_kernel launch");
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((n + 255) / 256), dim3(256), 0, s, partial, n, out);
+  MD_LAUNCH_CHECK("colsum_final_kernel launch");
+  return MD_OK;
+}
+
 // forward (saving activations) + loss + backward into p->g.  Scratch layout for a batch B:
 // Z1, A1, Z2, A2 (B x H each), F, dF (B x m), dZ2, dZ1 (B x H), loss partials.
 int forward_backward(Mlp* p, const float* d_y, const float* d_t, int64_t B, double* d_loss, hipStream_t s) {
   const int D = p->D, H = p->H, m = p->m;
   const size_t BH = static_cast<size_t>(B) * H, Bm = static_cast<size_t>(B) * m;
   const int nb = static_cast<int>((B + 255) / 256);
-  int st = ensure_scratch(p, 6 * BH + 2 * Bm + 2 * static_cast<size_t>(nb) + 64);
+  const size_t colpart = static_cast<size_t>(kColSlices) * (H > m ? H : m);
+  const size_t kpart = static_cast<size_t>(kSplitK) * H * (H > D ? (H > m ? H : m) : D);
+  int st = ensure_scratch(p, 6 * BH + 2 * Bm + 2 * static_cast<size_t>(nb) + 64 + colpart + kpart);
   if (st != MD_OK) return st;
   float* Z1 = p->scratch;
   float* A1 = Z1 + BH;
@@ -496,6 +566,8 @@ int forward_backward(Mlp* p, const float* d_y, const float* d_t, int64_t B, doub
   float* dZ2 = dF + Bm;
   float* dZ1 = dZ2 + BH;
   double* part = reinterpret_cast<double*>(dZ1 + BH);     // 6 BH + 2 Bm floats: 8-byte aligned
+  float* cpart = reinterpret_cast<float*>(part + nb + 32);
+  float* kpartb = cpart + colpart;
   const float* W1 = p->w;
   const float* b1 = W1 + static_cast<int64_t>(H) * D;
   const float* W2 = b1 + H;
@@ -521,21 +593,18 @@ int forward_backward(Mlp* p, const float* d_y, const float* d_t, int64_t B, doub
   }
   // backward
   // gW3 = dF^T A2 (m x H); gb3 = colsum dF
-  if ((st = gemm<EPI_STORE>(dF, 1, m, A2, H, 1, m, H, Bi, gW3, H, nullptr, nullptr, nullptr, s))) return st;
-  hipLaunchKernelGGL(colsum_kernel, dim3((m + 63) / 64), dim3(64), 0, s, dF, B, m, gb3);
-  MD_LAUNCH_CHECK("colsum_kernel launch");
+  if ((st = gemm_splitk(dF, 1, m, A2, H, 1, m, H, Bi, gW3, kpartb, s))) return st;
+  if ((st = colsum(dF, B, m, cpart, gb3, s))) return st;
   // dZ2 = (dF W3) * g'(Z2)   (B x H)
   if ((st = gemm<EPI_GELU_GRAD>(dF, m, 1, W3, H, 1, Bi, H, m, dZ2, H, nullptr, nullptr, Z2, s))) return st;
   // gW2 = dZ2^T A1 (H x H); gb2 = colsum dZ2
-  if ((st = gemm<EPI_STORE>(dZ2, 1, H, A1, H, 1, H, H, Bi, gW2, H, nullptr, nullptr, nullptr, s))) return st;
-  hipLaunchKernelGGL(colsum_kernel, dim3((H + 63) / 64), dim3(64), 0, s, dZ2, B, H, gb2);
-  MD_LAUNCH_CHECK("colsum_kernel launch");
+  if ((st = gemm_splitk(dZ2, 1, H, A1, H, 1, H, H, Bi, gW2, kpartb, s))) return st;
+  if ((st = colsum(dZ2, B, H, cpart, gb2, s))) return st;
   // dZ1 = (dZ2 W2) * g'(Z1)
   if ((st = gemm<EPI_GELU_GRAD>(dZ2, H, 1, W2, H, 1, Bi, H, H, dZ1, H, nullptr, nullptr, Z1, s))) return st;
   // gW1 = dZ1^T Y (H x D); gb1 = colsum dZ1
-  if ((st = gemm<EPI_STORE>(dZ1, 1, H, d_y, D, 1, H, D, Bi, gW1, D, nullptr, nullptr, nullptr, s))) return st;
-  hipLaunchKernelGGL(colsum_kernel, dim3((H + 63) / 64), dim3(64), 0, s, dZ1, B, H, gb1);
-  MD_LAUNCH_CHECK("colsum_kernel launch");
+  if ((st = gemm_splitk(dZ1, 1, H, d_y, D, 1, H, D, Bi, gW1, kpartb, s))) return st;
+  if ((st = colsum(dZ1, B, H, cpart, gb1, s))) return st;
   return MD_OK;
 }
 
