@@ -53,7 +53,8 @@ def parse():
                     help="also run a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline sweep (no BF16 / max-log / learned / batched objects)")
-    ap.add_argument("--learn-steps", type=int, default=3000, help="training steps per learned network")
+    ap.add_argument("--learn-steps", type=int, default=12000, help="training steps per learned network (8D)")
+    ap.add_argument("--learn-steps-16d", type=int, default=6000, help="training steps per learned network (16D)")
     ap.add_argument("--learn-pairs", type=int, default=1 << 24, help="training pairs per SNR point")
     ap.add_argument("--batch-insts", type=int, default=64, help="instances in the batched-sweep object")
     ap.add_argument("--learn-pairs-16d", type=int, default=1 << 22, help="training pairs per SNR point, 16D")
@@ -135,6 +136,7 @@ def extra_learned(md, wl, X, labels, N, tx, y, llr, steps, pairs):
         md.awgn_sample(X, wl.seed + 77, 0, pairs, math.sqrt(s2), tx=tt, y=ty)
         md.llr_exact(X, labels, ty, s2, out=tl)
         net = md.MLP(wl.D, 256, wl.m, seed=int(snr))
+        net.set_scales(1.0 / math.sqrt(s2), 1.0 / math.sqrt(s2))     # inputs and LLRs on the noise scale
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         trace = net.fit(ty, tl, steps=steps, batch=4096, lr_max=2e-3, lr_min=2e-5, seed=int(snr) + 5)
@@ -187,6 +189,7 @@ def extra_16d(md, steps, pairs):
         md.awgn_sample(X, wl.seed + 77, 0, pairs, math.sqrt(s2), tx=tt, y=ty)
         md.llr_exact(X, labels, ty, s2, out=tl)
         net = md.MLP(wl.D, 512, m, seed=int(snr))
+        net.set_scales(1.0 / math.sqrt(s2), 1.0 / math.sqrt(s2))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         net.fit(ty, tl, steps=steps, batch=4096, lr_max=2e-3, lr_min=2e-5, seed=int(snr) + 5)
@@ -376,7 +379,7 @@ def main():
         del tx, y, llr
         torch.cuda.empty_cache()
         out["detail"]["batched"] = extra_batched(md, args.batch_insts)
-        out["detail"]["16d"] = extra_16d(md, args.learn_steps, args.learn_pairs_16d)
+        out["detail"]["16d"] = extra_16d(md, args.learn_steps_16d, args.learn_pairs_16d)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl.X, wl.labels, 9.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -169,7 +169,8 @@ int ber_count(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const 
  * stays the reference that judges it (through gmi_reduce).  The glossary's ML entry is
  * the only mention of learning in the paper; the network and its training are this
  * library's design:
- *   f(y) = W3 g(W2 g(W1 y + b1) + b2) + b3,  hidden width H in both layers,
+ *   f(y) = s_out (W3 g(W2 g(W1 (s_in y) + b1) + b2) + b3),  hidden width H in both
+ *          layers, fixed scales s_in, s_out (default 1; mlp_set_scales),
  *   g(a) = a (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3))) / 2   (GELU, tanh form),
  *   loss = mean_b sum_k p_bk softplus(-f_bk) + (1 - p_bk) softplus(f_bk),
  *          p_bk = sigmoid(L_target_bk)   (distillation of the exact bit posteriors),
@@ -187,6 +188,11 @@ int mlp_destroy(void* mlp);
 /* Number of parameters P, or -1 for a NULL handle. */
 int64_t mlp_num_params(const void* mlp);
 int mlp_info(const void* mlp, int* D, int* hidden, int* m, int64_t* step);
+/* Fixed input and output scales s_in, s_out of f (finite, > 0; not trained; saved in
+ * checkpoints).  For a demapper at noise variance sigma2, s_in = s_out = 1/sqrt(sigma2)
+ * puts the inputs and the LLRs on the scale of the noise.  Returns MD_OK or MD_EINVAL. */
+int mlp_set_scales(void* mlp, float in_scale, float out_scale);
+int mlp_get_scales(const void* mlp, float* in_scale, float* out_scale);
 /* Copies P floats between host memory and the handle (synchronises the device).
  * which: 0 parameters, 1 last gradient, 2 Adam first moment, 3 Adam second moment. */
 int mlp_get(const void* mlp, int which, float* h_out);

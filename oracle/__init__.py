@@ -55,8 +55,8 @@ def _load():
     lib.orc_hard_decision.argtypes = [P, I, I, P, I64, P]
     lib.orc_gmi_terms.argtypes = [P, I64, I, P, P, P, P]
     lib.orc_gmi.argtypes = [P, I64, I, P, P, P, P, P]
-    lib.orc_mlp_forward.argtypes = [I, I, I, I, P, P, P, P, P, P, P, I64, P]
-    lib.orc_mlp_loss_grad.argtypes = [I, I, I, I, P, P, P, P, P, P, P, P, I64, P, P, P, P, P, P]
+    lib.orc_mlp_forward.argtypes = [I, I, I, I, P, P, P, P, P, P, Dbl, Dbl, P, I64, P]
+    lib.orc_mlp_loss_grad.argtypes = [I, I, I, I, P, P, P, P, P, P, Dbl, Dbl, P, P, I64, P, P, P, P, P, P]
     lib.orc_mlp_loss_grad.restype = Dbl
     lib.orc_adam_step.argtypes = [P, P, P, P, I64, I, Dbl, Dbl, Dbl, Dbl]
     lib.orc_num_threads.restype = I
@@ -216,9 +216,12 @@ def gmi(llr, tx, labels):
 
 
 class MLPParams:
-    """FP64 parameters of the D -> H1 -> H2 -> m GELU network (row-major [out][in])."""
+    """FP64 parameters of the D -> H1 -> H2 -> m GELU network (row-major [out][in]) and its
+    fixed input / output scales: f(y) = out_scale * net(in_scale * y)."""
 
-    def __init__(self, W1, b1, W2, b2, W3, b3):
+    def __init__(self, W1, b1, W2, b2, W3, b3, in_scale=1.0, out_scale=1.0):
+        self.in_scale = float(in_scale)
+        self.out_scale = float(out_scale)
         self.W1 = _f64(W1)
         self.b1 = _f64(b1)
         self.W2 = _f64(W2)
@@ -243,7 +246,7 @@ def mlp_forward(p: MLPParams, y) -> np.ndarray:
     D, H1, H2, m = p.dims
     N = y.shape[0]
     out = np.zeros((N, m), dtype=np.float64)
-    lib.orc_mlp_forward(D, H1, H2, m, *[_ptr(a) for a in p.flat()], _ptr(y), N, _ptr(out))
+    lib.orc_mlp_forward(D, H1, H2, m, *[_ptr(a) for a in p.flat()], p.in_scale, p.out_scale, _ptr(y), N, _ptr(out))
     return out
 
 
@@ -255,7 +258,8 @@ def mlp_loss_grad(p: MLPParams, y, target):
     D, H1, H2, m = p.dims
     B = y.shape[0]
     grads = [np.zeros_like(a) for a in p.flat()]
-    loss = lib.orc_mlp_loss_grad(D, H1, H2, m, *[_ptr(a) for a in p.flat()], _ptr(y), _ptr(target), B,
+    loss = lib.orc_mlp_loss_grad(D, H1, H2, m, *[_ptr(a) for a in p.flat()], p.in_scale, p.out_scale, _ptr(y),
+                                 _ptr(target), B,
                                  *[_ptr(g) for g in grads])
     return float(loss), grads
 

@@ -352,8 +352,9 @@ void orc_gmi(const double* llr, int64_t N, int m, const uint32_t* tx, const uint
 }
 
 /* ------------------------------------------------------------------------- */
-/* MLP demapper reference: f(y) = W3 g(W2 g(W1 y + b1) + b2) + b3 with the GELU
- * activation in its tanh form (Hendrycks & Gimpel):
+/* MLP demapper reference: f(y) = s_out (W3 g(W2 g(W1 (s_in y) + b1) + b2) + b3) with fixed
+ * (untrained) input and output scales s_in, s_out and the GELU activation in its tanh
+ * form (Hendrycks & Gimpel):
  *   g(a) = a (1 + tanh(k (a + 0.044715 a^3))) / 2,  k = sqrt(2 / pi).
  * Weights are row-major [out][in].  Loss per sample:
  * sum_k p_k softplus(-f_k) + (1 - p_k) softplus(f_k) with p_k = sigmoid(L_target_k),
@@ -373,7 +374,7 @@ static double orc_sigmoid(double t) {
 
 void orc_mlp_forward(int D, int H1, int H2, int m,
                      const double* W1, const double* b1, const double* W2, const double* b2,
-                     const double* W3, const double* b3,
+                     const double* W3, const double* b3, double s_in, double s_out,
                      const float* y, int64_t N, double* out) {
 #pragma omp parallel
     {
@@ -383,7 +384,7 @@ void orc_mlp_forward(int D, int H1, int H2, int m,
         for (int64_t n = 0; n < N; ++n) {
             for (int i = 0; i < H1; ++i) {
                 double z = b1[i];
-                for (int d = 0; d < D; ++d) z += W1[i * D + d] * (double)y[n * D + d];
+                for (int d = 0; d < D; ++d) z += W1[i * D + d] * (s_in * (double)y[n * D + d]);
                 h1[i] = orc_gelu(z);
             }
             for (int i = 0; i < H2; ++i) {
@@ -394,7 +395,7 @@ void orc_mlp_forward(int D, int H1, int H2, int m,
             for (int k = 0; k < m; ++k) {
                 double z = b3[k];
                 for (int d = 0; d < H2; ++d) z += W3[(int64_t)k * H2 + d] * h2[d];
-                out[n * m + k] = z;
+                out[n * m + k] = s_out * z;
             }
         }
         free(h1);
@@ -406,7 +407,7 @@ void orc_mlp_forward(int D, int H1, int H2, int m,
  * parameter (gradient arrays are overwritten). */
 double orc_mlp_loss_grad(int D, int H1, int H2, int m,
                          const double* W1, const double* b1, const double* W2, const double* b2,
-                         const double* W3, const double* b3,
+                         const double* W3, const double* b3, double s_in, double s_out,
                          const float* y, const float* target, int64_t B,
                          double* gW1, double* gb1, double* gW2, double* gb2, double* gW3, double* gb3) {
     memset(gW1, 0, sizeof(double) * (size_t)H1 * D);
@@ -428,7 +429,7 @@ double orc_mlp_loss_grad(int D, int H1, int H2, int m,
         const float* yn = y + n * D;
         for (int i = 0; i < H1; ++i) {
             double z = b1[i];
-            for (int d = 0; d < D; ++d) z += W1[i * D + d] * (double)yn[d];
+            for (int d = 0; d < D; ++d) z += W1[i * D + d] * (s_in * (double)yn[d]);
             z1[i] = z;
             h1[i] = orc_gelu(z);
         }
@@ -441,10 +442,10 @@ double orc_mlp_loss_grad(int D, int H1, int H2, int m,
         for (int k = 0; k < m; ++k) {
             double z = b3[k];
             for (int d = 0; d < H2; ++d) z += W3[(int64_t)k * H2 + d] * h2[d];
-            f[k] = z;
+            f[k] = s_out * z;                       /* the network output */
             double p = orc_sigmoid((double)target[n * m + k]);
-            loss += p * orc_softplus(-z) + (1.0 - p) * orc_softplus(z);
-            df[k] = (orc_sigmoid(z) - p) / (double)B;
+            loss += p * orc_softplus(-f[k]) + (1.0 - p) * orc_softplus(f[k]);
+            df[k] = s_out * (orc_sigmoid(f[k]) - p) / (double)B;   /* d loss / d z */
         }
         for (int k = 0; k < m; ++k) {
             gb3[k] += df[k];
@@ -462,7 +463,7 @@ double orc_mlp_loss_grad(int D, int H1, int H2, int m,
             for (int k = 0; k < H2; ++k) g += W2[(int64_t)k * H1 + i] * dz2[k];
             dz1[i] = g * orc_gelu_grad(z1[i]);
             gb1[i] += dz1[i];
-            for (int d = 0; d < D; ++d) gW1[i * D + d] += dz1[i] * (double)yn[d];
+            for (int d = 0; d < D; ++d) gW1[i * D + d] += dz1[i] * (s_in * (double)yn[d]);
         }
     }
     free(z1); free(h1); free(z2); free(h2); free(dz2); free(dz1); free(f); free(df);

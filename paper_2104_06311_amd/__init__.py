@@ -191,6 +191,17 @@ class MLP:
         check("mlp_info", lib().mlp_info(self._h, None, None, None, ctypes.byref(st)))
         return st.value
 
+    def set_scales(self, in_scale: float, out_scale: float):
+        """Fixed input / output scales: f(y) = out_scale * net(in_scale * y)."""
+        check("mlp_set_scales", lib().mlp_set_scales(self._h, float(in_scale), float(out_scale)))
+
+    @property
+    def scales(self):
+        import ctypes
+        a, b = ctypes.c_float(), ctypes.c_float()
+        check("mlp_get_scales", lib().mlp_get_scales(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def close(self):
         if self._h is not None:
             check("mlp_destroy", lib().mlp_destroy(self._h))

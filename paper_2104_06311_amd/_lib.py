@@ -38,6 +38,8 @@ SIGNATURES = {
     "mlp_num_params": (_I64, [_P]),
     "mlp_info": (_I, [_P, _P, _P, _P, _P]),
     "mlp_get": (_I, [_P, _I, _P]),
+    "mlp_set_scales": (_I, [_P, _F, _F]),
+    "mlp_get_scales": (_I, [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "mlp_set": (_I, [_P, _I, _P]),
     "mlp_grad": (_I, [_P, _P, _P, _I64, _P, _P]),
     "mlp_adam_step": (_I, [_P, _F, _P]),

@@ -48,125 +48,183 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ------------------------------------------------------------------ careful kernel
-// One wavefront per symbol, all arithmetic in FP64 (the inputs are FP32, so squared
-// distances are exact to double rounding).  Pass 1: per-subset maxima (wavefront
-// reductions) and the global maximum g.  Pass 2: one exponential per point,
-// e = exp(q - g), added to the m subsets the point belongs to.  A subset whose maximum
-// lies within kNearNat of g keeps every term that matters (a term lost to FP64
-// underflow is below e^-745 of g, so below e^-145 of the subset's largest term), and
-// its log-sum-exp is g + ln(sum); a subset further below g is summed again against its
-// own maximum in a pass of its own (in practice never).  Used for every symbol when M < 32 and for the symbols the fast
-// passes hand over.
-constexpr double kNearNat = 600.0;
+// Four wavefronts per block, one symbol each.  The block stages the label-ordered points in
+// LDS chunks of 512 that all four symbols read.  In a chunk, lane l takes the points
+// j = c0 + l + 64 t (t = 0..7), so label bits 0..5 are the lane, bits 6..8 are t and the
+// higher bits are the chunk index: each point is added to one position sum E[t] and to
+// the chunk total, and the chunk totals are routed by the chunk-index bits (the same
+// label-order geometry as the fast kernel, two FP64 adds per point instead of 2m).
+// All arithmetic is FP64 (the inputs are FP32, so squared distances are exact to double
+// rounding).
+//   exact:   pass 1 finds the global maximum g of q = -||y - x||^2 / (2 sigma2); pass 2
+//            accumulates e = exp(q - g).  A subset sum of at least 1e-290 has its
+//            largest term in the normal FP64 range, and the terms lost to underflow
+//            (below e^-745 of g) lie below e^-66 of that term, so its log-sum-exp is
+//            g + ln(sum).  A smaller sum means the subset lies more than ~667 nats below
+//            g: it is summed again against its own maximum (in practice never).
+//   max-log: pass 1 alone, with max in place of the sums.
+// Used for every symbol when M < 32 and for the symbols the fast passes hand over.
+constexpr int kCarefulWaves = 4;
+constexpr int kChunkPts = 512;                 // 512 rows of at most 31 floats: <= 62 KiB of LDS
+constexpr int kChunkBits = 9;
+constexpr int kMaxHigh = kMaxM - kChunkBits;   // label bits routed by chunk index
+constexpr double kTinySum = 1e-290;
 
-__device__ __forceinline__ double point_q(const double (&yv)[kMaxD], const float* __restrict__ xl, int j, int D,
-                                          double cnat) {
+__device__ __forceinline__ double point_q(const double (&yv)[kMaxD], const float* __restrict__ x, int D, double cnat) {
   double d2 = 0.0;
 #pragma unroll
   for (int d = 0; d < kMaxD; ++d) {
     if (d < D) {
-      const double df = yv[d] - static_cast<double>(xl[static_cast<int64_t>(j) * D + d]);
+      const double df = yv[d] - static_cast<double>(x[d]);
       d2 = fma(df, df, d2);
     }
   }
   return -cnat * d2;
 }
 
+// Log-sum-exp of subset (label bit b = bv) of received symbol yn straight from memory,
+// against the subset's own maximum (the rare far-subset path; kept out of line).
+__device__ __noinline__ double subset_lse(const float* __restrict__ yn, const float* __restrict__ xl, int M, int D,
+                                          int b, int bv, double cnat, int lane) {
+  double yv[kMaxD];
+#pragma unroll
+  for (int d = 0; d < kMaxD; ++d) yv[d] = d < D ? static_cast<double>(yn[d]) : 0.0;
+  double mk = -INFINITY;
+  for (int j = lane; j < M; j += 64)
+    if (((j >> b) & 1) == bv) mk = fmax(mk, point_q(yv, xl + static_cast<int64_t>(j) * D, D, cnat));
+  mk = wave_max(mk);
+  double a = 0.0;
+  for (int j = lane; j < M; j += 64)
+    if (((j >> b) & 1) == bv) a += exp(point_q(yv, xl + static_cast<int64_t>(j) * D, D, cnat) - mk);
+  return mk + log(wave_sum(a));
+}
+
 template <bool MAXLOG>
-__global__ void __launch_bounds__(256) llr_careful_kernel(const float* __restrict__ xl, int M, int m, int D,
-                                                          const float* __restrict__ y, int64_t N, double cnat,
-                                                          float* __restrict__ llr, const int* __restrict__ flags,
-                                                          const unsigned* __restrict__ list, int count_slot) {
-  const int lane = threadIdx.x & 63;
-  const int64_t wave_id = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) >> 6;
+__device__ __forceinline__ double comb(double a, double b) {
+  return MAXLOG ? fmax(a, b) : a + b;
+}
+template <bool MAXLOG>
+__device__ __forceinline__ double wave_comb(double v) {
+  return MAXLOG ? wave_max(v) : wave_sum(v);
+}
+
+template <bool MAXLOG>
+__global__ void __launch_bounds__(kCarefulWaves * 64) llr_careful_kernel(const float* __restrict__ xl, int M, int m,
+                                                                         int D, const float* __restrict__ y, int64_t N,
+                                                                         double cnat, float* __restrict__ llr,
+                                                                         const int* __restrict__ flags,
+                                                                         const unsigned* __restrict__ list,
+                                                                         int count_slot) {
+  extern __shared__ float pts[];                 // kChunkPts rows of Dp floats
+  const int Dp = D | 1;                          // odd row stride: no LDS bank conflicts
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t count = list ? static_cast<int64_t>(flags[count_slot]) : N;
   const bool invalid = flags[0] != 0;
-  for (int64_t item = wave_id; item < count; item += nwaves) {
-    const int64_t n = list ? static_cast<int64_t>(list[item]) : item;
+  const double ident = MAXLOG ? -INFINITY : 0.0;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * kCarefulWaves; base < count;
+       base += static_cast<int64_t>(gridDim.x) * kCarefulWaves) {
+    const int64_t item = base + wave;
+    const bool live = item < count;              // every wave still joins the block's barriers
+    const int64_t n = live ? (list ? static_cast<int64_t>(list[item]) : item) : 0;
+    double yv[kMaxD];
+#pragma unroll
+    for (int d = 0; d < kMaxD; ++d) yv[d] = (live && d < D) ? static_cast<double>(y[n * D + d]) : 0.0;
+    double E[8], H0[kMaxHigh], H1[kMaxHigh];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) E[t] = ident;
+#pragma unroll
+    for (int q = 0; q < kMaxHigh; ++q) {
+      H0[q] = ident;
+      H1[q] = ident;
+    }
+    double gmax = -INFINITY;
+    for (int pass = 0; pass < (MAXLOG ? 1 : 2); ++pass) {
+      const bool sums = !MAXLOG && pass == 1;
+      for (int c0 = 0; c0 < M; c0 += kChunkPts) {
+        const int cn = min(kChunkPts, M - c0);
+        __syncthreads();
+        const float* src = xl + static_cast<int64_t>(c0) * D;
+        for (int pt = threadIdx.x; pt < cn; pt += kCarefulWaves * 64)
+          for (int d = 0; d < D; ++d) pts[pt * Dp + d] = src[pt * D + d];
+        __syncthreads();
+        double ctot = ident;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int jj = lane + 64 * t;
+          if (jj < cn) {
+            const double q = point_q(yv, pts + jj * Dp, D, cnat);
+            if (MAXLOG) {
+              E[t] = fmax(E[t], q);
+              ctot = fmax(ctot, q);
+            } else if (!sums) {
+              gmax = fmax(gmax, q);
+            } else {
+              const double e = exp(q - gmax);
+              E[t] += e;
+              ctot += e;
+            }
+          }
+        }
+        if (MAXLOG || sums) {
+          const int chunk = c0 >> kChunkBits;
+#pragma unroll
+          for (int q = 0; q < kMaxHigh; ++q) {
+            const bool bit = (chunk >> q) & 1;
+            H1[q] = bit ? comb<MAXLOG>(H1[q], ctot) : H1[q];
+            H0[q] = bit ? H0[q] : comb<MAXLOG>(H0[q], ctot);
+          }
+        }
+      }
+      if (!MAXLOG && pass == 0) gmax = wave_max(gmax);
+    }
+    if (!live) continue;
     if (invalid) {
       if (lane < m) llr[n * m + lane] = __builtin_nanf("");
       continue;
     }
-    double yv[kMaxD];
+    // label-0 / label-1 subset sums (or maxima) of label bit b
+    double lane_tot = ident;
 #pragma unroll
-    for (int d = 0; d < kMaxD; ++d) yv[d] = d < D ? static_cast<double>(y[n * D + d]) : 0.0;
-    double mx0[kMaxM], mx1[kMaxM];
+    for (int t = 0; t < 8; ++t) lane_tot = comb<MAXLOG>(lane_tot, E[t]);
+    double S0[kMaxM], S1[kMaxM];
 #pragma unroll
-    for (int k = 0; k < kMaxM; ++k) {
-      mx0[k] = -INFINITY;
-      mx1[k] = -INFINITY;
-    }
-    for (int j = lane; j < M; j += 64) {
-      const double q = point_q(yv, xl, j, D, cnat);
+    for (int b = 0; b < kMaxM; ++b) {
+      S0[b] = ident;
+      S1[b] = ident;
+      if (b >= m) continue;
+      if (b < 6) {
+        const bool bit = (lane >> b) & 1;
+        S0[b] = wave_comb<MAXLOG>(bit ? ident : lane_tot);
+        S1[b] = wave_comb<MAXLOG>(bit ? lane_tot : ident);
+      } else if (b < kChunkBits) {
+        double a0 = ident, a1 = ident;
 #pragma unroll
-      for (int k = 0; k < kMaxM; ++k) {
-        if (k < m) {
-          const bool b = (j >> (m - 1 - k)) & 1;
-          if (b) mx1[k] = fmax(mx1[k], q);
-          else mx0[k] = fmax(mx0[k], q);
+        for (int t = 0; t < 8; ++t) {
+          if ((t >> (b - 6)) & 1) a1 = comb<MAXLOG>(a1, E[t]);
+          else a0 = comb<MAXLOG>(a0, E[t]);
         }
-      }
-    }
-    double gmax = -INFINITY;
-#pragma unroll
-    for (int k = 0; k < kMaxM; ++k) {
-      if (k < m) {
-        mx0[k] = wave_max(mx0[k]);
-        mx1[k] = wave_max(mx1[k]);
-        gmax = fmax(gmax, fmax(mx0[k], mx1[k]));
-      }
-    }
-    if (MAXLOG) {
-#pragma unroll
-      for (int k = 0; k < kMaxM; ++k)
-        if (k < m && lane == k) llr[n * m + k] = static_cast<float>(mx0[k] - mx1[k]);
-      continue;
-    }
-    double s0[kMaxM], s1[kMaxM];
-#pragma unroll
-    for (int k = 0; k < kMaxM; ++k) {
-      s0[k] = 0.0;
-      s1[k] = 0.0;
-    }
-    for (int j = lane; j < M; j += 64) {
-      const double e = exp(point_q(yv, xl, j, D, cnat) - gmax);
-#pragma unroll
-      for (int k = 0; k < kMaxM; ++k) {
-        if (k < m) {
-          const bool b = (j >> (m - 1 - k)) & 1;
-          s1[k] += b ? e : 0.0;
-          s0[k] += b ? 0.0 : e;
-        }
-      }
-    }
-    double lse0[kMaxM], lse1[kMaxM];
-#pragma unroll
-    for (int k = 0; k < kMaxM; ++k) {
-      if (k < m) {
-        lse0[k] = gmax + log(wave_sum(s0[k]));
-        lse1[k] = gmax + log(wave_sum(s1[k]));
-      }
-    }
-    // subsets far below the global maximum: sum again against their own maximum
-#pragma unroll
-    for (int k = 0; k < kMaxM; ++k) {
-      if (k >= m) continue;
-#pragma unroll
-      for (int bv = 0; bv < 2; ++bv) {
-        const double mk = bv ? mx1[k] : mx0[k];
-        if (!(gmax - mk > kNearNat)) continue;     // wave-uniform
-        double a = 0.0;
-        for (int j = lane; j < M; j += 64)
-          if (((j >> (m - 1 - k)) & 1) == bv) a += exp(point_q(yv, xl, j, D, cnat) - mk);
-        const double l = mk + log(wave_sum(a));
-        if (bv) lse1[k] = l;
-        else lse0[k] = l;
+        S0[b] = wave_comb<MAXLOG>(a0);
+        S1[b] = wave_comb<MAXLOG>(a1);
+      } else {
+        S0[b] = wave_comb<MAXLOG>(H0[b - kChunkBits]);
+        S1[b] = wave_comb<MAXLOG>(H1[b - kChunkBits]);
       }
     }
 #pragma unroll
-    for (int k = 0; k < kMaxM; ++k)
-      if (k < m && lane == k) llr[n * m + k] = static_cast<float>(lse0[k] - lse1[k]);
+    for (int b = 0; b < kMaxM; ++b) {
+      if (b >= m) continue;
+      double l0, l1;
+      if (MAXLOG) {
+        l0 = S0[b];
+        l1 = S1[b];
+      } else {
+        // wave-uniform: far subsets are summed again against their own maximum
+        l0 = S0[b] >= kTinySum ? gmax + log(S0[b]) : subset_lse(y + n * D, xl, M, D, b, 0, cnat, lane);
+        l1 = S1[b] >= kTinySum ? gmax + log(S1[b]) : subset_lse(y + n * D, xl, M, D, b, 1, cnat, lane);
+      }
+      const int k = m - 1 - b;                  // column k holds label bit m-1-k
+      if (lane == k) llr[n * m + k] = static_cast<float>(l0 - l1);
+    }
   }
 }
 
@@ -178,12 +236,13 @@ int launch_careful_t(const Prepared& P, int M, int D, const float* d_y, int64_t 
   int dev = 0, ncu = 0;
   MD_HIP_TRY(hipGetDevice(&dev));
   MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  int64_t grid = list ? static_cast<int64_t>(ncu) * 8 : (N + 3) / 4;
-  if (grid > static_cast<int64_t>(ncu) * 64) grid = static_cast<int64_t>(ncu) * 64;
+  int64_t grid = list ? static_cast<int64_t>(ncu) * 2 : (N + kCarefulWaves - 1) / kCarefulWaves;
+  if (grid > static_cast<int64_t>(ncu) * 16) grid = static_cast<int64_t>(ncu) * 16;
   if (grid < 1) grid = 1;
   const double cnat = 1.0 / (2.0 * sigma2);
-  hipLaunchKernelGGL(llr_careful_kernel<MAXLOG>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, P.xl, M,
-                     m, D, d_y, N, cnat, d_llr, P.flags, list, count_slot);
+  const size_t lds = sizeof(float) * static_cast<size_t>(kChunkPts) * (D | 1);
+  hipLaunchKernelGGL(llr_careful_kernel<MAXLOG>, dim3(static_cast<unsigned>(grid)), dim3(kCarefulWaves * 64), lds,
+                     stream, P.xl, M, m, D, d_y, N, cnat, d_llr, P.flags, list, count_slot);
   MD_LAUNCH_CHECK("llr_careful_kernel launch");
   return MD_OK;
 }

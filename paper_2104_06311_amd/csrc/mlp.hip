@@ -65,7 +65,8 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(const float* __restrict_
                                                         const float* __restrict__ B, int64_t sbr, int64_t sbc,
                                                         int M, int N, int K, float* __restrict__ C, int64_t ldc,
                                                         const float* __restrict__ bias, float* __restrict__ C2,
-                                                        const float* __restrict__ Z) {
+                                                        const float* __restrict__ Z, float ascale, float bscale,
+                                                        float cscale) {
   __shared__ __attribute__((aligned(16))) __bf16 As[64][16];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[64][16];
   const int tid = threadIdx.x;
@@ -88,8 +89,8 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(const float* __restrict_
       const int idx = tid * 4 + e;        // 0..1023
       const int r = idx >> 4, kk = idx & 15;
       const int gi = i0 + r, gk = k0 + kk, gj = j0 + r;
-      const float av = (gi < M && gk < ke) ? A[gi * sar + gk * sac] : 0.0f;
-      const float bv = (gj < N && gk < ke) ? B[gk * sbr + gj * sbc] : 0.0f;
+      const float av = (gi < M && gk < ke) ? A[gi * sar + gk * sac] * ascale : 0.0f;
+      const float bv = (gj < N && gk < ke) ? B[gk * sbr + gj * sbc] * bscale : 0.0f;
       As[r][kk] = static_cast<__bf16>(av);
       Bs[r][kk] = static_cast<__bf16>(bv);
     }
@@ -109,7 +110,7 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(const float* __restrict_
       const int64_t o = static_cast<int64_t>(i) * ldc + j;
       if (EPI == EPI_STORE) {
         if (bias) v += bias[j];
-        C[o] = v;
+        C[o] = v * cscale;
       } else if (EPI == EPI_BIAS_GELU) {
         v += bias[j];
         C[o] = v;
@@ -121,12 +122,15 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(const float* __restrict_
   }
 }
 
+// ascale / bscale multiply the A / B values as they are staged, cscale the stored result
+// (EPI_STORE): the network's fixed input and output scales.
 template <int EPI>
 int gemm(const float* A, int64_t sar, int64_t sac, const float* B, int64_t sbr, int64_t sbc, int M, int N, int K,
-         float* C, int64_t ldc, const float* bias, float* C2, const float* Z, hipStream_t s) {
+         float* C, int64_t ldc, const float* bias, float* C2, const float* Z, hipStream_t s, float ascale = 1.0f,
+         float bscale = 1.0f, float cscale = 1.0f) {
   dim3 grid((N + 63) / 64, (M + 63) / 64, 1);
   hipLaunchKernelGGL(gemm_bf16_kernel<EPI>, grid, dim3(256), 0, s, A, sar, sac, B, sbr, sbc, M, N, K, C, ldc, bias,
-                     C2, Z);
+                     C2, Z, ascale, bscale, cscale);
   MD_LAUNCH_CHECK("gemm_bf16_kernel launch");
   return MD_OK;
 }
@@ -146,10 +150,10 @@ constexpr int kSplitK = 16;
 // Weight-gradient products (small M x N, K = batch): K split over kSplitK slices so
 // that the grid covers the chip, partials in `part` (kSplitK * M * N floats).
 int gemm_splitk(const float* A, int64_t sar, int64_t sac, const float* B, int64_t sbr, int64_t sbc, int M, int N,
-                int K, float* C, float* part, hipStream_t s) {
+                int K, float* C, float* part, hipStream_t s, float bscale = 1.0f) {
   dim3 grid((N + 63) / 64, (M + 63) / 64, kSplitK);
   hipLaunchKernelGGL(gemm_bf16_kernel<EPI_STORE>, grid, dim3(256), 0, s, A, sar, sac, B, sbr, sbc, M, N, K, part,
-                     static_cast<int64_t>(N), nullptr, nullptr, nullptr);
+                     static_cast<int64_t>(N), nullptr, nullptr, nullptr, 1.0f, bscale, 1.0f);
   MD_LAUNCH_CHECK("gemm_bf16_kernel (split K) launch");
   const int64_t n = static_cast<int64_t>(M) * N;
   hipLaunchKernelGGL(splitk_reduce_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, part,
@@ -159,10 +163,10 @@ int gemm_splitk(const float* A, int64_t sar, int64_t sac, const float* B, int64_
 }
 
 // ------------------------------------------------------------------ loss, bias grads, Adam
-// One thread per sample: loss terms and dloss/df = (sigmoid(f) - sigmoid(L)) / B.
+// One thread per sample: loss terms of z = oscale f and dloss/df = oscale (sigmoid(z) - sigmoid(L)) / B.
 // partials[block] = sum of the block's per-sample losses (FP64, fixed order).
 __global__ void __launch_bounds__(256) loss_grad_kernel(const float* __restrict__ f, const float* __restrict__ tgt,
-                                                        int64_t B, int m, float* __restrict__ df,
+                                                        int64_t B, int m, float oscale, float* __restrict__ df,
                                                         double* __restrict__ partials) {
   __shared__ double sh[256];
   double acc = 0.0;
@@ -170,10 +174,10 @@ __global__ void __launch_bounds__(256) loss_grad_kernel(const float* __restrict_
   if (b < B) {
     const float invB = 1.0f / static_cast<float>(B);
     for (int k = 0; k < m; ++k) {
-      const float z = f[b * m + k];
+      const float z = oscale * f[b * m + k];       // the network output is oscale times the last layer
       const float p = sigmoidf_acc(tgt[b * m + k]);
       acc += static_cast<double>(p * softplusf(-z) + (1.0f - p) * softplusf(z));
-      df[b * m + k] = (sigmoidf_acc(z) - p) * invB;
+      df[b * m + k] = (sigmoidf_acc(z) - p) * (oscale * invB);
     }
   }
   sh[threadIdx.x] = acc;
@@ -370,8 +374,8 @@ __global__ void pack_infer_kernel(const float* __restrict__ w, int D, int H, int
 
 template <int NRB>
 __global__ void __launch_bounds__(512) mlp_infer_kernel(const char* __restrict__ img, InferLayout L, int D, int m,
-                                                        const float* __restrict__ y, int64_t N,
-                                                        float* __restrict__ llr) {
+                                                        const float* __restrict__ y, int64_t N, float in_scale,
+                                                        float out_scale, float* __restrict__ llr) {
   extern __shared__ uint4 smem[];
   char* lds = reinterpret_cast<char*>(smem);
   for (size_t i = threadIdx.x; i < L.bytes / 16; i += blockDim.x)
@@ -394,7 +398,7 @@ __global__ void __launch_bounds__(512) mlp_infer_kernel(const char* __restrict__
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
       const int k = 8 * h + v;
-      const float x = (k < D) ? (live ? y[n * D + k] : 0.0f) : (k == D ? 1.0f : 0.0f);
+      const float x = (k < D) ? (live ? y[n * D + k] * in_scale : 0.0f) : (k == D ? 1.0f : 0.0f);
       yb[v] = static_cast<__bf16>(x);
     }
     bf16x8 act[NRB][2];
@@ -443,7 +447,7 @@ __global__ void __launch_bounds__(512) mlp_infer_kernel(const char* __restrict__
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int k = 8 * (r >> 2) + 4 * h + (r & 3);
-        if (k < m) llr[n * m + k] = out[r];
+        if (k < m) llr[n * m + k] = out[r] * out_scale;
       }
     }
   }
@@ -487,6 +491,8 @@ struct Mlp {
   int64_t version = 0;    // bumped whenever w changes
   float* scratch = nullptr;
   size_t scratch_cap = 0;
+  float in_scale = 1.0f;  // fixed input scale: the first layer sees in_scale * y
+  float out_scale = 1.0f; // fixed output scale: f = out_scale * (last layer)
 };
 
 namespace {
@@ -582,10 +588,10 @@ int forward_backward(Mlp* p, const float* d_y, const float* d_t, int64_t B, doub
   float* gb3 = gW3 + static_cast<int64_t>(m) * H;
   const int Bi = static_cast<int>(B);
   // forward: Z1 = Y W1^T + b1, A1 = g(Z1); Z2 = A1 W2^T + b2, A2 = g(Z2); F = A2 W3^T + b3
-  if ((st = gemm<EPI_BIAS_GELU>(d_y, D, 1, W1, 1, D, Bi, H, D, Z1, H, b1, A1, nullptr, s))) return st;
+  if ((st = gemm<EPI_BIAS_GELU>(d_y, D, 1, W1, 1, D, Bi, H, D, Z1, H, b1, A1, nullptr, s, p->in_scale))) return st;
   if ((st = gemm<EPI_BIAS_GELU>(A1, H, 1, W2, 1, H, Bi, H, H, Z2, H, b2, A2, nullptr, s))) return st;
   if ((st = gemm<EPI_STORE>(A2, H, 1, W3, 1, H, Bi, m, H, F, m, b3, nullptr, nullptr, s))) return st;
-  hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(256), 0, s, F, d_t, B, m, dF, part);
+  hipLaunchKernelGGL(loss_grad_kernel, dim3(nb), dim3(256), 0, s, F, d_t, B, m, p->out_scale, dF, part);
   MD_LAUNCH_CHECK("loss_grad_kernel launch");
   if (d_loss) {
     hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, s, part, nb, B, d_loss);
@@ -603,7 +609,7 @@ int forward_backward(Mlp* p, const float* d_y, const float* d_t, int64_t B, doub
   // dZ1 = (dZ2 W2) * g'(Z1)
   if ((st = gemm<EPI_GELU_GRAD>(dZ2, H, 1, W2, H, 1, Bi, H, H, dZ1, H, nullptr, nullptr, Z1, s))) return st;
   // gW1 = dZ1^T Y (H x D); gb1 = colsum dZ1
-  if ((st = gemm_splitk(dZ1, 1, H, d_y, D, 1, H, D, Bi, gW1, kpartb, s))) return st;
+  if ((st = gemm_splitk(dZ1, 1, H, d_y, D, 1, H, D, Bi, gW1, kpartb, s, p->in_scale))) return st;
   if ((st = colsum(dZ1, B, H, cpart, gb1, s))) return st;
   return MD_OK;
 }
@@ -637,9 +643,12 @@ int infer_gemm(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s)
   float* A2 = A1 + chunk * H;
   for (int64_t n0 = 0; n0 < N; n0 += chunk) {
     const int nb = static_cast<int>(N - n0 < chunk ? N - n0 : chunk);
-    if ((st = gemm<EPI_BIAS_GELU>(d_y + n0 * D, D, 1, W1, 1, D, nb, H, D, Z, H, b1, A1, nullptr, s))) return st;
+    if ((st = gemm<EPI_BIAS_GELU>(d_y + n0 * D, D, 1, W1, 1, D, nb, H, D, Z, H, b1, A1, nullptr, s, p->in_scale)))
+      return st;
     if ((st = gemm<EPI_BIAS_GELU>(A1, H, 1, W2, 1, H, nb, H, H, Z, H, b2, A2, nullptr, s))) return st;
-    if ((st = gemm<EPI_STORE>(A2, H, 1, W3, 1, H, nb, m, H, d_llr + n0 * m, m, b3, nullptr, nullptr, s))) return st;
+    if ((st = gemm<EPI_STORE>(A2, H, 1, W3, 1, H, nb, m, H, d_llr + n0 * m, m, b3, nullptr, nullptr, s, 1.0f, 1.0f,
+                              p->out_scale)))
+      return st;
   }
   return MD_OK;
 }
@@ -662,7 +671,7 @@ int infer_fused_t(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t
   const int64_t tiles = (N + 31) / 32;
   if (grid > (tiles + 7) / 8) grid = (tiles + 7) / 8;
   hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(block), L.bytes, s, p->img, L, p->D, p->m, d_y, N,
-                     d_llr);
+                     p->in_scale, p->out_scale, d_llr);
   MD_LAUNCH_CHECK("mlp_infer_kernel launch");
   return MD_OK;
 }
@@ -708,11 +717,12 @@ uint32_t crc32(const void* data, size_t n, uint32_t crc = 0) {
 }
 
 struct CkptHeader {
-  char magic[8];          // "MDMLP\0\0\1"
+  char magic[8];          // "MDMLP\0\0\2"
   int32_t D, H, m, pad;
   int64_t P, step;
   uint64_t seed;
   uint32_t crc, pad2;
+  float in_scale, out_scale;
 };
 
 }  // namespace
@@ -890,14 +900,16 @@ int mlp_save(const void* mlp, const char* path) {
   MD_HIP_TRY(hipMemcpy(buf.data() + p->P, p->m1, sizeof(float) * 2 * p->P, hipMemcpyDeviceToHost));
   md::CkptHeader hd;
   std::memset(&hd, 0, sizeof(hd));
-  std::memcpy(hd.magic, "MDMLP\0\0\1", 8);
+  std::memcpy(hd.magic, "MDMLP\0\0\2", 8);
   hd.D = p->D;
   hd.H = p->H;
   hd.m = p->m;
   hd.P = p->P;
   hd.step = p->step;
   hd.seed = p->seed;
-  hd.crc = md::crc32(buf.data(), buf.size() * sizeof(float));
+  hd.in_scale = p->in_scale;
+  hd.out_scale = p->out_scale;
+  hd.crc = md::crc32(&hd.in_scale, 2 * sizeof(float), md::crc32(buf.data(), buf.size() * sizeof(float)));
   FILE* f = std::fopen(path, "wb");
   if (!f) return md::fail(MD_EINVAL, std::string("cannot open ") + path);
   const bool ok = std::fwrite(&hd, sizeof(hd), 1, f) == 1 &&
@@ -913,7 +925,8 @@ int mlp_load(const char* path, void** out) {
   FILE* f = std::fopen(path, "rb");
   if (!f) return md::fail(MD_EINVAL, std::string("cannot open ") + path);
   md::CkptHeader hd;
-  if (std::fread(&hd, sizeof(hd), 1, f) != 1 || std::memcmp(hd.magic, "MDMLP\0\0\1", 8) != 0 ||
+  if (std::fread(&hd, sizeof(hd), 1, f) != 1 || std::memcmp(hd.magic, "MDMLP\0\0\2", 8) != 0 ||
+      !(hd.in_scale > 0.0f && hd.in_scale < INFINITY && hd.out_scale > 0.0f && hd.out_scale < INFINITY) ||
       hd.P != md::param_count(hd.D, hd.H, hd.m)) {
     std::fclose(f);
     return md::fail(MD_EINVAL, "not an MLP checkpoint of this version");
@@ -921,7 +934,7 @@ int mlp_load(const char* path, void** out) {
   std::vector<float> buf(static_cast<size_t>(3 * hd.P));
   const bool ok = std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
   std::fclose(f);
-  if (!ok || md::crc32(buf.data(), buf.size() * sizeof(float)) != hd.crc)
+  if (!ok || md::crc32(&hd.in_scale, 2 * sizeof(float), md::crc32(buf.data(), buf.size() * sizeof(float))) != hd.crc)
     return md::fail(MD_EINVAL, "checkpoint is truncated or corrupt (CRC mismatch)");
   void* h = nullptr;
   int st = mlp_create(hd.D, hd.H, hd.m, hd.seed, &h);
@@ -930,8 +943,32 @@ int mlp_load(const char* path, void** out) {
   MD_HIP_TRY(hipMemcpy(p->w, buf.data(), sizeof(float) * p->P, hipMemcpyHostToDevice));
   MD_HIP_TRY(hipMemcpy(p->m1, buf.data() + p->P, sizeof(float) * 2 * p->P, hipMemcpyHostToDevice));
   p->step = hd.step;
+  p->in_scale = hd.in_scale;
+  p->out_scale = hd.out_scale;
   p->version += 1;
   *out = p;
+  return MD_OK;
+}
+
+int mlp_set_scales(void* mlp, float in_scale, float out_scale) {
+  md::set_error("");
+  md::Mlp* p = static_cast<md::Mlp*>(mlp);
+  int st = md::check_handle(p);
+  if (st != MD_OK) return st;
+  if (!(in_scale > 0.0f && in_scale < INFINITY && out_scale > 0.0f && out_scale < INFINITY))
+    return md::fail(MD_EINVAL, "scales must be finite and > 0");
+  p->in_scale = in_scale;
+  p->out_scale = out_scale;
+  return MD_OK;
+}
+
+int mlp_get_scales(const void* mlp, float* in_scale, float* out_scale) {
+  md::set_error("");
+  const md::Mlp* p = static_cast<const md::Mlp*>(mlp);
+  int st = md::check_handle(p);
+  if (st != MD_OK) return st;
+  if (in_scale) *in_scale = p->in_scale;
+  if (out_scale) *out_scale = p->out_scale;
   return MD_OK;
 }
 

@@ -44,26 +44,33 @@ def cosine(a, b):
     return float(np.dot(a.ravel(), b.ravel()) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
 
 
-@pytest.mark.parametrize("D,H,m,N", [(8, 256, 11, 3001), (3, 64, 4, 777), (5, 96, 6, 100), (16, 512, 16, 513),
-                                     (8, 40, 11, 64)])
-def test_forward_matches_oracle(D, H, m, N):
+@pytest.mark.parametrize("D,H,m,N,scales", [(8, 256, 11, 3001, None), (3, 64, 4, 777, None), (5, 96, 6, 100, None),
+                                            (16, 512, 16, 513, None), (8, 40, 11, 64, None),
+                                            (8, 256, 11, 2000, (4.47, 3.1)), (16, 512, 16, 300, (2.5, 0.5))])
+def test_forward_matches_oracle(D, H, m, N, scales):
     net = md().MLP(D, H, m, seed=11)
+    if scales:
+        net.set_scales(*scales)
+        assert net.scales == pytest.approx(scales)
     rng = np.random.default_rng(D + H)
     y = rng.standard_normal((N, D)).astype(np.float32)
     L = md().llr_learned(net, torch.from_numpy(y).cuda()).cpu().numpy()
-    ref = oracle.mlp_forward(oracle.MLPParams(*split_params(net.get(0), D, H, m)), y)
+    ref = oracle.mlp_forward(oracle.MLPParams(*split_params(net.get(0), D, H, m), *(scales or (1.0, 1.0))), y)
     assert np.all(np.isfinite(L))
     assert rel_err(L, ref) <= 2e-2 and cosine(L, ref) >= 0.999, (rel_err(L, ref), cosine(L, ref))
 
 
-@pytest.mark.parametrize("D,H,m,B", [(8, 256, 11, 4096), (4, 64, 6, 1000)])
-def test_gradients_match_oracle(D, H, m, B):
+@pytest.mark.parametrize("D,H,m,B,scales", [(8, 256, 11, 4096, None), (4, 64, 6, 1000, None),
+                                            (8, 256, 11, 4096, (4.47, 4.47))])
+def test_gradients_match_oracle(D, H, m, B, scales):
     net = md().MLP(D, H, m, seed=5)
+    if scales:
+        net.set_scales(*scales)
     rng = np.random.default_rng(3)
     y = rng.standard_normal((B, D)).astype(np.float32)
     t = (rng.standard_normal((B, m)) * 4).astype(np.float32)
     loss = net.grad(torch.from_numpy(y).cuda(), torch.from_numpy(t).cuda()).item()
-    p = oracle.MLPParams(*split_params(net.get(0), D, H, m))
+    p = oracle.MLPParams(*split_params(net.get(0), D, H, m), *(scales or (1.0, 1.0)))
     loss_ref, g_ref = oracle.mlp_loss_grad(p, y, t)
     assert abs(loss - loss_ref) <= 1e-2 * abs(loss_ref), (loss, loss_ref)
     g = split_params(net.get(1), D, H, m)
@@ -113,6 +120,7 @@ def test_training_learns_and_checkpoint_resumes_bit_exactly():
     X, labels = synth.product_4d_8psk()
     Xd, ld, s2, tx, y, L = _exact_dataset(X, labels, 8.0, 1 << 16, 3)
     net = md().MLP(4, 64, 6, seed=1)
+    net.set_scales(1.0 / math.sqrt(s2), 1.0 / math.sqrt(s2))
     trace = net.fit(y, L, steps=400, batch=1024, lr_max=3e-3, lr_min=1e-4, seed=7).cpu().numpy()
     assert trace[-50:].mean() < 0.8 * trace[:10].mean()
     # fresh symbols: learned GMI well above zero and below exact
@@ -125,7 +133,7 @@ def test_training_learns_and_checkpoint_resumes_bit_exactly():
         path = os.path.join(d, "net.ckpt")
         net.save(path)
         net2 = md().MLP.load(path)
-        assert net2.step == net.step
+        assert net2.step == net.step and net2.scales == net.scales
         for w in range(4):
             assert np.array_equal(net.get(w) if w != 1 else net.get(0), net2.get(w) if w != 1 else net2.get(0))
         assert torch.equal(md().llr_learned(net, yv), md().llr_learned(net2, yv))
@@ -148,3 +156,7 @@ def test_learned_edge_cases():
         md().llr_learned(net, torch.zeros((4, 7), dtype=torch.float32, device="cuda"))
     with pytest.raises(md().MdemapError):
         md().MLP(0, 16, 4)
+    with pytest.raises(md().MdemapError):
+        net.set_scales(0.0, 1.0)
+    with pytest.raises(md().MdemapError):
+        net.set_scales(1.0, float("inf"))

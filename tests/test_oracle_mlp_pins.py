@@ -55,9 +55,11 @@ def test_zero_network_loss_closed_form():
     assert abs(loss2 - m * math.log(2)) < 1e-12
 
 
-@pytest.mark.parametrize("seed", [0, 1])
+@pytest.mark.parametrize("seed", [0, 1, 2])
 def test_gradient_central_differences(seed):
     p = _params(seed=seed)
+    if seed == 2:                       # with the fixed input / output scales in play
+        p.in_scale, p.out_scale = 1.7, 2.5
     rng = np.random.default_rng(10 + seed)
     y = rng.standard_normal((7, 3)).astype(np.float32)
     tgt = (rng.standard_normal((7, 2)) * 3).astype(np.float32)
@@ -89,3 +91,23 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(w, w0 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-13, atol=1e-15)
     np.testing.assert_allclose(m1, 0.1 * g, rtol=1e-14)
     np.testing.assert_allclose(m2, 0.001 * g * g, rtol=1e-13)
+
+
+def test_fixed_scales_are_reparametrisations():
+    """f(y) = s_out net(s_in y): s_in equals scaling the first-layer weights, s_out equals
+    scaling the last layer's weights and bias, and the loss of the scaled network equals
+    the loss of the reparametrised one."""
+    p = _params(seed=4)
+    rng = np.random.default_rng(5)
+    y = rng.standard_normal((9, 3)).astype(np.float32)
+    tgt = (rng.standard_normal((9, 2)) * 3).astype(np.float32)
+    q = oracle.MLPParams(p.W1 * 1.7, p.b1, p.W2, p.b2, p.W3 * 2.5, p.b3 * 2.5)
+    p.in_scale, p.out_scale = 1.7, 2.5
+    np.testing.assert_allclose(oracle.mlp_forward(p, y), oracle.mlp_forward(q, y), rtol=1e-12, atol=1e-12)
+    lp, gp = oracle.mlp_loss_grad(p, y, tgt)
+    lq, gq = oracle.mlp_loss_grad(q, y, tgt)
+    assert abs(lp - lq) < 1e-12
+    # chain rule: d/dW1 of the scaled net = s_in * d/dW1' of the reparametrised one, and so on
+    np.testing.assert_allclose(gp[0], 1.7 * gq[0], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(gp[4], 2.5 * gq[4], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(gp[5], 2.5 * gq[5], rtol=1e-9, atol=1e-12)
