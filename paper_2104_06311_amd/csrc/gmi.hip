@@ -36,7 +36,9 @@ __device__ __forceinline__ float softplus_bits(float x) {
   constexpr float kLog2e = 1.4426950408889634f;
   const float u = __builtin_amdgcn_exp2f(-fabsf(x) * kLog2e);
   const float w = 1.0f + u;
-  const float l1p = (w == 1.0f) ? u * kLog2e : __builtin_amdgcn_logf(w) * (u * __builtin_amdgcn_rcpf(w - 1.0f));
+  const float dw = w - 1.0f;
+  const float a = __builtin_amdgcn_logf(w) * (u * __builtin_amdgcn_rcpf(dw));   // NaN when w == 1: not selected
+  const float l1p = dw != 0.0f ? a : u * kLog2e;
   return fmaxf(x, 0.0f) * kLog2e + l1p;
 }
 
@@ -52,31 +54,33 @@ __device__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// partials: per block, [sum T, sum T^2, sum t_0 .. sum t_{m-1}]
-__global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __restrict__ llr, int64_t N, int m,
+// partials: per block, [sum T, sum T^2, sum t_0 .. sum t_{m-1}].  Templated on m so that a
+// symbol's m LLRs are loaded together and the per-bit work has no branches.
+template <int MB>
+__global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __restrict__ llr, int64_t N,
                                                              const uint32_t* __restrict__ tx,
                                                              const uint32_t* __restrict__ labels,
                                                              double* __restrict__ partials) {
   __shared__ double sh[kBlock];
   Kahan sT{0.f, 0.f}, sT2{0.f, 0.f};
-  Kahan sb[kMaxM];
+  Kahan sb[MB];
 #pragma unroll
-  for (int k = 0; k < kMaxM; ++k) sb[k] = Kahan{0.f, 0.f};
+  for (int k = 0; k < MB; ++k) sb[k] = Kahan{0.f, 0.f};
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   for (int64_t n = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; n < N; n += stride) {
+    float L[MB];
+#pragma unroll
+    for (int k = 0; k < MB; ++k) L[k] = llr[n * MB + k];
     const uint32_t u = tx[n];
-    const bool ok = u < (1u << m);                       // an index outside the labels gives NaN
-    const uint32_t lab = ok ? labels[u] : 0u;
+    const bool ok = u < (1u << MB);                      // an index outside the labels gives NaN
+    const uint32_t lab = labels[ok ? u : 0u];
     float T = ok ? 0.0f : __builtin_nanf("");
 #pragma unroll
-    for (int k = 0; k < kMaxM; ++k) {
-      if (k < m) {
-        const float L = llr[n * m + k];
-        const float s = ((lab >> (m - 1 - k)) & 1u) ? 1.0f : -1.0f;   // -s_nk
-        const float t = softplus_bits(s * L);
-        sb[k].add(t);
-        T += t;
-      }
+    for (int k = 0; k < MB; ++k) {
+      const float s = ((lab >> (MB - 1 - k)) & 1u) ? 1.0f : -1.0f;   // -s_nk
+      const float t = softplus_bits(s * L[k]);
+      sb[k].add(t);
+      T += t;
     }
     sT.add(T);
     sT2.add(T * T);
@@ -87,14 +91,10 @@ __global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __rest
   if (threadIdx.x == 0) partials[0 * nb + blockIdx.x] = v;
   v = block_sum(sT2.get(), sh);
   if (threadIdx.x == 0) partials[1 * nb + blockIdx.x] = v;
-  // unrolled with a guard: a loop bounded by the runtime m would index sb dynamically and
-  // put the accumulators in scratch memory
 #pragma unroll
-  for (int k = 0; k < kMaxM; ++k) {
-    if (k < m) {
-      v = block_sum(sb[k].get(), sh);
-      if (threadIdx.x == 0) partials[(2 + k) * nb + blockIdx.x] = v;
-    }
+  for (int k = 0; k < MB; ++k) {
+    v = block_sum(sb[k].get(), sh);
+    if (threadIdx.x == 0) partials[(2 + k) * nb + blockIdx.x] = v;
   }
 }
 
@@ -204,7 +204,18 @@ int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const
                double* d_gmi_per_bit, double* d_se, char* ws, hipStream_t stream) {
   const int nb = gmi_blocks(N);
   double* partials = reinterpret_cast<double*>(ws);
-  hipLaunchKernelGGL(gmi_partial_kernel, dim3(nb), dim3(kBlock), 0, stream, d_llr, N, m, d_tx, d_labels, partials);
+  switch (m) {
+#define MD_GMI_CASE(MB_)                                                                                    \
+  case MB_:                                                                                               \
+    hipLaunchKernelGGL(gmi_partial_kernel<MB_>, dim3(nb), dim3(kBlock), 0, stream, d_llr, N, d_tx, d_labels, \
+                       partials);                                                                         \
+    break;
+    MD_GMI_CASE(1) MD_GMI_CASE(2) MD_GMI_CASE(3) MD_GMI_CASE(4) MD_GMI_CASE(5) MD_GMI_CASE(6) MD_GMI_CASE(7)
+    MD_GMI_CASE(8) MD_GMI_CASE(9) MD_GMI_CASE(10) MD_GMI_CASE(11) MD_GMI_CASE(12) MD_GMI_CASE(13) MD_GMI_CASE(14)
+    MD_GMI_CASE(15)
+    default: MD_GMI_CASE(16)
+#undef MD_GMI_CASE
+  }
   MD_LAUNCH_CHECK("gmi_partial_kernel launch");
   double* totals = partials + carve_size(sizeof(double) * static_cast<size_t>(nb) * (m + 2)) / sizeof(double);
   hipLaunchKernelGGL(gmi_column_kernel, dim3(m + 2), dim3(kBlock), 0, stream, partials, nb, totals);
