@@ -422,24 +422,17 @@ __global__ void __launch_bounds__(512) mlp_infer_kernel(const char* __restrict__
     for (int r = 0; r < 16; ++r) out[r] = b3[8 * (r >> 2) + 4 * h + (r & 3)];
 #pragma unroll 1
     for (int ob = 0; ob < NRB; ++ob) {
-      // two accumulation chains (K steps q = 0 and q = 1) so that consecutive matrix
-      // products do not wait on each other
-      floatx16 acc, acc1;
+      floatx16 acc;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        acc[r] = b2[32 * ob + 8 * (r >> 2) + 4 * h + (r & 3)];
-        acc1[r] = 0.0f;
-      }
+      for (int r = 0; r < 16; ++r) acc[r] = b2[32 * ob + 8 * (r >> 2) + 4 * h + (r & 3)];
 #pragma unroll
-      for (int rb = 0; rb < NRB; ++rb) {
-        bf16x8 a0, a1;
-        __builtin_memcpy(&a0, &f2[((ob * NRB + rb) * 2 + 0) * 64 + lane], 16);
-        __builtin_memcpy(&a1, &f2[((ob * NRB + rb) * 2 + 1) * 64 + lane], 16);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, act[rb][0], acc, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, act[rb][1], acc1, 0, 0, 0);
-      }
+      for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] += acc1[r];
+        for (int q = 0; q < 2; ++q) {
+          bf16x8 a;
+          __builtin_memcpy(&a, &f2[((ob * NRB + rb) * 2 + q) * 64 + lane], 16);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, act[rb][q], acc, 0, 0, 0);
+        }
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         bf16x8 act2;
