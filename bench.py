@@ -232,8 +232,7 @@ def counter_traffic(kernel_sources):
         return None, "counter summary incomplete"
 
 
-KERNEL_SOURCES = ["paper_2104_06311_amd/csrc/llr_fast.hpp", "paper_2104_06311_amd/csrc/llr_fast_exact.hip",
-                  "paper_2104_06311_amd/csrc/common.hpp"]
+KERNEL_SOURCES = ["paper_2104_06311_amd/csrc/llr_fast.hpp", "paper_2104_06311_amd/csrc/llr_fast_exact.hip"]
 
 
 def extra_batched(md, n_inst):

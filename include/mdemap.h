@@ -128,8 +128,9 @@ int llr_maxlog(const float* d_X, const uint32_t* d_labels, int M, int D, const f
 /* llr_path_counts -- waits for `stream` and reports, for the last llr_exact or
  * llr_maxlog call enqueued on it from this process, how many symbols the wide-range
  * second pass took (*n_wide; exact only) and how many the FP64 careful kernel took
- * (*n_careful; every symbol when M < 32).  Both are 0 if no call was made on the
- * stream since the last release_cache.  Returns MD_OK, MD_EINVAL, MD_EHIP. */
+ * (*n_careful).  Constellations of M <= 16 points take a one-thread-per-symbol kernel and
+ * report 0 and 0.  Both are 0 if no call was made on the stream since the last
+ * release_cache.  Returns MD_OK, MD_EINVAL, MD_EHIP. */
 int llr_path_counts(void* stream, int64_t* n_wide, int64_t* n_careful);
 
 /* ------------------------------------------------------------------ metric */
@@ -220,8 +221,9 @@ int mlp_save(const void* mlp, const char* path);
 int mlp_load(const char* path, void** out);
 
 /* ------------------------------------------------------------------ batched sweep */
-/* Many constellations (uneven M and D) at many noise levels in one persistent kernel
- * captured in a hipGraph: for every (instance i, noise level s) the channel of
+/* Many constellations (uneven M and D) at many noise levels in one captured hipGraph of
+ * persistent kernels, one per constellation class (K steps, label bits), each claiming
+ * its work items dynamically: for every (instance i, noise level s) the channel of
  * awgn_sample (seed_i, offset = s * N_i, N_i uses), the exact LLRs and their GMI, without
  * storing received symbols or LLRs.  The GMI equals gmi_reduce(llr_exact(...)) of the
  * same channel draw up to FP32 rounding.  The launch shape (wavefronts per block,

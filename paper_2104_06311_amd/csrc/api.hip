@@ -48,7 +48,6 @@ int demap(const float* d_X, const uint32_t* d_labels, int M, int D, const float*
   md::LastCall lc;
   lc.valid = true;
   lc.maxlog = maxlog;
-  lc.all_careful = M < 32;
   lc.N = N;
   md::record_last_call(s, lc);
   return md::launch_llr(P, M, D, d_y, N, sigma2, maxlog, prec == MD_PREC_BF16, d_llr, s);
@@ -97,10 +96,6 @@ int llr_path_counts(void* stream, int64_t* n_wide, int64_t* n_careful) {
   st = md::last_call(s, &lc, &flags);
   if (st != MD_OK) return st;
   if (!lc.valid || !flags) return MD_OK;
-  if (lc.all_careful) {
-    *n_careful = lc.N;
-    return MD_OK;
-  }
   int h[4] = {0, 0, 0, 0};
   MD_HIP_TRY(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s));
   MD_HIP_TRY(hipStreamSynchronize(s));

@@ -60,7 +60,6 @@ int workspace(hipStream_t stream, size_t bytes, char** out);
 struct LastCall {
   bool valid = false;
   bool maxlog = false;
-  bool all_careful = false;
   int64_t N = 0;
 };
 int stream_flags(hipStream_t stream, int** out);

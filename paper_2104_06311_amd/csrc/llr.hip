@@ -63,7 +63,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 //            g + ln(sum).  A smaller sum means the subset lies more than ~667 nats below
 //            g: it is summed again against its own maximum (in practice never).
 //   max-log: pass 1 alone, with max in place of the sums.
-// Used for every symbol when M < 32 and for the symbols the fast passes hand over.
+// Used for the symbols the fast passes hand over (M >= 32).
 constexpr int kCarefulWaves = 4;
 constexpr int kChunkPts = 512;                 // 512 rows of at most 31 floats: <= 62 KiB of LDS
 constexpr int kChunkBits = 9;
@@ -228,6 +228,74 @@ __global__ void __launch_bounds__(kCarefulWaves * 64) llr_careful_kernel(const f
   }
 }
 
+// ------------------------------------------------------------------ small constellations
+// M <= 16: one thread per symbol.  The M scores q_j = -||y - x_j||^2 / (2 sigma2) are
+// formed in FP64 (difference form); per label subset the maximum is taken in FP64 and the
+// sum of exp(q - max) <= 1 in FP32 (hardware exponential, every term relative to the
+// subset's own maximum, so nothing underflows that matters); LSE = max + ln(sum).
+constexpr int kSmallM = 16;
+
+template <bool MAXLOG>
+__global__ void __launch_bounds__(256) llr_small_kernel(const float* __restrict__ xl, int M, int m, int D,
+                                                        const float* __restrict__ y, int64_t N, double cnat,
+                                                        float* __restrict__ llr, const int* __restrict__ flags) {
+  const bool invalid = flags[0] != 0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t n = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+    if (invalid) {
+      for (int k = 0; k < m; ++k) llr[n * m + k] = __builtin_nanf("");
+      continue;
+    }
+    double q[kSmallM];
+#pragma unroll
+    for (int j = 0; j < kSmallM; ++j) {
+      q[j] = -INFINITY;
+      if (j < M) {
+        double d2 = 0.0;
+        for (int d = 0; d < D; ++d) {
+          const double df = static_cast<double>(y[n * D + d]) - static_cast<double>(xl[j * D + d]);
+          d2 = fma(df, df, d2);
+        }
+        q[j] = -cnat * d2;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b >= m) continue;
+      double mx[2] = {-INFINITY, -INFINITY};
+#pragma unroll
+      for (int j = 0; j < kSmallM; ++j)
+        if (j < M) mx[(j >> b) & 1] = fmax(mx[(j >> b) & 1], q[j]);
+      double lse[2];
+      if (MAXLOG) {
+        lse[0] = mx[0];
+        lse[1] = mx[1];
+      } else {
+        float sum[2] = {0.0f, 0.0f};
+#pragma unroll
+        for (int j = 0; j < kSmallM; ++j)
+          if (j < M) sum[(j >> b) & 1] += __expf(static_cast<float>(q[j] - mx[(j >> b) & 1]));
+        lse[0] = mx[0] + log(static_cast<double>(sum[0]));
+        lse[1] = mx[1] + log(static_cast<double>(sum[1]));
+      }
+      llr[n * m + (m - 1 - b)] = static_cast<float>(lse[0] - lse[1]);
+    }
+  }
+}
+
+template <bool MAXLOG>
+int launch_small_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
+                   hipStream_t stream) {
+  const int m = ilog2_pow2(M);
+  int64_t grid = (N + 255) / 256;
+  if (grid > 65536) grid = 65536;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(llr_small_kernel<MAXLOG>, dim3(static_cast<unsigned>(grid)), dim3(256), 0, stream, P.xl, M, m, D,
+                     d_y, N, 1.0 / (2.0 * sigma2), d_llr, P.flags);
+  MD_LAUNCH_CHECK("llr_small_kernel launch");
+  return MD_OK;
+}
+
 // list == nullptr: every symbol; otherwise the list with its length in flags[count_slot].
 template <bool MAXLOG>
 int launch_careful_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
@@ -259,9 +327,9 @@ void score_scales(double sigma2, float* alpha, float* c_over_alpha) {
 
 int launch_llr(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, bool maxlog,
                bool bf16, float* d_llr, hipStream_t stream) {
-  if (M < 32) {
-    return maxlog ? launch_careful_t<true>(P, M, D, d_y, N, sigma2, d_llr, nullptr, 0, stream)
-                  : launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, nullptr, 0, stream);
+  if (M <= kSmallM) {
+    return maxlog ? launch_small_t<true>(P, M, D, d_y, N, sigma2, d_llr, stream)
+                  : launch_small_t<false>(P, M, D, d_y, N, sigma2, d_llr, stream);
   }
   if (maxlog) {
     // max-log never loses range; its list holds only operands outside the FP16 split range

@@ -1,11 +1,14 @@
 // Batched sweep: channel draw, exact LLRs and GMI for many constellations (uneven M and
-// D) at many noise levels, in one persistent kernel launched from a captured hipGraph.
+// D) at many noise levels, in persistent kernels (one per constellation class) launched
+// together from one captured hipGraph.
 //
 // A plan holds one "problem" per (instance, noise level): its label-ordered constellation,
 // its MFMA fragments (which depend on the noise level through the score scales), the
 // channel stream and N.  Each problem is cut into work items of a fixed number of
-// symbol groups; items are ordered by cost (M times K steps, largest first) so that the
-// dynamically scheduled persistent blocks finish together.  For every item a block draws
+// symbol groups; items are grouped by class (K steps and label bits: one tile-loop shape,
+// one kernel instantiation) and ordered by cost (M times K steps, largest first), and the
+// blocks of a class's persistent kernel claim its items dynamically so that they finish
+// together.  For every item a block draws
 // the channel uses itself (the awgn_sample definition at offset = noise index * N), forms
 // the scores and subset sums with the same tile loop as llr_exact, and adds the item's
 // GMI loss sum_n sum_k log2(1 + S_other / S_sent) to a per-item FP64 slot -- LLRs and
@@ -13,7 +16,7 @@
 // queued with their received vector and label and re-evaluated in FP64 by a second kernel,
 // which adds its losses as 2^-40 fixed-point integers (order independent).  A final kernel
 // adds the item slots of each problem in a fixed order: the result is deterministic.
-// The graph: reset -> persistent sweep -> fallback -> final (no memset nodes).
+// The graph: reset -> one persistent kernel per class -> fallback -> final (no memset nodes).
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -242,9 +245,13 @@ __device__ void process_item(const Problem& P, const Item& I, int it, uint4* lds
   }
 }
 
-template <int WAVES, int SB>
+// One persistent kernel per class (K steps, label bits) of the plan: it claims the
+// class's items [item_begin, item_end) through its own counter, so every instantiation
+// carries the registers of one tile-loop shape only.
+template <int WAVES, int SB, int KS, int MBK>
 __global__ void __launch_bounds__(WAVES * 64) sweep_kernel(const Problem* __restrict__ probs,
-                                                           const Item* __restrict__ items, int n_items,
+                                                           const Item* __restrict__ items, int item_begin,
+                                                           int item_end, int* __restrict__ claim,
                                                            int* __restrict__ counters, double* __restrict__ item_sum,
                                                            FbRecord* __restrict__ fb) {
   extern __shared__ uint4 lds[];
@@ -252,29 +259,14 @@ __global__ void __launch_bounds__(WAVES * 64) sweep_kernel(const Problem* __rest
   __shared__ float wsum[WAVES];
   int staged_prob = -1;
   for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(&counters[0], 1);
+    if (threadIdx.x == 0) next = item_begin + atomicAdd(claim, 1);
     __syncthreads();
     const int it = __builtin_amdgcn_readfirstlane(next);     // uniform: scalar loads below
     __syncthreads();
-    if (it >= n_items) break;
+    if (it >= item_end) break;
     const Item I = items[it];
     const Problem P = probs[I.prob];
-    const int key = (P.ks - 1) * 16 + P.m;
-    switch (key) {
-#define MD_SWEEP_CASE(KS_, MB_, MBK_)                                                                    \
-  case (KS_ - 1) * 16 + MB_:                                                                         \
-    process_item<WAVES, SB, KS_, MBK_>(P, I, it, lds, staged_prob, item_sum, fb, counters, wsum);     \
-    break;
-      MD_SWEEP_CASE(1, 4, 5) MD_SWEEP_CASE(1, 5, 5) MD_SWEEP_CASE(1, 6, 6) MD_SWEEP_CASE(1, 7, 7)
-      MD_SWEEP_CASE(1, 8, 8) MD_SWEEP_CASE(1, 9, 9) MD_SWEEP_CASE(1, 10, 10) MD_SWEEP_CASE(1, 11, 11)
-      MD_SWEEP_CASE(1, 12, 12) MD_SWEEP_CASE(1, 13, 13)
-      MD_SWEEP_CASE(2, 4, 5) MD_SWEEP_CASE(2, 5, 5) MD_SWEEP_CASE(2, 6, 6) MD_SWEEP_CASE(2, 7, 7)
-      MD_SWEEP_CASE(2, 8, 8) MD_SWEEP_CASE(2, 9, 9) MD_SWEEP_CASE(2, 10, 10) MD_SWEEP_CASE(2, 11, 11)
-      MD_SWEEP_CASE(2, 12, 12) MD_SWEEP_CASE(2, 13, 13)
-#undef MD_SWEEP_CASE
-      default:
-        break;
-    }
+    process_item<WAVES, SB, KS, MBK>(P, I, it, lds, staged_prob, item_sum, fb, counters, wsum);
   }
 }
 
@@ -348,9 +340,10 @@ __global__ void __launch_bounds__(256) sweep_fallback_kernel(const Problem* __re
   }
 }
 
-__global__ void sweep_reset_kernel(int* __restrict__ counters, unsigned long long* __restrict__ fb_acc, int nprob) {
+__global__ void sweep_reset_kernel(int* __restrict__ counters, int ncounters, unsigned long long* __restrict__ fb_acc,
+                                   int nprob) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < 4) counters[i] = 0;
+  if (i < ncounters) counters[i] = 0;
   if (i < nprob) fb_acc[i] = 0ull;
 }
 
@@ -388,7 +381,14 @@ struct SweepPlan {
   std::vector<Problem> h_probs;
   std::vector<int*> h_flags;
   size_t lds_bytes = 0;
+  // classes of problems with one tile-loop shape: (K steps, label bits) and their item ranges
+  struct Class {
+    int ks, m, begin, end;
+  };
+  std::vector<Class> classes;
 };
+
+constexpr int kCounterBase = 4;    // counters[0..3]: unused, fallback count, overflow, unused
 
 namespace {
 
@@ -412,9 +412,9 @@ void free_plan(SweepPlan* p) {
   delete p;
 }
 
-template <int WAVES, int SB>
-int enqueue_sweep(SweepPlan* p, hipStream_t s) {
-  auto kern = sweep_kernel<WAVES, SB>;
+template <int WAVES, int SB, int KS, int MBK>
+int launch_class(SweepPlan* p, const SweepPlan::Class& c, int ci, hipStream_t s) {
+  auto kern = sweep_kernel<WAVES, SB, KS, MBK>;
   static bool attr_done = false;
   if (!attr_done) {
     // the kernel's static LDS (< 1 KiB) and the dynamic part share the 160 KiB of a CU
@@ -427,12 +427,46 @@ int enqueue_sweep(SweepPlan* p, hipStream_t s) {
   MD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kern), WAVES * 64,
                                                            p->lds_bytes));
   if (occ < 1) occ = 1;
-  hipLaunchKernelGGL(sweep_reset_kernel, dim3((std::max(p->nprob, 4) + 255) / 256), dim3(256), 0, s, p->d_counters,
-                     p->d_fb_acc, p->nprob);
-  MD_LAUNCH_CHECK("sweep_reset_kernel launch");
-  hipLaunchKernelGGL(kern, dim3(ncu * occ), dim3(WAVES * 64), p->lds_bytes, s, p->d_probs, p->d_items, p->n_items,
-                     p->d_counters, p->d_item_sum, p->d_fb);
+  int64_t grid = static_cast<int64_t>(ncu) * occ;
+  if (grid > c.end - c.begin) grid = c.end - c.begin;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(WAVES * 64), p->lds_bytes, s, p->d_probs,
+                     p->d_items, c.begin, c.end, p->d_counters + kCounterBase + ci, p->d_counters, p->d_item_sum,
+                     p->d_fb);
   MD_LAUNCH_CHECK("sweep_kernel launch");
+  return MD_OK;
+}
+
+template <int WAVES, int SB>
+int launch_class_shape(SweepPlan* p, const SweepPlan::Class& c, int ci, hipStream_t s) {
+  const int key = (c.ks - 1) * 16 + c.m;
+  switch (key) {
+#define MD_SWEEP_CASE(KS_, MB_, MBK_) \
+  case (KS_ - 1) * 16 + MB_:        \
+    return launch_class<WAVES, SB, KS_, MBK_>(p, c, ci, s);
+    MD_SWEEP_CASE(1, 4, 5) MD_SWEEP_CASE(1, 5, 5) MD_SWEEP_CASE(1, 6, 6) MD_SWEEP_CASE(1, 7, 7)
+    MD_SWEEP_CASE(1, 8, 8) MD_SWEEP_CASE(1, 9, 9) MD_SWEEP_CASE(1, 10, 10) MD_SWEEP_CASE(1, 11, 11)
+    MD_SWEEP_CASE(1, 12, 12) MD_SWEEP_CASE(1, 13, 13)
+    MD_SWEEP_CASE(2, 4, 5) MD_SWEEP_CASE(2, 5, 5) MD_SWEEP_CASE(2, 6, 6) MD_SWEEP_CASE(2, 7, 7)
+    MD_SWEEP_CASE(2, 8, 8) MD_SWEEP_CASE(2, 9, 9) MD_SWEEP_CASE(2, 10, 10) MD_SWEEP_CASE(2, 11, 11)
+    MD_SWEEP_CASE(2, 12, 12) MD_SWEEP_CASE(2, 13, 13)
+#undef MD_SWEEP_CASE
+    default:
+      return fail(MD_EUNSUPPORTED, "no sweep kernel for this constellation class");
+  }
+}
+
+int enqueue(SweepPlan* p, hipStream_t s) {
+  const int ncounters = kCounterBase + static_cast<int>(p->classes.size());
+  hipLaunchKernelGGL(sweep_reset_kernel, dim3((std::max(p->nprob, ncounters) + 255) / 256), dim3(256), 0, s,
+                     p->d_counters, ncounters, p->d_fb_acc, p->nprob);
+  MD_LAUNCH_CHECK("sweep_reset_kernel launch");
+  for (size_t ci = 0; ci < p->classes.size(); ++ci) {
+    const int st = p->waves == 16 ? launch_class_shape<16, 1>(p, p->classes[ci], static_cast<int>(ci), s)
+                                  : launch_class_shape<8, 2>(p, p->classes[ci], static_cast<int>(ci), s);
+    if (st != MD_OK) return st;
+  }
+  int ncu = 0;
+  MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
   hipLaunchKernelGGL(sweep_fallback_kernel, dim3(ncu * 4), dim3(256), 0, s, p->d_probs, p->d_fb, p->d_counters,
                      p->d_fb_acc);
   MD_LAUNCH_CHECK("sweep_fallback_kernel launch");
@@ -442,25 +476,27 @@ int enqueue_sweep(SweepPlan* p, hipStream_t s) {
   return MD_OK;
 }
 
-int enqueue(SweepPlan* p, hipStream_t s) {
-  if (p->waves == 16) return enqueue_sweep<16, 1>(p, s);
-  return enqueue_sweep<8, 2>(p, s);
-}
-
 // Builds the item list for the plan's launch shape (groups per item gpi).
 int build_items(SweepPlan* p) {
   const int per_group = p->waves * 32 * p->sb;
   const int per_item = per_group * p->gpi;
   std::vector<int> order(static_cast<size_t>(p->nprob));
   for (int i = 0; i < p->nprob; ++i) order[static_cast<size_t>(i)] = i;
+  // by class (K steps, label bits), most expensive class first, then by N
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     const Problem& A = p->h_probs[static_cast<size_t>(a)];
     const Problem& B = p->h_probs[static_cast<size_t>(b)];
-    return static_cast<int64_t>(A.M) * A.ks > static_cast<int64_t>(B.M) * B.ks;
+    const int64_t ca = static_cast<int64_t>(A.M) * A.ks, cb = static_cast<int64_t>(B.M) * B.ks;
+    if (ca != cb) return ca > cb;
+    if (A.ks != B.ks) return A.ks > B.ks;
+    return A.N > B.N;
   });
   std::vector<Item> items;
+  p->classes.clear();
   for (int pi : order) {
     Problem& P = p->h_probs[static_cast<size_t>(pi)];
+    if (p->classes.empty() || p->classes.back().ks != P.ks || p->classes.back().m != P.m)
+      p->classes.push_back(SweepPlan::Class{P.ks, P.m, static_cast<int>(items.size()), static_cast<int>(items.size())});
     P.item_begin = static_cast<int>(items.size());
     for (int64_t s0 = 0; s0 < P.N; s0 += per_item) {
       Item it;
@@ -470,6 +506,7 @@ int build_items(SweepPlan* p) {
       items.push_back(it);
     }
     P.item_end = static_cast<int>(items.size());
+    p->classes.back().end = P.item_end;
   }
   if (items.size() > static_cast<size_t>(1) << 30) return fail(MD_EINVAL, "too many work items");
   p->n_items = static_cast<int>(items.size());
@@ -553,7 +590,7 @@ int sweep_plan_create(const md_sweep_instance* inst, int n_inst, const double* s
   void* q = nullptr;
   if ((st = md::dev_alloc(p, sizeof(md::Problem) * p->nprob, &q))) return bail(st);
   p->d_probs = static_cast<md::Problem*>(q);
-  if ((st = md::dev_alloc(p, sizeof(int) * 4, &q))) return bail(st);
+  if ((st = md::dev_alloc(p, sizeof(int) * (md::kCounterBase + 2 * 16), &q))) return bail(st);
   p->d_counters = static_cast<int*>(q);
   if ((st = md::dev_alloc(p, sizeof(md::FbRecord) * md::kFbCap, &q))) return bail(st);
   p->d_fb = static_cast<md::FbRecord*>(q);

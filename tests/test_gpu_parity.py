@@ -201,6 +201,21 @@ def test_extreme_snr_range_fallback():
     assert_llr_close(L, ref, atol=ATOL, rtol=RTOL, what="extreme snr")
 
 
+@pytest.mark.parametrize("M,D", [(2, 1), (8, 3), (16, 2), (16, 30)])
+def test_small_constellations_far_and_extreme(M, D):
+    """M <= 16 (one thread per symbol, per-subset maxima): far symbols and tiny sigma2."""
+    X, labels = synth.gaussian_constellation(M, D, 40 + M + D)
+    labels = synth.random_labels(M, 3 + M)
+    rng = np.random.default_rng(M + D)
+    y = (rng.standard_normal((700, D)) * 20).astype(np.float32)
+    y[:350] = X[rng.integers(0, M, 350)] + 0.01 * rng.standard_normal((350, D)).astype(np.float32)
+    for s2 in (0.5, 1e-3, 1e-7):
+        L = md().llr_exact(to_dev(X), labels_dev(labels), to_dev(y), s2).cpu().numpy()
+        assert_llr_close(L, oracle.llr_exact(X, labels, y, s2), what=f"small M={M} s2={s2}")
+        Lm = md().llr_maxlog(to_dev(X), labels_dev(labels), to_dev(y), s2).cpu().numpy()
+        assert_llr_close(Lm, oracle.llr_maxlog(X, labels, y, s2), what=f"small max-log M={M} s2={s2}")
+
+
 def test_wide_range_pass_at_high_snr():
     """8D M=2048 at 20 dB: the far subset of about half the symbols lies beyond the first
     exponent window; those symbols take the two-window pass, a few the careful kernel."""
@@ -228,7 +243,7 @@ def test_path_counts_low_snr_and_small_m():
     X, labels = synth.gaussian_constellation(16, 2, 3)
     s2, Xd, tx, y, txh, yh = channel(X, labels, 6.0, 777, 12)
     md().llr_exact(Xd, labels_dev(labels), y, s2)
-    assert md().llr_path_counts() == (0, 777)      # M < 32: the careful kernel for all
+    assert md().llr_path_counts() == (0, 0)        # M <= 16: the one-thread-per-symbol kernel
 
 
 def test_ber_count_and_q_factor():

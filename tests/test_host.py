@@ -1,0 +1,37 @@
+"""Host-side logic that needs no GPU: the benchmark's one-GPU contract, its counter-summary
+reader, and the binding's argument checks that run before any library call."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_counter_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
+    import bench
+    traffic, note = bench.counter_traffic(bench.KERNEL_SOURCES)
+    if traffic is not None:
+        assert traffic > 7e8 and "calibrated" in note
+    # a source list whose hash differs from the summary's gives no traffic figure
+    t2, note2 = bench.counter_traffic(["bench.py"])
+    assert t2 is None and "changed" in note2
+
+
+def test_q_factor_round_trip():
+    import math
+    from paper_2104_06311_amd import q_factor_db
+    for q in (1.0, 3.0, 6.0, 7.5):
+        ber = 0.5 * math.erfc(q / math.sqrt(2.0))
+        assert abs(q_factor_db(ber) - 20 * math.log10(q)) < 1e-9
+    with pytest.raises(ValueError):
+        q_factor_db(0.6)
