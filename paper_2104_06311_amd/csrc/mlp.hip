@@ -34,20 +34,21 @@ namespace {
 
 constexpr float kGeluK2 = 1.5957691216057308f;    // 2 sqrt(2/pi)
 constexpr float kGeluC = 0.044715f;
-constexpr float kLog2e = 1.4426950408889634f;
 
-__device__ __forceinline__ float sigmoidf_fast(float v) {
-  // 1 / (1 + 2^(-v log2 e)); exact limits 0 and 1 for large |v|
-  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-v * kLog2e));
-}
+// The exponent of the sigmoid, -log2(e) 2k (a + c a^3), is evaluated as a (e1 + e2 a^2):
+// two multiplications and one fused multiply-add per activation.
+constexpr float kGeluE1 = static_cast<float>(-1.5957691216057308 * 1.4426950408889634);
+constexpr float kGeluE2 = static_cast<float>(-1.5957691216057308 * 0.044715 * 1.4426950408889634);
+
+// g(a) = a / (1 + 2^(a (e1 + e2 a^2))); exact limits a (a -> +inf) and -0 (a -> -inf)
 __device__ __forceinline__ float gelu(float a) {
-  const float v = kGeluK2 * fmaf(kGeluC * a * a, a, a);
-  return a * sigmoidf_fast(v);
+  const float w = a * fmaf(kGeluE2, a * a, kGeluE1);
+  return a * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(w));
 }
 __device__ __forceinline__ float gelu_grad(float a) {
-  const float v = kGeluK2 * fmaf(kGeluC * a * a, a, a);
-  const float s = sigmoidf_fast(v);
-  const float dv = kGeluK2 * fmaf(3.0f * kGeluC, a * a, 1.0f);
+  const float a2 = a * a;
+  const float s = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(a * fmaf(kGeluE2, a2, kGeluE1)));
+  const float dv = kGeluK2 * fmaf(3.0f * kGeluC, a2, 1.0f);
   return s + a * s * (1.0f - s) * dv;
 }
 __device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
@@ -291,6 +292,19 @@ __device__ __forceinline__ int unit_of_slot(int rb, int q, int kk) {
   return 32 * rb + 8 * (2 * q + (v >> 2)) + 4 * hh + (v & 3);
 }
 
+__device__ __forceinline__ floatx16 zero16() {
+  floatx16 z;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) z[r] = 0.0f;
+  return z;
+}
+// One 32x32x16 BF16 product; the A fragment is read from LDS.
+__device__ __forceinline__ floatx16 mfma_bf16(const uint4& a_lds, const bf16x8& b, const floatx16& c) {
+  bf16x8 a;
+  __builtin_memcpy(&a, &a_lds, 16);
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
 struct InferLayout {
   int H, nrb;
   size_t f1, f2, f3, b2, b3, bytes;    // byte offsets
@@ -373,7 +387,7 @@ __global__ void pack_infer_kernel(const float* __restrict__ w, int D, int H, int
 }
 
 template <int NRB>
-__global__ void __launch_bounds__(512) mlp_infer_kernel(const char* __restrict__ img, InferLayout L, int D, int m,
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))) mlp_infer_kernel(const char* __restrict__ img, InferLayout L, int D, int m,
                                                         const float* __restrict__ y, int64_t N, float in_scale,
                                                         float out_scale, float* __restrict__ llr) {
   extern __shared__ uint4 smem[];
@@ -401,47 +415,66 @@ __global__ void __launch_bounds__(512) mlp_infer_kernel(const char* __restrict__
       const float x = (k < D) ? (live ? y[n * D + k] * in_scale : 0.0f) : (k == D ? 1.0f : 0.0f);
       yb[v] = static_cast<__bf16>(x);
     }
+    // Layer 1 and the first block of layer 2.  The product of hidden block rb + 1 is issued
+    // before the activations of block rb are formed, and each block's activations enter the
+    // first layer-2 accumulation right away, so that matrix products and activations overlap.
     bf16x8 act[NRB][2];
+    floatx16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = b2[8 * (r >> 2) + 4 * h + (r & 3)];
+    floatx16 h1 = mfma_bf16(f1[lane], yb, zero16());
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) {
-      floatx16 acc;
+      floatx16 h1n;
+      if (rb + 1 < NRB) h1n = mfma_bf16(f1[(rb + 1) * 64 + lane], yb, zero16());
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-      bf16x8 a;
-      __builtin_memcpy(&a, &f1[rb * 64 + lane], 16);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, yb, acc, 0, 0, 0);
+      for (int q = 0; q < 2; ++q) {
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int v = 0; v < 8; ++v) act[rb][q][v] = static_cast<__bf16>(gelu(acc[8 * q + v]));
+        for (int v = 0; v < 8; ++v) act[rb][q][v] = static_cast<__bf16>(gelu(h1[8 * q + v]));
+        acc = mfma_bf16(f2[(rb * 2 + q) * 64 + lane], act[rb][q], acc);
+      }
+      if (rb + 1 < NRB) h1 = h1n;
+      __builtin_amdgcn_sched_barrier(0);   // keeps one hidden block in flight (no spills)
     }
-    // layer 2, one block of 32 output units at a time; each block's activations feed the
-    // two layer-3 K steps of that block right away, so only layer 1's activations stay live
+    // Layer 2 block ob is accumulated while the activations of block ob - 1 are formed and
+    // pushed through layer 3.
     floatx16 out;
 #pragma unroll
     for (int r = 0; r < 16; ++r) out[r] = b3[8 * (r >> 2) + 4 * h + (r & 3)];
 #pragma unroll 1
-    for (int ob = 0; ob < NRB; ++ob) {
-      floatx16 acc;
+    for (int ob = 1; ob < NRB; ++ob) {
+      floatx16 nxt;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = b2[32 * ob + 8 * (r >> 2) + 4 * h + (r & 3)];
+      for (int r = 0; r < 16; ++r) nxt[r] = b2[32 * ob + 8 * (r >> 2) + 4 * h + (r & 3)];
+      // all A fragments of this block are requested before the first product, so that LDS
+      // latency is paid once per block rather than once per product
+      const uint4* f2o = f2 + ob * NRB * 2 * 64 + lane;
+      uint4 fa[NRB][2];
 #pragma unroll
       for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          bf16x8 a;
-          __builtin_memcpy(&a, &f2[((ob * NRB + rb) * 2 + q) * 64 + lane], 16);
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, act[rb][q], acc, 0, 0, 0);
-        }
+        for (int q = 0; q < 2; ++q) fa[rb][q] = f2o[(rb * 2 + q) * 64];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) nxt = mfma_bf16(fa[rb][q], act[rb][q], nxt);
+      const uint4* f3o = f3 + (ob - 1) * 2 * 64 + lane;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         bf16x8 act2;
 #pragma unroll
         for (int v = 0; v < 8; ++v) act2[v] = static_cast<__bf16>(gelu(acc[8 * q + v]));
-        bf16x8 a;
-        __builtin_memcpy(&a, &f3[(ob * 2 + q) * 64 + lane], 16);
-        out = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, act2, out, 0, 0, 0);
+        out = mfma_bf16(f3o[q * 64], act2, out);
       }
+      acc = nxt;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      bf16x8 act2;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) act2[v] = static_cast<__bf16>(gelu(acc[8 * q + v]));
+      out = mfma_bf16(f3[((NRB - 1) * 2 + q) * 64 + lane], act2, out);
     }
     if (live) {
 #pragma unroll
