@@ -13,10 +13,12 @@
 // Training: a tiled GEMM (64x64 block tile, v_mfma_f32_32x32x16_bf16) with fused
 // epilogues (bias + GELU storing pre- and post-activation; multiplication by GELU'),
 // a loss kernel that also forms dloss/df, column sums for the bias gradients, and
-// an elementwise Adam kernel.  Inference (llr_learned) for H <= 256: one fused kernel
-// holds all weights in LDS as BF16 MFMA fragments; each wavefront pushes 32 symbols
-// through the three layers, and the hidden units of each layer are ordered so that
-// the MFMA result registers of one layer are directly the B operand of the next.
+// an elementwise Adam kernel.  Inference (llr_learned) for H <= 256 and D <= 15: one fused
+// kernel holds all weights in LDS as BF16 MFMA fragments; each wavefront pushes 32 symbols
+// through the three layers, and the hidden units of each layer are ordered so that the
+// MFMA result registers of one layer are directly the B operand of the next.  For H up to
+// 512 (or D up to 30) the same fragments are used, but the layer-2 weights are streamed
+// through LDS one output block at a time; other shapes use the training GEMMs.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -279,8 +281,8 @@ __global__ void gather_kernel(const float* __restrict__ y, const float* __restri
 
 // ------------------------------------------------------------------ fused inference
 // LDS image (BF16 fragments, built by pack_infer_kernel from the FP32 master weights):
-//   f1[rb][lane]           layer 1, hidden rows 32 rb + lane % 32, K slots 8 (lane/32) .. +7
-//                          of [y (D), 1 (bias), 0 ...]
+//   f1[rb][s][lane]        layer 1, hidden rows 32 rb + lane % 32, K slots 16 s + 8 (lane/32)
+//                          .. +7 of [y (D), 1 (bias), 0 ...], s < ks1 = ceil((D + 1) / 16)
 //   f2[ob][rb][q][lane]    layer 2: output rows 32 ob + lane % 32, input units of K step
 //                          (rb, q) in the order of the layer-1 result registers
 //   f3[rb][q][lane]        layer 3, output rows lane % 32 (rows >= m are zero)
@@ -306,17 +308,18 @@ __device__ __forceinline__ floatx16 mfma_bf16(const uint4& a_lds, const bf16x8& 
 }
 
 struct InferLayout {
-  int H, nrb;
-  size_t f1, f2, f3, b2, b3, bytes;    // byte offsets
+  int H, nrb, ks1;                      // hidden width, H / 32, layer-1 K steps of 16 slots
+  size_t f1, f2, f3, b2, b3, bytes;     // byte offsets
 };
 
-inline InferLayout infer_layout(int H) {
+inline InferLayout infer_layout(int H, int D) {
   InferLayout L;
   L.H = H;
   L.nrb = H / 32;
+  L.ks1 = (D + 1 + 15) / 16;
   size_t o = 0;
   L.f1 = o;
-  o += static_cast<size_t>(L.nrb) * 64 * 16;
+  o += static_cast<size_t>(L.nrb) * L.ks1 * 64 * 16;
   L.f2 = o;
   o += static_cast<size_t>(L.nrb) * L.nrb * 2 * 64 * 16;
   L.f3 = o;
@@ -338,18 +341,19 @@ __global__ void pack_infer_kernel(const float* __restrict__ w, int D, int H, int
   const float* b2 = W2 + static_cast<int64_t>(H) * H;
   const float* W3 = b2 + H;
   const float* b3 = W3 + static_cast<int64_t>(m) * H;
-  const int64_t n1 = static_cast<int64_t>(nrb) * 64;
+  const int64_t n1 = static_cast<int64_t>(nrb) * L.ks1 * 64;
   const int64_t n2 = static_cast<int64_t>(nrb) * nrb * 2 * 64;
   const int64_t n3 = static_cast<int64_t>(nrb) * 2 * 64;
   const int64_t total = n1 + n2 + n3 + H + 32;
   for (int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; t < total;
        t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     if (t < n1) {
-      const int rb = static_cast<int>(t / 64), lane = static_cast<int>(t % 64);
+      const int rb = static_cast<int>(t / (64 * L.ks1)), st = static_cast<int>((t / 64) % L.ks1);
+      const int lane = static_cast<int>(t % 64);
       const int row = 32 * rb + (lane & 31), hh = lane >> 5;
       __bf16 v8[8];
       for (int v = 0; v < 8; ++v) {
-        const int k = 8 * hh + v;
+        const int k = 16 * st + 8 * hh + v;
         const float x = k < D ? W1[static_cast<int64_t>(row) * D + k] : (k == D ? b1[row] : 0.0f);
         v8[v] = static_cast<__bf16>(x);
       }
@@ -475,6 +479,145 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2))
 #pragma unroll
       for (int v = 0; v < 8; ++v) act2[v] = static_cast<__bf16>(gelu(acc[8 * q + v]));
       out = mfma_bf16(f3[((NRB - 1) * 2 + q) * 64 + lane], act2, out);
+    }
+    if (live) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int k = 8 * (r >> 2) + 4 * h + (r & 3);
+        if (k < m) llr[n * m + k] = out[r] * out_scale;
+      }
+    }
+  }
+}
+
+// Inference for wider networks (H up to 512, D up to 31), whose layer-2 weights do not fit
+// in LDS.  A block of 8 wavefronts (256 symbols) keeps layer 1, layer 3 and the biases in
+// LDS and streams the layer-2 fragments one output block (32 rows, 2 H / 32 fragments) at a
+// time through two LDS buffers: while block ob is multiplied out of one buffer, block ob + 1
+// is loaded into the other, with one barrier per block.  The sequence of blocks continues
+// across symbol tiles (block 0 of the next tile follows block NRB - 1), so buffer j mod 2
+// always holds the j-th block of the block's stream.  Layer-1 activations of the
+// wavefront's 32 symbols stay in registers (H / 4 per lane).
+template <int NRB>
+__device__ __forceinline__ void stream_request(const uint4* __restrict__ g2, int ob, uint4 (&pre)[(NRB * 128 + 511) / 512]) {
+  constexpr int kChunk = NRB * 2 * 64;
+#pragma unroll
+  for (int i = 0; i < (kChunk + 511) / 512; ++i) {
+    const int idx = min(static_cast<int>(threadIdx.x) + 512 * i, kChunk - 1);   // in range; stored only if < kChunk
+    pre[i] = g2[static_cast<int64_t>(ob) * kChunk + idx];
+  }
+}
+template <int NRB>
+__device__ __forceinline__ void stream_store(uint4* __restrict__ dst, const uint4 (&pre)[(NRB * 128 + 511) / 512]) {
+  constexpr int kChunk = NRB * 2 * 64;
+#pragma unroll
+  for (int i = 0; i < (kChunk + 511) / 512; ++i) {
+    const int idx = static_cast<int>(threadIdx.x) + 512 * i;
+    if (idx < kChunk) dst[idx] = pre[i];
+  }
+}
+
+template <int NRB, int KS1>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(1, 2)))
+mlp_infer_stream_kernel(const char* __restrict__ img, InferLayout L, int D, int m, const float* __restrict__ y,
+                        int64_t N, float in_scale, float out_scale, float* __restrict__ llr) {
+  constexpr int kChunk = NRB * 2 * 64;              // uint4 per layer-2 output block
+  constexpr int kPre = (kChunk + 511) / 512;
+  extern __shared__ uint4 smem[];
+  const int s1 = NRB * KS1 * 64;                    // layer-1 fragments (uint4)
+  const int s3 = static_cast<int>((L.bytes - L.f3) / 16);   // layer-3 fragments and biases
+  uint4* lf1 = smem;
+  uint4* lf3 = smem + s1;
+  uint4* lch = smem + s1 + s3;                      // two buffers of kChunk
+  const uint4* g1 = reinterpret_cast<const uint4*>(img + L.f1);
+  const uint4* g2 = reinterpret_cast<const uint4*>(img + L.f2);
+  const uint4* g3 = reinterpret_cast<const uint4*>(img + L.f3);
+  for (int i = threadIdx.x; i < s1; i += 512) lf1[i] = g1[i];
+  for (int i = threadIdx.x; i < s3; i += 512) lf3[i] = g3[i];
+  {
+    uint4 pre[kPre];
+    stream_request<NRB>(g2, 0, pre);
+    stream_store<NRB>(lch, pre);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const float* b2 = reinterpret_cast<const float*>(lf3 + NRB * 2 * 64);
+  const float* b3 = b2 + 32 * NRB;
+  const int64_t nbt = (N + 255) / 256;
+  int buf = 0;
+  for (int64_t bt = blockIdx.x; bt < nbt; bt += gridDim.x) {
+    const int64_t n = bt * 256 + wave * 32 + (lane & 31);
+    const bool live = n < N;
+    bf16x8 yb[KS1];
+#pragma unroll
+    for (int st = 0; st < KS1; ++st)
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        const int k = 16 * st + 8 * h + v;
+        const float x = (k < D) ? (live ? y[n * D + k] * in_scale : 0.0f) : (k == D ? 1.0f : 0.0f);
+        yb[st][v] = static_cast<__bf16>(x);
+      }
+    bf16x8 act[NRB][2];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) {
+      floatx16 h1 = zero16();
+#pragma unroll
+      for (int st = 0; st < KS1; ++st) h1 = mfma_bf16(lf1[(rb * KS1 + st) * 64 + lane], yb[st], h1);
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) act[rb][q][v] = static_cast<__bf16>(gelu(h1[8 * q + v]));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    floatx16 out, acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[r] = b3[8 * (r >> 2) + 4 * h + (r & 3)];
+#pragma unroll 1
+    for (int ob = 0; ob < NRB; ++ob) {
+      // the next block of the stream: block ob + 1 of this tile, or block 0 of the next
+      uint4 pre[kPre];
+      stream_request<NRB>(g2, ob + 1 < NRB ? ob + 1 : 0, pre);
+      floatx16 nxt;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) nxt[r] = b2[32 * ob + 8 * (r >> 2) + 4 * h + (r & 3)];
+      const uint4* cb = lch + buf * kChunk + lane;
+#pragma unroll
+      for (int g = 0; g < NRB; g += 4) {
+        // four hidden blocks (eight fragments) requested together
+        uint4 fa[4][2];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            if (g + rb < NRB) fa[rb][q] = cb[((g + rb) * 2 + q) * 64];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            if (g + rb < NRB) nxt = mfma_bf16(fa[rb][q], act[g + rb][q], nxt);
+      }
+      if (ob > 0) {
+        const uint4* f3o = lf3 + (ob - 1) * 2 * 64 + lane;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          bf16x8 act2;
+#pragma unroll
+          for (int v = 0; v < 8; ++v) act2[v] = static_cast<__bf16>(gelu(acc[8 * q + v]));
+          out = mfma_bf16(f3o[q * 64], act2, out);
+        }
+      }
+      acc = nxt;
+      stream_store<NRB>(lch + (buf ^ 1) * kChunk, pre);
+      __syncthreads();
+      buf ^= 1;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      bf16x8 act2;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) act2[v] = static_cast<__bf16>(gelu(acc[8 * q + v]));
+      out = mfma_bf16(lf3[((NRB - 1) * 2 + q) * 64 + lane], act2, out);
     }
     if (live) {
 #pragma unroll
@@ -688,7 +831,7 @@ int infer_gemm(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s)
 
 template <int NRB>
 int infer_fused_t(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s) {
-  const InferLayout L = infer_layout(p->H);
+  const InferLayout L = infer_layout(p->H, p->D);
   auto kern = mlp_infer_kernel<NRB>;
   static bool attr_done = false;
   if (!attr_done) {
@@ -709,11 +852,42 @@ int infer_fused_t(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t
   return MD_OK;
 }
 
+// LDS of the streaming kernel: layer 1, layer 3 + biases, two layer-2 output blocks.
+size_t stream_lds_bytes(const InferLayout& L) {
+  return static_cast<size_t>(L.nrb) * L.ks1 * 1024 + (L.bytes - L.f3) + 2 * static_cast<size_t>(L.nrb) * 2 * 1024;
+}
+
+template <int NRB, int KS1>
+int infer_stream_t(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s) {
+  const InferLayout L = infer_layout(p->H, p->D);
+  auto kern = mlp_infer_stream_kernel<NRB, KS1>;
+  static bool attr_done = false;
+  if (!attr_done) {
+    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   160 * 1024));
+    attr_done = true;
+  }
+  int dev = 0, ncu = 0;
+  MD_HIP_TRY(hipGetDevice(&dev));
+  MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  int64_t grid = ncu;
+  const int64_t btiles = (N + 255) / 256;
+  if (grid > btiles) grid = btiles;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(512), stream_lds_bytes(L), s, p->img, L, p->D,
+                     p->m, d_y, N, p->in_scale, p->out_scale, d_llr);
+  MD_LAUNCH_CHECK("mlp_infer_stream_kernel launch");
+  return MD_OK;
+}
+
+#define MD_STREAM_CASE(NRB_, KS1_) \
+  case NRB_: return infer_stream_t<NRB_, KS1_>(p, d_y, N, d_llr, s);
+
 int infer(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s) {
-  const bool fused = p->H % 32 == 0 && p->H <= 256 && p->D <= 15 && p->m <= 32 &&
-                     infer_layout(p->H).bytes <= 160 * 1024;
-  if (!fused) return infer_gemm(p, d_y, N, d_llr, s);
-  const InferLayout L = infer_layout(p->H);
+  const InferLayout L = infer_layout(p->H, p->D);
+  const bool shape_ok = p->H % 32 == 0 && p->m <= 32;
+  const bool fused = shape_ok && p->H <= 256 && L.ks1 == 1 && L.bytes <= 160 * 1024;
+  const bool stream = shape_ok && !fused && p->H <= 512 && L.ks1 <= 2 && stream_lds_bytes(L) <= 160 * 1024;
+  if (!fused && !stream) return infer_gemm(p, d_y, N, d_llr, s);
   if (!p->img) {
     void* q = nullptr;
     if (hipMalloc(&q, L.bytes) != hipSuccess) {
@@ -727,17 +901,36 @@ int infer(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s) {
     MD_LAUNCH_CHECK("pack_infer_kernel launch");
     p->img_version = p->version;
   }
-  switch (L.nrb) {
-    case 1: return infer_fused_t<1>(p, d_y, N, d_llr, s);
-    case 2: return infer_fused_t<2>(p, d_y, N, d_llr, s);
-    case 3: return infer_fused_t<3>(p, d_y, N, d_llr, s);
-    case 4: return infer_fused_t<4>(p, d_y, N, d_llr, s);
-    case 5: return infer_fused_t<5>(p, d_y, N, d_llr, s);
-    case 6: return infer_fused_t<6>(p, d_y, N, d_llr, s);
-    case 7: return infer_fused_t<7>(p, d_y, N, d_llr, s);
-    default: return infer_fused_t<8>(p, d_y, N, d_llr, s);
+  if (fused) {
+    switch (L.nrb) {
+      case 1: return infer_fused_t<1>(p, d_y, N, d_llr, s);
+      case 2: return infer_fused_t<2>(p, d_y, N, d_llr, s);
+      case 3: return infer_fused_t<3>(p, d_y, N, d_llr, s);
+      case 4: return infer_fused_t<4>(p, d_y, N, d_llr, s);
+      case 5: return infer_fused_t<5>(p, d_y, N, d_llr, s);
+      case 6: return infer_fused_t<6>(p, d_y, N, d_llr, s);
+      case 7: return infer_fused_t<7>(p, d_y, N, d_llr, s);
+      default: return infer_fused_t<8>(p, d_y, N, d_llr, s);
+    }
   }
+  if (L.ks1 == 1) {
+    switch (L.nrb) {
+      MD_STREAM_CASE(9, 1) MD_STREAM_CASE(10, 1) MD_STREAM_CASE(11, 1) MD_STREAM_CASE(12, 1)
+      MD_STREAM_CASE(13, 1) MD_STREAM_CASE(14, 1) MD_STREAM_CASE(15, 1) MD_STREAM_CASE(16, 1)
+      default: break;
+    }
+  } else {
+    switch (L.nrb) {
+      MD_STREAM_CASE(1, 2) MD_STREAM_CASE(2, 2) MD_STREAM_CASE(3, 2) MD_STREAM_CASE(4, 2)
+      MD_STREAM_CASE(5, 2) MD_STREAM_CASE(6, 2) MD_STREAM_CASE(7, 2) MD_STREAM_CASE(8, 2)
+      MD_STREAM_CASE(9, 2) MD_STREAM_CASE(10, 2) MD_STREAM_CASE(11, 2) MD_STREAM_CASE(12, 2)
+      MD_STREAM_CASE(13, 2) MD_STREAM_CASE(14, 2) MD_STREAM_CASE(15, 2) MD_STREAM_CASE(16, 2)
+      default: break;
+    }
+  }
+  return fail(MD_EINVAL, "no inference kernel for this network shape");
 }
+#undef MD_STREAM_CASE
 
 uint32_t crc32(const void* data, size_t n, uint32_t crc = 0) {
   crc = ~crc;

@@ -46,8 +46,12 @@ def cosine(a, b):
 
 @pytest.mark.parametrize("D,H,m,N,scales", [(8, 256, 11, 3001, None), (3, 64, 4, 777, None), (5, 96, 6, 100, None),
                                             (16, 512, 16, 513, None), (8, 40, 11, 64, None),
-                                            (8, 256, 11, 2000, (4.47, 3.1)), (16, 512, 16, 300, (2.5, 0.5))])
+                                            (8, 256, 11, 2000, (4.47, 3.1)), (16, 512, 16, 300, (2.5, 0.5)),
+                                            (8, 288, 11, 1000, None), (20, 64, 5, 700, None), (30, 96, 7, 500, None),
+                                            (15, 256, 16, 257, None)])
 def test_forward_matches_oracle(D, H, m, N, scales):
+    """Fused kernel (H <= 256, D <= 15), weight-streaming kernel (H <= 512 or D up to 30)
+    and the generic-GEMM path (H not a multiple of 32) against the FP64 forward."""
     net = md().MLP(D, H, m, seed=11)
     if scales:
         net.set_scales(*scales)
@@ -146,6 +150,21 @@ def test_training_learns_and_checkpoint_resumes_bit_exactly():
         open(path, "wb").write(bytes(raw))
         with pytest.raises(md().MdemapError):
             md().MLP.load(path)
+
+
+@pytest.mark.parametrize("D,H,m,N", [(16, 512, 16, 200_003), (8, 256, 11, 300_007)])
+def test_forward_many_tiles_per_block(D, H, m, N):
+    """Enough symbols that every block walks several symbol tiles (the streamed layer-2
+    blocks continue from one tile into the next); compared on a strided sample of rows."""
+    net = md().MLP(D, H, m, seed=4)
+    net.set_scales(1.7, 2.0)
+    rng = np.random.default_rng(N)
+    y = rng.standard_normal((N, D)).astype(np.float32)
+    L = md().llr_learned(net, torch.from_numpy(y).cuda()).cpu().numpy()
+    idx = np.concatenate([np.arange(0, N, 61), np.arange(N - 300, N)])
+    ref = oracle.mlp_forward(oracle.MLPParams(*split_params(net.get(0), D, H, m), 1.7, 2.0), y[idx])
+    assert np.all(np.isfinite(L))
+    assert rel_err(L[idx], ref) <= 2e-2 and cosine(L[idx], ref) >= 0.999, (rel_err(L[idx], ref), cosine(L[idx], ref))
 
 
 def test_learned_edge_cases():
