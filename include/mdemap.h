@@ -251,6 +251,68 @@ int sweep_plan_info(const void* plan, int* waves, int* blocks_per_wave, int* gro
 int sweep_run(void* plan, double* d_gmi, int use_graph, void* stream);
 int sweep_plan_destroy(void* plan);
 
+/* ------------------------------------------------------------------ streaming receiver */
+/* Continuous demapping of a host-resident symbol stream, after the paper's real-time
+ * receiver (Experimental setup: ADC buffers moved to the GPU by DMA, several streams
+ * working on different buffers in parallel, events for the dependencies between buffers;
+ * Results: Q-factors from the BER in short bins over 20 s of continuous operation).
+ *
+ * The stream of `total` symbols is cut into buffers of buf_symbols symbols, which go
+ * round-robin to n_streams HIP streams (default priority).  Per buffer, its stream copies
+ * the received symbols (and the sent indices) from host to device, demaps them, counts
+ * the bit errors and the GMI of each statistics bin the buffer touches, and copies the
+ * decisions or the LLRs back to host memory.  Copies and kernels of different buffers
+ * overlap; an event per buffer marks its end: before a stream takes a new buffer the host
+ * waits for that stream's previous buffer (at most n_streams buffers in flight), and the
+ * events give each buffer's latency from the start of its host-to-device copy to the end
+ * of its device-to-host copy.
+ *
+ * Modes:
+ *   MD_RX_HARD   max-log LLRs; the decision is the label whose bit m-1-k is 1 where
+ *                column k is negative, i.e. the label of the nearest constellation point
+ *                (the paper's receiver decides hard).  Output: total uint32 labels.
+ *   MD_RX_EXACT  exact LLRs (llr_exact).  Output: total x m float32 LLRs.
+ * Statistics per bin b (symbols [b bin_symbols, (b+1) bin_symbols) of the stream): bit
+ * errors of the hard decisions (ber_count of the mode's LLRs) and the GMI of the mode's
+ * LLRs (gmi_reduce), each bin's GMI combined from its buffers' pieces in stream order
+ * (deterministic).  Bit errors equal ber_count over the bin; the GMI equals gmi_reduce
+ * over the bin up to the FP64 rounding of combining the pieces.  A bin spans at least one
+ * buffer (bin_symbols >= buf_symbols).
+ *
+ * The host arrays form a ring of N symbols (a looped capture): stream symbol i is
+ * h_y[i mod N] / h_tx[i mod N], and its output goes to h_out[i mod N]; when total > N, N
+ * must be a multiple of buf_symbols.  All host arrays must be pinned (hipHostMalloc, or
+ * torch's pin_memory): pageable memory cannot overlap copies and is rejected. */
+#define MD_RX_HARD  0
+#define MD_RX_EXACT 1
+
+typedef struct {
+  int mode;               /* MD_RX_HARD or MD_RX_EXACT */
+  int n_streams;          /* 1 .. 8 */
+  int64_t buf_symbols;    /* symbols per buffer, 1 .. 2^24 */
+  int64_t bin_symbols;    /* symbols per statistics bin, >= buf_symbols */
+} md_rx_config;
+
+/* Copies the constellation (M x D float32, device) and its labels (M uint32 permutation,
+ * device) and allocates every device buffer of the pipeline (synchronous).  sigma2 is the
+ * noise variance per real dimension that the LLRs assume. */
+int rx_create(const float* d_X, const uint32_t* d_labels, int M, int D, double sigma2, const md_rx_config* cfg,
+              void** out);
+/* Runs `total` stream symbols through the pipeline and returns when all are done.
+ *   h_y            N x D float32 received symbols (pinned host ring)
+ *   h_tx           N uint32 sent point indices (pinned host ring), or NULL: no statistics
+ *   h_out          N uint32 decisions (MD_RX_HARD) or N x m float32 LLRs (MD_RX_EXACT)
+ *                  (pinned host ring), or NULL: nothing copied back
+ *   h_bin_errors   ceil(total / bin_symbols) uint64 bit errors per bin, or NULL
+ *   h_bin_gmi      ceil(total / bin_symbols) doubles, GMI per bin (bits per symbol), or NULL
+ *   h_stats        4 doubles, or NULL: wall seconds, symbols per second, mean and maximum
+ *                  buffer latency in milliseconds
+ * h_bin_errors and h_bin_gmi need h_tx.  Returns MD_OK, MD_EINVAL (NULL or unpinned
+ * array, total < 0, N < 1, ring length not a multiple of buf_symbols), MD_ENOMEM, MD_EHIP. */
+int rx_run(void* rx, const float* h_y, const uint32_t* h_tx, int64_t N, int64_t total, void* h_out,
+           uint64_t* h_bin_errors, double* h_bin_gmi, double* h_stats);
+int rx_destroy(void* rx);
+
 /* ------------------------------------------------------------------ housekeeping */
 /* Frees every internal device workspace (synchronises the device first). */
 int release_cache(void);

@@ -12,7 +12,7 @@ import torch
 
 from ._lib import MdemapError, PREC, check, lib
 
-__all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "release_cache",
+__all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "RxStream", "release_cache",
            "MdemapError",
            "log2_exact"]
 
@@ -278,6 +278,74 @@ def llr_learned(mlp: MLP, y, out=None):
 
 
 # ----------------------------------------------------------------------------- batched sweep
+class RxStream:
+    """Streaming receiver (rx_* in mdemap.h): buffers of a host-resident symbol stream
+    demapped on several HIP streams with overlapping copies and kernels.  X float32 [M, D]
+    and labels int32 [M] on the GPU (copied at creation); mode "hard" (max-log LLRs, nearest-
+    point decisions) or "exact" (exact LLRs)."""
+
+    def __init__(self, X, labels, sigma2: float, mode: str = "hard", n_streams: int = 4,
+                 buf_symbols: int = 1 << 20, bin_symbols: int | None = None):
+        import ctypes
+        from ._lib import RX_MODE, RxConfig
+        _dev(X, "X", torch.float32, 2)
+        _dev(labels, "labels", torch.int32, 1)
+        if mode not in RX_MODE:
+            raise ValueError("mode must be 'hard' or 'exact'")
+        self.M, self.D = X.shape
+        self.m = self.M.bit_length() - 1
+        self.mode = mode
+        self.buf_symbols = int(buf_symbols)
+        self.bin_symbols = int(bin_symbols if bin_symbols is not None else buf_symbols)
+        cfg = RxConfig(RX_MODE[mode], int(n_streams), self.buf_symbols, self.bin_symbols)
+        h = ctypes.c_void_p()
+        check("rx_create", lib().rx_create(_ptr(X), _ptr(labels), self.M, self.D, float(sigma2), ctypes.byref(cfg),
+                                           ctypes.byref(h)))
+        self._h = h
+
+    def run(self, y, tx=None, total: int | None = None, out=None, stats: bool = True):
+        """Runs `total` stream symbols (default: the ring once) from the pinned host ring y
+        float32 [N, D] (and tx int32 [N]); decisions (hard, int32 [N]) or LLRs (exact,
+        float32 [N, m]) go to the pinned host ring `out` if given.  Returns a dict with the
+        per-bin bit errors and GMI (when tx is given) and the run's timing."""
+        import numpy as np
+        for name, t in (("y", y), ("tx", tx), ("out", out)):
+            if t is not None and (t.is_cuda or not t.is_pinned() or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous pinned host tensor")
+        if y.dtype != torch.float32 or y.dim() != 2 or y.shape[1] != self.D:
+            raise ValueError("y must be float32 [N, D]")
+        N = y.shape[0]
+        if tx is not None and (tx.dtype != torch.int32 or tx.shape != (N,)):
+            raise ValueError("tx must be int32 [N]")
+        if out is not None:
+            want = (torch.int32, (N,)) if self.mode == "hard" else (torch.float32, (N, self.m))
+            if out.dtype != want[0] or tuple(out.shape) != want[1]:
+                raise ValueError(f"out must be {want[0]} {list(want[1])}")
+        total = N if total is None else int(total)
+        nb = (total + self.bin_symbols - 1) // self.bin_symbols
+        err = np.zeros(nb, dtype=np.uint64) if tx is not None else None
+        gmi = np.zeros(nb, dtype=np.float64) if tx is not None else None
+        st = np.zeros(4, dtype=np.float64)
+        check("rx_run", lib().rx_run(self._h, y.data_ptr(), tx.data_ptr() if tx is not None else None, N, total,
+                                     out.data_ptr() if out is not None else None,
+                                     err.ctypes.data if err is not None else None,
+                                     gmi.ctypes.data if gmi is not None else None, st.ctypes.data if stats else None))
+        return {"bin_errors": err, "bin_gmi": gmi, "seconds": float(st[0]), "symbols_per_s": float(st[1]),
+                "latency_ms_mean": float(st[2]), "latency_ms_max": float(st[3])}
+
+    def close(self):
+        if self._h is not None:
+            check("rx_destroy", lib().rx_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "_h", None) is not None:
+                lib().rx_destroy(self._h)
+        except Exception:
+            pass
+
+
 class SweepPlan:
     """Batched channel + exact-LLR + GMI sweep over many constellations and noise levels
     (sweep_* in mdemap.h).  instances: list of (X, labels, N, seed) with X float32 [M, D]

@@ -52,6 +52,9 @@ SIGNATURES = {
     "sweep_plan_info": (_I, [_P, _P, _P, _P, _P]),
     "sweep_run": (_I, [_P, _P, _I, _P]),
     "sweep_plan_destroy": (_I, [_P]),
+    "rx_create": (_I, [_P, _P, _I, _I, _D, _P, ctypes.POINTER(ctypes.c_void_p)]),
+    "rx_run": (_I, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P]),
+    "rx_destroy": (_I, [_P]),
     "release_cache": (_I, []),
     "last_error": (ctypes.c_char_p, []),
     "mdemap_version": (_I, []),
@@ -62,6 +65,15 @@ class SweepInstance(ctypes.Structure):
     """md_sweep_instance of mdemap.h."""
     _fields_ = [("d_X", ctypes.c_void_p), ("d_labels", ctypes.c_void_p), ("M", ctypes.c_int), ("D", ctypes.c_int),
                 ("N", ctypes.c_int64), ("seed", ctypes.c_uint64)]
+
+
+class RxConfig(ctypes.Structure):
+    """md_rx_config of mdemap.h."""
+    _fields_ = [("mode", ctypes.c_int), ("n_streams", ctypes.c_int), ("buf_symbols", ctypes.c_int64),
+                ("bin_symbols", ctypes.c_int64)]
+
+
+RX_MODE = {"hard": 0, "exact": 1}
 
 
 class MdemapError(RuntimeError):

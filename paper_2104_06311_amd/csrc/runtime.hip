@@ -155,6 +155,29 @@ int check_labels_once(const uint32_t* d_labels, int M, hipStream_t stream) {
   return MD_OK;
 }
 
+// Frees the workspace and the stage counters of one (current device, stream) pair; the
+// caller has synchronised the stream and is about to destroy it.
+int release_stream_resources(hipStream_t stream) {
+  int dev = 0;
+  int st = current_device(&dev);
+  if (st != MD_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    auto it = g_ws.find({dev, stream});
+    if (it != g_ws.end()) {
+      if (it->second.ptr) MD_HIP_TRY(hipFree(it->second.ptr));
+      g_ws.erase(it);
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_fl_mu);
+  auto it = g_fl.find({dev, stream});
+  if (it != g_fl.end()) {
+    if (it->second.ptr) MD_HIP_TRY(hipFree(it->second.ptr));
+    g_fl.erase(it);
+  }
+  return MD_OK;
+}
+
 int release_workspaces() {
   std::lock_guard<std::mutex> lk(g_ws_mu);
   if (!g_ws.empty()) MD_HIP_TRY(hipDeviceSynchronize());

@@ -16,6 +16,10 @@ Constellations
     scaled in float64 so that the average energy per two real dimensions is 1,
     then rounded once to float32; label = point index.
   * BPSK and Gray QPSK (closed-form test cases).
+  * Square M-QAM (M = 4, 16, 64, 256) with a BRGC label per axis: point (i, q) sits at
+    (2i - L + 1, 2q - L + 1) / sqrt(E) with L = sqrt(M) and E = 2 (L^2 - 1) / 3 (unit
+    energy per 2D), label (g(i) << log2 L) | g(q), g(x) = x ^ (x >> 1); the paper's
+    test signals are QAM formats.
 
 SNR convention: sigma^2 = E_s / (D * SNR_lin), E_s = mean ||x||^2 (so SNR is the
 energy per real dimension over the noise variance per real dimension; for
@@ -49,6 +53,22 @@ def psk8_brgc(phase: float = 0.0):
     X = np.stack([np.cos(th), np.sin(th)], axis=1).astype(np.float32)
     labels = (i ^ (i >> 1)).astype(np.uint32)
     return X, labels
+
+
+def qam_gray(M: int):
+    L = int(round(math.sqrt(M)))
+    if L * L != M or L < 2 or (L & (L - 1)):
+        raise ValueError("square QAM needs M = 4^k")
+    b = L.bit_length() - 1
+    E = 2.0 * (L * L - 1) / 3.0
+    X = np.zeros((M, 2), dtype=np.float64)
+    labels = np.zeros(M, dtype=np.uint32)
+    for i in range(L):
+        for q in range(L):
+            j = i * L + q
+            X[j] = [(2 * i - L + 1) / math.sqrt(E), (2 * q - L + 1) / math.sqrt(E)]
+            labels[j] = ((i ^ (i >> 1)) << b) | (q ^ (q >> 1))
+    return X.astype(np.float32), labels
 
 
 def product_4d_8psk():

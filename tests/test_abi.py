@@ -68,6 +68,31 @@ def test_argument_validation_before_device_work():
     assert L.gmi_reduce(fake, 10, 4, fake, fake, None, None, None, None) == -1
 
 
+def test_receiver_arguments_are_checked_before_device_work():
+    from paper_2104_06311_amd._lib import RxConfig, lib
+    L = lib()
+    fake = ctypes.c_void_p(0x1000)
+    h = ctypes.c_void_p()
+
+    def create(M=16, D=2, s2=0.1, mode=0, streams=2, buf=1000, binsz=1000, cfg=True, out=True):
+        c = RxConfig(mode, streams, buf, binsz)
+        return L.rx_create(fake, fake, M, D, s2, ctypes.byref(c) if cfg else None, ctypes.byref(h) if out else None)
+
+    assert create(out=False) == -1
+    assert create(cfg=False) == -1
+    assert create(M=48) == -2
+    assert create(D=0) == -4 and create(D=31) == -4
+    for s2 in (0.0, -1.0, float("nan"), float("inf")):
+        assert create(s2=s2) == -1
+    assert create(mode=2) == -1
+    assert create(streams=0) == -1 and create(streams=9) == -1
+    assert create(buf=0) == -1 and create(buf=(1 << 24) + 1, binsz=1 << 25) == -1
+    assert create(buf=1000, binsz=999) == -1
+    assert b"bin_symbols" in L.last_error()
+    assert L.rx_run(None, fake, None, 10, 10, None, None, None, None) == -1
+    assert L.rx_destroy(None) == 0
+
+
 def test_no_device_is_reported_not_crashed():
     import torch
     if torch.cuda.is_available():

@@ -35,3 +35,20 @@ def test_q_factor_round_trip():
         assert abs(q_factor_db(ber) - 20 * math.log10(q)) < 1e-9
     with pytest.raises(ValueError):
         q_factor_db(0.6)
+
+
+def test_qam_gray_inputs():
+    """Square Gray QAM of the input generator: unit energy per 2D, a permutation of labels,
+    and neighbours on the grid differ in exactly one label bit."""
+    import numpy as np
+    import synth
+    for M in (4, 16, 64, 256):
+        X, labels = synth.qam_gray(M)
+        assert abs(float((X.astype(np.float64) ** 2).sum(1).mean()) - 1.0) < 1e-6
+        assert sorted(labels.tolist()) == list(range(M))
+        L = int(round(M ** 0.5))
+        for i in range(L):
+            for q in range(L):
+                j = i * L + q
+                for jj in ([(i + 1) * L + q] if i + 1 < L else []) + ([i * L + q + 1] if q + 1 < L else []):
+                    assert bin(int(labels[j]) ^ int(labels[jj])).count("1") == 1
