@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--learn-pairs", type=int, default=1 << 24, help="training pairs per SNR point")
     ap.add_argument("--batch-insts", type=int, default=64, help="instances in the batched-sweep object")
     ap.add_argument("--learn-pairs-16d", type=int, default=1 << 22, help="training pairs per SNR point, 16D")
+    ap.add_argument("--rx-seconds", type=float, default=4.0,
+                    help="length of each streaming-receiver run (the paper's traces last 20 s)")
     return ap.parse_args()
 
 
@@ -205,6 +207,57 @@ def extra_16d(md, steps, pairs):
                            "learned_speedup_vs_exact": t_ex / t_ln, "train_steps": steps, "train_pairs": pairs,
                            "train_s": train_s}
     return {"workload": "16d_m65536_gauss", "N_per_snr": N, "per_snr": res}
+
+
+def extra_rx(md, seconds):
+    """Streaming receiver: sustained symbols/s of a looped capture held in pinned host memory
+    (16 buffers of 2^20 symbols), buffers on 4 HIP streams, decisions or LLRs copied back to
+    pinned host memory, statistics in bins of 21 x 2^20 symbols (about the paper's 21 ms
+    bins at its 1 GBaud).  Every symbol crosses PCIe both ways inside the timed run."""
+    import math
+    import numpy as np
+    import torch
+    import synth
+    B = 1 << 20
+    ring = 16 * B
+    X8, l8 = synth.gaussian_constellation(2048, 8, seed=synth.SEED_BASE + 1)
+    X2, l2 = synth.qam_gray(16)
+    cases = [("8d_m2048_exact_9dB", X8, l8, 9.0, "exact"), ("8d_m2048_hard_9dB", X8, l8, 9.0, "hard"),
+             ("2d_qam16_gray_hard_12dB", X2, l2, 12.0, "hard")]
+    res = {}
+    for name, X, labels, snr, mode in cases:
+        s2 = synth.sigma2_from_snr_db(X, snr)
+        Xd = torch.from_numpy(X).cuda()
+        Ld = torch.from_numpy(labels.astype(np.int32)).cuda()
+        M, D = X.shape
+        m = M.bit_length() - 1
+        tx, y = md.awgn_sample(Xd, 4242, 0, ring, math.sqrt(s2))
+        y_h, tx_h = y.cpu().pin_memory(), tx.cpu().pin_memory()
+        del tx, y
+        out_h = (torch.empty(ring, dtype=torch.int32) if mode == "hard"
+                 else torch.empty((ring, m), dtype=torch.float32)).pin_memory()
+        rx = md.RxStream(Xd, Ld, s2, mode=mode, n_streams=4, buf_symbols=B, bin_symbols=21 * B)
+        rx.run(y_h, tx_h, total=4 * B, out=out_h)                       # warm-up
+        probe = rx.run(y_h, tx_h, total=ring, out=out_h)
+        total = max(ring, int(probe["symbols_per_s"] * seconds) // B * B)
+        r = rx.run(y_h, tx_h, total=total, out=out_h)
+        rx.close()
+        nbins = len(r["bin_errors"])
+        per_bin = [min(21 * B, total - b * 21 * B) for b in range(nbins)]
+        ber = [float(e) / (n * m) for e, n in zip(r["bin_errors"], per_bin)]
+        q = [md.q_factor_db(b) for b in ber if 0.0 < b < 0.5]
+        h2d = 4 * D + 4
+        d2h = 4 if mode == "hard" else 4 * m
+        res[name] = {"mode": mode, "M": M, "D": D, "symbols": total, "seconds": r["seconds"],
+                     "symbols_per_s": r["symbols_per_s"], "vs_1_gbaud": r["symbols_per_s"] / 1e9,
+                     "pcie_gb_per_s": r["symbols_per_s"] * (h2d + d2h) / 1e9,
+                     "bytes_per_symbol_h2d_d2h": [h2d, d2h],
+                     "latency_ms_mean": r["latency_ms_mean"], "latency_ms_max": r["latency_ms_max"],
+                     "bins": nbins, "ber": float(sum(int(e) for e in r["bin_errors"]) / (total * m)),
+                     "q_db_min": min(q) if q else None, "q_db_mean": float(np.mean(q)) if q else None,
+                     "gmi_mean": float(np.mean(r["bin_gmi"]))}
+        del y_h, tx_h, out_h
+    return {"buffers": "16 x 2^20 symbols, 4 streams, pinned host ring", "per_case": res}
 
 
 def counter_traffic(kernel_sources):
@@ -379,6 +432,7 @@ def main():
         torch.cuda.empty_cache()
         out["detail"]["batched"] = extra_batched(md, args.batch_insts)
         out["detail"]["16d"] = extra_16d(md, args.learn_steps_16d, args.learn_pairs_16d)
+        out["detail"]["rx_stream"] = extra_rx(md, args.rx_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl.X, wl.labels, 9.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)
