@@ -112,9 +112,9 @@ int awgn_sample(const float* d_X, int M, int D, uint64_t seed, uint64_t offset, 
  *   d_llr     out: N x m float32
  * Symbols whose subset sums leave the FP32 range in the first pass (a subset's best
  * point more than 196 base-2 units below the bias; high SNR) are evaluated again in
- * two exponent windows, and what neither window holds by a per-subset-maximum FP64
- * evaluation, so every finite input gives finite LLRs (llr_path_counts reports how
- * many symbols took each stage).
+ * two exponent windows (down to 386 units), what those miss in three (576 units), and
+ * what is still left by a per-subset-maximum FP64 evaluation, so every finite input
+ * gives finite LLRs (llr_path_counts reports how many symbols took each stage).
  * Returns MD_OK (N = 0 enqueues nothing), MD_EINVAL, MD_ENOTPOW2, MD_ELABEL,
  * MD_EDIM, MD_ENOMEM, MD_EHIP. */
 int llr_exact(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y,
@@ -127,8 +127,8 @@ int llr_maxlog(const float* d_X, const uint32_t* d_labels, int M, int D, const f
 
 /* llr_path_counts -- waits for `stream` and reports, for the last llr_exact or
  * llr_maxlog call enqueued on it from this process, how many symbols the wide-range
- * second pass took (*n_wide; exact only) and how many the FP64 careful kernel took
- * (*n_careful).  Constellations of M <= 16 points take a one-thread-per-symbol kernel and
+ * passes took (*n_wide, the symbols entering the two-window pass; exact only) and how
+ * many the FP64 careful kernel took (*n_careful).  Constellations of M <= 16 points take a one-thread-per-symbol kernel and
  * report 0 and 0.  Both are 0 if no call was made on the stream since the last
  * release_cache.  Returns MD_OK, MD_EINVAL, MD_EHIP. */
 int llr_path_counts(void* stream, int64_t* n_wide, int64_t* n_careful);

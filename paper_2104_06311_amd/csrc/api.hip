@@ -96,14 +96,14 @@ int llr_path_counts(void* stream, int64_t* n_wide, int64_t* n_careful) {
   st = md::last_call(s, &lc, &flags);
   if (st != MD_OK) return st;
   if (!lc.valid || !flags) return MD_OK;
-  int h[4] = {0, 0, 0, 0};
+  int h[5] = {0, 0, 0, 0, 0};
   MD_HIP_TRY(hipMemcpyAsync(h, flags, sizeof(h), hipMemcpyDeviceToHost, s));
   MD_HIP_TRY(hipStreamSynchronize(s));
   if (lc.maxlog) {
     *n_careful = h[1];
   } else {
     *n_wide = h[1];
-    *n_careful = h[3];
+    *n_careful = h[4];
   }
   return MD_OK;
 }

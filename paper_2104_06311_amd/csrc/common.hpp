@@ -78,9 +78,11 @@ struct Prepared {
   const float* xl;          // M x D float32, row s = point with label s
   const uint4* frag;        // MFMA A-operand fragments (see prep.hip)
   int* flags;               // [0] labels invalid, [1] first fallback count, [2] constellation
-                            // outside the FP16 split range, [3] second fallback count
-  unsigned* fb_list;        // symbols the fast pass could not finish (capacity N)
-  unsigned* fb_list2;       // symbols left for the careful kernel after the wide pass (capacity N)
+                            // outside the FP16 split range, [3] second fallback count,
+                            // [4] third fallback count (8 ints)
+  unsigned* fb_list;        // symbols the fast pass could not finish (capacity N); after the
+                            // second pass it is reused for the third list (careful kernel)
+  unsigned* fb_list2;       // symbols left after the two-window pass (capacity N)
   int ks;                   // number of 16-slot K steps of the fragment
   float alpha;              // power-of-two operand balance a
   float c_over_alpha;       // c / a, c = log2(e) / (2 sigma2)
@@ -89,7 +91,7 @@ struct Prepared {
 // Builds the label-ordered copy, fragments and flags for one call.  `ws` must point
 // at a workspace of at least prep_bytes(M, D, N) bytes.
 size_t prep_bytes(int M, int D, int64_t N);
-// `flags` (4 ints) may be given by the caller; otherwise they are carved from ws.
+// `flags` (8 ints) may be given by the caller; otherwise they are carved from ws.
 int prepare(const float* d_X, const uint32_t* d_labels, int M, int D, int64_t N, float alpha,
             float c_over_alpha, char* ws, hipStream_t stream, Prepared* out, int* flags = nullptr);
 

@@ -342,7 +342,9 @@ int launch_llr(const Prepared& P, int M, int D, const float* d_y, int64_t N, dou
   if (st != MD_OK) return st;
   st = launch_wide_exact(P, M, D, d_y, d_llr, stream);
   if (st != MD_OK) return st;
-  return launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, P.fb_list2, 3, stream);
+  st = launch_wide3_exact(P, M, D, d_y, d_llr, stream);
+  if (st != MD_OK) return st;
+  return launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, P.fb_list, 4, stream);
 }
 
 int launch_llr_careful_all(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, bool maxlog,

@@ -432,24 +432,24 @@ int launch_fast_m(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
   }
 }
 
-// ------------------------------------------------------------------ wide-range pass
-// Second pass of the exact path over the symbols the first pass listed.  Every symbol is
-// evaluated in two exponent windows at once, e = 2^(t + kExpBias) and
-// e' = 2^(t + kExpBias + kWideShift) (the two symbol blocks of tile_loop carry the same
-// symbols with the two biases).  Every partial sum holds points of one label subset
-// only, so each subset sum is taken from the window in which it kept its range: a
-// subset that underflowed in the first window (best point more than 196 units below the
-// bias) is exact in the second as long as its best point lies less than 196 + kWideShift
-// units below.  Symbols with neither window in range (or operands outside the FP16
-// split range) go on to the careful kernel through the second list.
+// ------------------------------------------------------------------ wide-range passes
+// Later passes of the exact path over the symbols an earlier pass listed.  Every symbol is
+// evaluated in NW exponent windows at once, e_w = 2^(t + kExpBias + w kWideShift) for
+// w < NW (the NW symbol blocks of tile_loop carry the same symbols with the NW biases).
+// Every partial sum holds points of one label subset only, so each subset sum is taken
+// from the first window in which it kept its range: window w covers subsets whose best
+// point lies less than 196 + w kWideShift units below the bias (and not so close to it
+// that the window overflows).  The second pass uses two windows (best points down to
+// 386 units), the third three (576 units).  Symbols with a subset in no window (or
+// operands outside the FP16 split range) go on through list_out.
 constexpr float kWideShift = 190.0f;
 
-template <int KS, int WAVES, int MB>
+template <int KS, int WAVES, int MB, int NW>
 __global__ void __launch_bounds__(WAVES * 64) llr_wide_kernel(const uint4* __restrict__ frag, int ntiles,
                                                               int chunk_tiles, int D,
                                                               const float* __restrict__ y, float cb, float cn,
                                                               float alpha, float* __restrict__ llr,
-                                                              int* __restrict__ flags,
+                                                              int* __restrict__ flags, int slot_in, int slot_out,
                                                               const unsigned* __restrict__ list_in,
                                                               unsigned* __restrict__ list_out) {
   constexpr int m = MB;
@@ -459,26 +459,26 @@ __global__ void __launch_bounds__(WAVES * 64) llr_wide_kernel(const uint4* __res
   const int wave = threadIdx.x >> 6;
   const int h = lane >> 5;
   const bool range_bad = flags[2] != 0;
-  const int64_t count = flags[1];
+  const int64_t count = flags[slot_in];
   const int64_t per_group = static_cast<int64_t>(WAVES) * 32;
   const int64_t ngroups = (count + per_group - 1) / per_group;
   const int nchunks = (ntiles + chunk_tiles - 1) / chunk_tiles;
   const int frag_per_tile = KS * 64;
-  _Float16* bst = reinterpret_cast<_Float16*>(lds + chunk_tiles * frag_per_tile) + wave * 2 * 32 * S;
+  _Float16* bst = reinterpret_cast<_Float16*>(lds + chunk_tiles * frag_per_tile) + wave * NW * 32 * S;
   bool staged = false;
 
   for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
     const int64_t item = g * per_group + static_cast<int64_t>(wave) * 32 + (lane & 31);
     const bool live = item < count;
     const int64_t n = live ? static_cast<int64_t>(list_in[item]) : 0;
-    half8 bf[2][KS];
-    SymAcc<MB> ac[2];
+    half8 bf[NW][KS];
+    SymAcc<MB> ac[NW];
     bool bad = range_bad;
 #pragma unroll
-    for (int w = 0; w < 2; ++w)
+    for (int w = 0; w < NW; ++w)
       bad |= build_symbol_operand<KS>(bst + (w * 32 + (lane & 31)) * S, y, n, live, D, cb, cn, alpha,
-                                      kExpBias + (w ? kWideShift : 0.0f), bf[w]);
-    acc_init<MB, 2, false>(ac);
+                                      kExpBias + w * kWideShift, bf[w]);
+    acc_init<MB, NW, false>(ac);
     for (int ch = 0; ch < nchunks; ++ch) {
       const int t0 = ch * chunk_tiles;
       const int tn = min(chunk_tiles, ntiles - t0);
@@ -490,11 +490,11 @@ __global__ void __launch_bounds__(WAVES * 64) llr_wide_kernel(const uint4* __res
         __syncthreads();
         staged = true;
       }
-      tile_loop<KS, MB, 2, false>(lds, t0, tn, lane, bf, ac);
+      tile_loop<KS, MB, NW, false>(lds, t0, tn, lane, bf, ac);
     }
-    float S0[2][MB], S1[2][MB];
+    float S0[NW][MB], S1[NW][MB];
 #pragma unroll
-    for (int w = 0; w < 2; ++w) combine_subsets<MB, false>(ac[w], false, S0[w], S1[w]);
+    for (int w = 0; w < NW; ++w) combine_subsets<MB, false>(ac[w], false, S0[w], S1[w]);
     const bool badp = __shfl_xor(static_cast<int>(bad), 32, 64) != 0;
     if (h == 0 && live) {
       float l2[2][MB];
@@ -503,16 +503,22 @@ __global__ void __launch_bounds__(WAVES * 64) llr_wide_kernel(const uint4* __res
       for (int b = 0; b < MB; ++b) {
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
-          const float a0 = v ? S1[0][b] : S0[0][b];
-          const float a1 = v ? S1[1][b] : S0[1][b];
-          const bool in0 = a0 >= 0x1p-96f && a0 <= 0x1p+126f;
-          const bool in1 = a1 >= 0x1p-96f && a1 <= 0x1p+126f;
-          ok = ok && (in0 || in1);
-          l2[v][b] = in0 ? log2f(a0) : log2f(a1) - kWideShift;
+          // the first window (in order) that kept the subset sum in range
+          bool found = false;
+          float val = 0.0f;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) {
+            const float a = v ? S1[w][b] : S0[w][b];
+            const bool in = a >= 0x1p-96f && a <= 0x1p+126f;
+            val = (!found && in) ? log2f(a) - w * kWideShift : val;
+            found = found || in;
+          }
+          ok = ok && found;
+          l2[v][b] = val;
         }
       }
       if (!ok) {
-        const int idx = atomicAdd(&flags[3], 1);
+        const int idx = atomicAdd(&flags[slot_out], 1);
         list_out[idx] = static_cast<unsigned>(n);
       } else {
 #pragma unroll
@@ -525,18 +531,19 @@ __global__ void __launch_bounds__(WAVES * 64) llr_wide_kernel(const uint4* __res
   }
 }
 
-template <int KS, int WAVES, int MB>
-int launch_wide_t(const Prepared& P, int M, const float* d_y, int D, float* d_llr, hipStream_t stream) {
+template <int KS, int WAVES, int MB, int NW>
+int launch_wide_t(const Prepared& P, int M, const float* d_y, int D, float* d_llr, int slot_in, int slot_out,
+                  const unsigned* list_in, unsigned* list_out, hipStream_t stream) {
   const int ntiles = M / 32;
   const int frag_tile_bytes = KS * 64 * 16;
-  const int bstage = WAVES * 2 * bstage_bytes<KS>();
+  const int bstage = WAVES * NW * bstage_bytes<KS>();
   int chunk_tiles = (160 * 1024 - bstage) / frag_tile_bytes;
   constexpr int G = Geo<MB>::G;
   chunk_tiles -= chunk_tiles % G;
   if (chunk_tiles > ntiles) chunk_tiles = ntiles;
   if (chunk_tiles < G) return fail(MD_EUNSUPPORTED, "constellation fragments do not fit in LDS");
   const size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
-  auto kern = llr_wide_kernel<KS, WAVES, MB>;
+  auto kern = llr_wide_kernel<KS, WAVES, MB, NW>;
   static bool attr_done = false;
   if (!attr_done) {
     MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -551,38 +558,41 @@ int launch_wide_t(const Prepared& P, int M, const float* d_y, int D, float* d_ll
   const double c = P.c_over_alpha * static_cast<double>(P.alpha);
   const float cb = static_cast<float>(2.0 * c / P.alpha);
   hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(ncu)), dim3(WAVES * 64), lds_bytes, stream, P.frag, ntiles,
-                     chunk_tiles, D, d_y, cb, P.c_over_alpha, P.alpha, d_llr, P.flags, P.fb_list, P.fb_list2);
+                     chunk_tiles, D, d_y, cb, P.c_over_alpha, P.alpha, d_llr, P.flags, slot_in, slot_out, list_in,
+                     list_out);
   MD_LAUNCH_CHECK("llr_wide_kernel launch");
   return MD_OK;
 }
 
-template <int KS>
-int launch_wide_m(const Prepared& P, int M, const float* d_y, int D, float* d_llr, hipStream_t stream) {
+template <int KS, int NW>
+int launch_wide_m(const Prepared& P, int M, const float* d_y, int D, float* d_llr, int slot_in, int slot_out,
+                  const unsigned* list_in, unsigned* list_out, hipStream_t stream) {
+  // three windows need about 1.5 times the accumulators of two: four wavefronts per block
+  // (one per SIMD) leave each wavefront the whole register file, so that what does not fit
+  // in the 256 architectural registers spills to accumulation registers, not to memory
+  constexpr int WAVES = NW > 2 ? 4 : 8;
+#define MD_WIDE_CASE(MB_)                                                                                   \
+  case MB_:                                                                                                 \
+    return launch_wide_t<KS, WAVES, MB_, NW>(P, M, d_y, D, d_llr, slot_in, slot_out, list_in, list_out, stream);
   switch (ilog2_pow2(M)) {
-    case 5: return launch_wide_t<KS, 8, 5>(P, M, d_y, D, d_llr, stream);
-    case 6: return launch_wide_t<KS, 8, 6>(P, M, d_y, D, d_llr, stream);
-    case 7: return launch_wide_t<KS, 8, 7>(P, M, d_y, D, d_llr, stream);
-    case 8: return launch_wide_t<KS, 8, 8>(P, M, d_y, D, d_llr, stream);
-    case 9: return launch_wide_t<KS, 8, 9>(P, M, d_y, D, d_llr, stream);
-    case 10: return launch_wide_t<KS, 8, 10>(P, M, d_y, D, d_llr, stream);
-    case 11: return launch_wide_t<KS, 8, 11>(P, M, d_y, D, d_llr, stream);
-    case 12: return launch_wide_t<KS, 8, 12>(P, M, d_y, D, d_llr, stream);
-    case 13: return launch_wide_t<KS, 8, 13>(P, M, d_y, D, d_llr, stream);
-    case 14: return launch_wide_t<KS, 8, 14>(P, M, d_y, D, d_llr, stream);
-    case 15: return launch_wide_t<KS, 8, 15>(P, M, d_y, D, d_llr, stream);
-    default: return launch_wide_t<KS, 8, 16>(P, M, d_y, D, d_llr, stream);
+    MD_WIDE_CASE(5) MD_WIDE_CASE(6) MD_WIDE_CASE(7) MD_WIDE_CASE(8) MD_WIDE_CASE(9) MD_WIDE_CASE(10)
+    MD_WIDE_CASE(11) MD_WIDE_CASE(12) MD_WIDE_CASE(13) MD_WIDE_CASE(14) MD_WIDE_CASE(15)
+    default: MD_WIDE_CASE(16)
   }
+#undef MD_WIDE_CASE
 }
 
-template <int UNUSED = 0>
-int launch_wide(const Prepared& P, int M, int D, const float* d_y, float* d_llr, hipStream_t stream) {
+// NW = 2: the second pass (list 1 -> list 2); NW = 3: the third pass (list 2 -> list 3).
+template <int NW>
+int launch_wide(const Prepared& P, int M, int D, const float* d_y, float* d_llr, int slot_in, int slot_out,
+                const unsigned* list_in, unsigned* list_out, hipStream_t stream) {
   switch (P.ks) {
-    case 1: return launch_wide_m<1>(P, M, d_y, D, d_llr, stream);
-    case 2: return launch_wide_m<2>(P, M, d_y, D, d_llr, stream);
-    case 3: return launch_wide_m<3>(P, M, d_y, D, d_llr, stream);
-    case 4: return launch_wide_m<4>(P, M, d_y, D, d_llr, stream);
-    case 5: return launch_wide_m<5>(P, M, d_y, D, d_llr, stream);
-    default: return launch_wide_m<6>(P, M, d_y, D, d_llr, stream);
+    case 1: return launch_wide_m<1, NW>(P, M, d_y, D, d_llr, slot_in, slot_out, list_in, list_out, stream);
+    case 2: return launch_wide_m<2, NW>(P, M, d_y, D, d_llr, slot_in, slot_out, list_in, list_out, stream);
+    case 3: return launch_wide_m<3, NW>(P, M, d_y, D, d_llr, slot_in, slot_out, list_in, list_out, stream);
+    case 4: return launch_wide_m<4, NW>(P, M, d_y, D, d_llr, slot_in, slot_out, list_in, list_out, stream);
+    case 5: return launch_wide_m<5, NW>(P, M, d_y, D, d_llr, slot_in, slot_out, list_in, list_out, stream);
+    default: return launch_wide_m<6, NW>(P, M, d_y, D, d_llr, slot_in, slot_out, list_in, list_out, stream);
   }
 }
 

@@ -22,8 +22,10 @@ int launch_fast_maxlog(const Prepared& P, int M, int D, const float* d_y, int64_
                        float* d_llr, hipStream_t stream);
 int launch_fast_bf16(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr,
                      hipStream_t stream);
-// Wide-range second pass over the first fallback list (exact LLRs).
+// Wide-range second pass over the first fallback list and third pass over the second
+// (exact LLRs; two and three exponent windows).
 int launch_wide_exact(const Prepared& P, int M, int D, const float* d_y, float* d_llr, hipStream_t stream);
+int launch_wide3_exact(const Prepared& P, int M, int D, const float* d_y, float* d_llr, hipStream_t stream);
 int launch_llr_careful_all(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2,
                            bool maxlog, float* d_llr, hipStream_t stream);
 

@@ -32,7 +32,7 @@ constexpr int kMaxSlots = 96;   // 16 * frag_ksteps(30)
 __global__ void prep_init_kernel(uint32_t* __restrict__ inv, int M, int* __restrict__ flags) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s < M) inv[s] = 0xFFFFFFFFu;
-  if (s < 4) flags[s] = 0;
+  if (s < 8) flags[s] = 0;
 }
 
 __global__ void prep_scatter_kernel(const uint32_t* __restrict__ labels, int M, uint32_t* __restrict__ inv,
@@ -117,7 +117,7 @@ size_t prep_bytes(int M, int D, int64_t N) {
   b += carve_size(sizeof(float) * static_cast<size_t>(M) * D);                 // xl
   b += carve_size(sizeof(uint4) * static_cast<size_t>(Mpad / 32) * KS * 64);      // frag
   b += carve_size(sizeof(uint32_t) * M);                                       // inv
-  b += carve_size(sizeof(int) * 4);                                            // flags
+  b += carve_size(sizeof(int) * 8);                                            // flags
   b += 2 * carve_size(sizeof(unsigned) * static_cast<size_t>(N > 0 ? N : 1)); // fallback lists
   return b;
 }
@@ -130,7 +130,7 @@ int prepare(const float* d_X, const uint32_t* d_labels, int M, int D, int64_t N,
   float* xl = cv.take<float>(static_cast<size_t>(M) * D);
   uint4* frag = cv.take<uint4>(static_cast<size_t>(Mpad / 32) * KS * 64);
   uint32_t* inv = cv.take<uint32_t>(M);
-  int* flags_carved = cv.take<int>(4);
+  int* flags_carved = cv.take<int>(8);
   int* flags = flags_given ? flags_given : flags_carved;
   unsigned* fb = cv.take<unsigned>(static_cast<size_t>(N > 0 ? N : 1));
   unsigned* fb2 = cv.take<unsigned>(static_cast<size_t>(N > 0 ? N : 1));

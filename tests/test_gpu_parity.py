@@ -235,6 +235,36 @@ def test_wide_range_pass_at_high_snr():
     assert_llr_close(Lm.cpu().numpy(), oracle.llr_maxlog(X, labels, yh, s2), what="max-log 20 dB")
 
 
+def test_three_window_pass_at_very_high_snr():
+    """8D M=2048 at 24 dB: most symbols have a subset whose best point lies 196 to 576
+    base-2 units below the bias.  They take the two- and three-window passes; only a
+    subset beyond 576 units would need the FP64 kernel.  The stage counts are checked
+    against the per-subset best scores, found here by brute force in FP64."""
+    X, labels = synth.gaussian_constellation(2048, 8, synth.SEED_BASE + 1)
+    s2, Xd, tx, y, txh, yh = channel(X, labels, 24.0, 3000, 13)
+    ld = labels_dev(labels)
+    L = md().llr_exact(Xd, ld, y, s2)
+    n_wide, n_careful = md().llr_path_counts()
+    ref = oracle.llr_exact(X, labels, yh, s2)
+    assert_llr_close(L.cpu().numpy(), ref, what="three-window pass")
+    assert abs(md().gmi_reduce(L, tx, ld)[0].item() - oracle.gmi(ref, txh, labels)[0]) <= 1e-4
+    # worst per-subset best score of every symbol, in base-2 units
+    c = math.log2(math.e) / (2.0 * s2)
+    Xf = X.astype(np.float64)
+    d2 = (yh.astype(np.float64) ** 2).sum(1)[:, None] - 2.0 * yh.astype(np.float64) @ Xf.T + (Xf ** 2).sum(1)[None, :]
+    t = -c * d2
+    lab = labels.astype(np.int64)
+    worst = np.zeros(len(yh))
+    for b in range(11):
+        bit = (lab >> b) & 1
+        worst = np.minimum(worst, np.minimum(t[:, bit == 0].max(1), t[:, bit == 1].max(1)))
+    print(f"24 dB: wide {n_wide}, careful {n_careful}, beyond 196: {(worst < -196).sum()}, "
+          f"beyond 386: {(worst < -386).sum()}, beyond 576: {(worst < -576).sum()}", flush=True)
+    assert (worst < -386).sum() > 100            # the three-window pass has work
+    assert (worst < -206).sum() <= n_wide <= (worst < -186).sum()
+    assert n_careful <= (worst < -566).sum()
+
+
 def test_path_counts_low_snr_and_small_m():
     X, labels = synth.gaussian_constellation(2048, 8, synth.SEED_BASE + 1)
     s2, Xd, tx, y, txh, yh = channel(X, labels, 6.0, 5000, 12)
