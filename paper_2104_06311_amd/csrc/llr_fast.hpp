@@ -288,6 +288,11 @@ __device__ __forceinline__ void combine_subsets(const SymAcc<MB>& A, bool half_t
   }
 }
 
+// log2 of a positive normal float: the hardware logarithm alone.  Every caller has
+// checked that its argument lies in [2^-96, 2^127], where log2f would add only the
+// scaling of denormal arguments around the same instruction.
+__device__ __forceinline__ float log2_normal(float x) { return __builtin_amdgcn_logf(x); }
+
 // Whether the FP32 subset sums of a symbol kept their range (exact path).
 template <int MB>
 __device__ __forceinline__ bool sums_in_range(const float (&S0)[MB], const float (&S1)[MB]) {
@@ -366,7 +371,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
 #pragma unroll
           for (int k = 0; k < m; ++k) {
             const int b = m - 1 - k;
-            llr[n * m + k] = MAXLOG ? kLn2 * (S0[b] - S1[b]) : kLn2 * (log2f(S0[b]) - log2f(S1[b]));
+            llr[n * m + k] = MAXLOG ? kLn2 * (S0[b] - S1[b]) : kLn2 * (log2_normal(S0[b]) - log2_normal(S1[b]));
           }
         }
       }
@@ -510,7 +515,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_wide_kernel(const uint4* __res
           for (int w = 0; w < NW; ++w) {
             const float a = v ? S1[w][b] : S0[w][b];
             const bool in = a >= 0x1p-96f && a <= 0x1p+126f;
-            val = (!found && in) ? log2f(a) - w * kWideShift : val;
+            val = (!found && in) ? log2_normal(a) - w * kWideShift : val;
             found = found || in;
           }
           ok = ok && found;
@@ -842,7 +847,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_bf16_kernel(const uint4* __res
 #pragma unroll
             for (int k = 0; k < m; ++k) {
               const int b = m - 1 - k;
-              llr[n * m + k] = kLn2 * (log2f(rowv[16 + b]) - log2f(rowv[b]));
+              llr[n * m + k] = kLn2 * (log2_normal(rowv[16 + b]) - log2_normal(rowv[b]));
             }
           }
         }

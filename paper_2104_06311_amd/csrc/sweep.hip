@@ -209,7 +209,7 @@ __device__ void process_item(const Problem& P, const Item& I, int it, uint4* lds
           for (int b = 0; b < MB; ++b)
             if (b < m) {
               const float sent = ((lab >> b) & 1u) ? S1[b] : S0[b];
-              T += log2f(S0[b] + S1[b]) - log2f(sent);
+              T += fastk::log2_normal(S0[b] + S1[b]) - fastk::log2_normal(sent);
             }
           acc_loss += T;
         } else {
