@@ -55,11 +55,18 @@ __device__ __forceinline__ bool build_symbol_operand(_Float16* row, const float*
                                                      bool live, int D, float cb, float cn, float alpha,
                                                      float bias, half8 (&bf)[KS]) {
   constexpr int S = 16 * KS;
+  constexpr int DMAX = (S - 4) / 3;          // 3 D + 4 slots fit in KS steps
   const int h = (threadIdx.x & 63) >> 5;
   float ysq = 0.0f;
   bool bad = false;
-  for (int d = 0; d < D; ++d) {
-    const float yd = live ? y[n * D + d] : 0.0f;
+  // all loads first, so that their latency is paid once per symbol, not once per dimension
+  float yv[DMAX];
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d) yv[d] = (live && d < D) ? y[n * D + d] : 0.0f;
+#pragma unroll
+  for (int d = 0; d < DMAX; ++d) {
+    if (d >= D) break;
+    const float yd = yv[d];
     ysq = fmaf(yd, yd, ysq);
     const float w = cb * yd;
     bad |= !(fabsf(w) <= 30000.0f);
