@@ -38,6 +38,9 @@ METRIC = "received symbols/s for exact LLR+GMI (8D, M=2048) and learned-vs-exact
 SIMD_CLOCKS = 256 * 4 * 2.4e9
 EXP_PEAK = SIMD_CLOCKS * 64 / 8                 # 1.966e13 exp/s
 PAIR_PEAK = SIMD_CLOCKS * 64 / (8 + 2 * 2)       # 1.311e13 pairs/s: 1 exp + 2 adds per pair
+# The 2-cycle add behind the FP32 vector peak needs packed FP32 instructions, which this
+# build does not emit; a non-packed wave64 add occupies the SIMD for 4 cycles.
+PAIR_FLOOR_NONPACKED = SIMD_CLOCKS * 64 / (8 + 2 * 4)   # 9.83e12 pairs/s
 
 
 def parse():
@@ -400,6 +403,10 @@ def main():
                 "peak_basis": "VALU issue of 1 v_exp_f32 (8 cycles/wave64) + 2 v_add_f32 (2 cycles/wave64) "
                               "per (symbol, point) pair; 256 CUs x 4 SIMDs x 2.4 GHz",
                 "frac_exp_pipe": achieved / EXP_PEAK, "exp_pipe_peak": EXP_PEAK / 1e12,
+                "frac_nonpacked_issue": achieved / PAIR_FLOOR_NONPACKED,
+                "nonpacked_issue_peak": PAIR_FLOOR_NONPACKED / 1e12,
+                "nonpacked_issue_basis": "1 v_exp_f32 (8 cycles) + 2 non-packed v_add_f32 (4 cycles each) "
+                                         "per 64 pairs, the issue floor of code built without packed FP32",
                 "kernel": "llr_fast_kernel<KS=2, 16 wavefronts, m=11, 1 block, exact> (llr_exact: "
                           "+ 3 prep kernels + wide-range and careful passes over empty lists)",
                 "per_launch": f"{pairs:.3e} (symbol, point) pairs = N*M", "avg_launch_ms": llr_avg_ms,
