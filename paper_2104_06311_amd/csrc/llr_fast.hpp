@@ -166,7 +166,10 @@ __device__ __forceinline__ void tile_loop(const uint4* __restrict__ lds, int t0,
         for (int ks = 0; ks < KS; ++ks)
           nxt[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], nxt[sb], 0, 0, 0);
       }
-      const int tpre = min(tg + i + 2, tn - 1);
+      // At the chunk's end this reads up to two tiles past it, into the symbol staging rows
+      // that follow every fragment buffer in LDS (at least 2 KS KiB); those products are
+      // never used.  Unclamped, the address is one base per group plus an immediate offset.
+      const int tpre = tg + i + 2;
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) ah[ks] = as_half8(lds[(tpre * KS + ks) * 64 + lane]);
       __builtin_amdgcn_sched_barrier(0);
