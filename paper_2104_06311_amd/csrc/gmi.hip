@@ -55,8 +55,9 @@ __device__ double block_sum(double v, double* sh) {
 }
 
 // partials: per block, [sum T, sum T^2, sum t_0 .. sum t_{m-1}].  Templated on m so that a
-// symbol's m LLRs are loaded together and the per-bit work has no branches.
-template <int MB>
+// symbol's m LLRs are loaded together and the per-bit work has no branches, and on PER_BIT
+// (the per-bit columns are left at zero when the caller does not want them).
+template <int MB, bool PER_BIT>
 __global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __restrict__ llr, int64_t N,
                                                              const uint32_t* __restrict__ tx,
                                                              const uint32_t* __restrict__ labels,
@@ -79,7 +80,7 @@ __global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __rest
     for (int k = 0; k < MB; ++k) {
       const float s = ((lab >> (MB - 1 - k)) & 1u) ? 1.0f : -1.0f;   // -s_nk
       const float t = softplus_bits(s * L[k]);
-      sb[k].add(t);
+      if (PER_BIT) sb[k].add(t);
       T += t;
     }
     sT.add(T);
@@ -93,7 +94,7 @@ __global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __rest
   if (threadIdx.x == 0) partials[1 * nb + blockIdx.x] = v;
 #pragma unroll
   for (int k = 0; k < MB; ++k) {
-    v = block_sum(sb[k].get(), sh);
+    v = PER_BIT ? block_sum(sb[k].get(), sh) : 0.0;
     if (threadIdx.x == 0) partials[(2 + k) * nb + blockIdx.x] = v;
   }
 }
@@ -207,8 +208,12 @@ int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const
   switch (m) {
 #define MD_GMI_CASE(MB_)                                                                                    \
   case MB_:                                                                                               \
-    hipLaunchKernelGGL(gmi_partial_kernel<MB_>, dim3(nb), dim3(kBlock), 0, stream, d_llr, N, d_tx, d_labels, \
-                       partials);                                                                         \
+    if (d_gmi_per_bit)                                                                                    \
+      hipLaunchKernelGGL((gmi_partial_kernel<MB_, true>), dim3(nb), dim3(kBlock), 0, stream, d_llr, N, d_tx,  \
+                         d_labels, partials);                                                             \
+    else                                                                                                  \
+      hipLaunchKernelGGL((gmi_partial_kernel<MB_, false>), dim3(nb), dim3(kBlock), 0, stream, d_llr, N, d_tx, \
+                         d_labels, partials);                                                             \
     break;
     MD_GMI_CASE(1) MD_GMI_CASE(2) MD_GMI_CASE(3) MD_GMI_CASE(4) MD_GMI_CASE(5) MD_GMI_CASE(6) MD_GMI_CASE(7)
     MD_GMI_CASE(8) MD_GMI_CASE(9) MD_GMI_CASE(10) MD_GMI_CASE(11) MD_GMI_CASE(12) MD_GMI_CASE(13) MD_GMI_CASE(14)
