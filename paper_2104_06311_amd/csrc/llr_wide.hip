@@ -1,4 +1,6 @@
-// Instantiation of the wide-range second and third passes of the exact demapper.
+// Instantiation of the wide-range second pass of the exact demapper (two windows); the
+// third pass is in llr_wide3.hip, a translation unit of its own so that the two compile in
+// parallel.
 #include "llr_fast.hpp"
 #include "llr_kernels.hpp"
 
@@ -7,12 +9,6 @@ namespace md {
 // list 1 (flags[1], fb_list) -> list 2 (flags[3], fb_list2), two windows
 int launch_wide_exact(const Prepared& P, int M, int D, const float* d_y, float* d_llr, hipStream_t stream) {
   return fastk::launch_wide<2>(P, M, D, d_y, d_llr, 1, 3, P.fb_list, P.fb_list2, stream);
-}
-
-// list 2 (flags[3], fb_list2) -> list 3 (flags[4], fb_list: list 1 is no longer needed),
-// three windows
-int launch_wide3_exact(const Prepared& P, int M, int D, const float* d_y, float* d_llr, hipStream_t stream) {
-  return fastk::launch_wide<3>(P, M, D, d_y, d_llr, 3, 4, P.fb_list2, P.fb_list, stream);
 }
 
 }  // namespace md
