@@ -48,7 +48,7 @@ def cosine(a, b):
                                             (16, 512, 16, 513, None), (8, 40, 11, 64, None),
                                             (8, 256, 11, 2000, (4.47, 3.1)), (16, 512, 16, 300, (2.5, 0.5)),
                                             (8, 288, 11, 1000, None), (20, 64, 5, 700, None), (30, 96, 7, 500, None),
-                                            (15, 256, 16, 257, None)])
+                                            (15, 256, 16, 257, None), (8, 512, 11, 1000, None)])
 def test_forward_matches_oracle(D, H, m, N, scales):
     """Fused kernel (H <= 256, D <= 15), weight-streaming kernel (H <= 512 or D up to 30)
     and the generic-GEMM path (H not a multiple of 32) against the FP64 forward."""

@@ -135,6 +135,27 @@ def test_qam16_hard_mode_and_no_statistics():
     rx.close()
 
 
+def test_exact_mode_small_constellation_many_streams():
+    """M = 16 (the one-thread-per-symbol kernel) in exact mode, 8 streams, buffers of 4097
+    symbols and bins of 3 buffers, LLRs checked element by element against one call."""
+    X, labels = synth.gaussian_constellation(16, 3, seed=8)
+    labels = synth.random_labels(16, 2)
+    N = 100_000
+    Xd, Ld, s2, tx, y = channel(X, labels, 5.0, N, seed=21)
+    rx = md().RxStream(Xd, Ld, s2, mode="exact", n_streams=8, buf_symbols=4097, bin_symbols=3 * 4097)
+    y_h, tx_h = y.cpu().pin_memory(), tx.cpu().pin_memory()
+    out = torch.empty((N, 4), dtype=torch.float32).pin_memory()
+    res = rx.run(y_h, tx_h, out=out)
+    rx.close()
+    L = md().llr_exact(Xd, Ld, y, s2)
+    assert torch.equal(out, L.cpu())
+    nb = (N + 3 * 4097 - 1) // (3 * 4097)
+    bins = [slice(b * 3 * 4097, min(N, (b + 1) * 3 * 4097)) for b in range(nb)]
+    e_ref, g_ref = bin_reference(L, tx, Ld, bins)
+    assert np.array_equal(res["bin_errors"], e_ref)
+    assert np.max(np.abs(res["bin_gmi"] - g_ref)) <= 1e-6
+
+
 def test_rx_rejects_bad_arguments():
     X, labels = synth.qam_gray(16)
     Xd = torch.from_numpy(X).cuda()
