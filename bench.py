@@ -141,7 +141,7 @@ def extra_learned(md, wl, X, labels, N, tx, y, llr, steps, pairs):
         md.awgn_sample(X, wl.seed + 77, 0, pairs, math.sqrt(s2), tx=tt, y=ty)
         md.llr_exact(X, labels, ty, s2, out=tl)
         net = md.MLP(wl.D, 256, wl.m, seed=int(snr))
-        net.set_scales(1.0 / math.sqrt(s2), 1.0 / math.sqrt(s2))     # inputs and LLRs on the noise scale
+        net.set_scales(1.0 / math.sqrt(s2), 1.0 / s2)     # inputs over sigma, LLRs over sigma^2
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         trace = net.fit(ty, tl, steps=steps, batch=4096, lr_max=2e-3, lr_min=2e-5, seed=int(snr) + 5)
@@ -194,7 +194,7 @@ def extra_16d(md, steps, pairs):
         md.awgn_sample(X, wl.seed + 77, 0, pairs, math.sqrt(s2), tx=tt, y=ty)
         md.llr_exact(X, labels, ty, s2, out=tl)
         net = md.MLP(wl.D, 512, m, seed=int(snr))
-        net.set_scales(1.0 / math.sqrt(s2), 1.0 / math.sqrt(s2))
+        net.set_scales(1.0 / math.sqrt(s2), 1.0 / s2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         net.fit(ty, tl, steps=steps, batch=4096, lr_max=2e-3, lr_min=2e-5, seed=int(snr) + 5)
