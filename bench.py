@@ -56,7 +56,7 @@ def parse():
                     help="also run a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline sweep (no BF16 / max-log / learned / batched objects)")
-    ap.add_argument("--learn-steps", type=int, default=24000, help="training steps per learned network (8D)")
+    ap.add_argument("--learn-steps", type=int, default=40000, help="training steps per learned network (8D)")
     ap.add_argument("--learn-steps-16d", type=int, default=6000, help="training steps per learned network (16D)")
     ap.add_argument("--learn-pairs", type=int, default=1 << 24, help="training pairs per SNR point")
     ap.add_argument("--batch-insts", type=int, default=64, help="instances in the batched-sweep object")

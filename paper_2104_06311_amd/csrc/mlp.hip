@@ -70,8 +70,13 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(const float* __restrict_
                                                         const float* __restrict__ bias, float* __restrict__ C2,
                                                         const float* __restrict__ Z, float ascale, float bscale,
                                                         float cscale) {
-  __shared__ __attribute__((aligned(16))) __bf16 As[64][16];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[64][16];
+  // K is staged 64 at a time (four 16-deep products per wavefront per barrier pair); the
+  // next stage is read from global memory into registers while the current one is
+  // multiplied.  Rows of the LDS tiles are padded to 144 bytes (9 x 16), so the 16-byte
+  // fragment reads of 32 consecutive rows hit distinct banks.
+  constexpr int KT = 64;
+  __shared__ __attribute__((aligned(16))) __bf16 As[64][KT + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[64][KT + 8];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int h = lane >> 5;
@@ -82,26 +87,51 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(const float* __restrict_
   const int kb = blockIdx.z * kper;
   const int ke = min(K, kb + kper);
   C += static_cast<int64_t>(blockIdx.z) * M * ldc;
+  // staging map of element e of this thread: consecutive threads take consecutive k when
+  // the operand's k stride is 1, consecutive rows otherwise (coalesced either way)
+  const bool a_kfast = sac == 1, b_kfast = sbr == 1;
+  auto coord = [&](bool kfast, int e, int* r, int* kk) {
+    const int idx = tid + 256 * e;
+    *r = kfast ? idx >> 6 : idx & 63;
+    *kk = kfast ? idx & 63 : idx >> 6;
+  };
+  float ra[16], rb[16];
+  auto load_stage = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      int r, kk;
+      coord(a_kfast, e, &r, &kk);
+      const int gi = i0 + r, gka = k0 + kk;
+      ra[e] = (gi < M && gka < ke) ? A[gi * sar + gka * sac] : 0.0f;
+      coord(b_kfast, e, &r, &kk);
+      const int gj = j0 + r, gkb = k0 + kk;
+      rb[e] = (gj < N && gkb < ke) ? B[gkb * sbr + gj * sbc] : 0.0f;
+    }
+  };
   floatx16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-  for (int k0 = kb; k0 < ke; k0 += 16) {
-    // stage a 64x16 A tile and a 16x64 B tile (B stored transposed: row j, column k)
+  if (kb < ke) load_stage(kb);
+  for (int k0 = kb; k0 < ke; k0 += KT) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = tid * 4 + e;        // 0..1023
-      const int r = idx >> 4, kk = idx & 15;
-      const int gi = i0 + r, gk = k0 + kk, gj = j0 + r;
-      const float av = (gi < M && gk < ke) ? A[gi * sar + gk * sac] * ascale : 0.0f;
-      const float bv = (gj < N && gk < ke) ? B[gk * sbr + gj * sbc] * bscale : 0.0f;
-      As[r][kk] = static_cast<__bf16>(av);
-      Bs[r][kk] = static_cast<__bf16>(bv);
+    for (int e = 0; e < 16; ++e) {
+      int r, kk;
+      coord(a_kfast, e, &r, &kk);
+      As[r][kk] = static_cast<__bf16>(ra[e] * ascale);
+      coord(b_kfast, e, &r, &kk);
+      Bs[r][kk] = static_cast<__bf16>(rb[e] * bscale);
     }
     __syncthreads();
-    bf16x8 a, b;
-    __builtin_memcpy(&a, &As[wi + (lane & 31)][8 * h], 16);
-    __builtin_memcpy(&b, &Bs[wj + (lane & 31)][8 * h], 16);
-    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    if (k0 + KT < ke) load_stage(k0 + KT);
+#pragma unroll
+    for (int sst = 0; sst < KT / 16; ++sst) {
+      if (k0 + 16 * sst < ke) {
+        bf16x8 a, b;
+        __builtin_memcpy(&a, &As[wi + (lane & 31)][16 * sst + 8 * h], 16);
+        __builtin_memcpy(&b, &Bs[wj + (lane & 31)][16 * sst + 8 * h], 16);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+    }
     __syncthreads();
   }
   const int j = j0 + wj + (lane & 31);
