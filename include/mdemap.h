@@ -313,6 +313,38 @@ int rx_run(void* rx, const float* h_y, const uint32_t* h_tx, int64_t N, int64_t 
            uint64_t* h_bin_errors, double* h_bin_gmi, double* h_stats);
 int rx_destroy(void* rx);
 
+/* ------------------------------------------------------------------ peak calibration */
+/* Measured rates of what the kernels above are bound by, on the current device: the
+ * roofline denominators.  The datasheet gives no rate for the exponential unit, and code
+ * built without packed FP32 instructions issues one FP32 add per lane per instruction,
+ * so both are measured here, next to the matrix-core and copy rates.
+ *
+ * One warm-up and one timed kernel run on `stream`; the call waits for them (it is
+ * synchronous) and writes the rate to *h_rate and the timed kernel's milliseconds to
+ * *h_ms (either may be NULL).  The compute kernels run 8 blocks of 256 threads per
+ * compute unit, each lane with 16 independent chains (or each wavefront with 4
+ * independent accumulators), so that instruction issue, not latency, bounds them.
+ * `work` is the number of loop iterations per lane for the compute kinds (0: a default
+ * of a few milliseconds) and the number of bytes for the copy.
+ *   MD_UB_EXP        v_exp_f32                                  -> exponentials/s
+ *   MD_UB_ADD_F32    v_add_f32 (non-packed)                     -> adds/s
+ *   MD_UB_MFMA_F16   v_mfma_f32_32x32x16_f16                    -> flop/s
+ *   MD_UB_MFMA_BF16  v_mfma_f32_32x32x16_bf16                   -> flop/s
+ *   MD_UB_MFMA_F32   v_mfma_f32_32x32x2_f32                     -> flop/s
+ *   MD_UB_COPY       d_dst[i] = d_src[i] over `work` bytes with 16-byte loads and stores;
+ *                    d_src and d_dst are device buffers of at least `work` bytes, 16-byte
+ *                    aligned, not overlapping (ignored by the other kinds)
+ *                                                               -> bytes read + written /s
+ * Returns MD_OK, MD_EINVAL (unknown kind, work < 0, a copy without buffers, with work not a
+ * positive multiple of 16 or with unaligned buffers), MD_ENOMEM, MD_EHIP. */
+#define MD_UB_EXP       0
+#define MD_UB_ADD_F32   1
+#define MD_UB_MFMA_F16  2
+#define MD_UB_MFMA_BF16 3
+#define MD_UB_MFMA_F32  4
+#define MD_UB_COPY      5
+int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rate, double* h_ms, void* stream);
+
 /* ------------------------------------------------------------------ housekeeping */
 /* Frees every internal device workspace (synchronises the device first). */
 int release_cache(void);

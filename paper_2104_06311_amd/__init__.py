@@ -13,7 +13,7 @@ import torch
 from ._lib import MdemapError, PREC, check, lib
 
 __all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "RxStream", "release_cache",
-           "MdemapError",
+           "ubench", "UBENCH_KINDS", "MdemapError",
            "log2_exact"]
 
 
@@ -158,6 +158,27 @@ def gmi_reduce(llr, tx, labels, per_bit: bool = True, se: bool = True):
 
 def release_cache():
     check("release_cache", lib().release_cache())
+
+
+UBENCH_KINDS = {"exp": 0, "add_f32": 1, "mfma_f16": 2, "mfma_bf16": 3, "mfma_f32": 4, "copy": 5}
+
+
+def ubench(kind: str, work: int = 0, src=None, dst=None):
+    """Measured peak rate of one instruction kind on the current device (see ubench in
+    mdemap.h): returns (rate, ms).  kind "copy" needs device tensors src and dst of at
+    least `work` bytes."""
+    import ctypes
+    if kind == "copy":
+        for name, t in (("src", src), ("dst", dst)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"ubench copy: {name} must be a contiguous device tensor")
+            if t.numel() * t.element_size() < work:
+                raise ValueError(f"ubench copy: {name} holds fewer than {work} bytes")
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    st = lib().ubench(UBENCH_KINDS[kind], int(work), _ptr(src) if src is not None else None,
+                      _ptr(dst) if dst is not None else None, ctypes.byref(rate), ctypes.byref(ms), _stream())
+    check("ubench", st)
+    return rate.value, ms.value
 
 
 # ----------------------------------------------------------------------------- learned demapper

@@ -57,6 +57,7 @@ SIGNATURES = {
     "rx_destroy": (_I, [_P]),
     "release_cache": (_I, []),
     "last_error": (ctypes.c_char_p, []),
+    "ubench": (_I, [_I, _I64, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P]),
     "mdemap_version": (_I, []),
 }
 

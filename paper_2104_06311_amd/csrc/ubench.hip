@@ -1,0 +1,181 @@
+// ubench: measured peak rates of the instructions the demapping kernels are bound by
+// (v_exp_f32, non-packed v_add_f32, the FP16/BF16/FP32 matrix products) and of a device
+// copy, on the current device.  Each compute kernel keeps 16 independent chains (or 4
+// independent accumulators) per lane, so that issue, not latency, bounds it; its result
+// feeds a store that is never taken, so the work cannot be removed.
+#include "common.hpp"
+
+namespace md {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kThreads = 256;
+constexpr int kChains = 16;
+constexpr float kNever = 1.2345678e30f;   // a sum the kernels never reach
+
+__global__ void __launch_bounds__(kThreads) ub_exp_kernel(int64_t iters, float seed, float* sink) {
+  float x[kChains];
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) x[c] = seed * static_cast<float>(threadIdx.x + c);
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) x[c] = __builtin_amdgcn_exp2f(-x[c]);
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) r += x[c];
+  if (r == kNever) sink[0] = r;
+}
+
+__global__ void __launch_bounds__(kThreads) ub_add_kernel(int64_t iters, float seed, float* sink) {
+  float x[kChains], s[kChains];
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) {
+    x[c] = seed * static_cast<float>(threadIdx.x + c);
+    s[c] = 0.0f;
+  }
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) s[c] += x[c];
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) r += s[c];
+  if (r == kNever) sink[0] = r;
+}
+
+// KIND 0: v_mfma_f32_32x32x16_f16, 1: v_mfma_f32_32x32x16_bf16, 2: v_mfma_f32_32x32x2_f32
+template <int KIND>
+__global__ void __launch_bounds__(kThreads) ub_mfma_kernel(int64_t iters, float seed, float* sink) {
+  floatx16 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[j][r] = 0.0f;
+  const float a0 = seed * static_cast<float>(threadIdx.x & 63);
+  half8 ah, bh;
+  bf16x8 ab, bb;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) {
+    ah[v] = static_cast<_Float16>(a0 + v);
+    bh[v] = static_cast<_Float16>(a0 - v);
+    ab[v] = static_cast<__bf16>(a0 + v);
+    bb[v] = static_cast<__bf16>(a0 - v);
+  }
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (KIND == 0) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh, acc[j], 0, 0, 0);
+      if constexpr (KIND == 1) acc[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, bb, acc[j], 0, 0, 0);
+      if constexpr (KIND == 2) acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, a0 + 1.0f, acc[j], 0, 0, 0);
+    }
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) r += acc[j][e];
+  if (r == kNever) sink[0] = r;
+}
+
+__global__ void __launch_bounds__(kThreads) ub_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                           int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+constexpr double kMfmaFlop[3] = {2.0 * 32 * 32 * 16, 2.0 * 32 * 32 * 16, 2.0 * 32 * 32 * 2};
+constexpr int64_t kDefaultIters[5] = {8192, 8192, 4096, 4096, 2048};
+
+int launch_kind(int kind, int64_t work, int blocks, const void* d_src, void* d_dst, float* sink, hipStream_t s) {
+  const int64_t iters = work > 0 ? work : kDefaultIters[kind];
+  switch (kind) {
+    case MD_UB_EXP: hipLaunchKernelGGL(ub_exp_kernel, dim3(blocks), dim3(kThreads), 0, s, iters, 1e-3f, sink); break;
+    case MD_UB_ADD_F32: hipLaunchKernelGGL(ub_add_kernel, dim3(blocks), dim3(kThreads), 0, s, iters, 1e-3f, sink); break;
+    case MD_UB_MFMA_F16:
+      hipLaunchKernelGGL(ub_mfma_kernel<0>, dim3(blocks), dim3(kThreads), 0, s, iters, 1e-3f, sink);
+      break;
+    case MD_UB_MFMA_BF16:
+      hipLaunchKernelGGL(ub_mfma_kernel<1>, dim3(blocks), dim3(kThreads), 0, s, iters, 1e-3f, sink);
+      break;
+    case MD_UB_MFMA_F32:
+      hipLaunchKernelGGL(ub_mfma_kernel<2>, dim3(blocks), dim3(kThreads), 0, s, iters, 1e-3f, sink);
+      break;
+    default: {
+      const int64_t n = work / 16;
+      int64_t g = (n + kThreads - 1) / kThreads;
+      if (g > blocks) g = blocks;
+      if (g < 1) g = 1;
+      hipLaunchKernelGGL(ub_copy_kernel, dim3(static_cast<unsigned>(g)), dim3(kThreads), 0, s,
+                         static_cast<const uint4*>(d_src), static_cast<uint4*>(d_dst), n);
+    }
+  }
+  MD_LAUNCH_CHECK("ubench kernel launch");
+  return MD_OK;
+}
+
+}  // namespace
+}  // namespace md
+
+extern "C" {
+
+int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rate, double* h_ms, void* stream) {
+  using namespace md;
+  if (kind < MD_UB_EXP || kind > MD_UB_COPY) return fail(MD_EINVAL, "ubench: unknown kind");
+  if (work < 0) return fail(MD_EINVAL, "ubench: work must be >= 0");
+  if (kind == MD_UB_COPY) {
+    if (d_src == nullptr || d_dst == nullptr) return fail(MD_EINVAL, "ubench: the copy needs d_src and d_dst");
+    if (work <= 0 || work % 16 != 0) return fail(MD_EINVAL, "ubench: the copy needs work > 0, a multiple of 16");
+    if ((reinterpret_cast<uintptr_t>(d_src) | reinterpret_cast<uintptr_t>(d_dst)) % 16 != 0)
+      return fail(MD_EINVAL, "ubench: copy buffers must be 16-byte aligned");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int dev = 0, ncu = 0;
+  MD_HIP_TRY(hipGetDevice(&dev));
+  MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int blocks = ncu * 8;
+  char* ws = nullptr;
+  if (int st = workspace(s, 256, &ws); st != MD_OK) return st;
+  float* sink = reinterpret_cast<float*>(ws);
+  hipEvent_t e0, e1;
+  MD_HIP_TRY(hipEventCreate(&e0));
+  if (hipError_t e = hipEventCreate(&e1); e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  int st = launch_kind(kind, work, blocks, d_src, d_dst, sink, s);   // warm-up
+  hipError_t he = hipSuccess;
+  if (st == MD_OK) he = hipEventRecord(e0, s);
+  if (st == MD_OK && he == hipSuccess) st = launch_kind(kind, work, blocks, d_src, d_dst, sink, s);
+  if (st == MD_OK && he == hipSuccess) he = hipEventRecord(e1, s);
+  if (st == MD_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+  float ms = 0.0f;
+  if (st == MD_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != MD_OK) return st;
+  if (he != hipSuccess) return hip_fail(he, "ubench timing");
+  const double sec = static_cast<double>(ms) * 1e-3;
+  const int64_t iters = work > 0 ? work : (kind < MD_UB_COPY ? kDefaultIters[kind] : 0);
+  const double lanes = static_cast<double>(blocks) * kThreads;
+  const double waves = lanes / 64.0;
+  double amount = 0.0;
+  switch (kind) {
+    case MD_UB_EXP:
+    case MD_UB_ADD_F32: amount = lanes * static_cast<double>(iters) * kChains; break;
+    case MD_UB_MFMA_F16:
+    case MD_UB_MFMA_BF16:
+    case MD_UB_MFMA_F32:
+      amount = waves * static_cast<double>(iters) * 4.0 * kMfmaFlop[kind - MD_UB_MFMA_F16];
+      break;
+    default: amount = 2.0 * static_cast<double>(work);
+  }
+  if (h_rate) *h_rate = sec > 0.0 ? amount / sec : 0.0;
+  if (h_ms) *h_ms = static_cast<double>(ms);
+  return MD_OK;
+}
+
+}  // extern "C"

@@ -105,3 +105,17 @@ def test_no_device_is_reported_not_crashed():
     assert L.gmi_reduce(fake, 10, 4, fake, fake, fake, None, None, None) == -7
     assert L.release_cache() == 0
     assert L.mdemap_version() >= 100
+
+
+def test_ubench_argument_validation_before_device_work():
+    from paper_2104_06311_amd._lib import lib
+    L = lib()
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: validation fails first
+    assert L.ubench(-1, 0, None, None, None, None, None) == -1
+    assert L.ubench(6, 0, None, None, None, None, None) == -1
+    assert L.ubench(0, -5, None, None, None, None, None) == -1
+    assert L.ubench(5, 1 << 20, None, fake, None, None, None) == -1      # copy without a source
+    assert L.ubench(5, 0, fake, fake, None, None, None) == -1            # copy of zero bytes
+    assert L.ubench(5, 1000, fake, fake, None, None, None) == -1         # not a multiple of 16
+    assert L.ubench(5, 1024, ctypes.c_void_p(0x1008), fake, None, None, None) == -1   # unaligned
+    assert b"ubench" in L.last_error()

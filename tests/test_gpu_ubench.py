@@ -1,0 +1,47 @@
+"""Peak calibration (ubench): every kind runs and reports a rate in a plausible band
+around the chip's published figure (256 compute units at 2.4 GHz), and the copy moves
+the bytes it claims to."""
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def md():
+    import paper_2104_06311_amd
+    return paper_2104_06311_amd
+
+
+# kind -> (lowest plausible, highest plausible) rate.  Published or unit-count figures:
+# exp 1.97e13/s (8 cycles per wave64), FP32 add 7.9e13/s at 2 cycles per wave64 (the
+# vector peak, which needs packed instructions; non-packed adds measure about 2.8
+# cycles), FP16/BF16 matrix 2.5e15 flop/s, FP32 matrix 1.57e14 flop/s, HBM 8e12 B/s.
+BANDS = {"exp": (4e12, 2.6e13), "add_f32": (8e12, 8.2e13), "mfma_f16": (8e14, 2.8e15),
+         "mfma_bf16": (8e14, 2.8e15), "mfma_f32": (4e13, 1.8e14)}
+
+
+@pytest.mark.parametrize("kind", sorted(BANDS))
+def test_compute_rates_are_plausible(kind):
+    rate, ms = md().ubench(kind)
+    lo, hi = BANDS[kind]
+    assert lo <= rate <= hi, (kind, rate)
+    assert 0.05 < ms < 200.0, (kind, ms)
+    # twice the iterations take about twice as long
+    doubled = {"exp": 16384, "add_f32": 16384, "mfma_f16": 8192, "mfma_bf16": 8192, "mfma_f32": 4096}
+    rate2, ms2 = md().ubench(kind, work=doubled[kind])
+    assert 1.5 < ms2 / ms < 2.6, (kind, ms, ms2)
+
+
+def test_copy_moves_the_bytes():
+    nbytes = 1 << 28
+    src = torch.arange(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    rate, ms = md().ubench("copy", nbytes, src, dst)
+    assert torch.equal(src, dst)
+    assert 1e12 <= rate <= 8.5e12, rate
+    # a partial copy touches only its prefix
+    dst.zero_()
+    md().ubench("copy", 4096, src, dst)
+    assert torch.equal(dst[:1024], src[:1024]) and int(dst[1024:].abs().max().item()) == 0
+    with pytest.raises(ValueError):
+        md().ubench("copy", nbytes * 2, src, dst)
