@@ -413,19 +413,24 @@ def main():
     llr = torch.empty((N, m), dtype=torch.float32, device=dev)
     gmis = torch.zeros(len(snrs), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in snrs]
-    llr_ms = []
+    # per SNR point: events before awgn_sample, before llr_exact, after llr_exact, after gmi_reduce
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in snrs]
+    llr_ms, awgn_ms, gmi_ms = [], [], []
 
     def step(record):
         for i, s2 in enumerate(sig2):
-            md.awgn_sample(X, wl.seed, i * N, N, math.sqrt(s2), tx=tx, y=y)
             if record:
                 ev[i][0].record(stream)
-            md.llr_exact(X, labels, y, s2, prec=args.prec, out=llr)
+            md.awgn_sample(X, wl.seed, i * N, N, math.sqrt(s2), tx=tx, y=y)
             if record:
                 ev[i][1].record(stream)
+            md.llr_exact(X, labels, y, s2, prec=args.prec, out=llr)
+            if record:
+                ev[i][2].record(stream)
             g, _, _ = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)
             gmis[i:i + 1].copy_(g)
+            if record:
+                ev[i][3].record(stream)
 
     for _ in range(args.warmup):
         step(False)
@@ -434,7 +439,9 @@ def main():
     for _ in range(args.steps):
         step(True)
         torch.cuda.synchronize()
-        llr_ms.extend(a.elapsed_time(b) for a, b in ev)
+        llr_ms.extend(e[1].elapsed_time(e[2]) for e in ev)
+        awgn_ms.extend(e[0].elapsed_time(e[1]) for e in ev)
+        gmi_ms.extend(e[2].elapsed_time(e[3]) for e in ev)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = 1e3 * dt / args.steps
@@ -479,6 +486,10 @@ def main():
         "roofline": roofline,
         "detail": {"gmi_bits": {f"{s:g}": round(float(g), 6) for s, g in zip(snrs, gmis.cpu().tolist())},
                    "llr_symbols_per_s": N / (llr_avg_ms * 1e-3),
+                   "per_point_ms": {"awgn_sample": float(np.mean(awgn_ms)), "llr_exact": llr_avg_ms,
+                                    "llr_exact_median": float(np.median(llr_ms)),
+                                    "gmi_reduce": float(np.mean(gmi_ms))},
+                   "demap_gmi_symbols_per_s": N / ((llr_avg_ms + float(np.mean(gmi_ms))) * 1e-3),
                    "wide_careful_symbols_at_14dB": list(md.llr_path_counts())},
     }
     if not args.no_extras:
