@@ -127,7 +127,7 @@ def extra_precisions(md, wl, X, labels, N, tx, y, llr):
 
 def extra_learned(md, wl, X, labels, N, tx, y, llr, steps, pairs):
     """Learned 8 -> 256 -> 256 -> 11 demapper, one network per SNR (6, 10, 14 dB), trained on
-    `pairs` (y, exact LLR) pairs of the same constellation; judged by the exact GMI on N
+    `pairs` (y, exact LLR) pairs of the same constellation; scored by the GMI of its LLRs on N
     fresh symbols; inference time against the exact kernel."""
     import math
     import time

@@ -167,7 +167,7 @@ int ber_count(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const 
 /* ------------------------------------------------------------------ learned demapper */
 /* A small network f: R^D -> R^m approximating the exact LLRs, trained on the GPU by the
  * library's own kernels on (y, exact-LLR) pairs that llr_exact produces; the exact path
- * stays the reference that judges it (through gmi_reduce).  The glossary's ML entry is
+ * stays the reference its GMI is measured against (through gmi_reduce).  The glossary's ML entry is
  * the only mention of learning in the paper; the network and its training are this
  * library's design:
  *   f(y) = s_out (W3 g(W2 g(W1 (s_in y) + b1) + b2) + b3),  hidden width H in both
