@@ -21,6 +21,10 @@ is in ``tests/test_oracle_pins.py``):
   hard_decision                pinned (brute force on tiny inputs)
   bit_errors, q_factor_db      pinned (BPSK/QPSK closed-form error rates, the
                                Gaussian tail identity)
+  ddlms                        pinned (frozen identity taps reduce it to the sampled
+                               input and a nearest-point search; the closed-form
+                               inverse of a widely-linear distortion is a fixed point;
+                               convergence to that inverse from identity taps)
 """
 from __future__ import annotations
 
@@ -59,6 +63,7 @@ def _load():
     lib.orc_mlp_loss_grad.argtypes = [I, I, I, I, P, P, P, P, P, P, Dbl, Dbl, P, P, I64, P, P, P, P, P, P]
     lib.orc_mlp_loss_grad.restype = Dbl
     lib.orc_adam_step.argtypes = [P, P, P, P, I64, I, Dbl, Dbl, Dbl, Dbl]
+    lib.orc_ddlms.argtypes = [P, I64, I64, P, I, P, P, Dbl, P, P, P, P]
     lib.orc_num_threads.restype = I
     _lib = lib
     return lib
@@ -275,3 +280,26 @@ def adam_step(w, g, m1, m2, t: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8)
 def num_threads() -> int:
     """OpenMP threads used by the parallel oracle loops."""
     return int(_load().orc_num_threads())
+
+
+def ddlms(x, C, h0, g0, mu: float):
+    """Four-tap widely-linear DD-LMS equaliser over B independent instances (see orc_ddlms
+    in oracle.c).  x: (2N + 2, B) complex64 samples, time-major; C: (M,) complex reference
+    points; h0, g0: 4 complex starting taps.  Returns (dec (N, B) uint32, z (N, B)
+    complex64, h (B, 4) complex128, g (B, 4) complex128)."""
+    lib = _load()
+    x = np.ascontiguousarray(x, dtype=np.complex64)
+    T, B = x.shape
+    N = (T - 2) // 2
+    if T != 2 * N + 2 or N < 0:
+        raise ValueError("x must hold 2 N + 2 samples per instance")
+    C = np.ascontiguousarray(C, dtype=np.complex64)
+    h0 = np.ascontiguousarray(h0, dtype=np.complex128)
+    g0 = np.ascontiguousarray(g0, dtype=np.complex128)
+    dec = np.zeros((N, B), dtype=np.uint32)
+    z = np.zeros((N, B), dtype=np.complex64)
+    h = np.zeros((B, 4), dtype=np.complex128)
+    g = np.zeros((B, 4), dtype=np.complex128)
+    lib.orc_ddlms(_ptr(x), B, N, _ptr(C), C.shape[0], _ptr(h0), _ptr(g0), float(mu), _ptr(dec), _ptr(z), _ptr(h),
+                  _ptr(g))
+    return dec, z, h, g

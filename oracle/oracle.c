@@ -486,3 +486,75 @@ void orc_adam_step(double* w, const double* g, double* mom1, double* mom2, int64
 
 /* Number of OpenMP threads the parallel loops above use. */
 int orc_num_threads(void) { return omp_get_max_threads(); }
+
+/* ------------------------------------------------------------------------- */
+/* Four-tap widely-linear decision-directed LMS equaliser: the step just before the
+ * demapper in the paper's receiver (section "Experimental setup", DSP-chain paragraph,
+ * which names a four-tap adaptive time-domain DD-LMS widely-linear equaliser after
+ * downsampling to 2 samples per symbol, and gives no equations).  Textbook complex LMS
+ * with a widely-linear output (a filter on the samples plus one on their conjugates),
+ * read as follows.  Per instance b, complex samples u_t (t = 0 .. 2N+1, 2 per symbol);
+ * symbol n sees the window w_j = u_{2n+j}, j = 0..3:
+ *   z_n = sum_j ( h_j w_j + g_j conj(w_j) )           (j ascending, the h term first)
+ *   d_n = argmin_i |z_n - c_i|^2 over the reference points c_i (the first minimum)
+ *   e_n = c_{d_n} - z_n
+ *   h_j <- h_j + mu e_n conj(w_j),   g_j <- g_j + mu e_n w_j    (with the old w_j)
+ * Complex products are (ac - bd) + i(ad + bc), every operation in double precision in
+ * the order written below (the file is built without contraction).  Layout: time-major,
+ * sample t of instance b is x[2 (t B + b)] (re) and x[2 (t B + b) + 1] (im); symbol n of
+ * instance b goes to dec[n B + b] and z[2 (n B + b)], the final taps of instance b to
+ * h_out[8 b + 2 j] (re), h_out[8 b + 2 j + 1] (im), likewise g_out.  h0 and g0 hold the
+ * starting taps (re, im interleaved) shared by all instances. */
+void orc_ddlms(const float* x, int64_t B, int64_t N, const float* C, int M, const double* h0, const double* g0,
+               double mu, uint32_t* dec, float* z, double* h_out, double* g_out) {
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < B; ++b) {
+        double hr[4], hi[4], gr[4], gi[4];
+        for (int j = 0; j < 4; ++j) {
+            hr[j] = h0[2 * j];
+            hi[j] = h0[2 * j + 1];
+            gr[j] = g0[2 * j];
+            gi[j] = g0[2 * j + 1];
+        }
+        for (int64_t n = 0; n < N; ++n) {
+            double wr[4], wi[4];
+            for (int j = 0; j < 4; ++j) {
+                const int64_t t = 2 * n + j;
+                wr[j] = (double)x[2 * (t * B + b)];
+                wi[j] = (double)x[2 * (t * B + b) + 1];
+            }
+            double zr = 0.0, zi = 0.0;
+            for (int j = 0; j < 4; ++j) {
+                zr = zr + (hr[j] * wr[j] - hi[j] * wi[j]);
+                zr = zr + (gr[j] * wr[j] + gi[j] * wi[j]);
+                zi = zi + (hr[j] * wi[j] + hi[j] * wr[j]);
+                zi = zi + (gi[j] * wr[j] - gr[j] * wi[j]);
+            }
+            double best = INFINITY;
+            int arg = 0;
+            for (int i = 0; i < M; ++i) {
+                const double dr = zr - (double)C[2 * i];
+                const double di = zi - (double)C[2 * i + 1];
+                const double d2 = dr * dr + di * di;
+                if (d2 < best) { best = d2; arg = i; }
+            }
+            const double er = (double)C[2 * arg] - zr;
+            const double ei = (double)C[2 * arg + 1] - zi;
+            for (int j = 0; j < 4; ++j) {
+                hr[j] = hr[j] + mu * (er * wr[j] + ei * wi[j]);
+                hi[j] = hi[j] + mu * (ei * wr[j] - er * wi[j]);
+                gr[j] = gr[j] + mu * (er * wr[j] - ei * wi[j]);
+                gi[j] = gi[j] + mu * (er * wi[j] + ei * wr[j]);
+            }
+            dec[n * B + b] = (uint32_t)arg;
+            z[2 * (n * B + b)] = (float)zr;
+            z[2 * (n * B + b) + 1] = (float)zi;
+        }
+        for (int j = 0; j < 4; ++j) {
+            h_out[8 * b + 2 * j] = hr[j];
+            h_out[8 * b + 2 * j + 1] = hi[j];
+            g_out[8 * b + 2 * j] = gr[j];
+            g_out[8 * b + 2 * j + 1] = gi[j];
+        }
+    }
+}

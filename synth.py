@@ -174,3 +174,23 @@ def batched_instances(n_inst: int = 64, seed: int = SEED_BASE + 2, n_min: int = 
         out.append(Workload(f"inst{i}", X, labels, [float(s) for s in range(2, 13)], int(Ns[i]),
                             seed * 1000 + i))
     return out
+
+
+def equaliser_input(B: int, N: int, M: int = 16, a: complex = 0.95 + 0.1j, b: complex = 0.08 - 0.04j,
+                    isi: complex = 0.25 + 0.05j, snr_db: float = 25.0, seed: int = SEED_BASE + 5):
+    """Seeded input of the widely-linear equaliser, time-major: B independent instances of
+    N + 1 square M-QAM symbols (Gray labels) at 2 samples per symbol through an IQ
+    imbalance (a s + b conj(s)), a half-symbol sample that mixes neighbours
+    (isi s_n + conj(isi) s_{n+1}) and complex AWGN.  Returns x ((2N + 2, B) complex64),
+    sent indices ((N + 1, B) uint32), reference points C ((M,) complex64) and labels."""
+    X, labels = qam_gray(M)
+    C = (X[:, 0].astype(np.float64) + 1j * X[:, 1].astype(np.float64))
+    rng = np.random.default_rng(seed)
+    tx = rng.integers(0, M, size=(N + 2, B), dtype=np.int64)
+    s = C[tx]
+    sig = 10.0 ** (-snr_db / 20.0) / math.sqrt(2.0)
+    x = np.zeros((2 * N + 2, B), dtype=np.complex128)
+    x[0::2] = a * s[:N + 1] + b * np.conj(s[:N + 1])
+    x[1::2] = isi * s[:N + 1] + np.conj(isi) * s[1:N + 2]
+    x += sig * (rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape))
+    return x.astype(np.complex64), tx[:N + 1].astype(np.uint32), C.astype(np.complex64), labels
