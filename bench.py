@@ -211,6 +211,34 @@ def extra_4d(md, N=100_000_000):
             "llr_exact_bytes_per_s": N * (4 * wl.D + 4 * wl.m) / (t_llr * 1e-3), "gmi": g}
 
 
+def extra_ddlms(md, B=262144, N=256):
+    """Widely-linear DD-LMS equaliser (ddlms_equalize) over B independent instances of N
+    16-QAM symbols at 2 samples per symbol: the seeded channel of 65,536 instances is
+    repeated 4 times along the instance axis (each instance runs its own recursion)."""
+    import numpy as np
+    import torch
+    import synth
+    base = 65536
+    x, tx, C, labels = synth.equaliser_input(base, N)
+    xd = torch.from_numpy(x).cuda().repeat(1, B // base).contiguous()
+    Cd = torch.from_numpy(C).cuda()
+    h0, g0 = [1, 0, 0, 0], [0, 0, 0, 0]
+    holder = {}
+    t = timed(lambda: holder.__setitem__("r", md.ddlms_equalize(xd, Cd, h0, g0, 0.01, want_taps=False)))
+    dec = holder["r"][0]
+    ser = float((dec[N // 2:, :base].cpu().numpy() != tx[N // 2:N]).mean())
+    M = C.shape[0]
+    # FP64 operations per symbol: output 64, distances 5 M, error 2, tap update 80
+    flops = 64 + 5 * M + 2 + 80
+    rate = B * N / (t * 1e-3)
+    return {"instances": B, "symbols_per_instance": N, "M": M, "ms": t, "symbols_per_s": rate,
+            "fp64_flop_per_symbol": flops, "fp64_flop_per_s": rate * flops,
+            "frac_fp64_issue": rate * flops / (78.6e12 / 2),
+            "fp64_issue_basis": "78.6 TFLOP/s FP64 vector counts an FMA as 2; the equaliser has no FMAs, so its "
+                                "ceiling is one FP64 operation per lane per cycle-slot, 39.3e12/s",
+            "symbol_error_rate_second_half": ser, "bytes_per_symbol": 2 * 8 + 4 + 8}
+
+
 def extra_16d(md, steps, pairs):
     """16D M = 65536 (16 bits), N = 1e6 at 10 and 16 dB: exact vs max-log vs a learned
     16 -> 512 -> 512 -> 16 network trained on `pairs` (y, exact LLR) pairs per SNR point."""
@@ -501,6 +529,7 @@ def main():
         out["detail"]["batched"] = extra_batched(md, args.batch_insts)
         out["detail"]["16d"] = extra_16d(md, args.learn_steps_16d, args.learn_pairs_16d)
         out["detail"]["4d"] = extra_4d(md)
+        out["detail"]["ddlms"] = extra_ddlms(md)
         out["detail"]["rx_stream"] = extra_rx(md, args.rx_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl.X, wl.labels, 9.0, args.cpu_seconds)

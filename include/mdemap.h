@@ -313,6 +313,36 @@ int rx_run(void* rx, const float* h_y, const uint32_t* h_tx, int64_t N, int64_t 
            uint64_t* h_bin_errors, double* h_bin_gmi, double* h_stats);
 int rx_destroy(void* rx);
 
+/* ------------------------------------------------------------------ equaliser */
+/* ddlms_equalize -- four-tap widely-linear decision-directed LMS equaliser, the step
+ * that feeds the demapper in the paper's receiver (section "Experimental setup": after
+ * downsampling to 2 samples per symbol, a four-tap adaptive time-domain DD-LMS
+ * widely-linear equaliser whose decisions are demapped; the paper gives no equations).
+ * B independent instances (buffers, sub-blocks or channels) run side by side, one
+ * sequential recursion each.  Per instance, complex samples u_t, t = 0 .. 2N+1; symbol n
+ * sees the window w_j = u_{2n+j}, j = 0..3, and
+ *   z_n = sum_j ( h_j w_j + g_j conj(w_j) )        (j ascending, the h term first)
+ *   d_n = argmin_i |z_n - C_i|^2                   (the first minimum)
+ *   e_n = C_{d_n} - z_n
+ *   h_j <- h_j + mu e_n conj(w_j),  g_j <- g_j + mu e_n w_j     (with the old w_j)
+ * in IEEE double with complex products (ac - bd) + i(ad + bc) and no contraction, so the
+ * results are fixed bit for bit by this definition.
+ *   d_x    (2N + 2) x B complex float32 samples, TIME-MAJOR: sample t of instance b at
+ *          d_x[2 (t B + b)] (re) and d_x[2 (t B + b) + 1] (im)
+ *   d_C    M complex float32 reference points (re, im), 1 <= M <= 1024 (pass the
+ *          demapper's 2D constellation to feed llr_* or ber_count with the decisions)
+ *   h_h0, h_g0  host, 8 doubles each: starting taps h_j, g_j (re, im), shared by all
+ *          instances
+ *   mu     step size, finite and >= 0
+ *   d_dec  out: N x B uint32 decisions (indices into d_C), time-major (n B + b)
+ *   d_z    out: N x B complex float32 equaliser outputs, time-major, or NULL
+ *   d_h, d_g  out: B x 8 doubles, the final taps of each instance, or NULL
+ * Returns MD_OK (B = 0 enqueues nothing; N = 0 only writes the starting taps), MD_EINVAL,
+ * MD_EHIP. */
+int ddlms_equalize(const float* d_x, int64_t B, int64_t N, const float* d_C, int M, const double* h_h0,
+                   const double* h_g0, double mu, uint32_t* d_dec, float* d_z, double* d_h, double* d_g,
+                   void* stream);
+
 /* ------------------------------------------------------------------ peak calibration */
 /* Measured rates of what the kernels above are bound by, on the current device: the
  * roofline denominators.  The datasheet gives no rate for the exponential unit, and code

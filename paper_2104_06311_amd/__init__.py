@@ -13,7 +13,7 @@ import torch
 from ._lib import MdemapError, PREC, check, lib
 
 __all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "RxStream", "release_cache",
-           "ubench", "UBENCH_KINDS", "MdemapError",
+           "ddlms_equalize", "ubench", "UBENCH_KINDS", "MdemapError",
            "log2_exact"]
 
 
@@ -158,6 +158,37 @@ def gmi_reduce(llr, tx, labels, per_bit: bool = True, se: bool = True):
 
 def release_cache():
     check("release_cache", lib().release_cache())
+
+
+def ddlms_equalize(x, C, h0, g0, mu: float, want_z: bool = True, want_taps: bool = True):
+    """Four-tap widely-linear DD-LMS equaliser over B independent instances (see
+    ddlms_equalize in mdemap.h).  x: (2N + 2, B) complex64 device tensor, time-major;
+    C: (M,) complex64 device tensor of reference points; h0, g0: 4 complex starting taps.
+    Returns (dec (N, B) int32, z (N, B) complex64 or None, h (B, 4) complex128 or None,
+    g (B, 4) complex128 or None)."""
+    import ctypes
+    import numpy as np
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.complex64 or x.dim() != 2 or not x.is_cuda:
+        raise ValueError("x must be a 2-D complex64 device tensor")
+    if not isinstance(C, torch.Tensor) or C.dtype != torch.complex64 or C.dim() != 1 or not C.is_cuda:
+        raise ValueError("C must be a 1-D complex64 device tensor")
+    x = x.contiguous()
+    C = C.contiguous()
+    T, B = x.shape
+    if T < 2 or T % 2:
+        raise ValueError("x must hold 2 N + 2 samples per instance")
+    N = (T - 2) // 2
+    t0 = np.ascontiguousarray(np.asarray(h0, dtype=np.complex128).reshape(4)).view(np.float64)
+    t1 = np.ascontiguousarray(np.asarray(g0, dtype=np.complex128).reshape(4)).view(np.float64)
+    dec = torch.empty((N, B), dtype=torch.int32, device=x.device)
+    z = torch.empty((N, B), dtype=torch.complex64, device=x.device) if want_z else None
+    h = torch.empty((B, 4), dtype=torch.complex128, device=x.device) if want_taps else None
+    g = torch.empty((B, 4), dtype=torch.complex128, device=x.device) if want_taps else None
+    st = lib().ddlms_equalize(_ptr(x), B, N, _ptr(C), C.shape[0], t0.ctypes.data_as(ctypes.c_void_p),
+                              t1.ctypes.data_as(ctypes.c_void_p), float(mu), _ptr(dec), _ptr(z), _ptr(h), _ptr(g),
+                              _stream())
+    check("ddlms_equalize", st)
+    return dec, z, h, g
 
 
 UBENCH_KINDS = {"exp": 0, "add_f32": 1, "mfma_f16": 2, "mfma_bf16": 3, "mfma_f32": 4, "copy": 5}

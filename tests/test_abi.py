@@ -119,3 +119,26 @@ def test_ubench_argument_validation_before_device_work():
     assert L.ubench(5, 1000, fake, fake, None, None, None) == -1         # not a multiple of 16
     assert L.ubench(5, 1024, ctypes.c_void_p(0x1008), fake, None, None, None) == -1   # unaligned
     assert b"ubench" in L.last_error()
+
+
+def test_equaliser_argument_validation_before_device_work():
+    from paper_2104_06311_amd._lib import lib
+    L = lib()
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: validation fails first
+    taps = (ctypes.c_double * 8)(1, 0, 0, 0, 0, 0, 0, 0)
+    bad = (ctypes.c_double * 8)(float("nan"), 0, 0, 0, 0, 0, 0, 0)
+    args = lambda B, N, M, mu, h=taps, g=taps, x=fake, dec=fake: (x, B, N, fake, M, h, g, mu, dec, None, None, None,
+                                                                   None)
+    assert L.ddlms_equalize(*args(-1, 10, 16, 0.01)) == -1
+    assert L.ddlms_equalize(*args(10, -1, 16, 0.01)) == -1
+    assert L.ddlms_equalize(*args(10, 10, 0, 0.01)) == -1
+    assert L.ddlms_equalize(*args(10, 10, 1025, 0.01)) == -1
+    assert L.ddlms_equalize(*args(10, 10, 16, -0.5)) == -1
+    assert L.ddlms_equalize(*args(10, 10, 16, float("inf"))) == -1
+    assert L.ddlms_equalize(*args(10, 10, 16, 0.01, h=None)) == -1
+    assert L.ddlms_equalize(*args(10, 10, 16, 0.01, g=bad)) == -1
+    assert L.ddlms_equalize(*args(10, 10, 16, 0.01, x=None)) == -1
+    assert L.ddlms_equalize(*args(10, 10, 16, 0.01, dec=None)) == -1
+    assert L.ddlms_equalize(*args(10, 1 << 40, 16, 0.01)) == -1
+    assert b"ddlms_equalize" in L.last_error()
+    assert L.ddlms_equalize(*args(0, 10, 16, 0.01)) == 0          # no instances: nothing to do
