@@ -25,6 +25,9 @@ is in ``tests/test_oracle_pins.py``):
                                input and a nearest-point search; the closed-form
                                inverse of a widely-linear distortion is a fixed point;
                                convergence to that inverse from identity taps)
+  kk_field                     pinned (Hilbert of a bin-centred cosine is the sine; the
+                               Kramers-Kronig theorem recovers a minimum-phase signal;
+                               the downshift moves a tone to DC)
 """
 from __future__ import annotations
 
@@ -303,3 +306,40 @@ def ddlms(x, C, h0, g0, mu: float):
     lib.orc_ddlms(_ptr(x), B, N, _ptr(C), C.shape[0], _ptr(h0), _ptr(g0), float(mu), _ptr(dec), _ptr(z), _ptr(h),
                   _ptr(g))
     return dec, z, h, g
+
+
+def kk_field(x, A: float, nu: float, nfft: int = 1024):
+    """Kramers-Kronig front end of the paper's receiver (section "Experimental setup", the
+    DSP-chain paragraph: square root and logarithm of the detected samples, a Hilbert
+    transform by 1024-point overlap-save FFTs, the field rebuilt from amplitude and phase
+    and downshifted to DC).  FP64, written from the definition:
+      l_t   = ln sqrt(x_t) = 0.5 ln x_t                      (x: real intensity samples)
+      phi   = Hilbert(l), block k of the stream: the FFT of the nfft samples starting at
+              k nfft/2 - nfft/4 (zero outside the stream) is multiplied by the analytic
+              mask (1, 2 .. 2, 1, 0 .. 0), transformed back, and the imaginary parts of
+              its middle nfft/2 samples are phi for t in [k nfft/2, (k+1) nfft/2)
+      E_t   = exp(l_t) (cos phi_t + i sin phi_t)
+      s_t   = (E_t - A) exp(-i 2 pi frac(nu t))             (carrier removed, downshifted)
+    x holds T samples, T a multiple of nfft/2.  Returns s as complex128."""
+    x = np.asarray(x, dtype=np.float64)
+    T = x.shape[0]
+    hop, pad = nfft // 2, nfft // 4
+    if T % hop:
+        raise ValueError("T must be a multiple of nfft / 2")
+    l = 0.5 * np.log(x)
+    U = np.zeros(nfft)
+    U[0] = 1.0
+    U[1:nfft // 2] = 2.0
+    U[nfft // 2] = 1.0
+    phi = np.zeros(T)
+    for k in range(T // hop):
+        idx = np.arange(k * hop - pad, k * hop - pad + nfft)
+        inside = (idx >= 0) & (idx < T)
+        seg = np.zeros(nfft)
+        seg[inside] = l[idx[inside]]
+        za = np.fft.ifft(np.fft.fft(seg) * U)
+        phi[k * hop:(k + 1) * hop] = za.imag[pad:pad + hop]
+    E = np.exp(l) * (np.cos(phi) + 1j * np.sin(phi))
+    t = np.arange(T, dtype=np.float64)
+    frac = nu * t - np.floor(nu * t)
+    return (E - A) * np.exp(-2j * np.pi * frac)
