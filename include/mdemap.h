@@ -343,6 +343,25 @@ int ddlms_equalize(const float* d_x, int64_t B, int64_t N, const float* d_C, int
                    const double* h_g0, double mu, uint32_t* d_dec, float* d_z, double* d_h, double* d_g,
                    void* stream);
 
+/* ------------------------------------------------------------------ Kramers-Kronig front end */
+/* kk_frontend -- the receiver's first step (section "Experimental setup": square root and
+ * logarithm of the detected samples, the phase by a Hilbert transform with 1024-point
+ * overlap-save FFTs, the optical field rebuilt from amplitude and phase and downshifted to
+ * DC).  For real intensity samples x_t > 0, t < T:
+ *   l_t   = 0.5 ln x_t
+ *   phi   = Hilbert(l) in blocks: for output samples [512 k, 512 k + 512) the 1024 samples
+ *           starting at 512 k - 256 (zero outside the stream) are transformed, multiplied
+ *           by the analytic mask (1, 2 .. 2, 1, 0 .. 0), transformed back, and the
+ *           imaginary parts of the middle 512 are the phases
+ *   s_t   = (exp(l_t) e^{i phi_t} - A) e^{-i 2 pi frac(nu t)}
+ * FP32 FFTs and transcendental functions; the downshift phase frac(nu t) in FP64.
+ *   d_x    T float32 intensity samples (T a multiple of 512, samples > 0)
+ *   A      carrier amplitude removed from the rebuilt field (finite, >= 0)
+ *   nu     downshift frequency in cycles per sample (finite)
+ *   d_out  out: T complex float32 samples (re, im)
+ * Returns MD_OK (T = 0 enqueues nothing), MD_EINVAL, MD_EHIP. */
+int kk_frontend(const float* d_x, int64_t T, float A, double nu, float* d_out, void* stream);
+
 /* ------------------------------------------------------------------ peak calibration */
 /* Measured rates of what the kernels above are bound by, on the current device: the
  * roofline denominators.  The datasheet gives no rate for the exponential unit, and code

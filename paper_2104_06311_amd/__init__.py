@@ -13,7 +13,7 @@ import torch
 from ._lib import MdemapError, PREC, check, lib
 
 __all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "RxStream", "release_cache",
-           "ddlms_equalize", "ubench", "UBENCH_KINDS", "MdemapError",
+           "ddlms_equalize", "kk_frontend", "ubench", "UBENCH_KINDS", "MdemapError",
            "log2_exact"]
 
 
@@ -189,6 +189,21 @@ def ddlms_equalize(x, C, h0, g0, mu: float, want_z: bool = True, want_taps: bool
                               _stream())
     check("ddlms_equalize", st)
     return dec, z, h, g
+
+
+def kk_frontend(x, A: float, nu: float, out=None):
+    """Kramers-Kronig front end (see kk_frontend in mdemap.h): x is a 1-D float32 device
+    tensor of T intensity samples (T a multiple of 512); returns T complex64 samples."""
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.float32 or x.dim() != 1 or not x.is_cuda:
+        raise ValueError("x must be a 1-D float32 device tensor")
+    x = x.contiguous()
+    T = x.shape[0]
+    if out is None:
+        out = torch.empty(T, dtype=torch.complex64, device=x.device)
+    elif out.dtype != torch.complex64 or out.shape != (T,) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous complex64 tensor of T samples")
+    check("kk_frontend", lib().kk_frontend(_ptr(x), T, float(A), float(nu), _ptr(out), _stream()))
+    return out
 
 
 UBENCH_KINDS = {"exp": 0, "add_f32": 1, "mfma_f16": 2, "mfma_bf16": 3, "mfma_f32": 4, "copy": 5}

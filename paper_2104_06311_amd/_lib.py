@@ -58,6 +58,7 @@ SIGNATURES = {
     "release_cache": (_I, []),
     "last_error": (ctypes.c_char_p, []),
     "ddlms_equalize": (_I, [_P, _I64, _I64, _P, _I, _P, _P, _D, _P, _P, _P, _P, _P]),
+    "kk_frontend": (_I, [_P, _I64, _F, _D, _P, _P]),
     "ubench": (_I, [_I, _I64, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P]),
     "mdemap_version": (_I, []),
 }

@@ -1,0 +1,122 @@
+// kk_frontend: the Kramers-Kronig front end of the paper's receiver (section "Experimental
+// setup", DSP-chain paragraph): square root and logarithm of the detected samples, the
+// phase by a Hilbert transform computed with 1024-point overlap-save FFTs, the field
+// rebuilt from amplitude and phase, the carrier removed and the result downshifted to DC.
+//
+// One workgroup per 512 output samples: it reads the 1024 samples around them (zero
+// outside the stream), takes l = 0.5 ln x, runs a 1024-point FFT in LDS, applies the
+// analytic-signal mask, transforms back, and keeps the middle 512 phases.  The FFT is a
+// radix-2 decimation-in-time over bit-reversed loads, in place: each stage's butterflies
+// touch disjoint pairs, one barrier per stage.  The inverse is conj(FFT(conj X)) / 1024.
+#include "common.hpp"
+
+namespace md {
+namespace {
+
+constexpr int kKkN = 1024;
+constexpr int kKkHop = 512;
+constexpr int kKkPad = 256;
+constexpr int kKkThreads = 256;
+
+__device__ __forceinline__ int bitrev10(int i) { return static_cast<int>(__brev(static_cast<unsigned>(i)) >> 22); }
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// In-place radix-2 DIT over a[] holding its input in bit-reversed order.
+__device__ __forceinline__ void fft1024(float2* a, const float2* tw) {
+  for (int lg = 1; lg <= 10; ++lg) {
+    const int half = 1 << (lg - 1);
+    const int stride = kKkN >> lg;            // twiddle index step: 1024 / L
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int bf = threadIdx.x + r * kKkThreads;
+      const int group = bf >> (lg - 1);
+      const int pos = bf & (half - 1);
+      const int i0 = (group << lg) + pos;
+      const int i1 = i0 + half;
+      const float2 u = a[i0];
+      const float2 v = cmul(a[i1], tw[pos * stride]);
+      a[i0] = make_float2(u.x + v.x, u.y + v.y);
+      a[i1] = make_float2(u.x - v.x, u.y - v.y);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kKkThreads) kk_kernel(const float* __restrict__ x, int64_t T, float A, double nu,
+                                                        float2* __restrict__ out) {
+  __shared__ float2 a[kKkN];
+  __shared__ float2 b[kKkN];
+  __shared__ float2 tw[kKkN / 2];
+  __shared__ float lmid[kKkHop];
+  const int tid = threadIdx.x;
+  const int64_t blk = blockIdx.x;
+  const int64_t start = blk * kKkHop - kKkPad;
+  for (int j = tid; j < kKkN / 2; j += kKkThreads) {
+    double s, c;
+    sincospi(static_cast<double>(j) / 512.0, &s, &c);   // exp(-2 pi i j / 1024)
+    tw[j] = make_float2(static_cast<float>(c), static_cast<float>(-s));
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = tid + q * kKkThreads;
+    const int64_t t = start + i;
+    const float l = (t >= 0 && t < T) ? 0.5f * logf(x[t]) : 0.0f;
+    a[bitrev10(i)] = make_float2(l, 0.0f);
+    if (i >= kKkPad && i < kKkPad + kKkHop) lmid[i - kKkPad] = l;
+  }
+  __syncthreads();
+  fft1024(a, tw);
+  // analytic mask (1, 2 .. 2, 1, 0 .. 0), conjugated into bit-reversed order
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = tid + q * kKkThreads;
+    const float m = (i == 0 || i == kKkN / 2) ? 1.0f : (i < kKkN / 2 ? 2.0f : 0.0f);
+    const float2 v = a[i];
+    b[bitrev10(i)] = make_float2(m * v.x, -(m * v.y));
+  }
+  __syncthreads();
+  fft1024(b, tw);
+  // middle 512 samples: phase = Im(conj(B) / 1024) = -Im(B) / 1024
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int i = kKkPad + tid + q * kKkThreads;
+    const float phi = -b[i].y * (1.0f / kKkN);
+    const float amp = expf(lmid[i - kKkPad]);
+    float sp, cp;
+    sincosf(phi, &sp, &cp);
+    const float er = amp * cp - A;
+    const float ei = amp * sp;
+    const int64_t t = start + i;
+    const double ph = nu * static_cast<double>(t);
+    const double frac = ph - floor(ph);
+    double rs, rc;
+    sincospi(2.0 * frac, &rs, &rc);                    // exp(-2 pi i frac) = (rc, -rs)
+    const float2 rot = make_float2(static_cast<float>(rc), static_cast<float>(-rs));
+    out[t] = cmul(make_float2(er, ei), rot);
+  }
+}
+
+}  // namespace
+}  // namespace md
+
+extern "C" {
+
+int kk_frontend(const float* d_x, int64_t T, float A, double nu, float* d_out, void* stream) {
+  using namespace md;
+  if (T < 0 || T % kKkHop != 0) return fail(MD_EINVAL, "kk_frontend: T must be a non-negative multiple of 512");
+  if (!std::isfinite(A) || A < 0.0f) return fail(MD_EINVAL, "kk_frontend: A must be finite and >= 0");
+  if (!std::isfinite(nu)) return fail(MD_EINVAL, "kk_frontend: nu must be finite");
+  if (T == 0) return MD_OK;
+  if (d_x == nullptr || d_out == nullptr) return fail(MD_EINVAL, "kk_frontend: d_x and d_out are required");
+  const int64_t blocks = T / kKkHop;
+  if (blocks > 0x7fffffff) return fail(MD_EINVAL, "kk_frontend: T too large");
+  hipLaunchKernelGGL(kk_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kKkThreads), 0,
+                     static_cast<hipStream_t>(stream), d_x, T, A, nu, reinterpret_cast<float2*>(d_out));
+  MD_LAUNCH_CHECK("kk_kernel launch");
+  return MD_OK;
+}
+
+}  // extern "C"

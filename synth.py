@@ -194,3 +194,20 @@ def equaliser_input(B: int, N: int, M: int = 16, a: complex = 0.95 + 0.1j, b: co
     x[1::2] = isi * s[:N + 1] + np.conj(isi) * s[1:N + 2]
     x += sig * (rng.standard_normal(x.shape) + 1j * rng.standard_normal(x.shape))
     return x.astype(np.complex64), tx[:N + 1].astype(np.uint32), C.astype(np.complex64), labels
+
+
+def kk_input(T: int, A: float = 1.5, K: int = 24, snr_db: float = 30.0, seed: int = SEED_BASE + 6):
+    """Seeded detected intensity of a Kramers-Kronig receiver: a carrier A plus a signal of
+    K random tones on the positive FFT bins 1..K of a 1024-point block (|s| <= 0.3 A, so
+    the field is minimum phase) with a little real noise on the intensity.  Returns
+    (x (T,) float32 intensities, s (T,) complex128 the signal)."""
+    rng = np.random.default_rng(seed)
+    c = rng.standard_normal(K) + 1j * rng.standard_normal(K)
+    c *= 0.3 * A / np.sum(np.abs(c))
+    t = np.arange(T)
+    s = np.zeros(T, dtype=np.complex128)
+    for k in range(1, K + 1):
+        s += c[k - 1] * np.exp(2j * np.pi * k * t / 1024)
+    x = np.abs(A + s) ** 2
+    x = x * (1.0 + 10.0 ** (-snr_db / 20.0) * rng.standard_normal(T))
+    return x.astype(np.float32), s

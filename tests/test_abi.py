@@ -142,3 +142,17 @@ def test_equaliser_argument_validation_before_device_work():
     assert L.ddlms_equalize(*args(10, 1 << 40, 16, 0.01)) == -1
     assert b"ddlms_equalize" in L.last_error()
     assert L.ddlms_equalize(*args(0, 10, 16, 0.01)) == 0          # no instances: nothing to do
+
+
+def test_kk_argument_validation_before_device_work():
+    from paper_2104_06311_amd._lib import lib
+    L = lib()
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: validation fails first
+    assert L.kk_frontend(fake, 1000, 1.0, 0.0, fake, None) == -1          # not a multiple of 512
+    assert L.kk_frontend(fake, -512, 1.0, 0.0, fake, None) == -1
+    assert L.kk_frontend(fake, 1024, -1.0, 0.0, fake, None) == -1
+    assert L.kk_frontend(fake, 1024, float("nan"), 0.0, fake, None) == -1
+    assert L.kk_frontend(fake, 1024, 1.0, float("inf"), fake, None) == -1
+    assert L.kk_frontend(None, 1024, 1.0, 0.0, fake, None) == -1
+    assert b"kk_frontend" in L.last_error()
+    assert L.kk_frontend(None, 0, 1.0, 0.0, None, None) == 0
