@@ -239,6 +239,24 @@ def extra_ddlms(md, B=262144, N=256):
             "symbol_error_rate_second_half": ser, "bytes_per_symbol": 2 * 8 + 4 + 8}
 
 
+def extra_kk(md, T=1 << 25):
+    """Kramers-Kronig front end over 2^25 intensity samples (8 ADC buffers of 2^22; one
+    seeded buffer repeated), carrier 1.5, downshift 0.129 cycles per sample."""
+    import torch
+    import synth
+    buf = 1 << 22
+    x, _ = synth.kk_input(buf)
+    xd = torch.from_numpy(x).cuda().repeat(T // buf).contiguous()
+    out = torch.empty(T, dtype=torch.complex64, device="cuda")
+    t = timed(lambda: md.kk_frontend(xd, 1.5, 0.129, out=out), reps=5)
+    rate = T / (t * 1e-3)
+    # two 1024-point complex FFTs (5 N log2 N flop each) per 512 output samples
+    fft_flop = 2 * 5 * 1024 * 10 / 512
+    return {"samples": T, "ms": t, "samples_per_s": rate, "vs_4_gsps": rate / 4e9,
+            "fft_flop_per_sample": fft_flop, "fft_flop_per_s": rate * fft_flop,
+            "bytes_per_sample": 12, "bytes_per_s": rate * 12}
+
+
 def extra_16d(md, steps, pairs):
     """16D M = 65536 (16 bits), N = 1e6 at 10 and 16 dB: exact vs max-log vs a learned
     16 -> 512 -> 512 -> 16 network trained on `pairs` (y, exact LLR) pairs per SNR point."""
@@ -530,6 +548,7 @@ def main():
         out["detail"]["16d"] = extra_16d(md, args.learn_steps_16d, args.learn_pairs_16d)
         out["detail"]["4d"] = extra_4d(md)
         out["detail"]["ddlms"] = extra_ddlms(md)
+        out["detail"]["kk"] = extra_kk(md)
         out["detail"]["rx_stream"] = extra_rx(md, args.rx_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl.X, wl.labels, 9.0, args.cpu_seconds)
