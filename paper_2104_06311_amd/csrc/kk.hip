@@ -6,8 +6,9 @@
 // One workgroup per 512 output samples: it reads the 1024 samples around them (zero
 // outside the stream), takes l = 0.5 ln x, runs a 1024-point FFT in LDS, applies the
 // analytic-signal mask, transforms back, and keeps the middle 512 phases.  The FFT is a
-// radix-2 decimation-in-time over bit-reversed loads, in place: each stage's butterflies
-// touch disjoint pairs, one barrier per stage.  The inverse is conj(FFT(conj X)) / 1024.
+// radix-4 decimation-in-time over base-4 digit-reversed loads, in place: five stages of
+// one butterfly per thread on disjoint quadruples, one barrier per stage.  The inverse is
+// conj(FFT(conj X)) / 1024.
 #include "common.hpp"
 
 namespace md {
@@ -18,29 +19,40 @@ constexpr int kKkHop = 512;
 constexpr int kKkPad = 256;
 constexpr int kKkThreads = 256;
 
-__device__ __forceinline__ int bitrev10(int i) { return static_cast<int>(__brev(static_cast<unsigned>(i)) >> 22); }
+// reversal of the five base-4 digits of a 10-bit index: the bit reversal with each bit
+// pair swapped back
+__device__ __forceinline__ int digrev4(int i) {
+  const int r = static_cast<int>(__brev(static_cast<unsigned>(i)) >> 22);
+  return ((r & 0x155) << 1) | ((r & 0x2AA) >> 1);
+}
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place radix-2 DIT over a[] holding its input in bit-reversed order.
+// In-place radix-4 DIT over a[] holding its input in digit-reversed order; stage s
+// combines four transforms of length L/4 into length L = 4^s with twiddles W_L^{k pos}.
 __device__ __forceinline__ void fft1024(float2* a, const float2* tw) {
-  for (int lg = 1; lg <= 10; ++lg) {
-    const int half = 1 << (lg - 1);
-    const int stride = kKkN >> lg;            // twiddle index step: 1024 / L
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int bf = threadIdx.x + r * kKkThreads;
-      const int group = bf >> (lg - 1);
-      const int pos = bf & (half - 1);
-      const int i0 = (group << lg) + pos;
-      const int i1 = i0 + half;
-      const float2 u = a[i0];
-      const float2 v = cmul(a[i1], tw[pos * stride]);
-      a[i0] = make_float2(u.x + v.x, u.y + v.y);
-      a[i1] = make_float2(u.x - v.x, u.y - v.y);
-    }
+  for (int st = 1; st <= 5; ++st) {
+    const int lq = 2 * (st - 1);               // log2 of a quarter of L
+    const int q = 1 << lq;
+    const int step = kKkN >> (2 * st);         // twiddle index step: 1024 / L
+    const int g = threadIdx.x >> lq;
+    const int p = threadIdx.x & (q - 1);
+    const int i0 = (g << (2 * st)) + p;
+    const int i1 = i0 + q, i2 = i1 + q, i3 = i2 + q;
+    const float2 a0 = a[i0];
+    const float2 a1 = cmul(a[i1], tw[p * step]);
+    const float2 a2 = cmul(a[i2], tw[2 * p * step]);
+    const float2 a3 = cmul(a[i3], tw[3 * p * step]);
+    const float2 t0 = make_float2(a0.x + a2.x, a0.y + a2.y);
+    const float2 t1 = make_float2(a0.x - a2.x, a0.y - a2.y);
+    const float2 t2 = make_float2(a1.x + a3.x, a1.y + a3.y);
+    const float2 t3 = make_float2(a1.x - a3.x, a1.y - a3.y);
+    a[i0] = make_float2(t0.x + t2.x, t0.y + t2.y);
+    a[i2] = make_float2(t0.x - t2.x, t0.y - t2.y);
+    a[i1] = make_float2(t1.x + t3.y, t1.y - t3.x);   // t1 - i t3
+    a[i3] = make_float2(t1.x - t3.y, t1.y + t3.x);   // t1 + i t3
     __syncthreads();
   }
 }
@@ -49,12 +61,12 @@ __global__ void __launch_bounds__(kKkThreads) kk_kernel(const float* __restrict_
                                                         float2* __restrict__ out) {
   __shared__ float2 a[kKkN];
   __shared__ float2 b[kKkN];
-  __shared__ float2 tw[kKkN / 2];
+  __shared__ float2 tw[3 * kKkN / 4];
   __shared__ float lmid[kKkHop];
   const int tid = threadIdx.x;
   const int64_t blk = blockIdx.x;
   const int64_t start = blk * kKkHop - kKkPad;
-  for (int j = tid; j < kKkN / 2; j += kKkThreads) {
+  for (int j = tid; j < 3 * kKkN / 4; j += kKkThreads) {
     double s, c;
     sincospi(static_cast<double>(j) / 512.0, &s, &c);   // exp(-2 pi i j / 1024)
     tw[j] = make_float2(static_cast<float>(c), static_cast<float>(-s));
@@ -64,18 +76,18 @@ __global__ void __launch_bounds__(kKkThreads) kk_kernel(const float* __restrict_
     const int i = tid + q * kKkThreads;
     const int64_t t = start + i;
     const float l = (t >= 0 && t < T) ? 0.5f * logf(x[t]) : 0.0f;
-    a[bitrev10(i)] = make_float2(l, 0.0f);
+    a[digrev4(i)] = make_float2(l, 0.0f);
     if (i >= kKkPad && i < kKkPad + kKkHop) lmid[i - kKkPad] = l;
   }
   __syncthreads();
   fft1024(a, tw);
-  // analytic mask (1, 2 .. 2, 1, 0 .. 0), conjugated into bit-reversed order
+  // analytic mask (1, 2 .. 2, 1, 0 .. 0), conjugated into digit-reversed order
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int i = tid + q * kKkThreads;
     const float m = (i == 0 || i == kKkN / 2) ? 1.0f : (i < kKkN / 2 ? 2.0f : 0.0f);
     const float2 v = a[i];
-    b[bitrev10(i)] = make_float2(m * v.x, -(m * v.y));
+    b[digrev4(i)] = make_float2(m * v.x, -(m * v.y));
   }
   __syncthreads();
   fft1024(b, tw);
