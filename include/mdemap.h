@@ -29,10 +29,13 @@
  *     grows on demand and frees in release_cache().  Calls on one stream are
  *     ordered; calls that overlap on different streams use different workspaces.
  *   - Labels are checked to be a permutation of [0, M): on the host the first time
- *     a given label buffer is seen (a synchronous copy, skipped while the stream is
- *     being captured into a graph), and on the device in every call (an invalid
- *     label set turns every output of that call into NaN).
- *   - Limits: 2 <= M <= 65536 and a power of two; 1 <= D <= 30; N >= 0.
+ *     a given label buffer (device, address, M) is seen (a synchronous copy, skipped
+ *     while the stream is being captured into a graph), and on the device in every
+ *     call (an invalid label set turns every output of that call into NaN).  Labels
+ *     rewritten in place at an address already checked are caught by the device check
+ *     only; release_cache() forgets the checked addresses.
+ *   - Limits: 2 <= M <= 65536 and a power of two; 1 <= D <= 30; N >= 0, and
+ *     N <= 2^31 - 1 symbols per llr_exact / llr_maxlog call.
  */
 #ifndef MDEMAP_H
 #define MDEMAP_H
@@ -164,6 +167,17 @@ int gmi_reduce(const float* d_llr, int64_t N, int m, const uint32_t* d_tx,
 int ber_count(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels,
               uint64_t* d_bit_errors, uint64_t* d_errors, void* stream);
 
+/* q_factor_db -- the Q-factor the paper reports for its measured bit-error rates (Results
+ * section: Q computed from the BER; the paper does not print the relation), by the
+ * Gaussian-tail relation BER = erfc(Q / sqrt 2) / 2:
+ *   BER = errors / n_bits,  *d_q_db = 20 log10( sqrt2 erfcinv(2 BER) )
+ * evaluated in FP64 on the device.  NaN when BER = 0 or BER >= 1/2 (no finite Q).
+ *   d_errors  1 uint64 bit-error count (device; ber_count's d_errors output)
+ *   n_bits    number of bits the count is over (> 0), e.g. N m
+ *   d_q_db    out: 1 double (device)
+ * Returns MD_OK, MD_EINVAL (n_bits <= 0, NULL pointer), MD_EHIP. */
+int q_factor_db(const uint64_t* d_errors, int64_t n_bits, double* d_q_db, void* stream);
+
 /* ------------------------------------------------------------------ learned demapper */
 /* A small network f: R^D -> R^m approximating the exact LLRs, trained on the GPU by the
  * library's own kernels on (y, exact-LLR) pairs that llr_exact produces; the exact path
@@ -172,7 +186,8 @@ int ber_count(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const 
  * library's design:
  *   f(y) = s_out (W3 g(W2 g(W1 (s_in y) + b1) + b2) + b3),  hidden width H in both
  *          layers, fixed scales s_in, s_out (default 1; mlp_set_scales),
- *   g(a) = a (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3))) / 2   (GELU, tanh form),
+ *   g(a) = a Phi(a), Phi the standard normal distribution function (GELU; the kernels
+ *          evaluate Phi by Abramowitz & Stegun 7.1.26, absolute error below 3e-7 in FP32),
  *   loss = mean_b sum_k p_bk softplus(-f_bk) + (1 - p_bk) softplus(f_bk),
  *          p_bk = sigmoid(L_target_bk)   (distillation of the exact bit posteriors),
  *   Adam (beta1 0.9, beta2 0.999, eps 1e-8) on FP32 master weights.
@@ -355,7 +370,11 @@ int ddlms_equalize(const float* d_x, int64_t B, int64_t N, const float* d_C, int
  *           imaginary parts of the middle 512 are the phases
  *   s_t   = (exp(l_t) e^{i phi_t} - A) e^{-i 2 pi frac(nu t)}
  * FP32 FFTs and transcendental functions; the downshift phase frac(nu t) in FP64.
- *   d_x    T float32 intensity samples (T a multiple of 512, samples > 0)
+ * A detected intensity is positive; a sample below 2^-126 (zero or negative after noise,
+ * or NaN) is taken as 2^-126, the smallest normal float, so that one bad sample gives a
+ * large negative log-amplitude instead of spreading NaN over the 1024-sample windows
+ * around it.
+ *   d_x    T float32 intensity samples (T a multiple of 512)
  *   A      carrier amplitude removed from the rebuilt field (finite, >= 0)
  *   nu     downshift frequency in cycles per sample (finite)
  *   d_out  out: T complex float32 samples (re, im)

@@ -65,6 +65,7 @@ def _load():
     lib.orc_mlp_forward.argtypes = [I, I, I, I, P, P, P, P, P, P, Dbl, Dbl, P, I64, P]
     lib.orc_mlp_loss_grad.argtypes = [I, I, I, I, P, P, P, P, P, P, Dbl, Dbl, P, P, I64, P, P, P, P, P, P]
     lib.orc_mlp_loss_grad.restype = Dbl
+    lib.orc_gelu_eval.argtypes = [P, I64, P, P]
     lib.orc_adam_step.argtypes = [P, P, P, P, I64, I, Dbl, Dbl, Dbl, Dbl]
     lib.orc_ddlms.argtypes = [P, I64, I64, P, I, P, P, Dbl, P, P, P, P]
     lib.orc_num_threads.restype = I
@@ -248,6 +249,15 @@ class MLPParams:
         return [self.W1, self.b1, self.W2, self.b2, self.W3, self.b3]
 
 
+def gelu(a):
+    """(g(a), g'(a)) of the network's activation, GELU g(a) = a Phi(a), at the points a."""
+    a = _f64(np.atleast_1d(a))
+    g = np.empty_like(a)
+    dg = np.empty_like(a)
+    _load().orc_gelu_eval(_ptr(a), a.size, _ptr(g), _ptr(dg))
+    return g, dg
+
+
 def mlp_forward(p: MLPParams, y) -> np.ndarray:
     lib = _load()
     y = _f32(y)
@@ -326,7 +336,7 @@ def kk_field(x, A: float, nu: float, nfft: int = 1024):
     hop, pad = nfft // 2, nfft // 4
     if T % hop:
         raise ValueError("T must be a multiple of nfft / 2")
-    l = 0.5 * np.log(x)
+    l = 0.5 * np.log(np.fmax(x, 2.0 ** -126))   # samples below the smallest normal float are floored
     U = np.zeros(nfft)
     U[0] = 1.0
     U[1:nfft // 2] = 2.0

@@ -353,20 +353,26 @@ void orc_gmi(const double* llr, int64_t N, int m, const uint32_t* tx, const uint
 
 /* ------------------------------------------------------------------------- */
 /* MLP demapper reference: f(y) = s_out (W3 g(W2 g(W1 (s_in y) + b1) + b2) + b3) with fixed
- * (untrained) input and output scales s_in, s_out and the GELU activation in its tanh
- * form (Hendrycks & Gimpel):
- *   g(a) = a (1 + tanh(k (a + 0.044715 a^3))) / 2,  k = sqrt(2 / pi).
+ * (untrained) input and output scales s_in, s_out and the GELU activation (Hendrycks &
+ * Gimpel) in its exact form, the input times the standard normal distribution function:
+ *   g(a) = a Phi(a),  Phi(a) = erfc(-a / sqrt 2) / 2,
+ *   g'(a) = Phi(a) + a phi(a),  phi(a) = exp(-a^2 / 2) / sqrt(2 pi).
+ * (erfc rather than 1 + erf keeps Phi accurate in the lower tail.)
  * Weights are row-major [out][in].  Loss per sample:
  * sum_k p_k softplus(-f_k) + (1 - p_k) softplus(f_k) with p_k = sigmoid(L_target_k),
  * averaged over the batch. */
 static double orc_gelu(double a) {
-    const double k = sqrt(2.0 / M_PI);
-    return 0.5 * a * (1.0 + tanh(k * (a + 0.044715 * a * a * a)));
+    return 0.5 * a * erfc(-a / M_SQRT2);
 }
 static double orc_gelu_grad(double a) {
-    const double k = sqrt(2.0 / M_PI);
-    double th = tanh(k * (a + 0.044715 * a * a * a));
-    return 0.5 * (1.0 + th) + 0.5 * a * (1.0 - th * th) * k * (1.0 + 3.0 * 0.044715 * a * a);
+    return 0.5 * erfc(-a / M_SQRT2) + a * exp(-0.5 * a * a) / sqrt(2.0 * M_PI);
+}
+/* The activation and its derivative at n points (exposed for the oracle's own pins). */
+void orc_gelu_eval(const double* a, int64_t n, double* g, double* dg) {
+    for (int64_t i = 0; i < n; ++i) {
+        g[i] = orc_gelu(a[i]);
+        dg[i] = orc_gelu_grad(a[i]);
+    }
 }
 static double orc_sigmoid(double t) {
     return t >= 0.0 ? 1.0 / (1.0 + exp(-t)) : exp(t) / (1.0 + exp(t));

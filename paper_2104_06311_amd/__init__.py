@@ -44,6 +44,16 @@ def _dev(t: torch.Tensor, name: str, dtype: torch.dtype, ndim: int):
     return t
 
 
+def _out(out, shape, dtype: torch.dtype, device):
+    """A caller-given output tensor must be a contiguous device tensor of the right shape."""
+    if out is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    _dev(out, "out", dtype, len(shape))
+    if tuple(out.shape) != tuple(shape) or out.device != device:
+        raise ValueError(f"out must be {list(shape)} on {device}")
+    return out
+
+
 def log2_exact(M: int) -> int:
     m = int(M).bit_length() - 1
     if M < 2 or (1 << m) != M:
@@ -55,10 +65,20 @@ def awgn_sample(X: torch.Tensor, seed: int, offset: int, N: int, sigma: float, t
     """(tx uint32[N] as int32 storage, y float32[N, D]) for the channel defined in mdemap.h."""
     _dev(X, "X", torch.float32, 2)
     M, D = X.shape
+    if N < 0:
+        raise ValueError("N must be >= 0")
     if tx is None:
         tx = torch.empty(N, dtype=torch.int32, device=X.device)
+    else:
+        _dev(tx, "tx", torch.int32, 1)
+        if tx.shape[0] != N or tx.device != X.device:
+            raise ValueError("tx must hold N entries on X's device")
     if y is None:
         y = torch.empty((N, D), dtype=torch.float32, device=X.device)
+    else:
+        _dev(y, "y", torch.float32, 2)
+        if tuple(y.shape) != (N, D) or y.device != X.device:
+            raise ValueError("y must be [N, D] on X's device")
     st = lib().awgn_sample(_ptr(X), M, D, seed & (2 ** 64 - 1), offset & (2 ** 64 - 1), N, float(sigma),
                            _ptr(tx), _ptr(y), _stream())
     check("awgn_sample", st)
@@ -74,6 +94,8 @@ def _demap_args(X, labels, y):
         raise ValueError("labels must have M entries")
     if y.shape[1] != D:
         raise ValueError("y must have D columns")
+    if labels.device != X.device or y.device != X.device:
+        raise ValueError("X, labels and y must be on one device")
     return M, D, y.shape[0]
 
 
@@ -81,8 +103,7 @@ def llr_exact(X, labels, y, sigma2: float, prec: str = "fp32", out=None):
     """Exact bit-wise LLRs float32[N, m] (column k = label bit m-1-k, sign ln P0/P1)."""
     M, D, N = _demap_args(X, labels, y)
     m = log2_exact(M)
-    if out is None:
-        out = torch.empty((N, m), dtype=torch.float32, device=X.device)
+    out = _out(out, (N, m), torch.float32, X.device)
     st = lib().llr_exact(_ptr(X), _ptr(labels), M, D, _ptr(y), N, float(sigma2), PREC[prec], _ptr(out), _stream())
     check("llr_exact", st)
     return out
@@ -92,8 +113,7 @@ def llr_maxlog(X, labels, y, sigma2: float, out=None):
     """Max-log bit-wise LLRs float32[N, m]."""
     M, D, N = _demap_args(X, labels, y)
     m = log2_exact(M)
-    if out is None:
-        out = torch.empty((N, m), dtype=torch.float32, device=X.device)
+    out = _out(out, (N, m), torch.float32, X.device)
     st = lib().llr_maxlog(_ptr(X), _ptr(labels), M, D, _ptr(y), N, float(sigma2), _ptr(out), _stream())
     check("llr_maxlog", st)
     return out
@@ -104,7 +124,14 @@ def ber_count(llr, tx, labels, per_bit: bool = True):
     hard decision of column k is 1 where the LLR is negative."""
     _dev(llr, "llr", torch.float32, 2)
     _dev(tx, "tx", torch.int32, 1)
+    _dev(labels, "labels", torch.int32, 1)
     N, m = llr.shape
+    if tx.shape[0] != N:
+        raise ValueError("tx must have N entries")
+    if labels.shape[0] != (1 << m):
+        raise ValueError("labels must have 2^m entries")
+    if tx.device != llr.device or labels.device != llr.device:
+        raise ValueError("llr, tx and labels must be on one device")
     errors = torch.zeros(1, dtype=torch.int64, device=llr.device)
     bit_errors = torch.zeros(m, dtype=torch.int64, device=llr.device) if per_bit else None
     check("ber_count", lib().ber_count(_ptr(llr), N, m, _ptr(tx), _ptr(labels), _ptr(bit_errors), _ptr(errors),
@@ -112,21 +139,15 @@ def ber_count(llr, tx, labels, per_bit: bool = True):
     return errors, bit_errors
 
 
-def q_factor_db(ber: float) -> float:
-    """Q-factor in dB of a bit-error rate, 20 log10(sqrt(2) erfcinv(2 BER)) (host scalar;
-    Newton steps on math.erfc)."""
-    import math
-    if not 0.0 < ber < 0.5:
-        raise ValueError("BER must lie in (0, 0.5)")
-    target = 2.0 * ber
-    x = 1.0
-    for _ in range(100):
-        f = math.erfc(x) - target
-        step = f / (-2.0 / math.sqrt(math.pi) * math.exp(-x * x))
-        x -= step
-        if abs(step) < 1e-15 * max(1.0, abs(x)):
-            break
-    return 20.0 * math.log10(math.sqrt(2.0) * x)
+def q_factor_db(errors, n_bits: int):
+    """Q-factor in dB of a bit-error count (device int64[1] tensor, e.g. ber_count's first
+    output) over n_bits bits: a device float64[1] tensor, NaN where BER is 0 or >= 1/2."""
+    _dev(errors, "errors", torch.int64, 1)
+    if errors.shape[0] != 1:
+        raise ValueError("errors must hold one count")
+    q = torch.empty(1, dtype=torch.float64, device=errors.device)
+    check("q_factor_db", lib().q_factor_db(_ptr(errors), int(n_bits), _ptr(q), _stream()))
+    return q
 
 
 def llr_path_counts():
@@ -148,6 +169,8 @@ def gmi_reduce(llr, tx, labels, per_bit: bool = True, se: bool = True):
         raise ValueError("tx must have N entries")
     if labels.shape[0] != (1 << m):
         raise ValueError("labels must have 2^m entries")
+    if tx.device != llr.device or labels.device != llr.device:
+        raise ValueError("llr, tx and labels must be on one device")
     g = torch.empty(1, dtype=torch.float64, device=llr.device)
     gb = torch.empty(m, dtype=torch.float64, device=llr.device) if per_bit else None
     s = torch.empty(1, dtype=torch.float64, device=llr.device) if se else None
@@ -338,8 +361,7 @@ def llr_learned(mlp: MLP, y, out=None):
     if y.shape[1] != mlp.D:
         raise ValueError("y must have D columns")
     N = y.shape[0]
-    if out is None:
-        out = torch.empty((N, mlp.m), dtype=torch.float32, device=y.device)
+    out = _out(out, (N, mlp.m), torch.float32, y.device)
     check("llr_learned", lib().llr_learned(mlp.handle, _ptr(y), N, _ptr(out), _stream()))
     return out
 

@@ -32,6 +32,7 @@ SIGNATURES = {
     "llr_maxlog": (_I, [_P, _P, _I, _I, _P, _I64, _D, _P, _P]),
     "gmi_reduce": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P, _P]),
     "ber_count": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P]),
+    "q_factor_db": (_I, [_P, _I64, _P, _P]),
     "llr_path_counts": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "mlp_create": (_I, [_I, _I, _I, _U64, ctypes.POINTER(ctypes.c_void_p)]),
     "mlp_destroy": (_I, [_P]),

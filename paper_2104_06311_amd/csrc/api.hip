@@ -1,5 +1,6 @@
 // C entry points: argument validation on the host, then prep + kernel launches on the
 // caller's stream.  Nothing here computes on the host.
+#include <climits>
 #include <cmath>
 
 #include "common.hpp"
@@ -17,16 +18,33 @@ int check_constellation(const void* d_X, int M, int D) {
   return MD_OK;
 }
 
+}  // namespace
+
+namespace md {
+
+int check_demap_args(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y, int64_t N,
+                     double sigma2, int prec, const float* d_llr) {
+  int st = check_constellation(d_X, M, D);
+  if (st != MD_OK) return st;
+  if (!d_labels) return fail(MD_EINVAL, "labels pointer is NULL");
+  if (N < 0) return fail(MD_EINVAL, "N is negative");
+  // the fallback lists hold 32-bit symbol indices behind a 32-bit counter
+  if (N > INT32_MAX) return fail(MD_EINVAL, "N above 2^31 - 1 symbols in one call");
+  if (N > 0 && (!d_y || !d_llr)) return fail(MD_EINVAL, "y or llr pointer is NULL");
+  if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return fail(MD_EINVAL, "sigma2 must be finite and > 0");
+  if (prec != MD_PREC_FP32 && prec != MD_PREC_BF16) return fail(MD_EINVAL, "unknown precision");
+  return MD_OK;
+}
+
+}  // namespace md
+
+namespace {
+
 int demap(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y, int64_t N, double sigma2,
           int prec, bool maxlog, float* d_llr, void* stream) {
   md::set_error("");
-  int st = check_constellation(d_X, M, D);
+  int st = md::check_demap_args(d_X, d_labels, M, D, d_y, N, sigma2, prec, d_llr);
   if (st != MD_OK) return st;
-  if (!d_labels) return md::fail(MD_EINVAL, "labels pointer is NULL");
-  if (N < 0) return md::fail(MD_EINVAL, "N is negative");
-  if (N > 0 && (!d_y || !d_llr)) return md::fail(MD_EINVAL, "y or llr pointer is NULL");
-  if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return md::fail(MD_EINVAL, "sigma2 must be finite and > 0");
-  if (prec != MD_PREC_FP32 && prec != MD_PREC_BF16) return md::fail(MD_EINVAL, "unknown precision");
   int dev = 0;
   st = md::current_device(&dev);
   if (st != MD_OK) return st;
@@ -140,6 +158,16 @@ int ber_count(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const 
   st = md::workspace(s, md::ber_workspace_bytes(N, m), &ws);
   if (st != MD_OK) return st;
   return md::launch_ber(d_llr, N, m, d_tx, d_labels, d_bit_errors, d_errors, ws, s);
+}
+
+int q_factor_db(const uint64_t* d_errors, int64_t n_bits, double* d_q_db, void* stream) {
+  md::set_error("");
+  if (n_bits <= 0) return md::fail(MD_EINVAL, "n_bits must be > 0");
+  if (!d_errors || !d_q_db) return md::fail(MD_EINVAL, "errors or q pointer is NULL");
+  int dev = 0;
+  int st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  return md::launch_q_factor(d_errors, n_bits, d_q_db, as_stream(stream));
 }
 
 }  // extern "C"

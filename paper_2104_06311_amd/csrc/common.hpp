@@ -72,6 +72,10 @@ int check_labels_once(const uint32_t* d_labels, int M, hipStream_t stream);
 
 int current_device(int* dev);
 
+// Raises the dynamic-LDS limit of kernel `kern` to `bytes` on the current device.  The
+// attribute belongs to a (kernel, device) pair, so it is set once per pair.
+int set_lds_limit(const void* kern, int bytes);
+
 // ---------------------------------------------------------------- prepared constellation
 // Device-side view of a prepared constellation (label order).
 struct Prepared {

@@ -126,12 +126,20 @@ __global__ void gmi_output_kernel(const double* __restrict__ tot, int64_t N, int
 }
 
 // Hard decisions from LLR signs (bit 1 where L < 0) against the sent labels: bit-error
-// counts per LLR column, integer sums per block, summed in a fixed order by one block.
+// counts per LLR column, integer sums per block (column-major partials: column k of block b
+// at partials[k * nblocks + b]), then one block per column sums them in a fixed order and
+// one thread adds the columns.
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 __global__ void __launch_bounds__(kBlock) ber_partial_kernel(const float* __restrict__ llr, int64_t N, int m,
                                                              const uint32_t* __restrict__ tx,
                                                              const uint32_t* __restrict__ labels,
                                                              unsigned long long* __restrict__ partials) {
-  __shared__ unsigned long long sh[kBlock];
+  __shared__ unsigned long long sh[kBlock / 64][kMaxM];
   uint32_t cnt[kMaxM];
 #pragma unroll
   for (int k = 0; k < kMaxM; ++k) cnt[k] = 0;
@@ -148,43 +156,59 @@ __global__ void __launch_bounds__(kBlock) ber_partial_kernel(const float* __rest
       }
     }
   }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < kMaxM; ++k) {
     if (k < m) {
-      sh[threadIdx.x] = cnt[k];
-      __syncthreads();
-      for (int w = kBlock / 2; w >= 1; w >>= 1) {
-        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) partials[static_cast<int64_t>(blockIdx.x) * m + k] = sh[0];
-      __syncthreads();
+      const unsigned long long v = wave_sum_u64(cnt[k]);
+      if (lane == 0) sh[wave][k] = v;
     }
+  }
+  __syncthreads();
+  if (threadIdx.x < m) {
+    unsigned long long a = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) a += sh[w][threadIdx.x];
+    partials[static_cast<int64_t>(threadIdx.x) * gridDim.x + blockIdx.x] = a;
   }
 }
 
-__global__ void __launch_bounds__(kBlock) ber_final_kernel(const unsigned long long* __restrict__ partials,
-                                                           int nblocks, int m,
-                                                           unsigned long long* __restrict__ bit_errors,
-                                                           unsigned long long* __restrict__ errors) {
-  __shared__ unsigned long long sh[kBlock];
-  unsigned long long total = 0;
-  for (int k = 0; k < m; ++k) {
-    unsigned long long a = 0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock) a += partials[static_cast<int64_t>(b) * m + k];
-    sh[threadIdx.x] = a;
-    __syncthreads();
-    for (int w = kBlock / 2; w >= 1; w >>= 1) {
-      if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-      if (bit_errors) bit_errors[k] = sh[0];
-      total += sh[0];
-    }
-    __syncthreads();
+// One block per column k: the block partials of the column summed in a fixed order.
+__global__ void __launch_bounds__(kBlock) ber_column_kernel(const unsigned long long* __restrict__ partials,
+                                                            int nblocks, unsigned long long* __restrict__ totals) {
+  __shared__ unsigned long long sh[kBlock / 64];
+  const int k = blockIdx.x;
+  unsigned long long a = 0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) a += partials[static_cast<int64_t>(k) * nblocks + b];
+  a = wave_sum_u64(a);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+    totals[k] = t;
   }
-  if (threadIdx.x == 0) errors[0] = total;
+}
+
+__global__ void ber_output_kernel(const unsigned long long* __restrict__ totals, int m,
+                                  unsigned long long* __restrict__ bit_errors, unsigned long long* __restrict__ errors) {
+  if (threadIdx.x != 0) return;
+  unsigned long long t = 0;
+  for (int k = 0; k < m; ++k) {
+    if (bit_errors) bit_errors[k] = totals[k];
+    t += totals[k];
+  }
+  errors[0] = t;
+}
+
+// Q-factor of a bit-error count: BER = errors / n_bits, Q = sqrt2 erfcinv(2 BER) (the
+// Gaussian-tail relation BER = erfc(Q / sqrt2) / 2), reported as 20 log10 Q; NaN where no
+// finite Q exists (BER = 0 or BER >= 1/2).
+__global__ void q_factor_kernel(const unsigned long long* __restrict__ errors, int64_t n_bits, double* __restrict__ q) {
+  if (threadIdx.x != 0) return;
+  const double ber = static_cast<double>(errors[0]) / static_cast<double>(n_bits);
+  q[0] = (ber > 0.0 && ber < 0.5) ? 20.0 * log10(1.4142135623730951 * erfcinv(2.0 * ber)) : __builtin_nan("");
 }
 
 int gmi_blocks(int64_t N) {
@@ -231,19 +255,31 @@ int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const
 }
 
 size_t ber_workspace_bytes(int64_t N, int m) {
-  return carve_size(sizeof(unsigned long long) * static_cast<size_t>(gmi_blocks(N)) * m);
+  return carve_size(sizeof(unsigned long long) * static_cast<size_t>(gmi_blocks(N)) * m) +
+         carve_size(sizeof(unsigned long long) * m);
 }
 
 int launch_ber(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels,
                uint64_t* d_bit_errors, uint64_t* d_errors, char* ws, hipStream_t stream) {
   const int nb = gmi_blocks(N);
   auto* partials = reinterpret_cast<unsigned long long*>(ws);
+  auto* totals = partials + carve_size(sizeof(unsigned long long) * static_cast<size_t>(nb) * m) /
+                                sizeof(unsigned long long);
   hipLaunchKernelGGL(ber_partial_kernel, dim3(nb), dim3(kBlock), 0, stream, d_llr, N, m, d_tx, d_labels, partials);
   MD_LAUNCH_CHECK("ber_partial_kernel launch");
-  hipLaunchKernelGGL(ber_final_kernel, dim3(1), dim3(kBlock), 0, stream, partials, nb, m,
+  hipLaunchKernelGGL(ber_column_kernel, dim3(m), dim3(kBlock), 0, stream, partials, nb, totals);
+  MD_LAUNCH_CHECK("ber_column_kernel launch");
+  hipLaunchKernelGGL(ber_output_kernel, dim3(1), dim3(64), 0, stream, totals, m,
                      reinterpret_cast<unsigned long long*>(d_bit_errors),
                      reinterpret_cast<unsigned long long*>(d_errors));
-  MD_LAUNCH_CHECK("ber_final_kernel launch");
+  MD_LAUNCH_CHECK("ber_output_kernel launch");
+  return MD_OK;
+}
+
+int launch_q_factor(const uint64_t* d_errors, int64_t n_bits, double* d_q, hipStream_t stream) {
+  hipLaunchKernelGGL(q_factor_kernel, dim3(1), dim3(64), 0, stream,
+                     reinterpret_cast<const unsigned long long*>(d_errors), n_bits, d_q);
+  MD_LAUNCH_CHECK("q_factor_kernel launch");
   return MD_OK;
 }
 

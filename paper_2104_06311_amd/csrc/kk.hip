@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(kKkThreads) kk_kernel(const float* __restrict_
   for (int q = 0; q < 4; ++q) {
     const int i = tid + q * kKkThreads;
     const int64_t t = start + i;
-    const float l = (t >= 0 && t < T) ? 0.5f * logf(x[t]) : 0.0f;
+    const float l = (t >= 0 && t < T) ? 0.5f * logf(fmaxf(x[t], 0x1p-126f)) : 0.0f;   // floor: see kk_frontend
     a[digrev4(i)] = make_float2(l, 0.0f);
     if (i >= kKkPad && i < kKkPad + kKkHop) lmid[i - kKkPad] = l;
   }

@@ -425,11 +425,9 @@ int launch_fast_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
   if (chunk_tiles < G) return fail(MD_EUNSUPPORTED, "constellation fragments do not fit in LDS");
   const size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
   auto kern = llr_fast_kernel<KS, WAVES, MB, SB, MAXLOG>;
-  static bool attr_done = false;
-  if (!attr_done) {
-    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    attr_done = true;
+  {
+    const int st_attr = set_lds_limit(reinterpret_cast<const void*>(kern), 160 * 1024);
+    if (st_attr != MD_OK) return st_attr;
   }
   int dev = 0, ncu = 0, occ = 0;
   MD_HIP_TRY(hipGetDevice(&dev));
@@ -581,11 +579,9 @@ int launch_wide_t(const Prepared& P, int M, const float* d_y, int D, float* d_ll
   if (chunk_tiles < G) return fail(MD_EUNSUPPORTED, "constellation fragments do not fit in LDS");
   const size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
   auto kern = llr_wide_kernel<KS, WAVES, MB, NW>;
-  static bool attr_done = false;
-  if (!attr_done) {
-    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    attr_done = true;
+  {
+    const int st_attr = set_lds_limit(reinterpret_cast<const void*>(kern), 160 * 1024);
+    if (st_attr != MD_OK) return st_attr;
   }
   int dev = 0, ncu = 0;
   MD_HIP_TRY(hipGetDevice(&dev));
@@ -898,11 +894,9 @@ int launch_bf16_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
   if (chunk_tiles < 1) return fail(MD_EUNSUPPORTED, "constellation fragments do not fit in LDS");
   const size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
   auto kern = llr_bf16_kernel<KS, WAVES, MB, SB>;
-  static bool attr_done = false;
-  if (!attr_done) {
-    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    attr_done = true;
+  {
+    const int st_attr = set_lds_limit(reinterpret_cast<const void*>(kern), 160 * 1024);
+    if (st_attr != MD_OK) return st_attr;
   }
   int dev = 0, ncu = 0, occ = 0;
   MD_HIP_TRY(hipGetDevice(&dev));

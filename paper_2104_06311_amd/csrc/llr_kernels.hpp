@@ -37,4 +37,10 @@ size_t ber_workspace_bytes(int64_t N, int m);
 int launch_ber(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels,
                uint64_t* d_bit_errors, uint64_t* d_errors, char* ws, hipStream_t stream);
 
+// Host-side checks shared by the demapping entry points (the MD_* status, last_error set).
+int check_demap_args(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y, int64_t N,
+                     double sigma2, int prec, const float* d_llr);
+
+int launch_q_factor(const uint64_t* d_errors, int64_t n_bits, double* d_q, hipStream_t stream);
+
 }  // namespace md

@@ -1,8 +1,8 @@
 // Learned demapper: a D -> H -> H -> m GELU network trained on (y, exact LLR) pairs by
 // the library's own BF16 MFMA kernels, and its inference.
 //
-//   f(y) = W3 g(W2 g(W1 y + b1) + b2) + b3,  g(a) = a sigmoid(2k (a + 0.044715 a^3)),
-//   k = sqrt(2/pi)  (the tanh form of GELU: a (1 + tanh(k (a + 0.044715 a^3))) / 2).
+//   f(y) = W3 g(W2 g(W1 y + b1) + b2) + b3,  g(a) = a Phi(a)  (GELU; Phi is the standard
+//   normal distribution function).
 //   loss = mean over the batch of sum_k p_k softplus(-f_k) + (1 - p_k) softplus(f_k),
 //   p_k = sigmoid(L_exact_k), so that dloss/df = (sigmoid(f) - p) / B.
 //
@@ -34,24 +34,38 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr float kGeluK2 = 1.5957691216057308f;    // 2 sqrt(2/pi)
-constexpr float kGeluC = 0.044715f;
+// GELU, g(a) = a Phi(a).  The upper tail Q(u) = erfc(u / sqrt 2) / 2 at u = |a| comes from
+// Abramowitz & Stegun 7.1.26 (Hastings' approximation; its error in erf is below 1.5e-7):
+//   erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^(-x^2),  t = 1 / (1 + p x),  x >= 0,
+// so Phi(a) = 1 - Q(|a|) for a >= 0 and Q(|a|) below, with an absolute error under 1e-7.
+// The derivative g'(a) = Phi(a) + a phi(a) reuses the same e^(-a^2/2).  The coefficients
+// below are A&S's halved (Q = erfc / 2) and p / sqrt 2 (x = |a| / sqrt 2).
+constexpr float kAsP = static_cast<float>(0.3275911 / 1.4142135623730951);
+constexpr float kAs1 = 0.5f * 0.254829592f;
+constexpr float kAs2 = 0.5f * -0.284496736f;
+constexpr float kAs3 = 0.5f * 1.421413741f;
+constexpr float kAs4 = 0.5f * -1.453152027f;
+constexpr float kAs5 = 0.5f * 1.061405429f;
+constexpr float kHalfLog2e = -0.72134752044448170f;   // -log2(e) / 2
+constexpr float kInvSqrt2Pi = 0.39894228040143268f;  // 1 / sqrt(2 pi)
 
-// The exponent of the sigmoid, -log2(e) 2k (a + c a^3), is evaluated as a (e1 + e2 a^2):
-// two multiplications and one fused multiply-add per activation.
-constexpr float kGeluE1 = static_cast<float>(-1.5957691216057308 * 1.4426950408889634);
-constexpr float kGeluE2 = static_cast<float>(-1.5957691216057308 * 0.044715 * 1.4426950408889634);
-
-// g(a) = a / (1 + 2^(a (e1 + e2 a^2))); exact limits a (a -> +inf) and -0 (a -> -inf)
+// Phi(a) and e^(-a^2/2); Phi is exactly 0 or 1 once the exponential underflows.
+__device__ __forceinline__ float normal_cdf(float a, float* ex) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(kAsP, fabsf(a), 1.0f));
+  const float e = __builtin_amdgcn_exp2f(kHalfLog2e * (a * a));
+  const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, kAs5, kAs4), kAs3), kAs2), kAs1);
+  const float q = poly * e;
+  *ex = e;
+  return a >= 0.0f ? 1.0f - q : q;
+}
 __device__ __forceinline__ float gelu(float a) {
-  const float w = a * fmaf(kGeluE2, a * a, kGeluE1);
-  return a * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(w));
+  float e;
+  return a * normal_cdf(a, &e);
 }
 __device__ __forceinline__ float gelu_grad(float a) {
-  const float a2 = a * a;
-  const float s = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(a * fmaf(kGeluE2, a2, kGeluE1)));
-  const float dv = kGeluK2 * fmaf(3.0f * kGeluC, a2, 1.0f);
-  return s + a * s * (1.0f - s) * dv;
+  float e;
+  const float p = normal_cdf(a, &e);
+  return fmaf(a * kInvSqrt2Pi, e, p);
 }
 __device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
 __device__ __forceinline__ float sigmoidf_acc(float t) {
@@ -863,11 +877,9 @@ template <int NRB>
 int infer_fused_t(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s) {
   const InferLayout L = infer_layout(p->H, p->D);
   auto kern = mlp_infer_kernel<NRB>;
-  static bool attr_done = false;
-  if (!attr_done) {
-    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   160 * 1024));
-    attr_done = true;
+  {
+    const int st_attr = set_lds_limit(reinterpret_cast<const void*>(kern), 160 * 1024);
+    if (st_attr != MD_OK) return st_attr;
   }
   int dev = 0, ncu = 0;
   MD_HIP_TRY(hipGetDevice(&dev));
@@ -891,11 +903,9 @@ template <int NRB, int KS1>
 int infer_stream_t(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s) {
   const InferLayout L = infer_layout(p->H, p->D);
   auto kern = mlp_infer_stream_kernel<NRB, KS1>;
-  static bool attr_done = false;
-  if (!attr_done) {
-    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   160 * 1024));
-    attr_done = true;
+  {
+    const int st_attr = set_lds_limit(reinterpret_cast<const void*>(kern), 160 * 1024);
+    if (st_attr != MD_OK) return st_attr;
   }
   int dev = 0, ncu = 0;
   MD_HIP_TRY(hipGetDevice(&dev));

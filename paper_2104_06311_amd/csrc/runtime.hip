@@ -3,6 +3,7 @@
 #include <map>
 #include <mutex>
 #include <set>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -54,6 +55,21 @@ struct FlagsEntry {
 std::mutex g_fl_mu;
 std::map<std::pair<int, hipStream_t>, FlagsEntry> g_fl;
 }  // namespace
+
+namespace {
+std::mutex g_attr_mu;
+std::set<std::tuple<int, const void*, int>> g_attr_done;
+}  // namespace
+
+int set_lds_limit(const void* kern, int bytes) {
+  int dev = 0;
+  MD_HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_attr_mu);
+  if (g_attr_done.count({dev, kern, bytes})) return MD_OK;
+  MD_HIP_TRY(hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  g_attr_done.insert({dev, kern, bytes});
+  return MD_OK;
+}
 
 int stream_flags(hipStream_t stream, int** out) {
   int dev = 0;

@@ -415,12 +415,9 @@ void free_plan(SweepPlan* p) {
 template <int WAVES, int SB, int KS, int MBK>
 int launch_class(SweepPlan* p, const SweepPlan::Class& c, int ci, hipStream_t s) {
   auto kern = sweep_kernel<WAVES, SB, KS, MBK>;
-  static bool attr_done = false;
-  if (!attr_done) {
-    // the kernel's static LDS (< 1 KiB) and the dynamic part share the 160 KiB of a CU
-    MD_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   kDynLds));
-    attr_done = true;
+  {
+    const int st_attr = set_lds_limit(reinterpret_cast<const void*>(kern), kDynLds);
+    if (st_attr != MD_OK) return st_attr;
   }
   int ncu = 0, occ = 0;
   MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));

@@ -58,6 +58,13 @@ def test_argument_validation_before_device_work():
     assert L.llr_exact(fake, fake, 64, 4, fake, 10, 0.1, 7, fake, None) == -1
     assert L.llr_maxlog(fake, fake, 64, 4, fake, 10, -0.1, fake, None) == -1
     assert b"sigma2" in L.last_error()
+    # more symbols in one call than the 32-bit fallback lists can index
+    assert L.llr_exact(fake, fake, 64, 4, fake, 2 ** 31, 0.1, 0, fake, None) == -1
+    assert b"2^31" in L.last_error()
+    # Q-factor: no bits, null pointers
+    assert L.q_factor_db(fake, 0, fake, None) == -1
+    assert L.q_factor_db(None, 10, fake, None) == -1
+    assert L.q_factor_db(fake, 10, None, None) == -1
     # awgn_sample
     assert L.awgn_sample(fake, 6, 2, 1, 0, 10, 0.1, fake, fake, None) == -2
     assert L.awgn_sample(fake, 8, 2, 1, 0, 10, -0.1, fake, fake, None) == -1
@@ -156,3 +163,24 @@ def test_kk_argument_validation_before_device_work():
     assert L.kk_frontend(None, 1024, 1.0, 0.0, fake, None) == -1
     assert b"kk_frontend" in L.last_error()
     assert L.kk_frontend(None, 0, 1.0, 0.0, None, None) == 0
+
+
+def test_binding_rejects_host_tensors_and_bad_outputs():
+    """The Python binding checks every tensor before passing its pointer: a host tensor
+    given where device memory is expected never reaches the library."""
+    import torch
+    import paper_2104_06311_amd as md
+    X = torch.zeros((64, 4))
+    labels = torch.arange(64, dtype=torch.int32)
+    llr = torch.zeros((10, 6))
+    tx = torch.zeros(10, dtype=torch.int32)
+    with pytest.raises(ValueError, match="GPU"):
+        md.ber_count(llr, tx, labels)
+    with pytest.raises(ValueError, match="GPU"):
+        md.awgn_sample(X, 1, 0, 10, 0.1)
+    with pytest.raises(ValueError, match="GPU"):
+        md.llr_exact(X, labels, torch.zeros((10, 4)), 0.1)
+    with pytest.raises(ValueError, match="GPU"):
+        md.q_factor_db(torch.zeros(1, dtype=torch.int64), 10)
+    with pytest.raises(TypeError):
+        md.gmi_reduce([0.0] * 10, tx, labels)

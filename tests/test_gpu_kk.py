@@ -55,3 +55,23 @@ def test_empty_and_rejected():
     assert out.shape == (0,)
     with pytest.raises(md().MdemapError):
         md().kk_frontend(torch.ones(1000, dtype=torch.float32, device="cuda"), 1.0, 0.0)
+
+
+def test_non_positive_samples_stay_local():
+    """A detected intensity of zero, a negative one (noise) and a NaN are floored at 2^-126
+    on both sides: every output stays finite, and the result equals the oracle's within
+    the FP32 bound scaled by the largest log-amplitude (|ln 2^-126| / 2 = 43.7), which the
+    FFT pair now carries."""
+    T, A = 8192, 1.5
+    x, _ = synth.kk_input(T, A=A, seed=11)
+    x[[700, 3001, 3002]] = [0.0, -0.25, np.nan]
+    out = md().kk_frontend(torch.from_numpy(x).cuda(), A, 0.129).cpu().numpy()
+    assert np.all(np.isfinite(out))
+    ref = oracle.kk_field(x, A, 0.129)
+    assert np.all(np.isfinite(ref))
+    lmax = 0.5 * 126 * np.log(2.0)
+    tol = 1e-4 * (1.0 + np.max(np.abs(ref)) + A) * lmax
+    assert np.max(np.abs(out - ref)) <= tol
+    # blocks whose windows do not reach the bad samples are unaffected: same bound as clean input
+    far = np.r_[0:0, 1536:2048, 4608:T]
+    assert np.max(np.abs(out[far] - ref[far])) <= 1e-4 * (1.0 + np.max(np.abs(ref)) + A)

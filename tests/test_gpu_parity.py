@@ -299,7 +299,14 @@ def test_ber_count_and_q_factor():
             assert abs(int(e.item()) - int(oracle.bit_errors(dec, txh, labels, 6).sum())) <= ties
         ber = int(e.item()) / (100_000 * 6)
         assert 0.0 < ber < 0.5
-        assert abs(md().q_factor_db(ber) - oracle.q_factor_db(ber)) < 1e-9
+        q = md().q_factor_db(e, 100_000 * 6).item()
+        assert abs(q - oracle.q_factor_db(ber)) < 1e-9
+    # no finite Q-factor without errors, or at BER >= 1/2
+    zero = torch.zeros(1, dtype=torch.int64, device="cuda")
+    assert math.isnan(md().q_factor_db(zero, 100).item())
+    assert math.isnan(md().q_factor_db(torch.full((1,), 50, dtype=torch.int64, device="cuda"), 100).item())
+    assert abs(md().q_factor_db(torch.full((1,), 27, dtype=torch.int64, device="cuda"), 10**10).item()
+               - oracle.q_factor_db(27e-10)) < 1e-9
 
 
 def test_empty_input_is_a_no_op_and_gmi_rejects_it():
@@ -327,6 +334,23 @@ def test_invalid_labels_are_rejected():
     bad2[0] = 64                         # out of range
     with pytest.raises(md().MdemapError):
         md().llr_maxlog(to_dev(X), labels_dev(bad2), y, 0.1)
+
+
+def test_labels_rewritten_in_place_are_caught_on_the_device():
+    """The host checks a label buffer once per (device, address, M); labels rewritten in
+    place afterwards are caught by the device check of every call (all outputs NaN), and
+    after release_cache() the host check runs again and reports MD_ELABEL."""
+    X, labels = synth.gaussian_constellation(64, 4, 2)
+    s2, Xd, tx, y, txh, yh = channel(X, labels, 8.0, 500, 3)
+    ld = labels_dev(labels)
+    assert torch.isfinite(md().llr_exact(Xd, ld, y, s2)).all()
+    ld[5] = ld[6]                        # now a duplicate label, same address
+    L = md().llr_exact(Xd, ld, y, s2)
+    assert torch.isnan(L).all()
+    md().release_cache()
+    with pytest.raises(md().MdemapError) as e:
+        md().llr_exact(Xd, ld, y, s2)
+    assert e.value.status == -3
 
 
 def test_results_do_not_depend_on_label_storage_order():

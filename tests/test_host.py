@@ -27,16 +27,6 @@ def test_counter_traffic_follows_the_kernel_sources(tmp_path, monkeypatch):
     assert t2 is None and "changed" in note2
 
 
-def test_q_factor_round_trip():
-    import math
-    from paper_2104_06311_amd import q_factor_db
-    for q in (1.0, 3.0, 6.0, 7.5):
-        ber = 0.5 * math.erfc(q / math.sqrt(2.0))
-        assert abs(q_factor_db(ber) - 20 * math.log10(q)) < 1e-9
-    with pytest.raises(ValueError):
-        q_factor_db(0.6)
-
-
 def test_qam_gray_inputs():
     """Square Gray QAM of the input generator: unit energy per 2D, a permutation of labels,
     and neighbours on the grid differ in exactly one label bit."""

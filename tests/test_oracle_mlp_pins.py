@@ -17,27 +17,51 @@ def _params(D=3, H1=5, H2=4, m=2, seed=0, scale=0.7):
         rng.standard_normal((m, H2)) * scale, rng.standard_normal(m) * 0.1)
 
 
-def _gelu_tanh_ref(a):
-    return 0.5 * a * (1.0 + math.tanh(math.sqrt(2.0 / math.pi) * (a + 0.044715 * a ** 3)))
+# Standard normal distribution function at 1 and its density at 0 (tabulated constants,
+# not computed by the oracle): Phi(1) = 0.841344746068542948585..., phi(0) = 1/sqrt(2 pi).
+PHI_1 = 0.8413447460685429486
+PDF_0 = 0.3989422804014326779
 
 
-def test_gelu_values_and_closeness_to_the_erf_form():
+def test_gelu_is_input_times_normal_cdf():
+    """GELU (Hendrycks & Gimpel) is a Phi(a): checked against scipy's normal distribution
+    function (Cephes ndtr, a library independent of the C library's erfc) on [-8, 8], with
+    the tabulated value Phi(1), the exact zero, the asymptotes and the derivative."""
+    from scipy.special import ndtr
+    a = np.linspace(-8.0, 8.0, 1601)
+    g, dg = oracle.gelu(a)
+    np.testing.assert_allclose(g, a * ndtr(a), rtol=1e-13, atol=1e-300)
+    assert g[800] == 0.0 and dg[800] == 0.5                       # g(0) = 0, g'(0) = Phi(0) = 1/2
+    g1, dg1 = oracle.gelu([1.0, -1.0])
+    assert abs(g1[0] - PHI_1) <= 1e-15                             # g(1) = Phi(1)
+    assert abs(g1[1] + (1.0 - PHI_1)) <= 1e-15                     # g(-1) = -Phi(-1) = -(1 - Phi(1))
+    # g'(1) = Phi(1) + phi(1), phi(1) = phi(0) e^(-1/2)
+    assert abs(dg1[0] - (PHI_1 + PDF_0 * math.exp(-0.5))) <= 1e-15
+    # asymptotes: g(a) - a -> 0 above, g(a) -> 0 below (faster than any power)
+    hi, _ = oracle.gelu([10.0, 40.0])
+    lo, _ = oracle.gelu([-10.0, -40.0])
+    assert hi[0] == 10.0 and hi[1] == 40.0
+    assert -1e-22 < lo[0] < 0.0 and -1e-300 < lo[1] <= 0.0
+    # g(-10) = -10 Phi(-10) and Phi(-10) = 7.6198530241605e-24 (lower-tail table value)
+    assert abs(lo[0] / -10.0 - 7.6198530241605e-24) <= 1e-35
+    # the derivative against central differences of the activation itself
+    h = 1e-6
+    gp, _ = oracle.gelu(a + h)
+    gm, _ = oracle.gelu(a - h)
+    np.testing.assert_allclose(dg, (gp - gm) / (2 * h), rtol=0, atol=2e-9)
+
+
+def test_one_unit_network_applies_gelu_twice():
     # one hidden unit per layer with identity weights exposes the activation itself
     p = oracle.MLPParams(np.array([[1.0]]), np.zeros(1), np.array([[1.0]]), np.zeros(1),
                          np.array([[1.0]]), np.zeros(1))
     a = np.linspace(-6, 6, 241)
     out = oracle.mlp_forward(p, a[:, None].astype(np.float32))[:, 0]
+    from scipy.special import ndtr
     a32 = a.astype(np.float32).astype(np.float64)
-    # exact special values: g(0) = 0, g(a) -> a for large a, g(-a) -> 0
+    g1 = a32 * ndtr(a32)
+    np.testing.assert_allclose(out, g1 * ndtr(g1), rtol=1e-12, atol=1e-300)
     assert out[120] == 0.0
-    # the tanh form stays within 2e-3 of the erf form a * Phi(a) (Hendrycks & Gimpel)
-    phi = np.array([0.5 * (1 + math.erf(v / math.sqrt(2))) for v in a32])
-    g1 = a32 * phi
-    g_erf = g1 * 0.5 * (1 + np.array([math.erf(v / math.sqrt(2)) for v in g1]))
-    assert np.max(np.abs(out - g_erf)) < 2e-3
-    # and the composition is the activation applied twice
-    g_once = np.array([_gelu_tanh_ref(v) for v in a32])
-    np.testing.assert_allclose(out, [_gelu_tanh_ref(v) for v in g_once], rtol=1e-12, atol=1e-15)
 
 
 def test_zero_network_loss_closed_form():
