@@ -264,6 +264,11 @@ int sweep_plan_info(const void* plan, int* waves, int* blocks_per_wave, int* gro
 /* Runs the sweep (use_graph = 1: one launch of the captured graph; 0: the same kernels
  * enqueued directly) and copies the n_inst x n_snr GMIs (bits per symbol) to d_gmi. */
 int sweep_run(void* plan, double* d_gmi, int use_graph, void* stream);
+/* After the last sweep_run on `stream` (the call waits for the stream): how many symbols
+ * of that run were re-evaluated by the FP64 fallback (their subset sums left the FP32
+ * range, or their operands the FP16 split range) and whether the fallback queue
+ * overflowed (then the run's GMIs are NaN).  Either pointer may be NULL. */
+int sweep_run_stats(const void* plan, int64_t* n_fallback, int* overflowed, void* stream);
 int sweep_plan_destroy(void* plan);
 
 /* ------------------------------------------------------------------ streaming receiver */
@@ -403,6 +408,9 @@ int kk_frontend(const float* d_x, int64_t T, float A, double nu, float* d_out, v
  *                    d_src and d_dst are device buffers of at least `work` bytes, 16-byte
  *                    aligned, not overlapping (ignored by the other kinds)
  *                                                               -> bytes read + written /s
+ *   MD_UB_EXP_ADD2   one v_exp_f32 and two independent v_add_f32 of its result per step
+ *                    (the exact demapper's work per (symbol, point) pair)
+ *                                                               -> steps/s
  * Returns MD_OK, MD_EINVAL (unknown kind, work < 0, a copy without buffers, with work not a
  * positive multiple of 16 or with unaligned buffers), MD_ENOMEM, MD_EHIP. */
 #define MD_UB_EXP       0
@@ -411,7 +419,20 @@ int kk_frontend(const float* d_x, int64_t T, float A, double nu, float* d_out, v
 #define MD_UB_MFMA_BF16 3
 #define MD_UB_MFMA_F32  4
 #define MD_UB_COPY      5
+#define MD_UB_EXP_ADD2  6
 int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rate, double* h_ms, void* stream);
+
+/* ------------------------------------------------------------------ kernel timing */
+/* Live timing of the demappers' dominant kernel (the fast pass of llr_exact and
+ * llr_maxlog, M > 16), for roofline figures.  kernel_timing(1, stream) makes every later
+ * demapping call on `stream` (current device) record a HIP event pair on that stream
+ * around its fast kernel (not around prep or the fallback passes; not while the stream
+ * is being captured); kernel_timing(0, stream) waits for the stream and stops it.
+ * kernel_timing_read waits for the stream, writes the summed milliseconds and the number
+ * of timed launches since the last read, and starts a new count.
+ * Returns MD_OK, MD_EINVAL (NULL output), MD_ENODEV, MD_EHIP. */
+int kernel_timing(int enable, void* stream);
+int kernel_timing_read(double* total_ms, int64_t* launches, void* stream);
 
 /* ------------------------------------------------------------------ housekeeping */
 /* Frees every internal device workspace (synchronises the device first). */

@@ -13,7 +13,7 @@ import torch
 from ._lib import MdemapError, PREC, check, lib
 
 __all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "RxStream", "release_cache",
-           "ddlms_equalize", "kk_frontend", "ubench", "UBENCH_KINDS", "MdemapError",
+           "ddlms_equalize", "kk_frontend", "ubench", "UBENCH_KINDS", "kernel_timing", "kernel_timing_read", "MdemapError",
            "log2_exact"]
 
 
@@ -229,7 +229,22 @@ def kk_frontend(x, A: float, nu: float, out=None):
     return out
 
 
-UBENCH_KINDS = {"exp": 0, "add_f32": 1, "mfma_f16": 2, "mfma_bf16": 3, "mfma_f32": 4, "copy": 5}
+def kernel_timing(enable: bool):
+    """Switch event timing of the demappers' fast kernel on or off on the current stream
+    (kernel_timing in mdemap.h)."""
+    check("kernel_timing", lib().kernel_timing(1 if enable else 0, _stream()))
+
+
+def kernel_timing_read():
+    """(summed milliseconds, launches) of the fast kernels timed on the current stream
+    since the last read (kernel_timing_read in mdemap.h)."""
+    import ctypes
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    check("kernel_timing_read", lib().kernel_timing_read(ctypes.byref(ms), ctypes.byref(n), _stream()))
+    return ms.value, n.value
+
+
+UBENCH_KINDS = {"exp": 0, "add_f32": 1, "mfma_f16": 2, "mfma_bf16": 3, "mfma_f32": 4, "copy": 5, "exp_add2": 6}
 
 
 def ubench(kind: str, work: int = 0, src=None, dst=None):
@@ -472,6 +487,13 @@ class SweepPlan:
             out = torch.empty((self.n_inst, self.n_snr), dtype=torch.float64, device="cuda")
         check("sweep_run", lib().sweep_run(self._h, _ptr(out), 1 if use_graph else 0, _stream()))
         return out
+
+    def stats(self):
+        """(symbols re-evaluated by the FP64 fallback in the last run, queue overflowed)."""
+        import ctypes
+        n, ov = ctypes.c_int64(), ctypes.c_int()
+        check("sweep_run_stats", lib().sweep_run_stats(self._h, ctypes.byref(n), ctypes.byref(ov), _stream()))
+        return n.value, bool(ov.value)
 
     def close(self):
         if self._h is not None:

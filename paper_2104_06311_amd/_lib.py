@@ -52,10 +52,13 @@ SIGNATURES = {
     "sweep_plan_create": (_I, [_P, _I, _P, _I, _I, ctypes.POINTER(ctypes.c_void_p)]),
     "sweep_plan_info": (_I, [_P, _P, _P, _P, _P]),
     "sweep_run": (_I, [_P, _P, _I, _P]),
+    "sweep_run_stats": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int), _P]),
     "sweep_plan_destroy": (_I, [_P]),
     "rx_create": (_I, [_P, _P, _I, _I, _D, _P, ctypes.POINTER(ctypes.c_void_p)]),
     "rx_run": (_I, [_P, _P, _P, _I64, _I64, _P, _P, _P, _P]),
     "rx_destroy": (_I, [_P]),
+    "kernel_timing": (_I, [_I, _P]),
+    "kernel_timing_read": (_I, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _P]),
     "release_cache": (_I, []),
     "last_error": (ctypes.c_char_p, []),
     "ddlms_equalize": (_I, [_P, _I64, _I64, _P, _I, _P, _P, _D, _P, _P, _P, _P, _P]),

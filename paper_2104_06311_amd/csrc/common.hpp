@@ -76,6 +76,13 @@ int current_device(int* dev);
 // attribute belongs to a (kernel, device) pair, so it is set once per pair.
 int set_lds_limit(const void* kern, int bytes);
 
+// Event timing of the demappers' fast kernel on one (current device, stream) pair, when
+// switched on by kernel_timing(): timing_begin records the first event of a pair before
+// the launch and returns its slot (or -1 when timing is off or the stream is capturing),
+// timing_end records the second after it.
+int timing_begin(hipStream_t stream);
+void timing_end(hipStream_t stream, int slot);
+
 // ---------------------------------------------------------------- prepared constellation
 // Device-side view of a prepared constellation (label order).
 struct Prepared {

@@ -57,6 +57,82 @@ std::map<std::pair<int, hipStream_t>, FlagsEntry> g_fl;
 }  // namespace
 
 namespace {
+struct TimingEntry {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pairs;   // recorded, not yet read
+  std::vector<hipEvent_t> pool;                           // created, free
+};
+std::mutex g_tm_mu;
+std::map<std::pair<int, hipStream_t>, TimingEntry> g_tm;
+
+hipEvent_t pool_event(TimingEntry& t) {
+  if (!t.pool.empty()) {
+    hipEvent_t e = t.pool.back();
+    t.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+void drop_events(TimingEntry& t) {
+  for (auto& pr : t.pairs) {
+    if (pr.first) (void)hipEventDestroy(pr.first);
+    if (pr.second) (void)hipEventDestroy(pr.second);
+  }
+  for (hipEvent_t e : t.pool) (void)hipEventDestroy(e);
+  t.pairs.clear();
+  t.pool.clear();
+}
+}  // namespace
+
+int timing_begin(hipStream_t stream) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return -1;
+  }
+  std::lock_guard<std::mutex> lk(g_tm_mu);
+  auto it = g_tm.find({dev, stream});
+  if (it == g_tm.end() || !it->second.on) return -1;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return -1;
+  }
+  TimingEntry& t = it->second;
+  hipEvent_t a = pool_event(t), b = pool_event(t);
+  if (!a || !b || hipEventRecord(a, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    if (a) t.pool.push_back(a);
+    if (b) t.pool.push_back(b);
+    return -1;
+  }
+  t.pairs.emplace_back(a, b);
+  return static_cast<int>(t.pairs.size()) - 1;
+}
+
+void timing_end(hipStream_t stream, int slot) {
+  if (slot < 0) return;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  std::lock_guard<std::mutex> lk(g_tm_mu);
+  auto it = g_tm.find({dev, stream});
+  if (it == g_tm.end() || slot >= static_cast<int>(it->second.pairs.size())) return;
+  if (hipEventRecord(it->second.pairs[static_cast<size_t>(slot)].second, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    it->second.pairs[static_cast<size_t>(slot)].second = nullptr;
+  }
+}
+
+namespace {
 std::mutex g_attr_mu;
 std::set<std::tuple<int, const void*, int>> g_attr_done;
 }  // namespace
@@ -230,6 +306,55 @@ int release_workspaces() {
 }  // namespace md
 
 extern "C" {
+
+int kernel_timing(int enable, void* stream) {
+  md::set_error("");
+  int dev = 0;
+  int st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(md::g_tm_mu);
+  md::TimingEntry& t = md::g_tm[{dev, s}];
+  if (!enable) {
+    MD_HIP_TRY(hipStreamSynchronize(s));
+    md::drop_events(t);
+  }
+  t.on = enable != 0;
+  return MD_OK;
+}
+
+int kernel_timing_read(double* total_ms, int64_t* launches, void* stream) {
+  md::set_error("");
+  if (!total_ms || !launches) return md::fail(MD_EINVAL, "output pointer is NULL");
+  *total_ms = 0.0;
+  *launches = 0;
+  int dev = 0;
+  int st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(md::g_tm_mu);
+  auto it = md::g_tm.find({dev, s});
+  if (it == md::g_tm.end()) return MD_OK;
+  md::TimingEntry& t = it->second;
+  MD_HIP_TRY(hipStreamSynchronize(s));
+  double sum = 0.0;
+  int64_t n = 0;
+  for (auto& pr : t.pairs) {
+    float ms = 0.0f;
+    if (pr.second && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      sum += ms;
+      ++n;
+    } else {
+      (void)hipGetLastError();
+    }
+    t.pool.push_back(pr.first);
+    if (pr.second) t.pool.push_back(pr.second);
+  }
+  t.pairs.clear();
+  *total_ms = sum;
+  *launches = n;
+  return MD_OK;
+}
 
 int release_cache(void) {
   md::set_error("");

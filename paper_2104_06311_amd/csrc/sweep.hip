@@ -722,6 +722,23 @@ int sweep_run(void* plan, double* d_gmi, int use_graph, void* stream) {
   return MD_OK;
 }
 
+int sweep_run_stats(const void* plan, int64_t* n_fallback, int* overflowed, void* stream) {
+  md::set_error("");
+  const md::SweepPlan* p = static_cast<const md::SweepPlan*>(plan);
+  if (!p) return md::fail(MD_EINVAL, "plan is NULL");
+  int dev = 0;
+  int st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  if (dev != p->device) return md::fail(MD_EINVAL, "the plan lives on another device");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  int h[3] = {0, 0, 0};
+  MD_HIP_TRY(hipMemcpyAsync(h, p->d_counters, sizeof(h), hipMemcpyDeviceToHost, s));
+  MD_HIP_TRY(hipStreamSynchronize(s));
+  if (n_fallback) *n_fallback = h[1];
+  if (overflowed) *overflowed = h[2] != 0 ? 1 : 0;
+  return MD_OK;
+}
+
 int sweep_plan_destroy(void* plan) {
   md::set_error("");
   md::SweepPlan* p = static_cast<md::SweepPlan*>(plan);

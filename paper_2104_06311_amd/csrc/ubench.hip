@@ -1,6 +1,6 @@
 // ubench: measured peak rates of the instructions the demapping kernels are bound by
-// (v_exp_f32, non-packed v_add_f32, the FP16/BF16/FP32 matrix products) and of a device
-// copy, on the current device.  Each compute kernel keeps 16 independent chains (or 4
+// (v_exp_f32, non-packed v_add_f32, their one-exponential-two-adds mix, the FP16/BF16/FP32
+// matrix products) and of a device copy, on the current device.  Each compute kernel keeps 16 independent chains (or 4
 // independent accumulators) per lane, so that issue, not latency, bounds it; its result
 // feeds a store that is never taken, so the work cannot be removed.
 #include "common.hpp"
@@ -47,6 +47,31 @@ __global__ void __launch_bounds__(kThreads) ub_add_kernel(int64_t iters, float s
   if (r == kNever) sink[0] = r;
 }
 
+// The exact demapper's per-pair mix: one exponential and two independent adds of its
+// result into different partial sums (the two accumulators start from different values,
+// so the compiler cannot merge them).
+__global__ void __launch_bounds__(kThreads) ub_exp_add2_kernel(int64_t iters, float seed, float* sink) {
+  float x[kChains], s0[kChains], s1[kChains];
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) {
+    x[c] = seed * static_cast<float>(threadIdx.x + c);
+    s0[c] = 0.0f;
+    s1[c] = 1.0f;
+  }
+  for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) {
+      x[c] = __builtin_amdgcn_exp2f(-x[c]);
+      s0[c] += x[c];
+      s1[c] += x[c];
+    }
+  }
+  float r = 0.0f;
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) r += s0[c] * s1[c];
+  if (r == kNever) sink[0] = r;
+}
+
 // KIND 0: v_mfma_f32_32x32x16_f16, 1: v_mfma_f32_32x32x16_bf16, 2: v_mfma_f32_32x32x2_f32
 template <int KIND>
 __global__ void __launch_bounds__(kThreads) ub_mfma_kernel(int64_t iters, float seed, float* sink) {
@@ -88,7 +113,7 @@ __global__ void __launch_bounds__(kThreads) ub_copy_kernel(const uint4* __restri
 }
 
 constexpr double kMfmaFlop[3] = {2.0 * 32 * 32 * 16, 2.0 * 32 * 32 * 16, 2.0 * 32 * 32 * 2};
-constexpr int64_t kDefaultIters[5] = {8192, 8192, 4096, 4096, 2048};
+constexpr int64_t kDefaultIters[7] = {8192, 8192, 4096, 4096, 2048, 0, 8192};
 
 int launch_kind(int kind, int64_t work, int blocks, const void* d_src, void* d_dst, float* sink, hipStream_t s) {
   const int64_t iters = work > 0 ? work : kDefaultIters[kind];
@@ -103,6 +128,9 @@ int launch_kind(int kind, int64_t work, int blocks, const void* d_src, void* d_d
       break;
     case MD_UB_MFMA_F32:
       hipLaunchKernelGGL(ub_mfma_kernel<2>, dim3(blocks), dim3(kThreads), 0, s, iters, 1e-3f, sink);
+      break;
+    case MD_UB_EXP_ADD2:
+      hipLaunchKernelGGL(ub_exp_add2_kernel, dim3(blocks), dim3(kThreads), 0, s, iters, 1e-3f, sink);
       break;
     default: {
       const int64_t n = work / 16;
@@ -124,7 +152,7 @@ extern "C" {
 
 int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rate, double* h_ms, void* stream) {
   using namespace md;
-  if (kind < MD_UB_EXP || kind > MD_UB_COPY) return fail(MD_EINVAL, "ubench: unknown kind");
+  if (kind < MD_UB_EXP || kind > MD_UB_EXP_ADD2) return fail(MD_EINVAL, "ubench: unknown kind");
   if (work < 0) return fail(MD_EINVAL, "ubench: work must be >= 0");
   if (kind == MD_UB_COPY) {
     if (d_src == nullptr || d_dst == nullptr) return fail(MD_EINVAL, "ubench: the copy needs d_src and d_dst");
@@ -159,12 +187,13 @@ int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rat
   if (st != MD_OK) return st;
   if (he != hipSuccess) return hip_fail(he, "ubench timing");
   const double sec = static_cast<double>(ms) * 1e-3;
-  const int64_t iters = work > 0 ? work : (kind < MD_UB_COPY ? kDefaultIters[kind] : 0);
+  const int64_t iters = work > 0 ? work : (kind != MD_UB_COPY ? kDefaultIters[kind] : 0);
   const double lanes = static_cast<double>(blocks) * kThreads;
   const double waves = lanes / 64.0;
   double amount = 0.0;
   switch (kind) {
     case MD_UB_EXP:
+    case MD_UB_EXP_ADD2:
     case MD_UB_ADD_F32: amount = lanes * static_cast<double>(iters) * kChains; break;
     case MD_UB_MFMA_F16:
     case MD_UB_MFMA_BF16:

@@ -107,3 +107,50 @@ def test_autotuned_plan_and_limits():
     bad = [(torch.from_numpy(X).cuda(), torch.from_numpy(labels.astype(np.int32)).cuda(), 100, 1)]
     with pytest.raises(md().MdemapError):
         md().SweepPlan(bad, np.array([[0.1]]))
+
+
+def oracle_gmi(host, inst, s2, i, s):
+    X, labels = host[i]
+    N, seed = inst[i][2], inst[i][3]
+    tx, y = oracle.awgn(X, seed, s * N, N, math.sqrt(s2[i, s]))
+    return oracle.gmi(oracle.llr_exact(X, labels, y, s2[i, s]), tx, labels)[0]
+
+
+def test_every_class_of_the_mixed_sweep_against_oracle():
+    """Each (M, D) class of the batched workload -- M in {16, 64, 256, 1024, 4096}, D in
+    {2, 4, 8} -- at 2, 7 and 12 dB, against awgn -> llr_exact -> gmi of the FP64 oracle."""
+    specs = [(M, D, 1500 + 97 * k) for k, (M, D) in enumerate(
+        [(M, D) for M in (16, 64, 256, 1024, 4096) for D in (2, 4, 8)])]
+    inst, host = make_instances(specs, seed=21)
+    s2 = sigma2_grid(host, [2.0, 7.0, 12.0])
+    for variant in (0, 3):
+        plan = md().SweepPlan(inst, s2, variant=variant)
+        g = plan.run().cpu().numpy()
+        n_fb, overflow = plan.stats()
+        assert not overflow
+        plan.close()
+        for i in range(len(specs)):
+            for s in range(3):
+                gr = oracle_gmi(host, inst, s2, i, s)
+                assert abs(g[i, s] - gr) <= 1e-4, (variant, specs[i], s, g[i, s], gr)
+
+
+def test_fp64_fallback_at_high_snr_against_oracle():
+    """At 20 and 24 dB the label-1 or label-0 subset of many symbols lies beyond the FP32
+    range of the fast pass: those symbols take the FP64 fallback kernel, whose 2^-40
+    fixed-point losses must still give the oracle's GMI."""
+    inst, host = make_instances([(2048, 8, 3000), (4096, 8, 2000), (1024, 4, 2500)], seed=33)
+    s2 = sigma2_grid(host, [20.0, 24.0])
+    plan = md().SweepPlan(inst, s2, variant=0)
+    g = plan.run().cpu().numpy()
+    n_fb, overflow = plan.stats()
+    assert n_fb > 0 and not overflow, (n_fb, overflow)
+    for i in range(3):
+        for s in range(2):
+            gr = oracle_gmi(host, inst, s2, i, s)
+            assert abs(g[i, s] - gr) <= 1e-4, (i, s, g[i, s], gr)
+    # the graph replays give the same fallback count and the same GMIs
+    g2 = plan.run().cpu().numpy()
+    assert plan.stats() == (n_fb, False)
+    assert np.array_equal(g, g2)
+    plan.close()

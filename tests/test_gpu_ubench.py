@@ -17,7 +17,7 @@ def md():
 # vector peak, which needs packed instructions; non-packed adds measure about 2.8
 # cycles), FP16/BF16 matrix 2.5e15 flop/s, FP32 matrix 1.57e14 flop/s, HBM 8e12 B/s.
 BANDS = {"exp": (4e12, 2.6e13), "add_f32": (8e12, 8.2e13), "mfma_f16": (8e14, 2.8e15),
-         "mfma_bf16": (8e14, 2.8e15), "mfma_f32": (4e13, 1.8e14)}
+         "mfma_bf16": (8e14, 2.8e15), "mfma_f32": (4e13, 1.8e14), "exp_add2": (3e12, 2.0e13)}
 
 
 @pytest.mark.parametrize("kind", sorted(BANDS))
@@ -27,7 +27,8 @@ def test_compute_rates_are_plausible(kind):
     assert lo <= rate <= hi, (kind, rate)
     assert 0.05 < ms < 200.0, (kind, ms)
     # twice the iterations take about twice as long
-    doubled = {"exp": 16384, "add_f32": 16384, "mfma_f16": 8192, "mfma_bf16": 8192, "mfma_f32": 4096}
+    doubled = {"exp": 16384, "add_f32": 16384, "mfma_f16": 8192, "mfma_bf16": 8192, "mfma_f32": 4096,
+               "exp_add2": 16384}
     rate2, ms2 = md().ubench(kind, work=doubled[kind])
     assert 1.5 < ms2 / ms < 2.6, (kind, ms, ms2)
 
@@ -45,3 +46,14 @@ def test_copy_moves_the_bytes():
     assert torch.equal(dst[:1024], src[:1024]) and int(dst[1024:].abs().max().item()) == 0
     with pytest.raises(ValueError):
         md().ubench("copy", nbytes * 2, src, dst)
+
+
+def test_exp_add2_mix_is_slower_than_exp_alone():
+    """The mix issues three instructions per step on the same port: it cannot beat the
+    exponential alone, and it cannot be slower than the three issued one after another."""
+    r_exp = md().ubench("exp")[0]
+    r_add = md().ubench("add_f32")[0]
+    r_mix = md().ubench("exp_add2")[0]
+    assert r_mix < r_exp, (r_mix, r_exp)
+    serial = 1.0 / (1.0 / r_exp + 2.0 / r_add)
+    assert r_mix > 0.8 * serial, (r_mix, serial)
