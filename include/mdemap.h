@@ -123,6 +123,20 @@ int awgn_sample(const float* d_X, int M, int D, uint64_t seed, uint64_t offset, 
 int llr_exact(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y,
               int64_t N, double sigma2, int prec, float* d_llr, void* stream);
 
+/* llr_exact_noalloc -- llr_exact for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, layout, results (bit for bit) and errors as llr_exact, but it calls no
+ * hipMalloc, hipFree or allocating routine: its prep buffers, stage counters and
+ * fallback lists live in a 24 MiB file-scope device array, one copy per device, held
+ * until the process ends.  Limits: N <= 2^20 symbols per call and at most 24 MiB of
+ * prep data (every M and D above fit at that N); beyond them MD_EINVAL, before anything
+ * is enqueued.  All calls on one device share its array and each call's prep kernels
+ * clear the counters it needs, so calls that overlap on one device (other streams,
+ * other threads) race: serialise them.  llr_path_counts does not report these calls.
+ * The first call on a device looks up the array's device address (no allocation). */
+int llr_exact_noalloc(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y,
+                      int64_t N, double sigma2, int prec, float* d_llr, void* stream);
+
 /* llr_maxlog -- max-log LLRs: L_nk = max_{b_k=0} q_nj - max_{b_k=1} q_nj.  Same
  * arguments, layout and errors as llr_exact (no precision argument). */
 int llr_maxlog(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y,

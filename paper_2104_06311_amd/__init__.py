@@ -12,7 +12,7 @@ import torch
 
 from ._lib import MdemapError, PREC, check, lib
 
-__all__ = ["awgn_sample", "llr_exact", "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "RxStream", "release_cache",
+__all__ = ["awgn_sample", "llr_exact", "llr_exact_noalloc", "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "RxStream", "release_cache",
            "ddlms_equalize", "kk_frontend", "ubench", "UBENCH_KINDS", "kernel_timing", "kernel_timing_read", "MdemapError",
            "log2_exact"]
 
@@ -106,6 +106,18 @@ def llr_exact(X, labels, y, sigma2: float, prec: str = "fp32", out=None):
     out = _out(out, (N, m), torch.float32, X.device)
     st = lib().llr_exact(_ptr(X), _ptr(labels), M, D, _ptr(y), N, float(sigma2), PREC[prec], _ptr(out), _stream())
     check("llr_exact", st)
+    return out
+
+
+def llr_exact_noalloc(X, labels, y, sigma2: float, prec: str = "fp32", out=None):
+    """llr_exact through the allocation-free entry point (N <= 2^20; calls overlapping on
+    one device race, see mdemap.h).  Pass `out` to keep the call free of allocations."""
+    M, D, N = _demap_args(X, labels, y)
+    m = log2_exact(M)
+    out = _out(out, (N, m), torch.float32, X.device)
+    st = lib().llr_exact_noalloc(_ptr(X), _ptr(labels), M, D, _ptr(y), N, float(sigma2), PREC[prec], _ptr(out),
+                                 _stream())
+    check("llr_exact_noalloc", st)
     return out
 
 

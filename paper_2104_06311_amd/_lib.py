@@ -30,6 +30,7 @@ SIGNATURES = {
     "awgn_sample": (_I, [_P, _I, _I, _U64, _U64, _I64, _D, _P, _P, _P]),
     "llr_exact": (_I, [_P, _P, _I, _I, _P, _I64, _D, _I, _P, _P]),
     "llr_maxlog": (_I, [_P, _P, _I, _I, _P, _I64, _D, _P, _P]),
+    "llr_exact_noalloc": (_I, [_P, _P, _I, _I, _P, _I64, _D, _I, _P, _P]),
     "gmi_reduce": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P, _P]),
     "ber_count": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P]),
     "q_factor_db": (_I, [_P, _I64, _P, _P]),
