@@ -58,6 +58,9 @@ def parse():
                     help="also run a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline sweep (no BF16 / max-log / learned / batched objects)")
+    ap.add_argument("--extras", default="all",
+                    help="comma-separated detail objects to run (precisions, learned, learned_structured, "
+                         "learned_capacity, batched, 16d, 4d, ddlms, kk, rx) or 'all'")
     ap.add_argument("--learn-steps", type=int, default=40000, help="training steps per learned network (8D)")
     ap.add_argument("--learn-steps-16d", type=int, default=6000, help="training steps per learned network (16D)")
     ap.add_argument("--learn-pairs", type=int, default=1 << 24, help="training pairs per SNR point")
@@ -199,6 +202,88 @@ def extra_learned(md, wl, X, labels, N, tx, y, llr, steps, pairs):
                            "final_loss": float(trace[-50:].mean().item())}
         net.close()
     return res
+
+
+def extra_learned_structured(md, N=10_000_000, steps=3000, pairs=1 << 20):
+    """Where the learned demapper pays: a structured 4D constellation (64-QAM x 64-QAM,
+    BRGC per axis, M = 4096, 12 bits) at 8 dB, whose label bits each depend on one real
+    coordinate.  A 4 -> 128 -> 128 -> 12 network trained by the library's kernels on
+    exact-LLR pairs, scored on N fresh symbols against the exact and max-log kernels
+    (GMI on the same received symbols; time per N symbols)."""
+    import math
+    import time
+    import numpy as np
+    import torch
+    import synth
+    X, labels = synth.qam_product_4d(64)
+    M, D = X.shape
+    m = 12
+    s2 = synth.sigma2_from_snr_db(X, 8.0)
+    Xd = torch.from_numpy(X).cuda()
+    ld = torch.from_numpy(labels.astype(np.int32)).cuda()
+    _, ty = md.awgn_sample(Xd, 5, 0, pairs, math.sqrt(s2))
+    tl = md.llr_exact(Xd, ld, ty, s2)
+    net = md.MLP(D, 128, m, seed=1)
+    net.set_scales(1.0 / math.sqrt(s2), 1.0 / s2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net.fit(ty, tl, steps=steps, batch=4096, lr_max=2e-3, lr_min=2e-5, seed=8, trace=False)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del ty, tl
+    tx, y = md.awgn_sample(Xd, 101, 0, N, math.sqrt(s2))
+    llr = torch.empty((N, m), device="cuda")
+    res = {"workload": "4d_m4096_qam64x64_8dB", "network": "4-128-128-12", "N": N, "train_steps": steps,
+           "train_pairs": pairs, "train_s": train_s}
+    for name, fn in (("exact", lambda: md.llr_exact(Xd, ld, y, s2, out=llr)),
+                     ("maxlog", lambda: md.llr_maxlog(Xd, ld, y, s2, out=llr)),
+                     ("learned", lambda: md.llr_learned(net, y, out=llr))):
+        t = timed(fn)
+        res[f"{name}_ms"] = t
+        res[f"{name}_symbols_per_s"] = N / (t * 1e-3)
+        res[f"gmi_{name}"] = md.gmi_reduce(llr, tx, ld, per_bit=False, se=False)[0].item()
+    res["gap_bits"] = res["gmi_exact"] - res["gmi_learned"]
+    res["learned_minus_maxlog"] = res["gmi_learned"] - res["gmi_maxlog"]
+    res["speedup_vs_exact"] = res["exact_ms"] / res["learned_ms"]
+    res["speedup_vs_maxlog"] = res["maxlog_ms"] / res["learned_ms"]
+    net.close()
+    return res
+
+
+def extra_learned_capacity(md, steps=10000, pairs=1 << 22, N=1_000_000):
+    """Why the configured 8 -> 256 -> 256 -> 11 network cannot come near the exact GMI on
+    Gaussian constellations with binary-index labels: with arbitrary labels every label
+    bit is a different unstructured function of the Voronoi cell, so the network has to
+    memorise M cells.  Same network width, recipe and SNR (10 dB), M from 64 to 2048
+    (Gaussian points, labels the index; M = 2048 is the configured constellation): the
+    gap grows with M."""
+    import math
+    import numpy as np
+    import torch
+    import synth
+    res = {}
+    for M in (64, 256, 1024, 2048):
+        # M = 2048 is the configured constellation itself; the smaller ones are drawn the same way
+        seed = synth.SEED_BASE + 1 if M == 2048 else synth.SEED_BASE + 11 + M
+        X, labels = synth.gaussian_constellation(M, 8, seed)
+        m = M.bit_length() - 1
+        s2 = synth.sigma2_from_snr_db(X, 10.0)
+        Xd = torch.from_numpy(X).cuda()
+        ld = torch.from_numpy(labels.astype(np.int32)).cuda()
+        _, ty = md.awgn_sample(Xd, 77, 0, pairs, math.sqrt(s2))
+        tl = md.llr_exact(Xd, ld, ty, s2)
+        net = md.MLP(8, 256, m, seed=10)
+        net.set_scales(1.0 / math.sqrt(s2), 1.0 / s2)
+        net.fit(ty, tl, steps=steps, batch=4096, lr_max=2e-3, lr_min=2e-5, seed=15, trace=False)
+        del ty, tl
+        tx, y = md.awgn_sample(Xd, 99, 0, N, math.sqrt(s2))
+        g_ex = md.gmi_reduce(md.llr_exact(Xd, ld, y, s2), tx, ld, per_bit=False, se=False)[0].item()
+        g_ml = md.gmi_reduce(md.llr_maxlog(Xd, ld, y, s2), tx, ld, per_bit=False, se=False)[0].item()
+        g_ln = md.gmi_reduce(md.llr_learned(net, y), tx, ld, per_bit=False, se=False)[0].item()
+        net.close()
+        res[str(M)] = {"m": m, "gmi_exact": g_ex, "gmi_maxlog": g_ml, "gmi_learned": g_ln, "gap_bits": g_ex - g_ln,
+                       "gap_fraction_of_m": (g_ex - g_ln) / m}
+    return {"network": "8-256-256-m", "snr_db": 10.0, "train_steps": steps, "train_pairs": pairs, "per_M": res}
 
 
 def measured_peaks(md):
@@ -471,6 +556,10 @@ def extra_batched(md, n_inst):
             "M_mix": sorted({int(w.M) for w in insts}), "D_mix": sorted({int(w.D) for w in insts})}
 
 
+EXTRAS = ("precisions", "learned", "learned_structured", "learned_capacity", "batched", "16d", "4d", "ddlms", "kk",
+          "rx")
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -588,17 +677,33 @@ def main():
                    "wide_careful_symbols_at_14dB": list(md.llr_path_counts())},
     }
     if not args.no_extras:
-        out["detail"].update(extra_precisions(md, wl, X, labels, N, tx, y, llr))
-        out["detail"]["learned"] = extra_learned(md, wl, X, labels, N, tx, y, llr, args.learn_steps,
-                                                 args.learn_pairs)
+        want = set(EXTRAS) if args.extras == "all" else set(args.extras.split(","))
+        unknown = want - set(EXTRAS)
+        if unknown:
+            raise SystemExit(f"unknown extras: {sorted(unknown)}")
+        det = out["detail"]
+        if "precisions" in want:
+            det.update(extra_precisions(md, wl, X, labels, N, tx, y, llr))
+        if "learned" in want:
+            det["learned"] = extra_learned(md, wl, X, labels, N, tx, y, llr, args.learn_steps, args.learn_pairs)
         del tx, y, llr
         torch.cuda.empty_cache()
-        out["detail"]["batched"] = extra_batched(md, args.batch_insts)
-        out["detail"]["16d"] = extra_16d(md, args.learn_steps_16d, args.learn_pairs_16d)
-        out["detail"]["4d"] = extra_4d(md)
-        out["detail"]["ddlms"] = extra_ddlms(md)
-        out["detail"]["kk"] = extra_kk(md)
-        out["detail"]["rx_stream"] = extra_rx(md, args.rx_seconds)
+        if "learned_structured" in want:
+            det["learned_structured"] = extra_learned_structured(md)
+        if "learned_capacity" in want:
+            det["learned_capacity"] = extra_learned_capacity(md)
+        if "batched" in want:
+            det["batched"] = extra_batched(md, args.batch_insts)
+        if "16d" in want:
+            det["16d"] = extra_16d(md, args.learn_steps_16d, args.learn_pairs_16d)
+        if "4d" in want:
+            det["4d"] = extra_4d(md)
+        if "ddlms" in want:
+            det["ddlms"] = extra_ddlms(md)
+        if "kk" in want:
+            det["kk"] = extra_kk(md)
+        if "rx" in want:
+            det["rx_stream"] = extra_rx(md, args.rx_seconds)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(md, wl.X, wl.labels, 9.0, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -16,6 +16,9 @@ Constellations
     scaled in float64 so that the average energy per two real dimensions is 1,
     then rounded once to float32; label = point index.
   * BPSK and Gray QPSK (closed-form test cases).
+  * 4D product of two square QAMs (M = 4096 for 64-QAM x 64-QAM), labels concatenated
+    like the 8-PSK product: a structured large constellation whose LLRs a small
+    network can represent (each bit depends on one real coordinate).
   * Square M-QAM (M = 4, 16, 64, 256) with a BRGC label per axis: point (i, q) sits at
     (2i - L + 1, 2q - L + 1) / sqrt(E) with L = sqrt(M) and E = 2 (L^2 - 1) / 3 (unit
     energy per 2D), label (g(i) << log2 L) | g(q), g(x) = x ^ (x >> 1); the paper's
@@ -81,6 +84,23 @@ def product_4d_8psk():
             X[j, 0:2] = X2[a]
             X[j, 2:4] = X2[b]
             labels[j] = (int(l2[a]) << 3) | int(l2[b])
+    return X, labels
+
+
+def qam_product_4d(M2: int = 64):
+    """4D product of two square M2-QAM (BRGC per axis, unit energy per 2D): point
+    j = M2 a + b is (x_a, x_b), label (l_a << log2 M2) | l_b; M = M2^2 points."""
+    X2, l2 = qam_gray(M2)
+    b2 = M2.bit_length() - 1
+    M = M2 * M2
+    X = np.zeros((M, 4), dtype=np.float32)
+    labels = np.zeros(M, dtype=np.uint32)
+    for a in range(M2):
+        for b in range(M2):
+            j = M2 * a + b
+            X[j, 0:2] = X2[a]
+            X[j, 2:4] = X2[b]
+            labels[j] = (int(l2[a]) << b2) | int(l2[b])
     return X, labels
 
 
