@@ -144,25 +144,43 @@ def timed(fn, reps=3):
     return sorted(ts)[len(ts) // 2]
 
 
-def extra_precisions(md, wl, X, labels, N, tx, y, llr):
-    """BF16 subset-sum variant and max-log on the same channel draws, at 4, 9 and 14 dB."""
+def oracle_gmi(X, labels, y, tx, sigma2):
+    """FP64 oracle GMI of received symbols y (host float32) with transmitted indices tx."""
+    import numpy as np
+    import oracle
+    L = oracle.llr_exact(X, labels, y, sigma2)
+    return oracle.gmi(L, tx.astype(np.uint32), labels)[0]
+
+
+def extra_precisions(md, wl, X, labels, N, tx, y, llr, n_oracle=50_000):
+    """Precision variants on the same channel draws at 4, 9 and 14 dB: FP32 scores (the
+    headline path), one-pass FP16 and BF16 scores, BF16 subset sums, max-log.  Each: time
+    per N symbols and GMI over N; and on the first n_oracle symbols the GMI of the same
+    variant against the FP64 oracle's GMI of those symbols (|dGMI|)."""
     import math
-    out = {"bf16": {}, "maxlog": {}}
+    out = {}
+    variants = (("fp32", lambda s2: md.llr_exact(X, labels, y, s2, out=llr)),
+                ("fp16", lambda s2: md.llr_exact(X, labels, y, s2, prec="fp16", out=llr)),
+                ("bf16_scores", lambda s2: md.llr_exact(X, labels, y, s2, prec="bf16_scores", out=llr)),
+                ("bf16_sums", lambda s2: md.llr_exact(X, labels, y, s2, prec="bf16", out=llr)),
+                ("maxlog", lambda s2: md.llr_maxlog(X, labels, y, s2, out=llr)))
     for snr in (4.0, 9.0, 14.0):
         s2 = wl.sigma2(snr)
         md.awgn_sample(X, wl.seed, 0, N, math.sqrt(s2), tx=tx, y=y)
-        md.llr_exact(X, labels, y, s2, out=llr)
-        g32 = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
-        t16 = timed(lambda: md.llr_exact(X, labels, y, s2, prec="bf16", out=llr))
-        g16 = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
-        tml = timed(lambda: md.llr_maxlog(X, labels, y, s2, out=llr))
-        gml = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
-        out["bf16"][f"{snr:g}"] = {"llr_ms": t16, "symbols_per_s": N / (t16 * 1e-3),
-                                   "exp_pipe_frac": N * wl.M / (t16 * 1e-3) / EXP_PEAK, "gmi": g16,
-                                   "gmi_minus_fp32": g16 - g32}
-        out["maxlog"][f"{snr:g}"] = {"llr_ms": tml, "symbols_per_s": N / (tml * 1e-3), "gmi": gml,
-                                     "gmi_minus_exact": gml - g32}
-    return out
+        y_h = y[:n_oracle].cpu().numpy()
+        tx_h = tx[:n_oracle].cpu().numpy()
+        g_or = oracle_gmi(wl.X, wl.labels, y_h, tx_h, s2)
+        row = {"gmi_oracle_subset": g_or}
+        for name, fn in variants:
+            t = timed(lambda: fn(s2))
+            g = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)[0].item()
+            g_sub = md.gmi_reduce(llr[:n_oracle], tx[:n_oracle], labels, per_bit=False, se=False)[0].item()
+            row[name] = {"llr_ms": t, "symbols_per_s": N / (t * 1e-3), "exp_pipe_frac": N * wl.M / (t * 1e-3) / EXP_PEAK,
+                         "gmi": g, "abs_dgmi_vs_oracle_subset": abs(g_sub - g_or)}
+        for name, _ in variants[1:]:
+            row[name]["gmi_minus_fp32"] = row[name]["gmi"] - row["fp32"]["gmi"]
+        out[f"{snr:g}"] = row
+    return {"precisions": out, "oracle_subset_symbols": n_oracle}
 
 
 def extra_learned(md, wl, X, labels, N, tx, y, llr, steps, pairs):
@@ -620,6 +638,7 @@ def main():
     dt = time.perf_counter() - t0
     fast_total_ms, fast_launches = md.kernel_timing_read()
     md.kernel_timing(False)
+    path_counts = list(md.llr_path_counts())     # of the last timed call (14 dB)
     ms_per_step = 1e3 * dt / args.steps
     sym_per_step = len(snrs) * N
     value = sym_per_step / (dt / args.steps)
@@ -643,6 +662,17 @@ def main():
                 "pair_issue": {"peak": PAIR_PEAK / 1e12, "unit": "Tpair/s", "frac": exps / PAIR_PEAK,
                                "basis": "VALU issue of 1 v_exp_f32 (8 cycles/wave64) + 2 v_add_f32 (2 cycles/"
                                         "wave64) per pair: this kernel's own instruction mix"}}
+
+    # error against the FP64 oracle for every result: each SNR point's GMI on its first
+    # n_check received symbols, GPU path against the oracle on the same symbols
+    n_check = 20_000
+    check = {}
+    for i, s2 in enumerate(sig2):
+        md.awgn_sample(X, wl.seed, i * N, n_check, math.sqrt(s2), tx=tx[:n_check], y=y[:n_check])
+        md.llr_exact(X, labels, y[:n_check], s2, out=llr[:n_check])
+        g_gpu = md.gmi_reduce(llr[:n_check], tx[:n_check], labels, per_bit=False, se=False)[0].item()
+        g_or = oracle_gmi(wl.X, wl.labels, y[:n_check].cpu().numpy(), tx[:n_check].cpu().numpy(), s2)
+        check[f"{snrs[i]:g}"] = abs(g_gpu - g_or)
 
     peaks = measured_peaks(md)
     roofline["measured_peaks"] = peaks
@@ -674,7 +704,9 @@ def main():
                                     "llr_exact_median": float(np.median(llr_ms)),
                                     "gmi_reduce": float(np.mean(gmi_ms))},
                    "demap_gmi_symbols_per_s": N / ((llr_avg_ms + float(np.mean(gmi_ms))) * 1e-3),
-                   "wide_careful_symbols_at_14dB": list(md.llr_path_counts())},
+                   "wide_careful_symbols_at_14dB": path_counts,
+                   "abs_dgmi_vs_oracle": {"symbols_per_point": n_check, "per_snr": check,
+                                          "max": max(check.values())}},
     }
     if not args.no_extras:
         want = set(EXTRAS) if args.extras == "all" else set(args.extras.split(","))

@@ -64,9 +64,23 @@ extern "C" {
  *     subset sums in FP32.
  *   MD_PREC_BF16: same scores; the exponentials are rounded to BF16 and the
  *     subset sums are formed by a BF16 MFMA contraction against the label-bit
- *     matrix with FP32 accumulation (LLR relative error about 2^-8). */
+ *     matrix with FP32 accumulation (LLR relative error about 2^-8).
+ *   MD_PREC_FP16: reduced-precision scores -- one unsplit FP16 MFMA pass whose K
+ *     dimension holds [a x (D), p_hi, p_lo, a, a] against [(2c/a) y (D), a, a, r_hi,
+ *     r_lo] (D + 4 slots, so D <= 12; the per-point and per-symbol biases keep a hi/lo
+ *     split), FP32 accumulation: every score carries an error of at most about
+ *     2^-10 sum_k |u_k w_k| base-2 units (u = a x, w = (2c/a) y), so each LLR moves by at
+ *     most 2 ln 2 times that; half the matrix work of MD_PREC_FP32.  Exponentials and
+ *     subset sums in FP32 after the same fixed exponent shift (no running maximum is
+ *     needed: every score is measured from -c ||y||^2).  Symbols whose sums leave the
+ *     FP32 range are evaluated by the FP64 kernel.
+ *   MD_PREC_BF16_SCORES: the same one-pass layout with BF16 operands (score error about
+ *     2^-8 sum_k |u_k w_k|).
+ * The reduced-precision variants are measured against the FP64 oracle, not pinned. */
 #define MD_PREC_FP32 0
+#define MD_PREC_FP16 1
 #define MD_PREC_BF16 2
+#define MD_PREC_BF16_SCORES 3
 
 /* ------------------------------------------------------------------ channel */
 /* awgn_sample -- draws N channel uses: a uniform transmitted index u_n in [0, M)
@@ -111,7 +125,8 @@ int awgn_sample(const float* d_X, int M, int D, uint64_t seed, uint64_t offset, 
  *   d_labels  M uint32, a permutation of [0, M); l_j is the label of point j
  *   d_y       N x D float32 received symbols
  *   sigma2    noise variance per real dimension (> 0, finite)
- *   prec      MD_PREC_FP32 or MD_PREC_BF16
+ *   prec      MD_PREC_FP32, MD_PREC_FP16, MD_PREC_BF16 or MD_PREC_BF16_SCORES (FP16 and
+ *             BF16_SCORES take D <= 12, else MD_EUNSUPPORTED)
  *   d_llr     out: N x m float32
  * Symbols whose subset sums leave the FP32 range in the first pass (a subset's best
  * point more than 196 base-2 units below the bias; high SNR) are evaluated again in

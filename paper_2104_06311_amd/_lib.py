@@ -17,7 +17,7 @@ STATUS_NAMES = {
     0: "MD_OK", -1: "MD_EINVAL", -2: "MD_ENOTPOW2", -3: "MD_ELABEL", -4: "MD_EDIM",
     -5: "MD_ENOMEM", -6: "MD_EHIP", -7: "MD_ENODEV", -8: "MD_EUNSUPPORTED",
 }
-PREC = {"fp32": 0, "bf16": 2}
+PREC = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16_scores": 3}
 
 # name -> (restype, argtypes)
 _P = ctypes.c_void_p

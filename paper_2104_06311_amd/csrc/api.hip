@@ -32,7 +32,10 @@ int check_demap_args(const float* d_X, const uint32_t* d_labels, int M, int D, c
   if (N > INT32_MAX) return fail(MD_EINVAL, "N above 2^31 - 1 symbols in one call");
   if (N > 0 && (!d_y || !d_llr)) return fail(MD_EINVAL, "y or llr pointer is NULL");
   if (!(sigma2 > 0.0) || !std::isfinite(sigma2)) return fail(MD_EINVAL, "sigma2 must be finite and > 0");
-  if (prec != MD_PREC_FP32 && prec != MD_PREC_BF16) return fail(MD_EINVAL, "unknown precision");
+  if (prec != MD_PREC_FP32 && prec != MD_PREC_FP16 && prec != MD_PREC_BF16 && prec != MD_PREC_BF16_SCORES)
+    return fail(MD_EINVAL, "unknown precision");
+  if ((prec == MD_PREC_FP16 || prec == MD_PREC_BF16_SCORES) && D > 12)
+    return fail(MD_EUNSUPPORTED, "one-pass FP16 / BF16 scores take D <= 12");
   return MD_OK;
 }
 
@@ -61,14 +64,15 @@ int demap(const float* d_X, const uint32_t* d_labels, int M, int D, const float*
   int* flags = nullptr;
   st = md::stream_flags(s, &flags);
   if (st != MD_OK) return st;
-  st = md::prepare(d_X, d_labels, M, D, N, alpha, c_over_alpha, ws, s, &P, flags);
+  st = md::prepare(d_X, d_labels, M, D, N, alpha, c_over_alpha, ws, s, &P, flags,
+                   maxlog ? 0 : md::score_layout(prec));
   if (st != MD_OK) return st;
   md::LastCall lc;
   lc.valid = true;
   lc.maxlog = maxlog;
   lc.N = N;
   md::record_last_call(s, lc);
-  return md::launch_llr(P, M, D, d_y, N, sigma2, maxlog, prec == MD_PREC_BF16, d_llr, s);
+  return md::launch_llr(P, M, D, d_y, N, sigma2, maxlog, prec, d_llr, s);
 }
 
 }  // namespace

@@ -95,17 +95,20 @@ struct Prepared {
                             // second pass it is reused for the third list (careful kernel)
   unsigned* fb_list2;       // symbols left after the two-window pass (capacity N)
   int ks;                   // number of 16-slot K steps of the fragment
+  int sc;                   // score contraction: 0 split FP16, 1 one FP16 pass, 2 one BF16 pass
   float alpha;              // power-of-two operand balance a
   float c_over_alpha;       // c / a, c = log2(e) / (2 sigma2)
 };
 
 // Builds the label-ordered copy, fragments and flags for one call.  `ws` must point
 // at a workspace of at least prep_bytes(M, D, N) bytes.
-size_t prep_bytes(int M, int D, int64_t N);
+size_t prep_bytes(int M, int D, int64_t N);   // an upper bound for every fragment layout
 // `flags` (8 ints) may be given by the caller; otherwise they are carved from ws.
+// sc selects the fragment layout of the score contraction (Prepared::sc).
 int prepare(const float* d_X, const uint32_t* d_labels, int M, int D, int64_t N, float alpha,
-            float c_over_alpha, char* ws, hipStream_t stream, Prepared* out, int* flags = nullptr);
+            float c_over_alpha, char* ws, hipStream_t stream, Prepared* out, int* flags = nullptr, int sc = 0);
 
-int frag_ksteps(int D);    // ceil((3 D + 4) / 16) steps of 16 K slots
+int frag_ksteps(int D);    // ceil((3 D + 4) / 16) steps of 16 K slots (split FP16 scores)
+int frag_ksteps_single(int D);   // ceil((D + 4) / 16) steps (one-pass FP16 or BF16 scores)
 
 }  // namespace md

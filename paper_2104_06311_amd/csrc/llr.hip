@@ -326,7 +326,7 @@ void score_scales(double sigma2, float* alpha, float* c_over_alpha) {
 }
 
 int launch_llr(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, bool maxlog,
-               bool bf16, float* d_llr, hipStream_t stream) {
+               int prec, float* d_llr, hipStream_t stream) {
   if (M <= kSmallM) {
     return maxlog ? launch_small_t<true>(P, M, D, d_y, N, sigma2, d_llr, stream)
                   : launch_small_t<false>(P, M, D, d_y, N, sigma2, d_llr, stream);
@@ -339,9 +339,18 @@ int launch_llr(const Prepared& P, int M, int D, const float* d_y, int64_t N, dou
     if (st != MD_OK) return st;
     return launch_careful_t<true>(P, M, D, d_y, N, sigma2, d_llr, P.fb_list, 1, stream);
   }
+  if (P.sc != 0) {
+    // reduced-precision scores: symbols outside the fast pass's range go straight to the
+    // FP64 kernel (their LLRs are then exact)
+    const int slot = timing_begin(stream);
+    int st = launch_fast_lowp(P, M, D, d_y, N, sigma2, d_llr, stream);
+    timing_end(stream, slot);
+    if (st != MD_OK) return st;
+    return launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, P.fb_list, 1, stream);
+  }
   const int slot = timing_begin(stream);
-  int st = bf16 ? launch_fast_bf16(P, M, D, d_y, N, d_llr, stream)
-                : launch_fast_exact(P, M, D, d_y, N, sigma2, d_llr, stream);
+  int st = prec == MD_PREC_BF16 ? launch_fast_bf16(P, M, D, d_y, N, d_llr, stream)
+                                : launch_fast_exact(P, M, D, d_y, N, sigma2, d_llr, stream);
   timing_end(stream, slot);
   if (st != MD_OK) return st;
   st = launch_wide_exact(P, M, D, d_y, d_llr, stream);

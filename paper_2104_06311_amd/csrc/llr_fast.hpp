@@ -22,6 +22,20 @@ __device__ __forceinline__ half8 as_half8(uint4 v) {
   return h;
 }
 
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// One K step of the score contraction.  SC 0 and 1 hold FP16 operands; SC 2 holds BF16
+// bits in the same 16-byte registers (the one-pass BF16 layout of prep.hip).
+template <int SC>
+__device__ __forceinline__ floatx16 score_mfma(half8 a, half8 b, floatx16 c) {
+  if constexpr (SC == 2) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b),
+                                                   c, 0, 0, 0);
+  } else {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+}
+
 // ------------------------------------------------------------------ fast kernel
 // e = 2^(t + kExpBias): with t <= 0 (up to rounding) every partial sum stays below
 // 2^(16 + 1 + kExpBias) < 2^128, and a subset only loses FP32 range (sum < 2^-96, the
@@ -50,12 +64,21 @@ constexpr int bstage_bytes() { return 32 * 16 * KS * 2; }
 // w = (2c/a) y and r = (bias - c ||y||^2)/a is assembled in the wave's LDS staging row
 // (lane half 0 writes), then every lane reads its 8-slot fragments.  Returns true when
 // an operand leaves the FP16 split range (the symbol then takes the fallback path).
-template <int KS>
+//
+// SC 1 and 2 (one-pass FP16 or BF16 scores): the row is [ w (D), a, a, r_hi, r_lo, 0 ... ]
+// with every slot rounded once to the operand format.
+template <int SC>
+__device__ __forceinline__ _Float16 op_round(float v) {
+  if constexpr (SC == 2) return __builtin_bit_cast(_Float16, static_cast<__bf16>(v));
+  else return static_cast<_Float16>(v);
+}
+
+template <int KS, int SC = 0>
 __device__ __forceinline__ bool build_symbol_operand(_Float16* row, const float* __restrict__ y, int64_t n,
                                                      bool live, int D, float cb, float cn, float alpha,
                                                      float bias, half8 (&bf)[KS]) {
   constexpr int S = 16 * KS;
-  constexpr int DMAX = (S - 4) / 3;          // 3 D + 4 slots fit in KS steps
+  constexpr int DMAX = SC == 0 ? (S - 4) / 3 : S - 4;   // 3 D + 4 (or D + 4) slots fit in KS steps
   const int h = (threadIdx.x & 63) >> 5;
   float ysq = 0.0f;
   bool bad = false;
@@ -70,25 +93,31 @@ __device__ __forceinline__ bool build_symbol_operand(_Float16* row, const float*
     ysq = fmaf(yd, yd, ysq);
     const float w = cb * yd;
     bad |= !(fabsf(w) <= 30000.0f);
-    const _Float16 hi = static_cast<_Float16>(w);
-    const _Float16 lo = static_cast<_Float16>(w - static_cast<float>(hi));
-    if (h == 0) {
-      row[d] = hi;
-      row[D + d] = hi;
-      row[2 * D + d] = lo;
+    if constexpr (SC == 0) {
+      const _Float16 hi = static_cast<_Float16>(w);
+      const _Float16 lo = static_cast<_Float16>(w - static_cast<float>(hi));
+      if (h == 0) {
+        row[d] = hi;
+        row[D + d] = hi;
+        row[2 * D + d] = lo;
+      }
+    } else {
+      if (h == 0) row[d] = op_round<SC>(w);
     }
   }
   const float r = bias / alpha - cn * ysq;
   bad |= !(fabsf(r) <= 30000.0f);
-  const _Float16 rhi = static_cast<_Float16>(r);
-  const _Float16 rlo = static_cast<_Float16>(r - static_cast<float>(rhi));
+  const _Float16 rhi = op_round<SC>(r);
+  const float rhi_f = SC == 2 ? static_cast<float>(__builtin_bit_cast(__bf16, rhi)) : static_cast<float>(rhi);
+  const _Float16 rlo = op_round<SC>(r - rhi_f);
   if (h == 0) {
-    const _Float16 a16 = static_cast<_Float16>(alpha);
-    row[3 * D] = a16;
-    row[3 * D + 1] = a16;
-    row[3 * D + 2] = rhi;
-    row[3 * D + 3] = rlo;
-    for (int k = 3 * D + 4; k < S; ++k) row[k] = static_cast<_Float16>(0.0f);
+    const _Float16 a16 = op_round<SC>(alpha);
+    const int nb = SC == 0 ? 3 * D : D;
+    row[nb] = a16;
+    row[nb + 1] = a16;
+    row[nb + 2] = rhi;
+    row[nb + 3] = rlo;
+    for (int k = nb + 4; k < S; ++k) row[k] = static_cast<_Float16>(0.0f);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -127,7 +156,7 @@ __device__ __forceinline__ void acc_init(SymAcc<MB> (&ac)[SB]) {
 
 // Accumulates the tiles [t0, t0 + tn) of one LDS-resident chunk (tile t of the chunk is at
 // lds[t * KS * 64 ...]; tn is a multiple of G) into the SB symbol blocks' partial sums.
-template <int KS, int MB, int SB, bool MAXLOG>
+template <int KS, int MB, int SB, bool MAXLOG, int SC = 0>
 __device__ __forceinline__ void tile_loop(const uint4* __restrict__ lds, int t0, int tn, int lane,
                                           const half8 (&bf)[SB][KS], SymAcc<MB> (&ac)[SB]) {
   constexpr int LOG2G = Geo<MB>::LOG2G;
@@ -144,8 +173,7 @@ __device__ __forceinline__ void tile_loop(const uint4* __restrict__ lds, int t0,
 #pragma unroll
       for (int rr = 0; rr < 16; ++rr) cur[sb][rr] = 0.0f;
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks)
-        cur[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], cur[sb], 0, 0, 0);
+      for (int ks = 0; ks < KS; ++ks) cur[sb] = score_mfma<SC>(ah[ks], bf[sb][ks], cur[sb]);
     }
     const int t1 = min(1, tn - 1);
 #pragma unroll
@@ -163,8 +191,7 @@ __device__ __forceinline__ void tile_loop(const uint4* __restrict__ lds, int t0,
 #pragma unroll
         for (int rr = 0; rr < 16; ++rr) nxt[sb][rr] = 0.0f;
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-          nxt[sb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[sb][ks], nxt[sb], 0, 0, 0);
+        for (int ks = 0; ks < KS; ++ks) nxt[sb] = score_mfma<SC>(ah[ks], bf[sb][ks], nxt[sb]);
       }
       // At the chunk's end this reads up to two tiles past it, into the symbol staging rows
       // that follow every fragment buffer in LDS (at least 2 KS KiB); those products are
@@ -337,7 +364,7 @@ __device__ __forceinline__ bool sums_in_range(const float (&S0)[MB], const float
   return smin >= 0x1p-96f && smax <= 0x1p+126f;
 }
 
-template <int KS, int WAVES, int MB, int SB, bool MAXLOG>
+template <int KS, int WAVES, int MB, int SB, bool MAXLOG, int SC = 0>
 __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __restrict__ frag, int ntiles,
                                                               int chunk_tiles, int D,
                                                               const float* __restrict__ y, int64_t N, float cb,
@@ -369,8 +396,8 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
     for (int sb = 0; sb < SB; ++sb) {
       const int64_t n = g * per_group + (static_cast<int64_t>(wave) * SB + sb) * 32 + (lane & 31);
       nsym[sb] = n;
-      const bool b = build_symbol_operand<KS>(bst + (sb * 32 + (lane & 31)) * S, y, n, n < N, D, cb, cn, alpha,
-                                              MAXLOG ? 0.0f : kExpBias, bf[sb]);
+      const bool b = build_symbol_operand<KS, SC>(bst + (sb * 32 + (lane & 31)) * S, y, n, n < N, D, cb, cn,
+                                                  alpha, MAXLOG ? 0.0f : kExpBias, bf[sb]);
       bad[sb] = b || range_bad;
     }
     acc_init<MB, SB, MAXLOG>(ac);
@@ -385,7 +412,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
         __syncthreads();
         staged = true;
       }
-      tile_loop<KS, MB, SB, MAXLOG>(lds, t0, tn, lane, bf, ac);
+      tile_loop<KS, MB, SB, MAXLOG, SC>(lds, t0, tn, lane, bf, ac);
     }
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) {
@@ -411,7 +438,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
   }
 }
 
-template <int KS, int WAVES, int MB, int SB, bool MAXLOG>
+template <int KS, int WAVES, int MB, int SB, bool MAXLOG, int SC = 0>
 int launch_fast_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
                   hipStream_t stream) {
   const int ntiles = M / 32;
@@ -424,7 +451,7 @@ int launch_fast_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
   if (chunk_tiles > ntiles) chunk_tiles = ntiles;
   if (chunk_tiles < G) return fail(MD_EUNSUPPORTED, "constellation fragments do not fit in LDS");
   const size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
-  auto kern = llr_fast_kernel<KS, WAVES, MB, SB, MAXLOG>;
+  auto kern = llr_fast_kernel<KS, WAVES, MB, SB, MAXLOG, SC>;
   {
     const int st_attr = set_lds_limit(reinterpret_cast<const void*>(kern), 160 * 1024);
     if (st_attr != MD_OK) return st_attr;
@@ -448,22 +475,22 @@ int launch_fast_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
   return MD_OK;
 }
 
-template <int KS, int W, int SBV, bool MAXLOG>
+template <int KS, int W, int SBV, bool MAXLOG, int SC = 0>
 int launch_fast_m(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
                   hipStream_t stream) {
   switch (ilog2_pow2(M)) {
-    case 5: return launch_fast_t<KS, W, 5, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 6: return launch_fast_t<KS, W, 6, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 7: return launch_fast_t<KS, W, 7, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 8: return launch_fast_t<KS, W, 8, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 9: return launch_fast_t<KS, W, 9, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 10: return launch_fast_t<KS, W, 10, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 11: return launch_fast_t<KS, W, 11, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 12: return launch_fast_t<KS, W, 12, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 13: return launch_fast_t<KS, W, 13, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 14: return launch_fast_t<KS, W, 14, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 15: return launch_fast_t<KS, W, 15, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    default: return launch_fast_t<KS, W, 16, SBV, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 5: return launch_fast_t<KS, W, 5, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 6: return launch_fast_t<KS, W, 6, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 7: return launch_fast_t<KS, W, 7, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 8: return launch_fast_t<KS, W, 8, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 9: return launch_fast_t<KS, W, 9, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 10: return launch_fast_t<KS, W, 10, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 11: return launch_fast_t<KS, W, 11, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 12: return launch_fast_t<KS, W, 12, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 13: return launch_fast_t<KS, W, 13, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 14: return launch_fast_t<KS, W, 14, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 15: return launch_fast_t<KS, W, 15, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    default: return launch_fast_t<KS, W, 16, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
   }
 }
 
@@ -663,6 +690,14 @@ int launch_fast(const Prepared& P, int M, int D, const float* d_y, int64_t N, do
     case 5: return launch_fast_m<5, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
     default: return launch_fast_m<6, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
   }
+}
+
+// One-pass FP16 (SC 1) or BF16 (SC 2) scores, exact LLRs: one K step (D <= 12).
+template <int SC>
+int launch_fast_lowp(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
+                     hipStream_t stream) {
+  if (P.ks != 1 || P.sc != SC) return fail(MD_EUNSUPPORTED, "reduced-precision scores need D <= 12");
+  return launch_fast_m<1, 16, 1, false, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
 }
 
 

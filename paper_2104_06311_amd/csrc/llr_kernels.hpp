@@ -15,13 +15,20 @@ void score_scales(double sigma2, float* alpha, float* c_over_alpha);
 // Fast MFMA path (M >= 32) followed by the careful kernel on the fallback list, or the
 // careful kernel on every symbol (M < 32).
 int launch_llr(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, bool maxlog,
-               bool bf16, float* d_llr, hipStream_t stream);
+               int prec, float* d_llr, hipStream_t stream);
 int launch_fast_exact(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
                       hipStream_t stream);
 int launch_fast_maxlog(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2,
                        float* d_llr, hipStream_t stream);
 int launch_fast_bf16(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr,
                      hipStream_t stream);
+// One-pass FP16 or BF16 scores (P.sc 1 or 2, one K step), exact LLRs.
+int launch_fast_lowp(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
+                     hipStream_t stream);
+// Fragment layout (Prepared::sc) that llr_exact's precision `prec` needs.
+inline int score_layout(int prec) {
+  return prec == MD_PREC_FP16 ? 1 : (prec == MD_PREC_BF16_SCORES ? 2 : 0);
+}
 // Wide-range second pass over the first fallback list and third pass over the second
 // (exact LLRs; two and three exponent windows).
 int launch_wide_exact(const Prepared& P, int M, int D, const float* d_y, float* d_llr, hipStream_t stream);

@@ -68,9 +68,9 @@ int llr_exact_noalloc(const float* d_X, const uint32_t* d_labels, int M, int D, 
   md::score_scales(sigma2, &alpha, &c_over_alpha);
   md::Prepared P;
   // flags == nullptr: the stage counters are carved from the scratch array as well
-  st = md::prepare(d_X, d_labels, M, D, N, alpha, c_over_alpha, ws, s, &P, nullptr);
+  st = md::prepare(d_X, d_labels, M, D, N, alpha, c_over_alpha, ws, s, &P, nullptr, md::score_layout(prec));
   if (st != MD_OK) return st;
-  return md::launch_llr(P, M, D, d_y, N, sigma2, false, prec == MD_PREC_BF16, d_llr, s);
+  return md::launch_llr(P, M, D, d_y, N, sigma2, false, prec, d_llr, s);
 }
 
 }  // extern "C"

@@ -20,6 +20,13 @@
 // 16 * (l / 32) + r: every lane owns 16 consecutive labels of one symbol.
 // frag[(tile * KS + ks) * 64 + lane] is the 8-half A operand of that lane: row lane % 32,
 // slots 16 ks + 8 (lane / 32) .. +7.
+//
+// One-pass layouts (the reduced-precision variants of llr_exact): each factor is rounded
+// once, to FP16 or to BF16, and the K dimension holds D + 4 slots
+//   point (A) side:  [ u (D), p_hi, p_lo, a, a, 0 ... ]
+//   symbol (B) side: [ w (D), a,    a,    r_hi, r_lo, 0 ... ]
+// (the biases keep a hi/lo split in the same format), so one MFMA per tile serves
+// D <= 12 at a score error of about 2^-10 (FP16) or 2^-8 (BF16) of sum_k |u_k w_k|.
 #include <cmath>
 
 #include "common.hpp"
@@ -53,9 +60,19 @@ __device__ __forceinline__ void split_half(float v, _Float16* hi, _Float16* lo) 
   *lo = static_cast<_Float16>(v - static_cast<float>(h));
 }
 
+// The BF16 bits of v (round to nearest even), carried in an FP16 slot of the row.
+__device__ __forceinline__ _Float16 bf16_bits(float v) {
+  return __builtin_bit_cast(_Float16, static_cast<__bf16>(v));
+}
+__device__ __forceinline__ void split_bf16(float v, _Float16* hi, _Float16* lo) {
+  const __bf16 h = static_cast<__bf16>(v);
+  *hi = __builtin_bit_cast(_Float16, h);
+  *lo = bf16_bits(v - static_cast<float>(h));
+}
+
 // One thread per label slot s (padded to a multiple of 32).
 __global__ void prep_build_kernel(const float* __restrict__ X, const uint32_t* __restrict__ labels,
-                                  const uint32_t* __restrict__ inv, int M, int Mpad, int D, int KS,
+                                  const uint32_t* __restrict__ inv, int M, int Mpad, int D, int KS, int sc,
                                   float alpha, float c_over_alpha, float* __restrict__ xl,
                                   uint4* __restrict__ frag, int* __restrict__ flags) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -75,20 +92,31 @@ __global__ void prep_build_kernel(const float* __restrict__ X, const uint32_t* _
       nrm += static_cast<double>(v) * static_cast<double>(v);
       const float u = alpha * v;
       range |= !(fabsf(u) <= 30000.0f);
-      _Float16 hi, lo;
-      split_half(u, &hi, &lo);
-      row[d] = hi;
-      row[D + d] = lo;
-      row[2 * D + d] = hi;
+      if (sc == 0) {
+        _Float16 hi, lo;
+        split_half(u, &hi, &lo);
+        row[d] = hi;
+        row[D + d] = lo;
+        row[2 * D + d] = hi;
+      } else {
+        row[d] = sc == 1 ? static_cast<_Float16>(u) : bf16_bits(u);
+      }
     }
     const float p = -c_over_alpha * static_cast<float>(nrm);
     range |= !(fabsf(p) <= 30000.0f);
     _Float16 hi, lo;
-    split_half(p, &hi, &lo);
-    row[3 * D] = hi;
-    row[3 * D + 1] = lo;
-    row[3 * D + 2] = static_cast<_Float16>(alpha);
-    row[3 * D + 3] = static_cast<_Float16>(alpha);
+    const int nb = sc == 0 ? 3 * D : D;       // first bias slot
+    if (sc == 2) {
+      split_bf16(p, &hi, &lo);
+      row[nb + 2] = bf16_bits(alpha);
+      row[nb + 3] = bf16_bits(alpha);
+    } else {
+      split_half(p, &hi, &lo);
+      row[nb + 2] = static_cast<_Float16>(alpha);
+      row[nb + 3] = static_cast<_Float16>(alpha);
+    }
+    row[nb] = hi;
+    row[nb + 1] = lo;
     if (range) flags[2] = 1;          // outside the FP16 split range (or NaN)
   }
   // padded slots (s >= M, only when M < 32) keep an all-zero row; the kernels that use
@@ -109,6 +137,7 @@ __global__ void prep_build_kernel(const float* __restrict__ X, const uint32_t* _
 }  // namespace
 
 int frag_ksteps(int D) { return (3 * D + 4 + 15) / 16; }
+int frag_ksteps_single(int D) { return (D + 4 + 15) / 16; }
 
 size_t prep_bytes(int M, int D, int64_t N) {
   const int Mpad = ((M + 31) / 32) * 32;
@@ -123,9 +152,9 @@ size_t prep_bytes(int M, int D, int64_t N) {
 }
 
 int prepare(const float* d_X, const uint32_t* d_labels, int M, int D, int64_t N, float alpha,
-            float c_over_alpha, char* ws, hipStream_t stream, Prepared* out, int* flags_given) {
+            float c_over_alpha, char* ws, hipStream_t stream, Prepared* out, int* flags_given, int sc) {
   const int Mpad = ((M + 31) / 32) * 32;
-  const int KS = frag_ksteps(D);
+  const int KS = sc == 0 ? frag_ksteps(D) : frag_ksteps_single(D);
   Carver cv{ws, 0};
   float* xl = cv.take<float>(static_cast<size_t>(M) * D);
   uint4* frag = cv.take<uint4>(static_cast<size_t>(Mpad / 32) * KS * 64);
@@ -140,7 +169,7 @@ int prepare(const float* d_X, const uint32_t* d_labels, int M, int D, int64_t N,
   hipLaunchKernelGGL(prep_scatter_kernel, dim3((M + bs - 1) / bs), dim3(bs), 0, stream, d_labels, M, inv, flags);
   MD_LAUNCH_CHECK("prep_scatter_kernel launch");
   hipLaunchKernelGGL(prep_build_kernel, dim3((Mpad + bs - 1) / bs), dim3(bs), 0, stream, d_X, d_labels, inv, M,
-                     Mpad, D, KS, alpha, c_over_alpha, xl, frag, flags);
+                     Mpad, D, KS, sc, alpha, c_over_alpha, xl, frag, flags);
   MD_LAUNCH_CHECK("prep_build_kernel launch");
   out->xl = xl;
   out->frag = frag;
@@ -148,6 +177,7 @@ int prepare(const float* d_X, const uint32_t* d_labels, int M, int D, int64_t N,
   out->fb_list = fb;
   out->fb_list2 = fb2;
   out->ks = KS;
+  out->sc = sc;
   out->alpha = alpha;
   out->c_over_alpha = c_over_alpha;
   return MD_OK;

@@ -56,6 +56,10 @@ def test_argument_validation_before_device_work():
     assert L.llr_exact(fake, None, 64, 4, fake, 10, 0.1, 0, fake, None) == -1
     assert L.llr_exact(fake, fake, 64, 4, None, 10, 0.1, 0, fake, None) == -1
     assert L.llr_exact(fake, fake, 64, 4, fake, 10, 0.1, 7, fake, None) == -1
+    assert L.llr_exact(fake, fake, 64, 4, fake, 10, 0.1, 4, fake, None) == -1
+    # one-pass FP16 / BF16 scores: D <= 12
+    assert L.llr_exact(fake, fake, 64, 13, fake, 10, 0.1, 1, fake, None) == -8
+    assert L.llr_exact(fake, fake, 64, 13, fake, 10, 0.1, 3, fake, None) == -8
     assert L.llr_maxlog(fake, fake, 64, 4, fake, 10, -0.1, fake, None) == -1
     assert b"sigma2" in L.last_error()
     # more symbols in one call than the 32-bit fallback lists can index
