@@ -3,12 +3,22 @@
 // phase by a Hilbert transform computed with 1024-point overlap-save FFTs, the field
 // rebuilt from amplitude and phase, the carrier removed and the result downshifted to DC.
 //
-// One workgroup per 512 output samples: it reads the 1024 samples around them (zero
-// outside the stream), takes l = 0.5 ln x, runs a 1024-point FFT in LDS, applies the
-// analytic-signal mask, transforms back, and keeps the middle 512 phases.  The FFT is a
-// radix-4 decimation-in-time over base-4 digit-reversed loads, in place: five stages of
-// one butterfly per thread on disjoint quadruples, one barrier per stage.  The inverse is
-// conj(FFT(conj X)) / 1024.
+// One workgroup per 1024 output samples, i.e. two 512-sample blocks a and b of the
+// overlap-save scheme.  Both blocks' log-amplitudes are real, so they share one complex
+// FFT pair: z = l_a + i l_b (each the 1024 samples around its block, zero outside the
+// stream), Z = FFT(z), then w = IFFT(-i sgn(k) Z) (sgn 0 at k = 0 and k = 512).  The
+// multiplier -i sgn(k) maps the spectrum of a real signal to that of its Hilbert
+// transform (the analytic mask 1 + sgn(k) applied to l gives l + i H(l)), and it is
+// linear, so w = H(l_a) + i H(l_b): the real part holds block a's phases, the imaginary
+// part block b's.  The FFT is a radix-4 decimation-in-time over base-4 digit-reversed
+// loads, in place in LDS: five stages of one butterfly per thread on disjoint
+// quadruples, one barrier per stage; the inverse is conj(FFT(conj W)) / 1024.  The
+// twiddle factors are computed once per device (FP64, rounded to FP32) into a device
+// table that every workgroup copies to LDS.  Logarithm, exponential, sine and cosine use
+// the hardware instructions (base 2, and revolutions for sine and cosine); the
+// downshift phase frac(nu t) is formed in FP64 from one product per workgroup.
+#include <mutex>
+
 #include "common.hpp"
 
 namespace md {
@@ -18,6 +28,40 @@ constexpr int kKkN = 1024;
 constexpr int kKkHop = 512;
 constexpr int kKkPad = 256;
 constexpr int kKkThreads = 256;
+constexpr int kKkSpan = kKkN + kKkHop;     // samples a workgroup reads: 1536
+constexpr int kKkTw = 3 * kKkN / 4;
+
+__device__ float2 g_kk_tw[kKkTw];          // exp(-2 pi i j / 1024), j < 768, one table per device
+
+__global__ void kk_twiddle_kernel() {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kKkTw) return;
+  double s, c;
+  sincospi(static_cast<double>(j) / 512.0, &s, &c);
+  g_kk_tw[j] = make_float2(static_cast<float>(c), static_cast<float>(-s));
+}
+
+std::mutex g_tw_mu;
+bool g_tw_done[64] = {};
+
+// Fills this device's twiddle table once, on a private stream that the call waits for
+// (so the caller's stream, even one being captured, is not involved).
+int ensure_twiddles() {
+  int dev = 0;
+  MD_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(MD_ENODEV, "kk_frontend: device index above 63");
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  if (g_tw_done[dev]) return MD_OK;
+  hipStream_t ts = nullptr;
+  MD_HIP_TRY(hipStreamCreateWithFlags(&ts, hipStreamNonBlocking));
+  hipLaunchKernelGGL(kk_twiddle_kernel, dim3((kKkTw + 255) / 256), dim3(256), 0, ts);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(ts);
+  (void)hipStreamDestroy(ts);
+  if (e != hipSuccess) return hip_fail(e, "kk_twiddle_kernel");
+  g_tw_done[dev] = true;
+  return MD_OK;
+}
 
 // reversal of the five base-4 digits of a 10-bit index: the bit reversal with each bit
 // pair swapped back
@@ -57,57 +101,72 @@ __device__ __forceinline__ void fft1024(float2* a, const float2* tw) {
   }
 }
 
+constexpr float kHalfLn2 = 0.34657359027997265471f;     // ln(2) / 2
+constexpr float kLog2e = 1.44269504088896340736f;
+constexpr float kInv2Pi = 0.15915494309189533577f;
+
 __global__ void __launch_bounds__(kKkThreads) kk_kernel(const float* __restrict__ x, int64_t T, float A, double nu,
                                                         float2* __restrict__ out) {
   __shared__ float2 a[kKkN];
-  __shared__ float2 b[kKkN];
-  __shared__ float2 tw[3 * kKkN / 4];
-  __shared__ float lmid[kKkHop];
+  __shared__ float2 tw[kKkTw];
+  __shared__ float l[kKkSpan];
   const int tid = threadIdx.x;
-  const int64_t blk = blockIdx.x;
-  const int64_t start = blk * kKkHop - kKkPad;
-  for (int j = tid; j < 3 * kKkN / 4; j += kKkThreads) {
-    double s, c;
-    sincospi(static_cast<double>(j) / 512.0, &s, &c);   // exp(-2 pi i j / 1024)
-    tw[j] = make_float2(static_cast<float>(c), static_cast<float>(-s));
+  const int64_t start = static_cast<int64_t>(blockIdx.x) * (2 * kKkHop) - kKkPad;   // first sample of block a's window
+  const bool has_b = start + kKkPad + kKkHop < T;                                    // block b lies inside the stream
+  for (int j = tid; j < kKkTw; j += kKkThreads) tw[j] = g_kk_tw[j];
+  // l = 0.5 ln x over the workgroup's 1536 samples (block a's window, then the 512 more of b's)
+#pragma unroll
+  for (int q = 0; q < kKkSpan / kKkThreads; ++q) {
+    const int i = tid + q * kKkThreads;
+    const int64_t t = start + i;
+    // floor: see kk_frontend
+    l[i] = (t >= 0 && t < T) ? kHalfLn2 * __builtin_amdgcn_logf(fmaxf(x[t], 0x1p-126f)) : 0.0f;
   }
+  __syncthreads();
+  // z = l_a + i l_b in digit-reversed order (block b's window starts 512 samples later)
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int i = tid + q * kKkThreads;
-    const int64_t t = start + i;
-    const float l = (t >= 0 && t < T) ? 0.5f * logf(fmaxf(x[t], 0x1p-126f)) : 0.0f;   // floor: see kk_frontend
-    a[digrev4(i)] = make_float2(l, 0.0f);
-    if (i >= kKkPad && i < kKkPad + kKkHop) lmid[i - kKkPad] = l;
+    a[digrev4(i)] = make_float2(l[i], has_b ? l[i + kKkHop] : 0.0f);
   }
   __syncthreads();
   fft1024(a, tw);
-  // analytic mask (1, 2 .. 2, 1, 0 .. 0), conjugated into digit-reversed order
+  // W = -i sgn(k) Z, stored as conj(W) in digit-reversed order for the inverse; the
+  // butterfly partners read in place, so go through registers and a barrier
+  float2 v[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const int i = tid + q * kKkThreads;
-    const float m = (i == 0 || i == kKkN / 2) ? 1.0f : (i < kKkN / 2 ? 2.0f : 0.0f);
-    const float2 v = a[i];
-    b[digrev4(i)] = make_float2(m * v.x, -(m * v.y));
+    const int k = tid + q * kKkThreads;
+    const float2 z = a[k];
+    // -i z = (z.y, -z.x); conj of that = (z.y, z.x); for sgn = -1 the negatives
+    const float sg = (k == 0 || k == kKkN / 2) ? 0.0f : (k < kKkN / 2 ? 1.0f : -1.0f);
+    v[q] = make_float2(sg * z.y, sg * z.x);
   }
   __syncthreads();
-  fft1024(b, tw);
-  // middle 512 samples: phase = Im(conj(B) / 1024) = -Im(B) / 1024
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const int i = kKkPad + tid + q * kKkThreads;
-    const float phi = -b[i].y * (1.0f / kKkN);
-    const float amp = expf(lmid[i - kKkPad]);
-    float sp, cp;
-    sincosf(phi, &sp, &cp);
-    const float er = amp * cp - A;
-    const float ei = amp * sp;
-    const int64_t t = start + i;
-    const double ph = nu * static_cast<double>(t);
-    const double frac = ph - floor(ph);
-    double rs, rc;
-    sincospi(2.0 * frac, &rs, &rc);                    // exp(-2 pi i frac) = (rc, -rs)
-    const float2 rot = make_float2(static_cast<float>(rc), static_cast<float>(-rs));
-    out[t] = cmul(make_float2(er, ei), rot);
+  for (int q = 0; q < 4; ++q) a[digrev4(tid + q * kKkThreads)] = v[q];
+  __syncthreads();
+  fft1024(a, tw);
+  // w = conj(a) / 1024: H(l_a) = a.x / 1024, H(l_b) = -a.y / 1024; the middle 512 of each
+  const double fb = nu * static_cast<double>(start) - floor(nu * static_cast<double>(start));
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = tid + (q & 1) * kKkThreads;       // 0 .. 511 within the block's kept part
+    const int blkb = q >> 1;
+    if (blkb && !has_b) continue;
+    const int i = kKkPad + r;                         // index in the block's window
+    const float2 w = a[i];
+    const float phi = (blkb ? -w.y : w.x) * (1.0f / kKkN);
+    const float amp = __builtin_amdgcn_exp2f(kLog2e * l[i + blkb * kKkHop]);
+    const float rev = phi * kInv2Pi;                  // the hardware sine and cosine take revolutions
+    const float er = amp * __builtin_amdgcn_cosf(rev) - A;
+    const float ei = amp * __builtin_amdgcn_sinf(rev);
+    const int off = i + blkb * kKkHop;                // offset of the sample from start
+    double ph = fb + nu * static_cast<double>(off);
+    ph -= floor(ph);                                  // frac(nu t), t = start + off
+    const float f = static_cast<float>(ph);
+    const float2 rot = make_float2(__builtin_amdgcn_cosf(f), -__builtin_amdgcn_sinf(f));
+    out[start + off] = cmul(make_float2(er, ei), rot);
   }
 }
 
@@ -118,15 +177,19 @@ extern "C" {
 
 int kk_frontend(const float* d_x, int64_t T, float A, double nu, float* d_out, void* stream) {
   using namespace md;
+  set_error("");
   if (T < 0 || T % kKkHop != 0) return fail(MD_EINVAL, "kk_frontend: T must be a non-negative multiple of 512");
   if (!std::isfinite(A) || A < 0.0f) return fail(MD_EINVAL, "kk_frontend: A must be finite and >= 0");
   if (!std::isfinite(nu)) return fail(MD_EINVAL, "kk_frontend: nu must be finite");
   if (T == 0) return MD_OK;
   if (d_x == nullptr || d_out == nullptr) return fail(MD_EINVAL, "kk_frontend: d_x and d_out are required");
-  const int64_t blocks = T / kKkHop;
+  const int64_t blocks = (T / kKkHop + 1) / 2;
   if (blocks > 0x7fffffff) return fail(MD_EINVAL, "kk_frontend: T too large");
-  hipLaunchKernelGGL(kk_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kKkThreads), 0,
-                     static_cast<hipStream_t>(stream), d_x, T, A, nu, reinterpret_cast<float2*>(d_out));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int st = ensure_twiddles();
+  if (st != MD_OK) return st;
+  hipLaunchKernelGGL(kk_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kKkThreads), 0, s, d_x, T, A, nu,
+                     reinterpret_cast<float2*>(d_out));
   MD_LAUNCH_CHECK("kk_kernel launch");
   return MD_OK;
 }
