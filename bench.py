@@ -51,7 +51,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=10_000_000, help="received symbols per SNR point")
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "fp16", "bf16", "bf16_scores"])
+    ap.add_argument("--unfused", action="store_true",
+                    help="llr_exact then gmi_reduce per SNR point instead of the fused llr_exact_gmi")
     ap.add_argument("--cpu-seconds", type=float, default=5.0, help="target duration of one oracle run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -520,7 +522,8 @@ def counter_traffic(kernel_sources):
         return None, "counter summary incomplete"
 
 
-KERNEL_SOURCES = ["paper_2104_06311_amd/csrc/llr_fast.hpp", "paper_2104_06311_amd/csrc/llr_fast_exact.hip"]
+KERNEL_SOURCES = ["paper_2104_06311_amd/csrc/llr_fast.hpp", "paper_2104_06311_amd/csrc/llr_fast_exact.hip",
+                  "paper_2104_06311_amd/csrc/llr_fast_gmi.hip"]
 
 
 def extra_batched(md, n_inst):
@@ -539,8 +542,16 @@ def extra_batched(md, n_inst):
         s2.append([w.sigma2(s) for s in w.snr_db])
     s2 = np.array(s2)
     t0 = time.perf_counter()
+    md.SweepPlan.tuning_clear()
     plan = md.SweepPlan(specs, s2, variant=-1)
     plan_s = time.perf_counter() - t0
+    classes = []
+    for ks, mb, shape, items, ms in plan.classes(with_times=True):
+        members = [w for w in insts if int(w.M).bit_length() - 1 == mb and (3 * w.D + 4 + 15) // 16 == ks]
+        cp = float(sum(w.N * w.M for w in members)) * s2.shape[1]
+        classes.append({"k_steps": ks, "label_bits": mb, "shape": shape, "items": items, "kernel_ms": ms,
+                        "instances": len(members), "D": sorted({int(w.D) for w in members}), "pairs": cp,
+                        "exp_frac": cp / (ms * 1e-3) / EXP_PEAK if ms > 0 else None})
     g = plan.run()
     t_graph = timed(lambda: plan.run(out=g), reps=3)
     nmax = max(w.N for w in insts)
@@ -570,6 +581,7 @@ def extra_batched(md, n_inst):
             "graph_symbols_per_s": total / (t_graph * 1e-3), "graph_exp_frac": pairs / (t_graph * 1e-3) / EXP_PEAK,
             "graph_pair_frac": pairs / (t_graph * 1e-3) / PAIR_PEAK,
             "launch_shape": list(plan.shape), "work_items": plan.n_items, "plan_create_s": plan_s,
+            "classes": classes,
             "max_abs_gmi_diff_vs_per_instance": diff,
             "M_mix": sorted({int(w.M) for w in insts}), "D_mix": sorted({int(w.D) for w in insts})}
 
@@ -614,10 +626,16 @@ def main():
             md.awgn_sample(X, wl.seed, i * N, N, math.sqrt(s2), tx=tx, y=y)
             if record:
                 ev[i][1].record(stream)
-            md.llr_exact(X, labels, y, s2, prec=args.prec, out=llr)
-            if record:
-                ev[i][2].record(stream)
-            g, _, _ = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)
+            if args.unfused:
+                md.llr_exact(X, labels, y, s2, prec=args.prec, out=llr)
+                if record:
+                    ev[i][2].record(stream)
+                g, _, _ = md.gmi_reduce(llr, tx, labels, per_bit=False, se=False)
+            else:
+                # exact LLRs written to llr and their GMI from the fused epilogue
+                _, g, _ = md.llr_exact_gmi(X, labels, y, tx, s2, prec=args.prec, out=llr, se=False)
+                if record:
+                    ev[i][2].record(stream)
             gmis[i:i + 1].copy_(g)
             if record:
                 ev[i][3].record(stream)
@@ -692,17 +710,20 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "symbols/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if args.prec == "fp32" else "bf16", "data": "synthetic",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "bf16_scores": "bf16"}[args.prec], "data": "synthetic",
         "config": {"workload": "8d_m2048_gauss_sweep", "M": M, "D": D, "N_per_snr": N,
                    "snr_db": snrs, "prec": args.prec,
-                   "step": "awgn_sample + llr_exact + gmi_reduce per SNR point"},
+                   "step": ("awgn_sample + llr_exact + gmi_reduce" if args.unfused else
+                            "awgn_sample + llr_exact_gmi (exact LLRs written, GMI from the fused epilogue)")
+                           + " per SNR point"},
         "roofline": roofline,
         "detail": {"gmi_bits": {f"{s:g}": round(float(g), 6) for s, g in zip(snrs, gmis.cpu().tolist())},
                    "llr_symbols_per_s": N / (llr_avg_ms * 1e-3),
-                   "per_point_ms": {"awgn_sample": float(np.mean(awgn_ms)), "llr_exact": llr_avg_ms,
+                   "per_point_ms": {"awgn_sample": float(np.mean(awgn_ms)),
+                                    ("llr_exact" if args.unfused else "llr_exact_gmi"): llr_avg_ms,
                                     "llr_fast_kernel": fast_ms,
-                                    "llr_exact_median": float(np.median(llr_ms)),
-                                    "gmi_reduce": float(np.mean(gmi_ms))},
+                                    "median": float(np.median(llr_ms)),
+                                    ("gmi_reduce" if args.unfused else "gmi_copy"): float(np.mean(gmi_ms))},
                    "demap_gmi_symbols_per_s": N / ((llr_avg_ms + float(np.mean(gmi_ms))) * 1e-3),
                    "wide_careful_symbols_at_14dB": path_counts,
                    "abs_dgmi_vs_oracle": {"symbols_per_point": n_check, "per_snr": check,

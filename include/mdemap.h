@@ -56,6 +56,7 @@ extern "C" {
 #define MD_EHIP         -6   /* a HIP runtime call failed (message in last_error) */
 #define MD_ENODEV       -7   /* no GPU visible */
 #define MD_EUNSUPPORTED -8   /* combination not implemented */
+#define MD_ENONFINITE   -9   /* gmi_status: the last GMI saw non-finite loss terms */
 
 /* Precision of llr_exact.
  *   MD_PREC_FP32: scores by one split-FP16 MFMA contraction whose K dimension holds
@@ -91,24 +92,25 @@ extern "C" {
  *   key = (seed & 0xffffffff, seed >> 32); g = offset + n (64-bit);
  *   Philox4x32-10 (Salmon et al., SC'11) of counter (g_lo, g_hi, sub, domain).
  *   u_n = word0 >> (32 - m) of counter (g_lo, g_hi, 0, 1).
- *   For pair p = 0 .. ceil(D/2)-1, words r0..r3 of counter (g_lo, g_hi, p, 2):
- *     J1 = (r0 >> 6) * 2^26 + (r1 >> 6), U1 = (2 J1 + 1) * 2^-53;
- *     J2 = (r2 >> 6) * 2^26 + (r3 >> 6), quadrant Q = J2 >> 50,
- *     T = J2 mod 2^50 (the angle is 2 pi (2 J2 + 1) 2^-53);
- *     ln U1 from U1 = f 2^e, f in [1,2) (f/2 and e+1 if f > sqrt2),
- *       s = (f-1)/(f+1), P = Horner in s^2 of 1/(2i+1), i = 9..0 (fma),
- *       ln U1 = fma(e, LN2_HI, fma(e, LN2_LO, (2s) P)) with the fdlibm split
- *       LN2_HI = 0x1.62e42feep-1, LN2_LO = 0x1.a39ef35793c76p-33;
- *     R = sqrt(-2 ln U1) (IEEE correctly rounded);
- *     if T < 2^49: phi = ((2T+1) 2^-51) * PIO2 gives (cos, sin) = (C, S)
- *       else phi' from T' = 2^50 - 1 - T gives (cos, sin) = (S', C'),
- *       with PIO2 = 0x1.921fb54442d18p+0, w = phi^2,
- *       S = phi * Horner_w(+-1/(2i+1)!, i = 8..0), C = Horner_w(+-1/(2i)!, i = 9..0);
+ *   For pair p = 0 .. ceil(D/2)-1, words r0..r3 of counter (g_lo, g_hi, p, 2), in IEEE
+ *   single precision (every operation correctly rounded, fma where written):
+ *     U1 = f 2^-e, f = 1 + (r0 >> 9) 2^-23, e = 1 + clz(r1) (33 if r1 = 0);
+ *     if f > SQRT2 (0x1.6a09e6p+0): f = f/2, k = e - 1, else k = e;
+ *     s = (f-1)/(f+1), w = s*s, P = Horner in w of 1/(2i+1), i = 5..0 (fmaf),
+ *     ln U1 = fmaf(-k, LN2_HI, fmaf(-k, LN2_LO, (2s) P)) with LN2_HI = 0x1.62e300p-1,
+ *       LN2_LO = 0x1.2fefa2p-17;
+ *     R = sqrtf(-2 ln U1);
+ *     quadrant Q = r2 >> 30, T = (r2 >> 7) mod 2^23 (the angle is
+ *       2 pi (Q + (2T+1) 2^-24) / 4);
+ *     if T < 2^22: phi = ((2T+1) 2^-24) * PIO2 gives (cos, sin) = (C, S)
+ *       else phi' from T' = 2^23 - 1 - T gives (cos, sin) = (S', C'),
+ *       with PIO2 = 0x1.921fb6p+0, w = phi^2,
+ *       S = phi * Horner_w(+-1/(2i+1)!, i = 5..0), C = Horner_w(+-1/(2i)!, i = 6..0)
+ *       (each coefficient the float nearest 1/n!);
  *     rotate by Q quarter turns: (c, s) -> (c, s), (-s, c), (-c, -s), (s, -c);
  *     z_{2p} = R c, z_{2p+1} = R s (the latter dropped when 2p+1 = D);
- *   y_nd = (float) fma(sigma, z_d, (double) X[u_n][d]).
- * All arithmetic is IEEE double with round-to-nearest, no contraction beyond the
- * fma written above.
+ *   y_nd = (float) fma(sigma, (double) z_d, (double) X[u_n][d])   (IEEE double fma).
+ * Round-to-nearest throughout, no contraction beyond the fmas written above.
  *
  *   d_X    M x D float32 constellation (row u is point u; labels are not used)
  *   sigma  noise standard deviation per real dimension, sigma >= 0 (host FP64)
@@ -177,10 +179,33 @@ int llr_path_counts(void* stream, int64_t* n_wide, int64_t* n_careful);
  *   d_gmi_per_bit  out: m doubles (1 - mean loss of column k) or NULL
  *   d_se           out: 1 double, std(T_n)/sqrt(N), or NULL
  * N = 0 is MD_EINVAL (the GMI of an empty sample is undefined).  Non-finite LLRs
- * give a NaN GMI. */
+ * (or a transmitted index outside [0, M)) give a NaN GMI, and the call records on
+ * the device how many symbols had a non-finite loss term: gmi_status reads it. */
 int gmi_reduce(const float* d_llr, int64_t N, int m, const uint32_t* d_tx,
                const uint32_t* d_labels, double* d_gmi, double* d_gmi_per_bit, double* d_se,
                void* stream);
+
+/* gmi_status -- waits for `stream` and reports how many symbols had a non-finite loss
+ * term in the last gmi_reduce or llr_exact_gmi enqueued on it (0 if none was made):
+ * MD_OK when there were none, MD_ENONFINITE (with the count in *n_nonfinite and
+ * last_error) otherwise.  The asynchronous calls cannot return this status themselves. */
+int gmi_status(void* stream, int64_t* n_nonfinite);
+
+/* llr_exact_gmi -- llr_exact and gmi_reduce in one pass: the exact LLRs are written to
+ * d_llr as by llr_exact, and the fast kernel's epilogue forms each finished symbol's loss
+ * term T_n = sum_k log2((S0_k + S1_k) / S_sent,k) from the subset sums it already holds,
+ * so no separate pass reads the LLRs back; the symbols that the later (wide-range or
+ * FP64) passes finish take their term from their final LLRs in the reduction.  The GMI
+ * equals gmi_reduce's of the same LLRs up to FP32 rounding of the terms; the reduction is
+ * deterministic (fixed order); S0_k + S1_k is the total over all points for every k, so
+ * the epilogue takes one logarithm of it.  Arguments as llr_exact, plus d_tx (N transmitted
+ * indices), d_gmi (1 double out) and d_se (1 double out, or NULL); no per-bit GMI.
+ * M <= 16, MD_PREC_BF16 and D > 9 (FP32 scores) run the two calls in sequence.
+ * N = 0 is MD_EINVAL.
+ * Workspace: llr_exact's plus 4 N bytes.  Returns as llr_exact. */
+int llr_exact_gmi(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y, int64_t N,
+                  double sigma2, int prec, const uint32_t* d_tx, float* d_llr, double* d_gmi, double* d_se,
+                  void* stream);
 
 /* ber_count -- hard decisions and bit errors (the paper's receiver decides hard and
  * reports the Q-factor of the measured bit-error rate, see its Results section): the
@@ -270,10 +295,14 @@ int mlp_load(const char* path, void** out);
  * its work items dynamically: for every (instance i, noise level s) the channel of
  * awgn_sample (seed_i, offset = s * N_i, N_i uses), the exact LLRs and their GMI, without
  * storing received symbols or LLRs.  The GMI equals gmi_reduce(llr_exact(...)) of the
- * same channel draw up to FP32 rounding.  The launch shape (wavefronts per block,
- * 32-symbol blocks per wavefront, symbol groups per work item) is measured on the plan's
- * own workload when variant = -1, else fixed: 0 (8, 2, 1), 1 (8, 2, 4), 2 (16, 1, 1),
- * 3 (16, 1, 4).  The plan snapshots the constellations' fragments at creation; d_X and
+ * same channel draw up to FP32 rounding.  Every class has its own launch shape
+ * (wavefronts per block, 32-symbol blocks per wavefront, symbol groups per work item):
+ * 0 (8, 2, 1), 1 (8, 2, 4), 2 (16, 1, 1), 3 (16, 1, 4).  variant 0..3 fixes one shape for
+ * all classes; variant = -1 autotunes: the plan is run once under each shape with its
+ * class kernels timed by events, and each class keeps the shape its kernel ran fastest
+ * under; the choices are cached per (device, K steps, label bits) for the process, so a
+ * later plan whose classes are all known is built without measuring (sweep_tuning_clear
+ * forgets them).  The plan snapshots the constellations' fragments at creation; d_X and
  * d_labels must stay valid and unchanged while the plan lives (the channel reads d_X).
  * Limits: M in {16 .. 8192}, 1 <= D <= 8, instances x noise levels <= 2^20; more than
  * 2^20 symbols of one run needing the FP64 fallback makes that run's GMIs NaN. */
@@ -288,8 +317,16 @@ typedef struct {
 /* sigma2: host array n_inst x n_snr (row i = instance i).  Synchronous. */
 int sweep_plan_create(const md_sweep_instance* inst, int n_inst, const double* sigma2, int n_snr, int variant,
                       void** out);
-/* The chosen launch shape and the number of work items. */
+/* The launch shape of the plan's first (most expensive) class and the number of work items. */
 int sweep_plan_info(const void* plan, int* waves, int* blocks_per_wave, int* groups_per_item, int* n_items);
+/* Class i of the plan (0 = most expensive): K steps, label bits, launch shape (0..3), work
+ * items, and the kernel time the autotuner measured for the class under that shape (ms;
+ * -1 when this plan measured nothing: fixed variant or cached choice); any output may be
+ * NULL.  MD_EINVAL when i is not a class index (classes are numbered from 0). */
+int sweep_plan_class(const void* plan, int i, int* k_steps, int* label_bits, int* shape, int* n_items,
+                     float* tuned_ms);
+/* Forgets the autotuner's cached shapes (every device). */
+int sweep_tuning_clear(void);
 /* Runs the sweep (use_graph = 1: one launch of the captured graph; 0: the same kernels
  * enqueued directly) and copies the n_inst x n_snr GMIs (bits per symbol) to d_gmi. */
 int sweep_run(void* plan, double* d_gmi, int use_graph, void* stream);
@@ -462,6 +499,20 @@ int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rat
  * Returns MD_OK, MD_EINVAL (NULL output), MD_ENODEV, MD_EHIP. */
 int kernel_timing(int enable, void* stream);
 int kernel_timing_read(double* total_ms, int64_t* launches, void* stream);
+
+/* ------------------------------------------------------------------ failure injection */
+/* Test hook for the failure paths: the k-th next device allocation the library makes
+ * (workspaces, stage counters, plans, networks, receivers; k = 0: the very next one)
+ * fails as if the device were out of memory, so that the caller sees MD_ENOMEM and can
+ * check that nothing leaked; k < 0 switches it off.  Process-wide.  Returns MD_OK. */
+int alloc_fault_inject(int k);
+
+/* The device memory the library holds right now through its own allocations (stream
+ * workspaces and counters, sweep plans, networks, receivers; not the fixed per-device
+ * arrays of llr_exact_noalloc and kk_frontend): bytes and number of allocations.  After
+ * release_cache and the destroy calls of every handle it returns to zero.  Returns MD_OK,
+ * MD_EINVAL (NULL output). */
+int alloc_stats(int64_t* live_bytes, int64_t* live_allocs);
 
 /* ------------------------------------------------------------------ housekeeping */
 /* Frees every internal device workspace (synchronises the device first). */

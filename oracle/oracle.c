@@ -67,91 +67,80 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
 }
 
 /* ------------------------------------------------------------------------- */
-/* Natural log of U = K * 2^-53 for an odd 53-bit-or-shorter integer K > 0,
- * evaluated as the generator definition fixes it:
- *   K = f * 2^b with f in [1,2) (b = index of K's top bit), e = b - 53;
- *   if f > sqrt(2): f = f/2, e = e+1;
- *   s = (f-1)/(f+1), w = s*s,
- *   P = Horner over w of 1/(2i+1), i = 9..0, with fma,
- *   ln f = (2 s) * P,
- *   ln U = fma(e, LN2_HI, fma(e, LN2_LO, ln f)).
- * (ln f = 2 atanh s; LN2_HI/LN2_LO is the fdlibm split of ln 2.) */
-static double orc_gen_log_u(uint64_t K) {
-    int b = 63 - __builtin_clzll(K);
-    double f = (double)K;            /* exact: K < 2^53 */
-    f = ldexp(f, -b);                /* exact power-of-two scaling */
-    double e = (double)(b - 53);
-    const double SQRT2 = 0x1.6a09e667f3bcdp+0;
-    if (f > SQRT2) {
-        f = f * 0.5;
-        e = e + 1.0;
+/* The channel's normal pair, in IEEE single precision exactly as the generator
+ * definition fixes it (every operation correctly rounded, fma where written):
+ *   radius: U = f 2^-e with f = 1 + (r0 >> 9) 2^-23 and e = 1 + clz(r1) (33 if r1 = 0),
+ *     so U is uniform on (0, 1) with 23 bits inside each binade;
+ *     if f > sqrt2: f = f/2, k = e - 1, else k = e;
+ *     s = (f-1)/(f+1), w = s*s, P = Horner over w of 1/(2i+1), i = 5..0;
+ *     ln U = fma(-k, LN2_HI, fma(-k, LN2_LO, (2 s) P))   (ln f = 2 atanh s);
+ *     R = sqrt(-2 ln U);
+ *   angle: q = r2 >> 30 quarter turns plus t = (2T+1) 2^-24 of a quarter turn,
+ *     T = (r2 >> 7) mod 2^23; for t <= 1/2 sin and cos of phi = t pi/2 by Taylor
+ *     polynomials in phi^2 (sin to phi^11, cos to phi^12), otherwise the complement
+ *     t' = 1 - t with the two swapped;
+ *   (z0, z1) = R (cos, sin) after q quarter turns. */
+static const float GEN_SQRT2 = 0x1.6a09e6p+0f;
+static const float GEN_LN2_HI = 0x1.62e300p-1f;
+static const float GEN_LN2_LO = 0x1.2fefa2p-17f;
+static const float GEN_PIO2 = 0x1.921fb6p+0f;
+
+static float orc_gen_log_u(uint32_t r0, uint32_t r1) {
+    int e = (r1 == 0u) ? 33 : 1 + __builtin_clz(r1);
+    float f = 1.0f + (float)(r0 >> 9) * 0x1p-23f;     /* exact */
+    float k = (float)e;
+    if (f > GEN_SQRT2) {
+        f = f * 0.5f;
+        k = k - 1.0f;
     }
-    double s = (f - 1.0) / (f + 1.0);
-    double w = s * s;
-    double P = 1.0 / 19.0;
-    P = fma(P, w, 1.0 / 17.0);
-    P = fma(P, w, 1.0 / 15.0);
-    P = fma(P, w, 1.0 / 13.0);
-    P = fma(P, w, 1.0 / 11.0);
-    P = fma(P, w, 1.0 / 9.0);
-    P = fma(P, w, 1.0 / 7.0);
-    P = fma(P, w, 1.0 / 5.0);
-    P = fma(P, w, 1.0 / 3.0);
-    P = fma(P, w, 1.0);
-    double lnf = (2.0 * s) * P;
-    const double LN2_HI = 0x1.62e42feep-1;          /* 6.93147180369123816490e-01 */
-    const double LN2_LO = 0x1.a39ef35793c76p-33;    /* 1.90821492927058770002e-10 */
-    return fma(e, LN2_HI, fma(e, LN2_LO, lnf));
+    float s = (f - 1.0f) / (f + 1.0f);
+    float w = s * s;
+    float P = 1.0f / 11.0f;
+    P = fmaf(P, w, 1.0f / 9.0f);
+    P = fmaf(P, w, 1.0f / 7.0f);
+    P = fmaf(P, w, 1.0f / 5.0f);
+    P = fmaf(P, w, 1.0f / 3.0f);
+    P = fmaf(P, w, 1.0f);
+    float lnf = (2.0f * s) * P;
+    return fmaf(-k, GEN_LN2_HI, fmaf(-k, GEN_LN2_LO, lnf));
 }
 
-/* sin and cos of phi = t * (pi/2) for t = (2T+1) * 2^-51 in (0, 1/2], by Taylor
- * polynomials in w = phi^2 (sin to phi^17, cos to phi^18), Horner with fma. */
-static void orc_gen_sincos_quarter(uint64_t T, double* s_out, double* c_out) {
-    const double PIO2 = 0x1.921fb54442d18p+0;
-    double t = (double)(2 * T + 1) * 0x1p-51;       /* exact */
-    double phi = t * PIO2;
-    double w = phi * phi;
-    double S = 1.0 / 355687428096000.0;              /* 1/17! */
-    S = fma(S, w, -1.0 / 1307674368000.0);           /* 1/15! */
-    S = fma(S, w, 1.0 / 6227020800.0);               /* 1/13! */
-    S = fma(S, w, -1.0 / 39916800.0);                /* 1/11! */
-    S = fma(S, w, 1.0 / 362880.0);                   /* 1/9!  */
-    S = fma(S, w, -1.0 / 5040.0);                    /* 1/7!  */
-    S = fma(S, w, 1.0 / 120.0);                      /* 1/5!  */
-    S = fma(S, w, -1.0 / 6.0);                       /* 1/3!  */
-    S = fma(S, w, 1.0);
-    double C = -1.0 / 6402373705728000.0;            /* 1/18! */
-    C = fma(C, w, 1.0 / 20922789888000.0);           /* 1/16! */
-    C = fma(C, w, -1.0 / 87178291200.0);             /* 1/14! */
-    C = fma(C, w, 1.0 / 479001600.0);                /* 1/12! */
-    C = fma(C, w, -1.0 / 3628800.0);                 /* 1/10! */
-    C = fma(C, w, 1.0 / 40320.0);                    /* 1/8!  */
-    C = fma(C, w, -1.0 / 720.0);                     /* 1/6!  */
-    C = fma(C, w, 1.0 / 24.0);                       /* 1/4!  */
-    C = fma(C, w, -1.0 / 2.0);                       /* 1/2!  */
-    C = fma(C, w, 1.0);
+static void orc_gen_sincos_quarter(uint32_t T, float* s_out, float* c_out) {
+    float t = (float)(2u * T + 1u) * 0x1p-24f;        /* exact */
+    float phi = t * GEN_PIO2;
+    float w = phi * phi;
+    float S = -1.0f / 39916800.0f;                    /* 1/11! */
+    S = fmaf(S, w, 1.0f / 362880.0f);                 /* 1/9!  */
+    S = fmaf(S, w, -1.0f / 5040.0f);                  /* 1/7!  */
+    S = fmaf(S, w, 1.0f / 120.0f);                    /* 1/5!  */
+    S = fmaf(S, w, -1.0f / 6.0f);                     /* 1/3!  */
+    S = fmaf(S, w, 1.0f);
+    float C = 1.0f / 479001600.0f;                    /* 1/12! */
+    C = fmaf(C, w, -1.0f / 3628800.0f);               /* 1/10! */
+    C = fmaf(C, w, 1.0f / 40320.0f);                  /* 1/8!  */
+    C = fmaf(C, w, -1.0f / 720.0f);                   /* 1/6!  */
+    C = fmaf(C, w, 1.0f / 24.0f);                     /* 1/4!  */
+    C = fmaf(C, w, -1.0f / 2.0f);                     /* 1/2!  */
+    C = fmaf(C, w, 1.0f);
     *s_out = phi * S;
     *c_out = C;
 }
 
 /* One Box-Muller pair from the four Philox words of (symbol g, pair p, domain 2). */
-static void orc_gen_normal_pair(const uint32_t r[4], double* z0, double* z1) {
-    uint64_t J1 = ((uint64_t)(r[0] >> 6) << 26) | (uint64_t)(r[1] >> 6);   /* 52 bits */
-    uint64_t J2 = ((uint64_t)(r[2] >> 6) << 26) | (uint64_t)(r[3] >> 6);   /* 52 bits */
-    double lnU1 = orc_gen_log_u(2 * J1 + 1);                               /* U1 = (2 J1 + 1) 2^-53 */
-    double R = sqrt(-2.0 * lnU1);
-    uint64_t q = J2 >> 50;                                                  /* quadrant of 2 pi U2 */
-    uint64_t T = J2 & ((1ull << 50) - 1);                                   /* position inside it */
-    double sp, cp, c, s;
-    if (T < (1ull << 49)) {
+static void orc_gen_normal_pair(const uint32_t r[4], float* z0, float* z1) {
+    float R = sqrtf(-2.0f * orc_gen_log_u(r[0], r[1]));
+    uint32_t q = r[2] >> 30;
+    uint32_t T = (r[2] >> 7) & 0x7FFFFFu;
+    float sp, cp, c, s;
+    if (T < (1u << 22)) {
         orc_gen_sincos_quarter(T, &sp, &cp);
         c = cp; s = sp;
     } else {
-        /* phi = pi/2 - phi' with phi' = (2 T' + 1) 2^-51 pi/2 */
-        orc_gen_sincos_quarter((1ull << 50) - 1 - T, &sp, &cp);
+        /* phi = pi/2 - phi' with phi' = (2 T' + 1) 2^-24 pi/2 */
+        orc_gen_sincos_quarter((1u << 23) - 1u - T, &sp, &cp);
         c = sp; s = cp;
     }
-    double ct, st;
+    float ct, st;
     switch ((int)q) {
         case 0: ct = c;  st = s;  break;
         case 1: ct = -s; st = c;  break;
@@ -165,7 +154,10 @@ static void orc_gen_normal_pair(const uint32_t r[4], double* z0, double* z1) {
 /* The normal pair for four given Philox words (exported so the transform can be
  * checked against libm's log, atan2 and hypot). */
 void orc_gen_box_muller(const uint32_t r[4], double z[2]) {
-    orc_gen_normal_pair(r, &z[0], &z[1]);
+    float z0, z1;
+    orc_gen_normal_pair(r, &z0, &z1);
+    z[0] = z0;
+    z[1] = z1;
 }
 
 /* Channel: u_n uniform on {0..M-1}, z_n ~ N(0, I_D), y_n = fl32(x_{u_n} + sigma z_n).
@@ -188,11 +180,11 @@ void orc_awgn(const float* X, int M, int D, uint64_t seed, uint64_t offset, int6
         for (int p = 0; p < npairs; ++p) {
             uint32_t c2[4] = {(uint32_t)g, (uint32_t)(g >> 32), (uint32_t)p, 2u};
             orc_philox4x32_10(c2, key, r);
-            double z0, z1;
+            float z0, z1;
             orc_gen_normal_pair(r, &z0, &z1);
             int d0 = 2 * p, d1 = 2 * p + 1;
-            y[n * D + d0] = (float)fma(sigma, z0, (double)X[(int64_t)u * D + d0]);
-            if (d1 < D) y[n * D + d1] = (float)fma(sigma, z1, (double)X[(int64_t)u * D + d1]);
+            y[n * D + d0] = (float)fma(sigma, (double)z0, (double)X[(int64_t)u * D + d0]);
+            if (d1 < D) y[n * D + d1] = (float)fma(sigma, (double)z1, (double)X[(int64_t)u * D + d1]);
         }
     }
 }

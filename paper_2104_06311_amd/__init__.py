@@ -12,7 +12,8 @@ import torch
 
 from ._lib import MdemapError, PREC, check, lib
 
-__all__ = ["awgn_sample", "llr_exact", "llr_exact_noalloc", "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "RxStream", "release_cache",
+__all__ = ["awgn_sample", "llr_exact", "llr_exact_noalloc", "llr_exact_gmi", "gmi_status", "alloc_fault_inject", "alloc_stats",
+           "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "RxStream", "release_cache",
            "ddlms_equalize", "kk_frontend", "ubench", "UBENCH_KINDS", "kernel_timing", "kernel_timing_read", "MdemapError",
            "log2_exact"]
 
@@ -189,6 +190,46 @@ def gmi_reduce(llr, tx, labels, per_bit: bool = True, se: bool = True):
     st = lib().gmi_reduce(_ptr(llr), N, m, _ptr(tx), _ptr(labels), _ptr(g), _ptr(gb), _ptr(s), _stream())
     check("gmi_reduce", st)
     return g, gb, s
+
+
+def gmi_status():
+    """Number of symbols with a non-finite loss term in the last GMI on the current stream
+    (waits for the stream).  Returns the count; 0 means the GMI is a finite average."""
+    import ctypes
+    n = ctypes.c_int64()
+    st = lib().gmi_status(_stream(), ctypes.byref(n))
+    if st not in (0, -9):
+        check("gmi_status", st)
+    return n.value
+
+
+def llr_exact_gmi(X, labels, y, tx, sigma2: float, prec: str = "fp32", out=None, se: bool = True):
+    """Exact LLRs float32[N, m] and their GMI (float64[1], SE float64[1] or None) from one
+    fused pass (llr_exact_gmi in mdemap.h)."""
+    M, D, N = _demap_args(X, labels, y)
+    _dev(tx, "tx", torch.int32, 1)
+    if tx.shape[0] != N or tx.device != X.device:
+        raise ValueError("tx must hold N indices on the constellation's device")
+    m = log2_exact(M)
+    out = _out(out, (N, m), torch.float32, X.device)
+    g = torch.empty(1, dtype=torch.float64, device=X.device)
+    sv = torch.empty(1, dtype=torch.float64, device=X.device) if se else None
+    check("llr_exact_gmi", lib().llr_exact_gmi(_ptr(X), _ptr(labels), M, D, _ptr(y), N, float(sigma2), PREC[prec],
+                                               _ptr(tx), _ptr(out), _ptr(g), _ptr(sv), _stream()))
+    return out, g, sv
+
+
+def alloc_fault_inject(k: int):
+    """Test hook: the k-th next device allocation of the library fails (k < 0: off)."""
+    check("alloc_fault_inject", lib().alloc_fault_inject(int(k)))
+
+
+def alloc_stats():
+    """(bytes, allocations) of device memory the library holds right now."""
+    import ctypes
+    nb, na = ctypes.c_int64(), ctypes.c_int64()
+    check("alloc_stats", lib().alloc_stats(ctypes.byref(nb), ctypes.byref(na)))
+    return nb.value, na.value
 
 
 def release_cache():
@@ -499,6 +540,23 @@ class SweepPlan:
             out = torch.empty((self.n_inst, self.n_snr), dtype=torch.float64, device="cuda")
         check("sweep_run", lib().sweep_run(self._h, _ptr(out), 1 if use_graph else 0, _stream()))
         return out
+
+    def classes(self, with_times: bool = False):
+        """[(K steps, label bits, launch shape 0..3, work items)] of the plan's classes, plus
+        the autotuner's measured class time in ms (-1 if none) when with_times."""
+        import ctypes
+        out = []
+        while True:
+            v = [ctypes.c_int() for _ in range(4)]
+            t = ctypes.c_float()
+            if lib().sweep_plan_class(self._h, len(out), *[ctypes.byref(x) for x in v], ctypes.byref(t)) != 0:
+                return out
+            out.append(tuple(x.value for x in v) + ((t.value,) if with_times else ()))
+
+    @staticmethod
+    def tuning_clear():
+        """Forget the autotuner's cached launch shapes."""
+        check("sweep_tuning_clear", lib().sweep_tuning_clear())
 
     def stats(self):
         """(symbols re-evaluated by the FP64 fallback in the last run, queue overflowed)."""

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libmdemap.so")
 MD_OK = 0
 STATUS_NAMES = {
     0: "MD_OK", -1: "MD_EINVAL", -2: "MD_ENOTPOW2", -3: "MD_ELABEL", -4: "MD_EDIM",
-    -5: "MD_ENOMEM", -6: "MD_EHIP", -7: "MD_ENODEV", -8: "MD_EUNSUPPORTED",
+    -5: "MD_ENOMEM", -6: "MD_EHIP", -7: "MD_ENODEV", -8: "MD_EUNSUPPORTED", -9: "MD_ENONFINITE",
 }
 PREC = {"fp32": 0, "fp16": 1, "bf16": 2, "bf16_scores": 3}
 
@@ -32,6 +32,10 @@ SIGNATURES = {
     "llr_maxlog": (_I, [_P, _P, _I, _I, _P, _I64, _D, _P, _P]),
     "llr_exact_noalloc": (_I, [_P, _P, _I, _I, _P, _I64, _D, _I, _P, _P]),
     "gmi_reduce": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P, _P]),
+    "gmi_status": (_I, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "llr_exact_gmi": (_I, [_P, _P, _I, _I, _P, _I64, _D, _I, _P, _P, _P, _P, _P]),
+    "alloc_fault_inject": (_I, [_I]),
+    "alloc_stats": (_I, [ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "ber_count": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P]),
     "q_factor_db": (_I, [_P, _I64, _P, _P]),
     "llr_path_counts": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
@@ -52,6 +56,8 @@ SIGNATURES = {
     "mlp_load": (_I, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]),
     "sweep_plan_create": (_I, [_P, _I, _P, _I, _I, ctypes.POINTER(ctypes.c_void_p)]),
     "sweep_plan_info": (_I, [_P, _P, _P, _P, _P]),
+    "sweep_plan_class": (_I, [_P, _I, _P, _P, _P, _P, _P]),
+    "sweep_tuning_clear": (_I, []),
     "sweep_run": (_I, [_P, _P, _I, _P]),
     "sweep_run_stats": (_I, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int), _P]),
     "sweep_plan_destroy": (_I, [_P]),

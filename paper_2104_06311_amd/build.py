@@ -24,7 +24,8 @@ def sources():
 # products of the next tile ahead of the exponentials of the current one); LLVM's
 # post-register-allocation scheduler does not honour those barriers and moves the second
 # product of a tile next to its consumers, so it is switched off for these files.
-NO_POST_RA_SCHED = {"llr_fast_exact.hip", "llr_fast_maxlog.hip", "llr_fast_bf16.hip", "llr_wide.hip",
+NO_POST_RA_SCHED = {"llr_fast_exact.hip", "llr_fast_maxlog.hip", "llr_fast_bf16.hip", "llr_wide.hip", "llr_fast_gmi.hip",
+                    "llr_fast_lowp.hip",
                     "llr_wide3.hip", "sweep.hip"}
 
 

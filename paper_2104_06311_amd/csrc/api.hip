@@ -144,7 +144,81 @@ int gmi_reduce(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const
   // calls on one stream run in order, so the partials may reuse the demappers' workspace
   st = md::workspace(s, md::gmi_workspace_bytes(N, m), &ws);
   if (st != MD_OK) return st;
-  return md::launch_gmi(d_llr, N, m, d_tx, d_labels, d_gmi, d_gmi_per_bit, d_se, ws, s);
+  int* flags = nullptr;
+  st = md::stream_flags(s, &flags);
+  if (st != MD_OK) return st;
+  return md::launch_gmi(d_llr, N, m, d_tx, d_labels, d_gmi, d_gmi_per_bit, d_se, ws, md::gmi_status_word(flags), s);
+}
+
+int gmi_status(void* stream, int64_t* n_nonfinite) {
+  md::set_error("");
+  if (!n_nonfinite) return md::fail(MD_EINVAL, "output pointer is NULL");
+  *n_nonfinite = 0;
+  int dev = 0;
+  int st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  hipStream_t s = as_stream(stream);
+  int* flags = nullptr;
+  st = md::stream_flags(s, &flags);
+  if (st != MD_OK) return st;
+  long long h = 0;
+  MD_HIP_TRY(hipMemcpyAsync(&h, md::gmi_status_word(flags), sizeof(h), hipMemcpyDeviceToHost, s));
+  MD_HIP_TRY(hipStreamSynchronize(s));
+  *n_nonfinite = h;
+  if (h > 0)
+    return md::fail(MD_ENONFINITE, std::to_string(h) + " symbols had a non-finite GMI term (non-finite LLR or a "
+                                                         "transmitted index outside the labels)");
+  return MD_OK;
+}
+
+int llr_exact_gmi(const float* d_X, const uint32_t* d_labels, int M, int D, const float* d_y, int64_t N,
+                  double sigma2, int prec, const uint32_t* d_tx, float* d_llr, double* d_gmi, double* d_se,
+                  void* stream) {
+  md::set_error("");
+  int st = md::check_demap_args(d_X, d_labels, M, D, d_y, N, sigma2, prec, d_llr);
+  if (st != MD_OK) return st;
+  if (N <= 0) return md::fail(MD_EINVAL, "GMI needs N > 0 symbols");
+  if (!d_tx || !d_gmi) return md::fail(MD_EINVAL, "tx or gmi pointer is NULL");
+  const int m = md::ilog2_pow2(M);
+  const int sc = md::score_layout(prec);
+  const int ks = sc == 0 ? md::frag_ksteps(D) : md::frag_ksteps_single(D);
+  if (M <= 16 || prec == MD_PREC_BF16 || !md::fused_gmi_supported(sc, ks)) {
+    // no fused epilogue on these paths: the two calls in sequence
+    st = demap(d_X, d_labels, M, D, d_y, N, sigma2, prec, false, d_llr, stream);
+    if (st != MD_OK) return st;
+    return gmi_reduce(d_llr, N, m, d_tx, d_labels, d_gmi, nullptr, d_se, stream);
+  }
+  int dev = 0;
+  st = md::current_device(&dev);
+  if (st != MD_OK) return st;
+  hipStream_t s = as_stream(stream);
+  st = md::check_labels_once(d_labels, M, s);
+  if (st != MD_OK) return st;
+  const size_t pb = md::prep_bytes(M, D, N);
+  const size_t tb = md::carve_size(sizeof(float) * static_cast<size_t>(N));
+  char* ws = nullptr;
+  st = md::workspace(s, pb + tb + md::gmi_workspace_bytes(N, m), &ws);
+  if (st != MD_OK) return st;
+  int* flags = nullptr;
+  st = md::stream_flags(s, &flags);
+  if (st != MD_OK) return st;
+  md::Prepared P;
+  float alpha = 1.0f, c_over_alpha = 1.0f;
+  md::score_scales(sigma2, &alpha, &c_over_alpha);
+  st = md::prepare(d_X, d_labels, M, D, N, alpha, c_over_alpha, ws, s, &P, flags, md::score_layout(prec));
+  if (st != MD_OK) return st;
+  P.gmi_tx = d_tx;
+  P.gmi_labels = d_labels;
+  P.gmi_terms = reinterpret_cast<float*>(ws + pb);
+  md::LastCall lc;
+  lc.valid = true;
+  lc.maxlog = false;
+  lc.N = N;
+  md::record_last_call(s, lc);
+  st = md::launch_llr(P, M, D, d_y, N, sigma2, false, prec, d_llr, s);
+  if (st != MD_OK) return st;
+  return md::launch_gmi_terms(P.gmi_terms, d_llr, N, m, d_tx, d_labels, d_gmi, d_se, ws + pb + tb,
+                              md::gmi_status_word(flags), s);
 }
 
 int ber_count(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels,

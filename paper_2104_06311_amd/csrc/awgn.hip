@@ -1,7 +1,7 @@
 // awgn_sample: counter-based AWGN channel (Philox4x32-10 + Box-Muller), bit-exact by
-// definition.  Every floating-point step below is an IEEE double operation written out
-// explicitly (contraction is off for this file), so any launch geometry -- and any
-// independent implementation of the same definition -- gives identical bits.
+// definition.  Every floating-point step below is a correctly rounded IEEE operation
+// written out explicitly (contraction is off for this file), so any launch geometry --
+// and any independent implementation of the same definition -- gives identical bits.
 #include "common.hpp"
 #include "rng.hpp"
 
@@ -31,11 +31,12 @@ __global__ void __launch_bounds__(256) awgn_kernel(const float* __restrict__ X, 
     const int npairs = (D + 1) >> 1;
     for (int p = 0; p < npairs; ++p) {
       const Philox4 r = philox10(glo, ghi, static_cast<uint32_t>(p), 2u, k0, k1);
-      double z0, z1;
+      float z0, z1;
       gen_normal_pair(r, &z0, &z1);
       const int d0 = 2 * p;
-      yn[d0] = static_cast<float>(__builtin_fma(sigma, z0, static_cast<double>(xu[d0])));
-      if (d0 + 1 < D) yn[d0 + 1] = static_cast<float>(__builtin_fma(sigma, z1, static_cast<double>(xu[d0 + 1])));
+      yn[d0] = static_cast<float>(__builtin_fma(sigma, static_cast<double>(z0), static_cast<double>(xu[d0])));
+      if (d0 + 1 < D)
+        yn[d0 + 1] = static_cast<float>(__builtin_fma(sigma, static_cast<double>(z1), static_cast<double>(xu[d0 + 1])));
     }
   }
 }

@@ -55,6 +55,12 @@ inline size_t carve_size(size_t bytes) { return ((bytes + 255) & ~size_t(255)); 
 // Returns a device buffer of at least `bytes` bytes private to (current device, stream).
 int workspace(hipStream_t stream, size_t bytes, char** out);
 
+// hipMalloc behind the library's allocation-failure injection (alloc_fault_inject): every
+// device allocation the library makes goes through here.
+hipError_t dev_malloc(void** p, size_t bytes);
+// hipFree of memory from dev_malloc (keeps the library's count of live allocations).
+hipError_t dev_free(void* p);
+
 // Stage counters of the demapping calls on (current device, stream): a 16-byte device
 // buffer that stays at one address until release_cache, plus what the last call was.
 struct LastCall {
@@ -63,6 +69,9 @@ struct LastCall {
   int64_t N = 0;
 };
 int stream_flags(hipStream_t stream, int** out);
+// The GMI status word inside a stream's counter buffer: the number of symbols whose
+// loss term was not finite in the last gmi_reduce / llr_exact_gmi on that stream.
+inline long long* gmi_status_word(int* flags) { return reinterpret_cast<long long*>(flags + 32); }
 void record_last_call(hipStream_t stream, const LastCall& lc);
 int last_call(hipStream_t stream, LastCall* lc, int** flags);
 
@@ -98,6 +107,12 @@ struct Prepared {
   int sc;                   // score contraction: 0 split FP16, 1 one FP16 pass, 2 one BF16 pass
   float alpha;              // power-of-two operand balance a
   float c_over_alpha;       // c / a, c = log2(e) / (2 sigma2)
+  // fused GMI epilogue (llr_exact_gmi): transmitted indices, labels and the per-symbol loss
+  // terms T_n the fast pass writes (NaN for symbols it leaves to later passes); all null
+  // when the call only demaps
+  const uint32_t* gmi_tx = nullptr;
+  const uint32_t* gmi_labels = nullptr;
+  float* gmi_terms = nullptr;
 };
 
 // Builds the label-ordered copy, fragments and flags for one call.  `ws` must point

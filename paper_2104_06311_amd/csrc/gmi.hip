@@ -54,7 +54,7 @@ __device__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// partials: per block, [sum T, sum T^2, sum t_0 .. sum t_{m-1}].  Templated on m so that a
+// partials: per block, [sum T, sum T^2, sum t_0 .. sum t_{m-1}, count of non-finite T].  Templated on m so that a
 // symbol's m LLRs are loaded together and the per-bit work has no branches, and on PER_BIT
 // (the per-bit columns are left at zero when the caller does not want them).
 template <int MB, bool PER_BIT>
@@ -67,6 +67,7 @@ __global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __rest
   Kahan sb[MB];
 #pragma unroll
   for (int k = 0; k < MB; ++k) sb[k] = Kahan{0.f, 0.f};
+  int nonfinite = 0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
   for (int64_t n = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; n < N; n += stride) {
     float L[MB];
@@ -83,6 +84,7 @@ __global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __rest
       if (PER_BIT) sb[k].add(t);
       T += t;
     }
+    nonfinite += !isfinite(T);
     sT.add(T);
     sT2.add(T * T);
   }
@@ -97,6 +99,51 @@ __global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __rest
     v = PER_BIT ? block_sum(sb[k].get(), sh) : 0.0;
     if (threadIdx.x == 0) partials[(2 + k) * nb + blockIdx.x] = v;
   }
+  v = block_sum(static_cast<double>(nonfinite), sh);
+  if (threadIdx.x == 0) partials[(2 + MB) * nb + blockIdx.x] = v;
+}
+
+// The same partials from the per-symbol loss terms T_n that the fused demapping pass
+// wrote; a NaN term marks a symbol the fast pass left to the later passes (or a bad
+// index), whose term is formed here from its final LLRs like gmi_partial_kernel does.
+// No per-bit columns.
+template <int MB>
+__global__ void __launch_bounds__(kBlock) gmi_terms_partial_kernel(const float* __restrict__ terms,
+                                                                   const float* __restrict__ llr, int64_t N,
+                                                                   const uint32_t* __restrict__ tx,
+                                                                   const uint32_t* __restrict__ labels,
+                                                                   double* __restrict__ partials) {
+  __shared__ double sh[kBlock];
+  Kahan sT{0.f, 0.f}, sT2{0.f, 0.f};
+  int nonfinite = 0;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
+  for (int64_t n = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; n < N; n += stride) {
+    float T = terms[n];
+    if (isnan(T)) {
+      const uint32_t u = tx[n];
+      const bool ok = u < (1u << MB);
+      const uint32_t lab = labels[ok ? u : 0u];
+      T = ok ? 0.0f : __builtin_nanf("");
+#pragma unroll
+      for (int k = 0; k < MB; ++k) {
+        const float s = ((lab >> (MB - 1 - k)) & 1u) ? 1.0f : -1.0f;
+        T += softplus_bits(s * llr[n * MB + k]);
+      }
+    }
+    nonfinite += !isfinite(T);
+    sT.add(T);
+    sT2.add(T * T);
+  }
+  const int64_t nb = gridDim.x;
+  double v = block_sum(sT.get(), sh);
+  if (threadIdx.x == 0) partials[0 * nb + blockIdx.x] = v;
+  v = block_sum(sT2.get(), sh);
+  if (threadIdx.x == 0) partials[1 * nb + blockIdx.x] = v;
+#pragma unroll
+  for (int k = 0; k < MB; ++k)
+    if (threadIdx.x == 0) partials[(2 + k) * nb + blockIdx.x] = 0.0;
+  v = block_sum(static_cast<double>(nonfinite), sh);
+  if (threadIdx.x == 0) partials[(2 + MB) * nb + blockIdx.x] = v;
 }
 
 // One block per column: the block partials of column c summed in a fixed order.
@@ -111,11 +158,13 @@ __global__ void __launch_bounds__(kBlock) gmi_column_kernel(const double* __rest
 }
 
 __global__ void gmi_output_kernel(const double* __restrict__ tot, int64_t N, int m, double* __restrict__ gmi,
-                                  double* __restrict__ gmi_per_bit, double* __restrict__ se) {
+                                  double* __restrict__ gmi_per_bit, double* __restrict__ se,
+                                  long long* __restrict__ status) {
   const int k = threadIdx.x;
   const double Nd = static_cast<double>(N);
   if (gmi_per_bit && k < m) gmi_per_bit[k] = 1.0 - tot[2 + k] / Nd;
   if (k == 0) {
+    status[0] = static_cast<long long>(tot[2 + m]);   // symbols with a non-finite loss term
     const double mean = tot[0] / Nd;
     gmi[0] = static_cast<double>(m) - mean;
     if (se) {
@@ -221,12 +270,45 @@ int gmi_blocks(int64_t N) {
 }  // namespace
 
 size_t gmi_workspace_bytes(int64_t N, int m) {
-  return carve_size(sizeof(double) * static_cast<size_t>(gmi_blocks(N)) * (m + 2)) +
-         carve_size(sizeof(double) * (m + 2));
+  return carve_size(sizeof(double) * static_cast<size_t>(gmi_blocks(N)) * (m + 3)) +
+         carve_size(sizeof(double) * (m + 3));
+}
+
+namespace {
+int launch_gmi_tail(double* partials, int nb, int64_t N, int m, double* d_gmi, double* d_gmi_per_bit, double* d_se,
+                    long long* status, hipStream_t stream) {
+  double* totals = partials + carve_size(sizeof(double) * static_cast<size_t>(nb) * (m + 3)) / sizeof(double);
+  hipLaunchKernelGGL(gmi_column_kernel, dim3(m + 3), dim3(kBlock), 0, stream, partials, nb, totals);
+  MD_LAUNCH_CHECK("gmi_column_kernel launch");
+  hipLaunchKernelGGL(gmi_output_kernel, dim3(1), dim3(64), 0, stream, totals, N, m, d_gmi, d_gmi_per_bit, d_se,
+                     status);
+  MD_LAUNCH_CHECK("gmi_output_kernel launch");
+  return MD_OK;
+}
+}  // namespace
+
+int launch_gmi_terms(const float* d_terms, const float* d_llr, int64_t N, int m, const uint32_t* d_tx,
+                     const uint32_t* d_labels, double* d_gmi, double* d_se, char* ws, long long* status,
+                     hipStream_t stream) {
+  const int nb = gmi_blocks(N);
+  double* partials = reinterpret_cast<double*>(ws);
+  switch (m) {
+#define MD_GMI_CASE(MB_)                                                                                    \
+  case MB_:                                                                                               \
+    hipLaunchKernelGGL((gmi_terms_partial_kernel<MB_>), dim3(nb), dim3(kBlock), 0, stream, d_terms, d_llr, N, \
+                       d_tx, d_labels, partials);                                                         \
+    break;
+    MD_GMI_CASE(5) MD_GMI_CASE(6) MD_GMI_CASE(7) MD_GMI_CASE(8) MD_GMI_CASE(9) MD_GMI_CASE(10) MD_GMI_CASE(11)
+    MD_GMI_CASE(12) MD_GMI_CASE(13) MD_GMI_CASE(14) MD_GMI_CASE(15)
+    default: MD_GMI_CASE(16)
+#undef MD_GMI_CASE
+  }
+  MD_LAUNCH_CHECK("gmi_terms_partial_kernel launch");
+  return launch_gmi_tail(partials, nb, N, m, d_gmi, nullptr, d_se, status, stream);
 }
 
 int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels, double* d_gmi,
-               double* d_gmi_per_bit, double* d_se, char* ws, hipStream_t stream) {
+               double* d_gmi_per_bit, double* d_se, char* ws, long long* status, hipStream_t stream) {
   const int nb = gmi_blocks(N);
   double* partials = reinterpret_cast<double*>(ws);
   switch (m) {
@@ -246,12 +328,7 @@ int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const
 #undef MD_GMI_CASE
   }
   MD_LAUNCH_CHECK("gmi_partial_kernel launch");
-  double* totals = partials + carve_size(sizeof(double) * static_cast<size_t>(nb) * (m + 2)) / sizeof(double);
-  hipLaunchKernelGGL(gmi_column_kernel, dim3(m + 2), dim3(kBlock), 0, stream, partials, nb, totals);
-  MD_LAUNCH_CHECK("gmi_column_kernel launch");
-  hipLaunchKernelGGL(gmi_output_kernel, dim3(1), dim3(64), 0, stream, totals, N, m, d_gmi, d_gmi_per_bit, d_se);
-  MD_LAUNCH_CHECK("gmi_output_kernel launch");
-  return MD_OK;
+  return launch_gmi_tail(partials, nb, N, m, d_gmi, d_gmi_per_bit, d_se, status, stream);
 }
 
 size_t ber_workspace_bytes(int64_t N, int m) {

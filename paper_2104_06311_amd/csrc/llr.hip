@@ -343,14 +343,16 @@ int launch_llr(const Prepared& P, int M, int D, const float* d_y, int64_t N, dou
     // reduced-precision scores: symbols outside the fast pass's range go straight to the
     // FP64 kernel (their LLRs are then exact)
     const int slot = timing_begin(stream);
-    int st = launch_fast_lowp(P, M, D, d_y, N, sigma2, d_llr, stream);
+    int st = P.gmi_terms ? launch_fast_gmi(P, M, D, d_y, N, sigma2, d_llr, stream)
+                         : launch_fast_lowp(P, M, D, d_y, N, sigma2, d_llr, stream);
     timing_end(stream, slot);
     if (st != MD_OK) return st;
     return launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, P.fb_list, 1, stream);
   }
   const int slot = timing_begin(stream);
-  int st = prec == MD_PREC_BF16 ? launch_fast_bf16(P, M, D, d_y, N, d_llr, stream)
-                                : launch_fast_exact(P, M, D, d_y, N, sigma2, d_llr, stream);
+  int st = P.gmi_terms ? launch_fast_gmi(P, M, D, d_y, N, sigma2, d_llr, stream)
+           : prec == MD_PREC_BF16 ? launch_fast_bf16(P, M, D, d_y, N, d_llr, stream)
+                                  : launch_fast_exact(P, M, D, d_y, N, sigma2, d_llr, stream);
   timing_end(stream, slot);
   if (st != MD_OK) return st;
   st = launch_wide_exact(P, M, D, d_y, d_llr, stream);

@@ -364,13 +364,16 @@ __device__ __forceinline__ bool sums_in_range(const float (&S0)[MB], const float
   return smin >= 0x1p-96f && smax <= 0x1p+126f;
 }
 
-template <int KS, int WAVES, int MB, int SB, bool MAXLOG, int SC = 0>
+template <int KS, int WAVES, int MB, int SB, bool MAXLOG, int SC = 0, bool GMI = false>
 __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __restrict__ frag, int ntiles,
                                                               int chunk_tiles, int D,
                                                               const float* __restrict__ y, int64_t N, float cb,
                                                               float cn, float alpha, float* __restrict__ llr,
                                                               int* __restrict__ flags,
-                                                              unsigned* __restrict__ fb_list) {
+                                                              unsigned* __restrict__ fb_list,
+                                                              const uint32_t* __restrict__ gmi_tx,
+                                                              const uint32_t* __restrict__ gmi_labels,
+                                                              float* __restrict__ gmi_terms) {
   constexpr int m = MB;
   constexpr int S = 16 * KS;                 // K slots per symbol
   extern __shared__ uint4 lds[];
@@ -392,6 +395,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
     SymAcc<MB> ac[SB];
     bool bad[SB];
     int64_t nsym[SB];
+    uint32_t lab_sent[SB];
 #pragma unroll
     for (int sb = 0; sb < SB; ++sb) {
       const int64_t n = g * per_group + (static_cast<int64_t>(wave) * SB + sb) * 32 + (lane & 31);
@@ -399,6 +403,12 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
       const bool b = build_symbol_operand<KS, SC>(bst + (sb * 32 + (lane & 31)) * S, y, n, n < N, D, cb, cn,
                                                   alpha, MAXLOG ? 0.0f : kExpBias, bf[sb]);
       bad[sb] = b || range_bad;
+      if constexpr (GMI) {
+        // the sent label, fetched now so that the tile loop hides the two dependent loads
+        const uint32_t u = (h == 0 && n < N) ? gmi_tx[n] : 0u;
+        const bool ok = u < (1u << MB);
+        lab_sent[sb] = ok ? gmi_labels[u] : 0xFFFFFFFFu;   // all ones: an index outside the labels
+      }
     }
     acc_init<MB, SB, MAXLOG>(ac);
     for (int ch = 0; ch < nchunks; ++ch) {
@@ -423,14 +433,31 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
       if (h == 0 && n < N) {
         if (invalid) {
           for (int k = 0; k < m; ++k) llr[n * m + k] = __builtin_nanf("");
+          if constexpr (GMI) gmi_terms[n] = __builtin_nanf("");
         } else if (bad[sb] || badp || (!MAXLOG && !sums_in_range<MB>(S0, S1))) {
           const int idx = atomicAdd(&flags[1], 1);
           fb_list[idx] = static_cast<unsigned>(n);
+          if constexpr (GMI) gmi_terms[n] = __builtin_nanf("");   // taken from its final LLRs later
         } else {
+          float l2s0[MB], l2s1[MB];
 #pragma unroll
           for (int k = 0; k < m; ++k) {
             const int b = m - 1 - k;
-            llr[n * m + k] = MAXLOG ? kLn2 * (S0[b] - S1[b]) : kLn2 * (log2_normal(S0[b]) - log2_normal(S1[b]));
+            if (!MAXLOG) {
+              l2s0[b] = log2_normal(S0[b]);
+              l2s1[b] = log2_normal(S1[b]);
+            }
+            llr[n * m + k] = MAXLOG ? kLn2 * (S0[b] - S1[b]) : kLn2 * (l2s0[b] - l2s1[b]);
+          }
+          if constexpr (GMI) {
+            // GMI loss of the symbol, sum over bits of log2((S0 + S1) / S_sent); S0 + S1 is
+            // the sum over all points for every bit, so one logarithm serves all of them
+            const uint32_t lab = lab_sent[sb];
+            const float l2tot = log2_normal(S0[0] + S1[0]);
+            float T = lab != 0xFFFFFFFFu ? 0.0f : __builtin_nanf("");
+#pragma unroll
+            for (int b = 0; b < MB; ++b) T += l2tot - (((lab >> b) & 1u) ? l2s1[b] : l2s0[b]);
+            gmi_terms[n] = T;
           }
         }
       }
@@ -438,7 +465,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
   }
 }
 
-template <int KS, int WAVES, int MB, int SB, bool MAXLOG, int SC = 0>
+template <int KS, int WAVES, int MB, int SB, bool MAXLOG, int SC = 0, bool GMI = false>
 int launch_fast_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
                   hipStream_t stream) {
   const int ntiles = M / 32;
@@ -451,7 +478,7 @@ int launch_fast_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
   if (chunk_tiles > ntiles) chunk_tiles = ntiles;
   if (chunk_tiles < G) return fail(MD_EUNSUPPORTED, "constellation fragments do not fit in LDS");
   const size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
-  auto kern = llr_fast_kernel<KS, WAVES, MB, SB, MAXLOG, SC>;
+  auto kern = llr_fast_kernel<KS, WAVES, MB, SB, MAXLOG, SC, GMI>;
   {
     const int st_attr = set_lds_limit(reinterpret_cast<const void*>(kern), 160 * 1024);
     if (st_attr != MD_OK) return st_attr;
@@ -470,27 +497,28 @@ int launch_fast_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
   const float cb = static_cast<float>(2.0 * c / P.alpha);
   const float cn = P.c_over_alpha;
   hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(WAVES * 64), lds_bytes, stream, P.frag, ntiles,
-                     chunk_tiles, D, d_y, N, cb, cn, P.alpha, d_llr, P.flags, P.fb_list);
+                     chunk_tiles, D, d_y, N, cb, cn, P.alpha, d_llr, P.flags, P.fb_list, P.gmi_tx, P.gmi_labels,
+                     P.gmi_terms);
   MD_LAUNCH_CHECK("llr_fast_kernel launch");
   return MD_OK;
 }
 
-template <int KS, int W, int SBV, bool MAXLOG, int SC = 0>
+template <int KS, int W, int SBV, bool MAXLOG, int SC = 0, bool GMI = false>
 int launch_fast_m(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
                   hipStream_t stream) {
   switch (ilog2_pow2(M)) {
-    case 5: return launch_fast_t<KS, W, 5, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 6: return launch_fast_t<KS, W, 6, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 7: return launch_fast_t<KS, W, 7, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 8: return launch_fast_t<KS, W, 8, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 9: return launch_fast_t<KS, W, 9, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 10: return launch_fast_t<KS, W, 10, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 11: return launch_fast_t<KS, W, 11, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 12: return launch_fast_t<KS, W, 12, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 13: return launch_fast_t<KS, W, 13, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 14: return launch_fast_t<KS, W, 14, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 15: return launch_fast_t<KS, W, 15, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    default: return launch_fast_t<KS, W, 16, SBV, MAXLOG, SC>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 5: return launch_fast_t<KS, W, 5, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 6: return launch_fast_t<KS, W, 6, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 7: return launch_fast_t<KS, W, 7, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 8: return launch_fast_t<KS, W, 8, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 9: return launch_fast_t<KS, W, 9, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 10: return launch_fast_t<KS, W, 10, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 11: return launch_fast_t<KS, W, 11, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 12: return launch_fast_t<KS, W, 12, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 13: return launch_fast_t<KS, W, 13, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 14: return launch_fast_t<KS, W, 14, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 15: return launch_fast_t<KS, W, 15, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    default: return launch_fast_t<KS, W, 16, SBV, MAXLOG, SC, GMI>(P, M, D, d_y, N, sigma2, d_llr, stream);
   }
 }
 
@@ -690,6 +718,20 @@ int launch_fast(const Prepared& P, int M, int D, const float* d_y, int64_t N, do
     case 5: return launch_fast_m<5, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
     default: return launch_fast_m<6, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
   }
+}
+
+// Exact LLRs with the fused GMI epilogue (P.gmi_terms set): split scores with one or two
+// K steps (D <= 9), or one-pass scores (D <= 12).
+inline bool fused_gmi_supported(int sc, int ks) { return sc == 0 ? ks <= 2 : ks == 1; }
+
+template <int UNUSED = 0>
+int launch_fast_gmi(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
+                    hipStream_t stream) {
+  if (!fused_gmi_supported(P.sc, P.ks)) return fail(MD_EUNSUPPORTED, "no fused GMI epilogue for this shape");
+  if (P.sc == 1) return launch_fast_m<1, 16, 1, false, 1, true>(P, M, D, d_y, N, sigma2, d_llr, stream);
+  if (P.sc == 2) return launch_fast_m<1, 16, 1, false, 2, true>(P, M, D, d_y, N, sigma2, d_llr, stream);
+  if (P.ks == 1) return launch_fast_m<1, 16, 1, false, 0, true>(P, M, D, d_y, N, sigma2, d_llr, stream);
+  return launch_fast_m<2, 16, 1, false, 0, true>(P, M, D, d_y, N, sigma2, d_llr, stream);
 }
 
 // One-pass FP16 (SC 1) or BF16 (SC 2) scores, exact LLRs: one K step (D <= 12).

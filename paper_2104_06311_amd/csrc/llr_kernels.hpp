@@ -25,6 +25,11 @@ int launch_fast_bf16(const Prepared& P, int M, int D, const float* d_y, int64_t 
 // One-pass FP16 or BF16 scores (P.sc 1 or 2, one K step), exact LLRs.
 int launch_fast_lowp(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
                      hipStream_t stream);
+// Exact LLRs with the fused GMI epilogue (P.gmi_terms set), for the shapes
+// fused_gmi_supported(P.sc, P.ks) accepts.
+int launch_fast_gmi(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
+                    hipStream_t stream);
+bool fused_gmi_supported(int sc, int ks);
 // Fragment layout (Prepared::sc) that llr_exact's precision `prec` needs.
 inline int score_layout(int prec) {
   return prec == MD_PREC_FP16 ? 1 : (prec == MD_PREC_BF16_SCORES ? 2 : 0);
@@ -37,8 +42,13 @@ int launch_llr_careful_all(const Prepared& P, int M, int D, const float* d_y, in
                            bool maxlog, float* d_llr, hipStream_t stream);
 
 size_t gmi_workspace_bytes(int64_t N, int m);
+// `status` (device) receives the number of symbols whose loss term was not finite.
 int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels, double* d_gmi,
-               double* d_gmi_per_bit, double* d_se, char* ws, hipStream_t stream);
+               double* d_gmi_per_bit, double* d_se, char* ws, long long* status, hipStream_t stream);
+// GMI from the loss terms of the fused demapping pass (NaN terms: formed from the LLRs).
+int launch_gmi_terms(const float* d_terms, const float* d_llr, int64_t N, int m, const uint32_t* d_tx,
+                     const uint32_t* d_labels, double* d_gmi, double* d_se, char* ws, long long* status,
+                     hipStream_t stream);
 
 size_t ber_workspace_bytes(int64_t N, int m);
 int launch_ber(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels,

@@ -730,12 +730,12 @@ int ensure_scratch(Mlp* p, size_t floats) {
   if (p->scratch_cap >= floats) return MD_OK;
   if (p->scratch) {
     MD_HIP_TRY(hipDeviceSynchronize());
-    MD_HIP_TRY(hipFree(p->scratch));
+    MD_HIP_TRY(md::dev_free(p->scratch));
     p->scratch = nullptr;
     p->scratch_cap = 0;
   }
   void* q = nullptr;
-  if (hipMalloc(&q, floats * sizeof(float)) != hipSuccess) {
+  if (md::dev_malloc(&q, floats * sizeof(float)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(MD_ENOMEM, "MLP scratch allocation failed");
   }
@@ -930,7 +930,7 @@ int infer(Mlp* p, const float* d_y, int64_t N, float* d_llr, hipStream_t s) {
   if (!fused && !stream) return infer_gemm(p, d_y, N, d_llr, s);
   if (!p->img) {
     void* q = nullptr;
-    if (hipMalloc(&q, L.bytes) != hipSuccess) {
+    if (md::dev_malloc(&q, L.bytes) != hipSuccess) {
       (void)hipGetLastError();
       return fail(MD_ENOMEM, "MLP inference image allocation failed");
     }
@@ -1014,7 +1014,7 @@ int mlp_create(int D, int hidden, int m, uint64_t seed, void** out) {
   p->device = dev;
   p->seed = seed;
   void* q = nullptr;
-  if (hipMalloc(&q, sizeof(float) * 4 * static_cast<size_t>(p->P)) != hipSuccess) {
+  if (md::dev_malloc(&q, sizeof(float) * 4 * static_cast<size_t>(p->P)) != hipSuccess) {
     (void)hipGetLastError();
     delete p;
     return md::fail(MD_ENOMEM, "MLP parameter allocation failed");
@@ -1029,7 +1029,7 @@ int mlp_create(int D, int hidden, int m, uint64_t seed, void** out) {
   if (hipMemcpy(p->w, init.data(), sizeof(float) * p->P, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(p->g, zeros.data(), sizeof(float) * 3 * p->P, hipMemcpyHostToDevice) != hipSuccess) {
     hipError_t e = hipGetLastError();
-    (void)hipFree(p->w);
+    (void)md::dev_free(p->w);
     delete p;
     return md::hip_fail(e, "MLP parameter upload");
   }
@@ -1042,9 +1042,9 @@ int mlp_destroy(void* mlp) {
   md::Mlp* p = static_cast<md::Mlp*>(mlp);
   if (!p) return MD_OK;
   MD_HIP_TRY(hipDeviceSynchronize());
-  if (p->w) MD_HIP_TRY(hipFree(p->w));
-  if (p->img) MD_HIP_TRY(hipFree(p->img));
-  if (p->scratch) MD_HIP_TRY(hipFree(p->scratch));
+  if (p->w) MD_HIP_TRY(md::dev_free(p->w));
+  if (p->img) MD_HIP_TRY(md::dev_free(p->img));
+  if (p->scratch) MD_HIP_TRY(md::dev_free(p->scratch));
   delete p;
   return MD_OK;
 }
@@ -1115,7 +1115,7 @@ int mlp_fit(void* mlp, const float* d_y, const float* d_target, int64_t N, int64
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   void* q = nullptr;
   // the batch buffers are private to this call (freed after the stream drains)
-  if (hipMalloc(&q, sizeof(float) * static_cast<size_t>(B) * (p->D + p->m)) != hipSuccess) {
+  if (md::dev_malloc(&q, sizeof(float) * static_cast<size_t>(B) * (p->D + p->m)) != hipSuccess) {
     (void)hipGetLastError();
     return md::fail(MD_ENOMEM, "batch allocation failed");
   }
@@ -1136,7 +1136,7 @@ int mlp_fit(void* mlp, const float* d_y, const float* d_target, int64_t N, int64
     if (st == MD_OK) st = md::adam(p, lr, s);
   }
   hipError_t e1 = hipStreamSynchronize(s);
-  hipError_t e2 = hipFree(yb);
+  hipError_t e2 = md::dev_free(yb);
   if (st != MD_OK) return st;
   if (e1 != hipSuccess) return md::hip_fail(e1, "hipStreamSynchronize");
   if (e2 != hipSuccess) return md::hip_fail(e2, "hipFree");

@@ -1,7 +1,8 @@
 // Device side of the counter-based AWGN channel (Philox4x32-10 + Box-Muller), shared by
 // awgn_sample and the batched sweep.  The definition is written out in mdemap.h; every
-// floating-point step is an IEEE double operation with contraction switched off, so the
-// bits do not depend on where or how the generator runs.
+// floating-point step is a correctly rounded IEEE operation (single precision for the
+// normal pair, one double fma for the received value) with contraction switched off, so
+// the bits do not depend on where or how the generator runs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -45,75 +46,76 @@ __device__ __forceinline__ Philox4 philox10(uint32_t c0, uint32_t c1, uint32_t c
   return out;
 }
 
-// ln(K 2^-53) for odd K < 2^53: f 2^b = K, atanh series of (f-1)/(f+1) in f^2, fdlibm ln2 split.
-__device__ __forceinline__ double gen_log_u(uint64_t K) {
+// One normal pair from the four words of (symbol g, pair p, domain 2), in IEEE single
+// precision (correctly rounded +, -, *, /, sqrt and fma; no contraction):
+//   radius: U = f 2^-e, f = 1 + (r0 >> 9) 2^-23, e = 1 + clz(r1) (33 when r1 = 0);
+//     ln U = ln f - k ln 2 with f halved and k = e - 1 when f > sqrt2 (else k = e),
+//     ln f = 2s P(s^2), s = (f - 1)/(f + 1), P = Horner of 1/(2i+1), i = 5..0;
+//     R = sqrt(-2 ln U);
+//   angle: quadrant q = r2 >> 30, T = (r2 >> 7) mod 2^23, t = (2T + 1) 2^-24 of the
+//     quadrant; sin and cos by Taylor polynomials on [0, pi/4] (t folded at 1/2);
+//   z0 = R cos, z1 = R sin after q quarter turns.
+constexpr float kGenSqrt2 = 0x1.6a09e6p+0f;
+constexpr float kGenLn2Hi = 0x1.62e300p-1f;     // 0.693145751953125: k * hi exact for k < 2^8
+constexpr float kGenLn2Lo = 0x1.2fefa2p-17f;    // ln 2 - hi, rounded
+constexpr float kGenPio2 = 0x1.921fb6p+0f;
+
+__device__ __forceinline__ float gen_log_u(uint32_t r0, uint32_t r1) {
 #pragma clang fp contract(off)
-  const int b = 63 - __clzll(static_cast<long long>(K));
-  double f = static_cast<double>(K);
-  f = __builtin_ldexp(f, -b);
-  double e = static_cast<double>(b - 53);
-  if (f > 0x1.6a09e667f3bcdp+0) {
-    f = f * 0.5;
-    e = e + 1.0;
+  const int e = r1 == 0u ? 33 : 1 + __clz(static_cast<int>(r1));
+  float f = 1.0f + static_cast<float>(r0 >> 9) * 0x1p-23f;      // exact
+  float k = static_cast<float>(e);
+  if (f > kGenSqrt2) {
+    f = f * 0.5f;
+    k = k - 1.0f;
   }
-  const double s = (f - 1.0) / (f + 1.0);
-  const double w = s * s;
-  double p = 1.0 / 19.0;
-  p = __builtin_fma(p, w, 1.0 / 17.0);
-  p = __builtin_fma(p, w, 1.0 / 15.0);
-  p = __builtin_fma(p, w, 1.0 / 13.0);
-  p = __builtin_fma(p, w, 1.0 / 11.0);
-  p = __builtin_fma(p, w, 1.0 / 9.0);
-  p = __builtin_fma(p, w, 1.0 / 7.0);
-  p = __builtin_fma(p, w, 1.0 / 5.0);
-  p = __builtin_fma(p, w, 1.0 / 3.0);
-  p = __builtin_fma(p, w, 1.0);
-  const double lnf = (2.0 * s) * p;
-  return __builtin_fma(e, 0x1.62e42feep-1, __builtin_fma(e, 0x1.a39ef35793c76p-33, lnf));
+  const float s = (f - 1.0f) / (f + 1.0f);
+  const float w = s * s;
+  float P = 1.0f / 11.0f;
+  P = __builtin_fmaf(P, w, 1.0f / 9.0f);
+  P = __builtin_fmaf(P, w, 1.0f / 7.0f);
+  P = __builtin_fmaf(P, w, 1.0f / 5.0f);
+  P = __builtin_fmaf(P, w, 1.0f / 3.0f);
+  P = __builtin_fmaf(P, w, 1.0f);
+  const float lnf = (2.0f * s) * P;
+  return __builtin_fmaf(-k, kGenLn2Hi, __builtin_fmaf(-k, kGenLn2Lo, lnf));
 }
 
-// sin/cos of ((2T+1) 2^-51) * pi/2 for T < 2^49 by Taylor polynomials (degree 17 / 18).
-__device__ __forceinline__ void gen_sincos_quarter(uint64_t T, double* s_out, double* c_out) {
+// sin and cos of phi = t pi/2, t = (2T + 1) 2^-24 <= 1/2, by Taylor polynomials in
+// w = phi^2 (sin to phi^11, cos to phi^12), Horner with fma.
+__device__ __forceinline__ void gen_sincos_quarter(uint32_t T, float* s_out, float* c_out) {
 #pragma clang fp contract(off)
-  const double t = static_cast<double>(2 * T + 1) * 0x1p-51;
-  const double phi = t * 0x1.921fb54442d18p+0;
-  const double w = phi * phi;
-  double S = 1.0 / 355687428096000.0;
-  S = __builtin_fma(S, w, -1.0 / 1307674368000.0);
-  S = __builtin_fma(S, w, 1.0 / 6227020800.0);
-  S = __builtin_fma(S, w, -1.0 / 39916800.0);
-  S = __builtin_fma(S, w, 1.0 / 362880.0);
-  S = __builtin_fma(S, w, -1.0 / 5040.0);
-  S = __builtin_fma(S, w, 1.0 / 120.0);
-  S = __builtin_fma(S, w, -1.0 / 6.0);
-  S = __builtin_fma(S, w, 1.0);
-  double C = -1.0 / 6402373705728000.0;
-  C = __builtin_fma(C, w, 1.0 / 20922789888000.0);
-  C = __builtin_fma(C, w, -1.0 / 87178291200.0);
-  C = __builtin_fma(C, w, 1.0 / 479001600.0);
-  C = __builtin_fma(C, w, -1.0 / 3628800.0);
-  C = __builtin_fma(C, w, 1.0 / 40320.0);
-  C = __builtin_fma(C, w, -1.0 / 720.0);
-  C = __builtin_fma(C, w, 1.0 / 24.0);
-  C = __builtin_fma(C, w, -1.0 / 2.0);
-  C = __builtin_fma(C, w, 1.0);
+  const float t = static_cast<float>(2u * T + 1u) * 0x1p-24f;     // exact
+  const float phi = t * kGenPio2;
+  const float w = phi * phi;
+  float S = -1.0f / 39916800.0f;
+  S = __builtin_fmaf(S, w, 1.0f / 362880.0f);
+  S = __builtin_fmaf(S, w, -1.0f / 5040.0f);
+  S = __builtin_fmaf(S, w, 1.0f / 120.0f);
+  S = __builtin_fmaf(S, w, -1.0f / 6.0f);
+  S = __builtin_fmaf(S, w, 1.0f);
+  float C = 1.0f / 479001600.0f;
+  C = __builtin_fmaf(C, w, -1.0f / 3628800.0f);
+  C = __builtin_fmaf(C, w, 1.0f / 40320.0f);
+  C = __builtin_fmaf(C, w, -1.0f / 720.0f);
+  C = __builtin_fmaf(C, w, 1.0f / 24.0f);
+  C = __builtin_fmaf(C, w, -1.0f / 2.0f);
+  C = __builtin_fmaf(C, w, 1.0f);
   *s_out = phi * S;
   *c_out = C;
 }
 
-__device__ __forceinline__ void gen_normal_pair(const Philox4& r, double* z0, double* z1) {
+__device__ __forceinline__ void gen_normal_pair(const Philox4& r, float* z0, float* z1) {
 #pragma clang fp contract(off)
-  const uint64_t J1 = (static_cast<uint64_t>(r.w[0] >> 6) << 26) | static_cast<uint64_t>(r.w[1] >> 6);
-  const uint64_t J2 = (static_cast<uint64_t>(r.w[2] >> 6) << 26) | static_cast<uint64_t>(r.w[3] >> 6);
-  const double R = __builtin_sqrt(-2.0 * gen_log_u(2 * J1 + 1));
-  const uint32_t q = static_cast<uint32_t>(J2 >> 50);
-  const uint64_t T = J2 & ((1ull << 50) - 1);
-  const bool upper = T >= (1ull << 49);
-  double sq, cq;
-  gen_sincos_quarter(upper ? ((1ull << 50) - 1 - T) : T, &sq, &cq);
-  const double c = upper ? sq : cq;
-  const double s = upper ? cq : sq;
-  double ct, st;
+  const float R = __builtin_sqrtf(-2.0f * gen_log_u(r.w[0], r.w[1]));
+  const uint32_t q = r.w[2] >> 30;
+  const uint32_t T = (r.w[2] >> 7) & 0x7FFFFFu;
+  const bool upper = T >= (1u << 22);
+  float sq, cq;
+  gen_sincos_quarter(upper ? ((1u << 23) - 1u - T) : T, &sq, &cq);
+  const float c = upper ? sq : cq;
+  const float s = upper ? cq : sq;
+  float ct, st;
   switch (q) {
     case 0: ct = c; st = s; break;
     case 1: ct = -s; st = c; break;
@@ -136,11 +138,12 @@ __device__ __forceinline__ uint32_t channel_symbol(const float* __restrict__ X, 
   const int npairs = (D + 1) >> 1;
   for (int p = 0; p < npairs; ++p) {
     const Philox4 r = philox10(glo, ghi, static_cast<uint32_t>(p), 2u, k0, k1);
-    double z0, z1;
+    float z0, z1;
     gen_normal_pair(r, &z0, &z1);
     const int d0 = 2 * p;
-    yout[d0] = static_cast<float>(__builtin_fma(sigma, z0, static_cast<double>(xu[d0])));
-    if (d0 + 1 < D) yout[d0 + 1] = static_cast<float>(__builtin_fma(sigma, z1, static_cast<double>(xu[d0 + 1])));
+    yout[d0] = static_cast<float>(__builtin_fma(sigma, static_cast<double>(z0), static_cast<double>(xu[d0])));
+    if (d0 + 1 < D)
+      yout[d0 + 1] = static_cast<float>(__builtin_fma(sigma, static_cast<double>(z1), static_cast<double>(xu[d0 + 1])));
   }
   return u;
 }

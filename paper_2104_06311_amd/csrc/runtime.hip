@@ -1,9 +1,11 @@
 // Host runtime of the library: error strings, per-(device, stream) workspaces and the
 // host-side label check cache.
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <set>
 #include <tuple>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -35,6 +37,44 @@ int current_device(int* dev) {
   if (e != hipSuccess || n == 0) return fail(MD_ENODEV, "no GPU visible");
   MD_HIP_TRY(hipGetDevice(dev));
   return MD_OK;
+}
+
+namespace {
+// allocation-failure injection (alloc_fault_inject): -1 off, k >= 0 the k-th next fails
+std::atomic<int> g_fail_in{-1};
+}  // namespace
+
+namespace {
+std::mutex g_live_mu;
+std::unordered_map<void*, size_t> g_live;   // device allocations the library holds
+}  // namespace
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+  int k = g_fail_in.load();
+  while (k >= 0) {
+    if (g_fail_in.compare_exchange_weak(k, k - 1)) {
+      if (k == 0) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+      }
+      break;
+    }
+  }
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live[*p] = bytes;
+  }
+  return e;
+}
+
+hipError_t dev_free(void* p) {
+  if (!p) return hipSuccess;
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.erase(p);
+  }
+  return hipFree(p);
 }
 
 namespace {
@@ -155,10 +195,16 @@ int stream_flags(hipStream_t stream, int** out) {
   FlagsEntry& f = g_fl[{dev, stream}];
   if (!f.ptr) {
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, 256);
+    hipError_t e = dev_malloc(&p, 256);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(MD_ENOMEM, "allocation of the stage counters failed");
+    }
+    // the GMI status word (bytes 128..135) reads 0 until a GMI call writes it
+    e = hipMemset(p, 0, 256);
+    if (e != hipSuccess) {
+      (void)dev_free(p);
+      return hip_fail(e, "hipMemset(stage counters)");
     }
     f.ptr = static_cast<int*>(p);
   }
@@ -203,12 +249,12 @@ int workspace(hipStream_t stream, size_t bytes, char** out) {
     if (w.ptr) {
       // the old buffer may still be in use by work queued on this stream
       MD_HIP_TRY(hipStreamSynchronize(stream));
-      MD_HIP_TRY(hipFree(w.ptr));
+      MD_HIP_TRY(dev_free(w.ptr));
       w.ptr = nullptr;
       w.cap = 0;
     }
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, cap);
+    hipError_t e = dev_malloc(&p, cap);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(MD_ENOMEM, "workspace allocation of " + std::to_string(cap) + " bytes failed");
@@ -257,14 +303,14 @@ int release_stream_resources(hipStream_t stream) {
     std::lock_guard<std::mutex> lk(g_ws_mu);
     auto it = g_ws.find({dev, stream});
     if (it != g_ws.end()) {
-      if (it->second.ptr) MD_HIP_TRY(hipFree(it->second.ptr));
+      if (it->second.ptr) MD_HIP_TRY(dev_free(it->second.ptr));
       g_ws.erase(it);
     }
   }
   std::lock_guard<std::mutex> lk(g_fl_mu);
   auto it = g_fl.find({dev, stream});
   if (it != g_fl.end()) {
-    if (it->second.ptr) MD_HIP_TRY(hipFree(it->second.ptr));
+    if (it->second.ptr) MD_HIP_TRY(dev_free(it->second.ptr));
     g_fl.erase(it);
   }
   return MD_OK;
@@ -278,7 +324,7 @@ int release_workspaces() {
       int cur = 0;
       MD_HIP_TRY(hipGetDevice(&cur));
       MD_HIP_TRY(hipSetDevice(kv.first.first));
-      hipError_t e = hipFree(kv.second.ptr);
+      hipError_t e = dev_free(kv.second.ptr);
       MD_HIP_TRY(hipSetDevice(cur));
       if (e != hipSuccess) return hip_fail(e, "hipFree(workspace)");
     }
@@ -294,7 +340,7 @@ int release_workspaces() {
       int cur = 0;
       MD_HIP_TRY(hipGetDevice(&cur));
       MD_HIP_TRY(hipSetDevice(kv.first.first));
-      hipError_t e = hipFree(kv.second.ptr);
+      hipError_t e = dev_free(kv.second.ptr);
       MD_HIP_TRY(hipSetDevice(cur));
       if (e != hipSuccess) return hip_fail(e, "hipFree(stage counters)");
     }
@@ -306,6 +352,23 @@ int release_workspaces() {
 }  // namespace md
 
 extern "C" {
+
+int alloc_fault_inject(int k) {
+  md::set_error("");
+  md::g_fail_in.store(k < 0 ? -1 : k);
+  return MD_OK;
+}
+
+int alloc_stats(int64_t* live_bytes, int64_t* live_allocs) {
+  md::set_error("");
+  if (!live_bytes || !live_allocs) return md::fail(MD_EINVAL, "output pointer is NULL");
+  std::lock_guard<std::mutex> lk(md::g_live_mu);
+  int64_t b = 0;
+  for (const auto& kv : md::g_live) b += static_cast<int64_t>(kv.second);
+  *live_bytes = b;
+  *live_allocs = static_cast<int64_t>(md::g_live.size());
+  return MD_OK;
+}
 
 int kernel_timing(int enable, void* stream) {
   md::set_error("");

@@ -106,11 +106,11 @@ void free_lane(Lane& L) {
     (void)hipStreamSynchronize(L.s);
     (void)release_stream_resources(L.s);
   }
-  if (L.y) (void)hipFree(L.y);
-  if (L.tx) (void)hipFree(L.tx);
-  if (L.llr) (void)hipFree(L.llr);
-  if (L.dec) (void)hipFree(L.dec);
-  if (L.d_res) (void)hipFree(L.d_res);
+  if (L.y) (void)md::dev_free(L.y);
+  if (L.tx) (void)md::dev_free(L.tx);
+  if (L.llr) (void)md::dev_free(L.llr);
+  if (L.dec) (void)md::dev_free(L.dec);
+  if (L.d_res) (void)md::dev_free(L.d_res);
   if (L.h_res) (void)hipHostFree(L.h_res);
   if (L.beg) (void)hipEventDestroy(L.beg);
   if (L.end) (void)hipEventDestroy(L.end);
@@ -120,8 +120,8 @@ void free_lane(Lane& L) {
 
 void destroy(RxStream* r) {
   for (Lane& L : r->lanes) free_lane(L);
-  if (r->X) (void)hipFree(r->X);
-  if (r->labels) (void)hipFree(r->labels);
+  if (r->X) (void)md::dev_free(r->X);
+  if (r->labels) (void)md::dev_free(r->labels);
   (void)hipGetLastError();
   delete r;
 }
@@ -129,7 +129,7 @@ void destroy(RxStream* r) {
 template <class T>
 int dev_alloc(T** p, size_t count) {
   void* q = nullptr;
-  if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) {
+  if (md::dev_malloc(&q, count * sizeof(T)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(MD_ENOMEM, "streaming receiver: device allocation failed");
   }

@@ -21,7 +21,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <set>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -381,12 +385,28 @@ struct SweepPlan {
   std::vector<Problem> h_probs;
   std::vector<int*> h_flags;
   size_t lds_bytes = 0;
-  // classes of problems with one tile-loop shape: (K steps, label bits) and their item ranges
+  // classes of problems with one tile-loop shape: (K steps, label bits), their item ranges
+  // and their launch shape (an index into kShapes)
   struct Class {
-    int ks, m, begin, end;
+    int ks, m, begin, end, v;
   };
   std::vector<Class> classes;
+  std::map<std::pair<int, int>, int> class_var;   // (K steps, label bits) -> launch shape
+  std::map<std::pair<int, int>, int> tuned;       // the autotuner's choices for this plan
+  std::map<std::pair<int, int>, float> tuned_ms;  // and the class kernel times they gave
 };
+
+// Launch shapes: wavefronts per block, 32-symbol blocks per wavefront, symbol groups per
+// work item.
+struct Shape {
+  int waves, sb, gpi;
+};
+constexpr Shape kShapes[4] = {{8, 2, 1}, {8, 2, 4}, {16, 1, 1}, {16, 1, 4}};
+
+// Autotuner choices, per device and constellation class (K steps, label bits): measured
+// once per process, reused by every later plan with the same classes.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune;
 
 constexpr int kCounterBase = 4;    // counters[0..3]: unused, fallback count, overflow, unused
 
@@ -394,7 +414,7 @@ namespace {
 
 int dev_alloc(SweepPlan* p, size_t bytes, void** out) {
   void* q = nullptr;
-  if (hipMalloc(&q, bytes > 0 ? bytes : 16) != hipSuccess) {
+  if (dev_malloc(&q, bytes > 0 ? bytes : 16) != hipSuccess) {
     (void)hipGetLastError();
     return fail(MD_ENOMEM, "sweep plan allocation failed");
   }
@@ -408,7 +428,7 @@ void free_plan(SweepPlan* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-  for (void* q : p->allocs) (void)hipFree(q);
+  for (void* q : p->allocs) (void)md::dev_free(q);
   delete p;
 }
 
@@ -452,15 +472,19 @@ int launch_class_shape(SweepPlan* p, const SweepPlan::Class& c, int ci, hipStrea
   }
 }
 
-int enqueue(SweepPlan* p, hipStream_t s) {
+// ev: NULL, or two events per class recorded around that class's kernel (autotuning).
+int enqueue(SweepPlan* p, hipStream_t s, const std::vector<hipEvent_t>* ev = nullptr) {
   const int ncounters = kCounterBase + static_cast<int>(p->classes.size());
   hipLaunchKernelGGL(sweep_reset_kernel, dim3((std::max(p->nprob, ncounters) + 255) / 256), dim3(256), 0, s,
                      p->d_counters, ncounters, p->d_fb_acc, p->nprob);
   MD_LAUNCH_CHECK("sweep_reset_kernel launch");
   for (size_t ci = 0; ci < p->classes.size(); ++ci) {
-    const int st = p->waves == 16 ? launch_class_shape<16, 1>(p, p->classes[ci], static_cast<int>(ci), s)
-                                  : launch_class_shape<8, 2>(p, p->classes[ci], static_cast<int>(ci), s);
+    const SweepPlan::Class& c = p->classes[ci];
+    if (ev) MD_HIP_TRY(hipEventRecord((*ev)[2 * ci], s));
+    const int st = kShapes[c.v].waves == 16 ? launch_class_shape<16, 1>(p, c, static_cast<int>(ci), s)
+                                            : launch_class_shape<8, 2>(p, c, static_cast<int>(ci), s);
     if (st != MD_OK) return st;
+    if (ev) MD_HIP_TRY(hipEventRecord((*ev)[2 * ci + 1], s));
   }
   int ncu = 0;
   MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
@@ -473,10 +497,9 @@ int enqueue(SweepPlan* p, hipStream_t s) {
   return MD_OK;
 }
 
-// Builds the item list for the plan's launch shape (groups per item gpi).
+// Builds the item list for the launch shapes of the plan's classes (class_var; shape 0
+// for a class without an entry) and every problem's LDS chunk size.
 int build_items(SweepPlan* p) {
-  const int per_group = p->waves * 32 * p->sb;
-  const int per_item = per_group * p->gpi;
   std::vector<int> order(static_cast<size_t>(p->nprob));
   for (int i = 0; i < p->nprob; ++i) order[static_cast<size_t>(i)] = i;
   // by class (K steps, label bits), most expensive class first, then by N
@@ -492,8 +515,18 @@ int build_items(SweepPlan* p) {
   p->classes.clear();
   for (int pi : order) {
     Problem& P = p->h_probs[static_cast<size_t>(pi)];
+    const auto cv = p->class_var.find({P.ks, P.m});
+    const int v = cv == p->class_var.end() ? 0 : cv->second;
+    const Shape sh = kShapes[v];
     if (p->classes.empty() || p->classes.back().ks != P.ks || p->classes.back().m != P.m)
-      p->classes.push_back(SweepPlan::Class{P.ks, P.m, static_cast<int>(items.size()), static_cast<int>(items.size())});
+      p->classes.push_back(
+          SweepPlan::Class{P.ks, P.m, static_cast<int>(items.size()), static_cast<int>(items.size()), v});
+    // dynamic LDS: fragment chunk (whole tile groups), then the symbol staging rows
+    const int bstage = sh.waves * sh.sb * fastk::bstage_bytes<kMaxKS>();
+    int ct = (kDynLds - bstage) / (P.ks * 64 * 16);
+    ct -= ct % 8;
+    P.chunk_tiles = std::min(ct, P.ntiles);
+    const int per_item = sh.waves * 32 * sh.sb * sh.gpi;
     P.item_begin = static_cast<int>(items.size());
     for (int64_t s0 = 0; s0 < P.N; s0 += per_item) {
       Item it;
@@ -648,50 +681,67 @@ int sweep_plan_create(const md_sweep_instance* inst, int n_inst, const double* s
       return bail(md::fail(MD_EUNSUPPORTED, "problem " + std::to_string(pi) +
                                                 ": constellation outside the FP16 split range at this noise level"));
   }
-  // launch shape: autotuned when variant < 0
-  const int shapes[4][3] = {{8, 2, 1}, {8, 2, 4}, {16, 1, 1}, {16, 1, 4}};
-  auto configure = [&](int v) -> int {
-    p->waves = shapes[v][0];
-    p->sb = shapes[v][1];
-    p->gpi = shapes[v][2];
-    // dynamic LDS: fragment chunk, then the symbol staging rows (static LDS < 1 KiB)
-    const int dyn = md::kDynLds;
-    const int bstage = p->waves * p->sb * md::fastk::bstage_bytes<md::kMaxKS>();
-    for (auto& P : p->h_probs) {
-      const int tile_bytes = P.ks * 64 * 16;
-      int ct = (dyn - bstage) / tile_bytes;
-      ct -= ct % 8;
-      P.chunk_tiles = std::min(ct, P.ntiles);
-    }
-    p->lds_bytes = static_cast<size_t>(dyn);
-    return md::build_items(p);
-  };
-  int chosen = variant;
+  // launch shapes per class: fixed (variant >= 0), from the autotuner's cache, or measured
+  p->lds_bytes = static_cast<size_t>(md::kDynLds);
+  std::set<std::pair<int, int>> keys;
+  for (const auto& P : p->h_probs) keys.insert({P.ks, P.m});
+  bool cached = variant < 0;
   if (variant < 0) {
-    // time every launch shape on this plan and keep the fastest
-    float best = 1e30f;
-    for (int v = 0; v < 4; ++v) {
-      if ((st = configure(v))) return bail(st);
-      if ((st = md::enqueue(p, p->cap_stream))) return bail(st);
-      hipEvent_t a, b;
-      (void)hipEventCreate(&a);
-      (void)hipEventCreate(&b);
-      (void)hipEventRecord(a, p->cap_stream);
-      st = md::enqueue(p, p->cap_stream);
-      (void)hipEventRecord(b, p->cap_stream);
-      if (hipEventSynchronize(b) != hipSuccess) st = md::hip_fail(hipGetLastError(), "autotune");
-      float ms = 0.0f;
-      (void)hipEventElapsedTime(&ms, a, b);
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
-      if (st) return bail(st);
-      if (ms < best) {
-        best = ms;
-        chosen = v;
+    std::lock_guard<std::mutex> lk(md::g_tune_mu);
+    for (const auto& k : keys) {
+      const auto it = md::g_tune.find({dev, k.first, k.second});
+      if (it == md::g_tune.end()) {
+        cached = false;
+        break;
       }
+      p->class_var[k] = it->second;
     }
   }
-  if ((st = configure(chosen))) return bail(st);
+  if (variant >= 0) {
+    for (const auto& k : keys) p->class_var[k] = variant;
+  } else if (!cached) {
+    // run the whole plan once per shape, timing every class's kernel with events, and give
+    // each class the shape under which its own kernel was fastest
+    std::map<std::pair<int, int>, float> best;
+    for (int v = 0; v < 4; ++v) {
+      for (const auto& k : keys) p->class_var[k] = v;
+      if ((st = md::build_items(p))) return bail(st);
+      const size_t nc = p->classes.size();
+      std::vector<hipEvent_t> ev(2 * nc, nullptr);
+      for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) st = md::hip_fail(hipGetLastError(), "autotune events");
+      if (!st) st = md::enqueue(p, p->cap_stream);                 // warm-up
+      if (!st) st = md::enqueue(p, p->cap_stream, &ev);
+      if (!st && hipStreamSynchronize(p->cap_stream) != hipSuccess) st = md::hip_fail(hipGetLastError(), "autotune");
+      for (size_t ci = 0; ci < nc && !st; ++ci) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[2 * ci], ev[2 * ci + 1]) != hipSuccess) {
+          st = md::hip_fail(hipGetLastError(), "autotune timing");
+          break;
+        }
+        const std::pair<int, int> k{p->classes[ci].ks, p->classes[ci].m};
+        const auto b = best.find(k);
+        if (b == best.end() || ms < b->second) {
+          best[k] = ms;
+          p->tuned[k] = v;
+          p->tuned_ms[k] = ms;
+        }
+      }
+      for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+      if (st) return bail(st);
+    }
+    std::lock_guard<std::mutex> lk(md::g_tune_mu);
+    for (const auto& kv : p->tuned) {
+      p->class_var[kv.first] = kv.second;
+      md::g_tune[{dev, kv.first.first, kv.first.second}] = kv.second;
+    }
+  }
+  if ((st = md::build_items(p))) return bail(st);
+  const md::Shape sh0 = md::kShapes[p->classes.front().v];
+  p->waves = sh0.waves;
+  p->sb = sh0.sb;
+  p->gpi = sh0.gpi;
   if ((st = md::capture(p))) return bail(st);
   *out = p;
   return MD_OK;
@@ -704,6 +754,31 @@ int sweep_plan_info(const void* plan, int* variant_waves, int* variant_sb, int* 
   if (variant_sb) *variant_sb = p->sb;
   if (groups_per_item) *groups_per_item = p->gpi;
   if (n_items) *n_items = p->n_items;
+  return MD_OK;
+}
+
+int sweep_plan_class(const void* plan, int i, int* k_steps, int* label_bits, int* shape, int* n_items,
+                     float* tuned_ms) {
+  md::set_error("");
+  const md::SweepPlan* p = static_cast<const md::SweepPlan*>(plan);
+  if (!p) return md::fail(MD_EINVAL, "plan is NULL");
+  if (i < 0 || i >= static_cast<int>(p->classes.size())) return md::fail(MD_EINVAL, "no such class");
+  const md::SweepPlan::Class& c = p->classes[static_cast<size_t>(i)];
+  if (k_steps) *k_steps = c.ks;
+  if (label_bits) *label_bits = c.m;
+  if (shape) *shape = c.v;
+  if (n_items) *n_items = c.end - c.begin;
+  if (tuned_ms) {
+    const auto it = p->tuned_ms.find({c.ks, c.m});
+    *tuned_ms = it == p->tuned_ms.end() ? -1.0f : it->second;
+  }
+  return MD_OK;
+}
+
+int sweep_tuning_clear(void) {
+  md::set_error("");
+  std::lock_guard<std::mutex> lk(md::g_tune_mu);
+  md::g_tune.clear();
   return MD_OK;
 }
 

