@@ -389,6 +389,7 @@ struct SweepPlan {
   // and their launch shape (an index into kShapes)
   struct Class {
     int ks, m, begin, end, v;
+    size_t lds;   // dynamic LDS of the class kernel: its largest fragment chunk + staging rows
   };
   std::vector<Class> classes;
   std::map<std::pair<int, int>, int> class_var;   // (K steps, label bits) -> launch shape
@@ -442,11 +443,11 @@ int launch_class(SweepPlan* p, const SweepPlan::Class& c, int ci, hipStream_t s)
   int ncu = 0, occ = 0;
   MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
   MD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kern), WAVES * 64,
-                                                           p->lds_bytes));
+                                                           c.lds));
   if (occ < 1) occ = 1;
   int64_t grid = static_cast<int64_t>(ncu) * occ;
   if (grid > c.end - c.begin) grid = c.end - c.begin;
-  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(WAVES * 64), p->lds_bytes, s, p->d_probs,
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(WAVES * 64), c.lds, s, p->d_probs,
                      p->d_items, c.begin, c.end, p->d_counters + kCounterBase + ci, p->d_counters, p->d_item_sum,
                      p->d_fb);
   MD_LAUNCH_CHECK("sweep_kernel launch");
@@ -520,12 +521,19 @@ int build_items(SweepPlan* p) {
     const Shape sh = kShapes[v];
     if (p->classes.empty() || p->classes.back().ks != P.ks || p->classes.back().m != P.m)
       p->classes.push_back(
-          SweepPlan::Class{P.ks, P.m, static_cast<int>(items.size()), static_cast<int>(items.size()), v});
-    // dynamic LDS: fragment chunk (whole tile groups), then the symbol staging rows
+          SweepPlan::Class{P.ks, P.m, static_cast<int>(items.size()), static_cast<int>(items.size()), v, 0});
+    // dynamic LDS: fragment chunk (whole tile groups), then the symbol staging rows; a class
+    // asks for no more than its largest chunk needs, so that small constellations run
+    // several blocks per compute unit
     const int bstage = sh.waves * sh.sb * fastk::bstage_bytes<kMaxKS>();
     int ct = (kDynLds - bstage) / (P.ks * 64 * 16);
     ct -= ct % 8;
     P.chunk_tiles = std::min(ct, P.ntiles);
+    // the tile loop's prefetch reads up to two tiles past a chunk's end (into the staging
+    // rows that follow it), so the staging rows must span at least two tiles
+    const size_t need = static_cast<size_t>(P.chunk_tiles) * P.ks * 64 * 16 +
+                        std::max<size_t>(bstage, static_cast<size_t>(2) * P.ks * 64 * 16);
+    p->classes.back().lds = std::max(p->classes.back().lds, need);
     const int per_item = sh.waves * 32 * sh.sb * sh.gpi;
     P.item_begin = static_cast<int>(items.size());
     for (int64_t s0 = 0; s0 < P.N; s0 += per_item) {
