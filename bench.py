@@ -481,8 +481,8 @@ def extra_rx(md, seconds):
         rx.close()
         nbins = len(r["bin_errors"])
         per_bin = [min(21 * B, total - b * 21 * B) for b in range(nbins)]
-        ber = [float(e) / (n * m) for e, n in zip(r["bin_errors"], per_bin)]
-        q = [md.q_factor_db(b) for b in ber if 0.0 < b < 0.5]
+        q = [md.q_factor_db(torch.tensor([int(e)], dtype=torch.int64, device="cuda"), n * m).item()
+             for e, n in zip(r["bin_errors"], per_bin) if 0 < 2 * int(e) < n * m]
         h2d = 4 * D + 4
         d2h = 4 if mode == "hard" else 4 * m
         res[name] = {"mode": mode, "M": M, "D": D, "symbols": total, "seconds": r["seconds"],

@@ -90,17 +90,20 @@ extern "C" {
  * (seed, offset) window is reproducible on any launch geometry and on the CPU:
  *
  *   key = (seed & 0xffffffff, seed >> 32); g = offset + n (64-bit);
- *   Philox4x32-10 (Salmon et al., SC'11) of counter (g_lo, g_hi, sub, domain).
- *   u_n = word0 >> (32 - m) of counter (g_lo, g_hi, 0, 1).
- *   For pair p = 0 .. ceil(D/2)-1, words r0..r3 of counter (g_lo, g_hi, p, 2), in IEEE
- *   single precision (every operation correctly rounded, fma where written):
- *     U1 = f 2^-e, f = 1 + (r0 >> 9) 2^-23, e = 1 + clz(r1) (33 if r1 = 0);
- *     if f > SQRT2 (0x1.6a09e6p+0): f = f/2, k = e - 1, else k = e;
+ *   Philox4x32-10 (Salmon et al., SC'11) of counter (g_lo, g_hi, j, 1), j = 0, 1, ...,
+ *   gives channel use n one stream of words: word 4j + i is output word i of block j.
+ *   u_n = word 0 >> (32 - m).
+ *   Pair p = 0 .. ceil(D/2)-1 takes the radius word a = word 2p+1 and the angle word
+ *   b = word 2p+2 (so 8D draws three blocks, 2D one), in IEEE single precision (every
+ *   operation correctly rounded, fma where written):
+ *     v = (float)(a | 1) (round to nearest even), U1 = v 2^-32 in [2^-32, 1];
+ *     v = f 2^E with f in [1, 2) from its bits, k = E - 32;
+ *     if f > SQRT2 (0x1.6a09e6p+0): f = f/2, k = k + 1;
  *     s = (f-1)/(f+1), w = s*s, P = Horner in w of 1/(2i+1), i = 5..0 (fmaf),
- *     ln U1 = fmaf(-k, LN2_HI, fmaf(-k, LN2_LO, (2s) P)) with LN2_HI = 0x1.62e300p-1,
+ *     ln U1 = fmaf(k, LN2_HI, fmaf(k, LN2_LO, (2s) P)) with LN2_HI = 0x1.62e300p-1,
  *       LN2_LO = 0x1.2fefa2p-17;
  *     R = sqrtf(-2 ln U1);
- *     quadrant Q = r2 >> 30, T = (r2 >> 7) mod 2^23 (the angle is
+ *     quadrant Q = b >> 30, T = (b >> 7) mod 2^23 (the angle is
  *       2 pi (Q + (2T+1) 2^-24) / 4);
  *     if T < 2^22: phi = ((2T+1) 2^-24) * PIO2 gives (cos, sin) = (C, S)
  *       else phi' from T' = 2^23 - 1 - T gives (cos, sin) = (S', C'),

@@ -107,7 +107,7 @@ def philox4x32_10(ctr, key) -> np.ndarray:
 
 
 def box_muller(words) -> np.ndarray:
-    """The generator's normal pair (z0, z1) for four Philox output words."""
+    """The generator's normal pair (z0, z1) for a radius word and an angle word."""
     lib = _load()
     w = _u32(words)
     z = np.zeros(2, dtype=np.float64)

@@ -24,7 +24,7 @@
  *
  * plus a re-implementation, from its written definition, of the counter-based
  * AWGN generator that the library's awgn_sample follows (Philox4x32-10, Salmon et
- * al., SC'11, then a Box-Muller transform evaluated with IEEE double +,-,*,/,
+ * al., SC'11, then a Box-Muller transform evaluated with IEEE single +,-,*,/,
  * fma and sqrt only), and an FP64 reference of the small MLP demapper with its
  * analytic backward pass and an Adam step.
  *
@@ -68,15 +68,17 @@ void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint3
 
 /* ------------------------------------------------------------------------- */
 /* The channel's normal pair, in IEEE single precision exactly as the generator
- * definition fixes it (every operation correctly rounded, fma where written):
- *   radius: U = f 2^-e with f = 1 + (r0 >> 9) 2^-23 and e = 1 + clz(r1) (33 if r1 = 0),
- *     so U is uniform on (0, 1) with 23 bits inside each binade;
- *     if f > sqrt2: f = f/2, k = e - 1, else k = e;
+ * definition fixes it (every operation correctly rounded, fma where written), from a
+ * radius word a and an angle word b:
+ *   radius: v = (float)(a | 1), rounded to nearest even, and U = v 2^-32, uniform on
+ *     [2^-32, 1] with 24 bits inside each binade; v = f 2^E with f in [1, 2) read
+ *     from its bits, k = E - 32;
+ *     if f > sqrt2: f = f/2, k = k + 1;
  *     s = (f-1)/(f+1), w = s*s, P = Horner over w of 1/(2i+1), i = 5..0;
- *     ln U = fma(-k, LN2_HI, fma(-k, LN2_LO, (2 s) P))   (ln f = 2 atanh s);
+ *     ln U = fma(k, LN2_HI, fma(k, LN2_LO, (2 s) P))   (ln f = 2 atanh s);
  *     R = sqrt(-2 ln U);
- *   angle: q = r2 >> 30 quarter turns plus t = (2T+1) 2^-24 of a quarter turn,
- *     T = (r2 >> 7) mod 2^23; for t <= 1/2 sin and cos of phi = t pi/2 by Taylor
+ *   angle: q = b >> 30 quarter turns plus t = (2T+1) 2^-24 of a quarter turn,
+ *     T = (b >> 7) mod 2^23; for t <= 1/2 sin and cos of phi = t pi/2 by Taylor
  *     polynomials in phi^2 (sin to phi^11, cos to phi^12), otherwise the complement
  *     t' = 1 - t with the two swapped;
  *   (z0, z1) = R (cos, sin) after q quarter turns. */
@@ -85,13 +87,18 @@ static const float GEN_LN2_HI = 0x1.62e300p-1f;
 static const float GEN_LN2_LO = 0x1.2fefa2p-17f;
 static const float GEN_PIO2 = 0x1.921fb6p+0f;
 
-static float orc_gen_log_u(uint32_t r0, uint32_t r1) {
-    int e = (r1 == 0u) ? 33 : 1 + __builtin_clz(r1);
-    float f = 1.0f + (float)(r0 >> 9) * 0x1p-23f;     /* exact */
-    float k = (float)e;
+static float orc_gen_log_u(uint32_t a) {
+    float v = (float)(a | 1u);                        /* correctly rounded */
+    uint32_t bits;
+    memcpy(&bits, &v, sizeof bits);
+    int E = (int)(bits >> 23) - 127;                  /* v >= 1: a normal number */
+    uint32_t fb = (bits & 0x007FFFFFu) | 0x3F800000u;
+    float f;
+    memcpy(&f, &fb, sizeof f);
+    float k = (float)(E - 32);
     if (f > GEN_SQRT2) {
         f = f * 0.5f;
-        k = k - 1.0f;
+        k = k + 1.0f;
     }
     float s = (f - 1.0f) / (f + 1.0f);
     float w = s * s;
@@ -102,7 +109,7 @@ static float orc_gen_log_u(uint32_t r0, uint32_t r1) {
     P = fmaf(P, w, 1.0f / 3.0f);
     P = fmaf(P, w, 1.0f);
     float lnf = (2.0f * s) * P;
-    return fmaf(-k, GEN_LN2_HI, fmaf(-k, GEN_LN2_LO, lnf));
+    return fmaf(k, GEN_LN2_HI, fmaf(k, GEN_LN2_LO, lnf));
 }
 
 static void orc_gen_sincos_quarter(uint32_t T, float* s_out, float* c_out) {
@@ -126,11 +133,11 @@ static void orc_gen_sincos_quarter(uint32_t T, float* s_out, float* c_out) {
     *c_out = C;
 }
 
-/* One Box-Muller pair from the four Philox words of (symbol g, pair p, domain 2). */
-static void orc_gen_normal_pair(const uint32_t r[4], float* z0, float* z1) {
-    float R = sqrtf(-2.0f * orc_gen_log_u(r[0], r[1]));
-    uint32_t q = r[2] >> 30;
-    uint32_t T = (r[2] >> 7) & 0x7FFFFFu;
+/* One Box-Muller pair from a radius word a and an angle word b. */
+static void orc_gen_normal_pair(uint32_t a, uint32_t b, float* z0, float* z1) {
+    float R = sqrtf(-2.0f * orc_gen_log_u(a));
+    uint32_t q = b >> 30;
+    uint32_t T = (b >> 7) & 0x7FFFFFu;
     float sp, cp, c, s;
     if (T < (1u << 22)) {
         orc_gen_sincos_quarter(T, &sp, &cp);
@@ -151,42 +158,46 @@ static void orc_gen_normal_pair(const uint32_t r[4], float* z0, float* z1) {
     *z1 = R * st;
 }
 
-/* The normal pair for four given Philox words (exported so the transform can be
- * checked against libm's log, atan2 and hypot). */
-void orc_gen_box_muller(const uint32_t r[4], double z[2]) {
+/* The normal pair for a radius word w[0] and an angle word w[1] (exported so the
+ * transform can be checked against libm's log, atan2 and hypot). */
+void orc_gen_box_muller(const uint32_t w[2], double z[2]) {
     float z0, z1;
-    orc_gen_normal_pair(r, &z0, &z1);
+    orc_gen_normal_pair(w[0], w[1], &z0, &z1);
     z[0] = z0;
     z[1] = z1;
 }
 
 /* Channel: u_n uniform on {0..M-1}, z_n ~ N(0, I_D), y_n = fl32(x_{u_n} + sigma z_n).
- * Counter (g_lo, g_hi, sub, domain) with g = offset + n, key = (seed_lo, seed_hi);
- * domain 1 gives u_n = word0 >> (32 - m); domain 2, sub = p gives the normal pair
- * feeding dimensions 2p and 2p+1. */
+ * Channel use n (g = offset + n, key = (seed_lo, seed_hi)) reads one stream of words:
+ * block j of the stream is the Philox output of counter (g_lo, g_hi, j, 1), and word
+ * 4j + i is its output word i.  Word 0 gives u_n = word >> (32 - m); pair p takes words
+ * 2p + 1 (radius) and 2p + 2 (angle) and feeds dimensions 2p and 2p + 1. */
 void orc_awgn(const float* X, int M, int D, uint64_t seed, uint64_t offset, int64_t N,
               double sigma, uint32_t* tx, float* y) {
     int m = 0;
     while ((1 << m) < M) ++m;
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     int npairs = (D + 1) / 2;
+    int nwords = 1 + 2 * npairs;
+    int nblocks = (nwords + 3) / 4;
+    uint32_t* words = (uint32_t*)malloc(sizeof(uint32_t) * 4 * (size_t)nblocks);
     for (int64_t n = 0; n < N; ++n) {
         uint64_t g = offset + (uint64_t)n;
-        uint32_t ctr[4] = {(uint32_t)g, (uint32_t)(g >> 32), 0u, 1u};
-        uint32_t r[4];
-        orc_philox4x32_10(ctr, key, r);
-        uint32_t u = r[0] >> (32 - m);
+        for (int j = 0; j < nblocks; ++j) {
+            uint32_t ctr[4] = {(uint32_t)g, (uint32_t)(g >> 32), (uint32_t)j, 1u};
+            orc_philox4x32_10(ctr, key, words + 4 * j);
+        }
+        uint32_t u = words[0] >> (32 - m);
         tx[n] = u;
         for (int p = 0; p < npairs; ++p) {
-            uint32_t c2[4] = {(uint32_t)g, (uint32_t)(g >> 32), (uint32_t)p, 2u};
-            orc_philox4x32_10(c2, key, r);
             float z0, z1;
-            orc_gen_normal_pair(r, &z0, &z1);
+            orc_gen_normal_pair(words[2 * p + 1], words[2 * p + 2], &z0, &z1);
             int d0 = 2 * p, d1 = 2 * p + 1;
             y[n * D + d0] = (float)fma(sigma, (double)z0, (double)X[(int64_t)u * D + d0]);
             if (d1 < D) y[n * D + d1] = (float)fma(sigma, (double)z1, (double)X[(int64_t)u * D + d1]);
         }
     }
+    free(words);
 }
 
 /* ------------------------------------------------------------------------- */

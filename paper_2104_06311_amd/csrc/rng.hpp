@@ -46,28 +46,30 @@ __device__ __forceinline__ Philox4 philox10(uint32_t c0, uint32_t c1, uint32_t c
   return out;
 }
 
-// One normal pair from the four words of (symbol g, pair p, domain 2), in IEEE single
-// precision (correctly rounded +, -, *, /, sqrt and fma; no contraction):
-//   radius: U = f 2^-e, f = 1 + (r0 >> 9) 2^-23, e = 1 + clz(r1) (33 when r1 = 0);
-//     ln U = ln f - k ln 2 with f halved and k = e - 1 when f > sqrt2 (else k = e),
-//     ln f = 2s P(s^2), s = (f - 1)/(f + 1), P = Horner of 1/(2i+1), i = 5..0;
-//     R = sqrt(-2 ln U);
-//   angle: quadrant q = r2 >> 30, T = (r2 >> 7) mod 2^23, t = (2T + 1) 2^-24 of the
+// One normal pair from two Philox words (a radius word and an angle word), in IEEE single
+// precision (correctly rounded +, -, *, /, sqrt, fma and integer-to-float conversion; no
+// contraction):
+//   radius: v = float(a | 1) (round to nearest even), U = v 2^-32 in [2^-32, 1];
+//     v = f 2^E with f in [1, 2) from its bits; k = E - 32, and f halved, k + 1 when
+//     f > sqrt2; ln U = ln f + k ln 2 with ln f = 2s P(s^2), s = (f - 1)/(f + 1),
+//     P = Horner of 1/(2i+1), i = 5..0; R = sqrt(-2 ln U);
+//   angle: quadrant q = b >> 30, T = (b >> 7) mod 2^23, t = (2T + 1) 2^-24 of the
 //     quadrant; sin and cos by Taylor polynomials on [0, pi/4] (t folded at 1/2);
 //   z0 = R cos, z1 = R sin after q quarter turns.
 constexpr float kGenSqrt2 = 0x1.6a09e6p+0f;
-constexpr float kGenLn2Hi = 0x1.62e300p-1f;     // 0.693145751953125: k * hi exact for k < 2^8
+constexpr float kGenLn2Hi = 0x1.62e300p-1f;     // 0.693145751953125: k * hi exact for |k| < 2^8
 constexpr float kGenLn2Lo = 0x1.2fefa2p-17f;    // ln 2 - hi, rounded
 constexpr float kGenPio2 = 0x1.921fb6p+0f;
 
-__device__ __forceinline__ float gen_log_u(uint32_t r0, uint32_t r1) {
+__device__ __forceinline__ float gen_log_u(uint32_t a) {
 #pragma clang fp contract(off)
-  const int e = r1 == 0u ? 33 : 1 + __clz(static_cast<int>(r1));
-  float f = 1.0f + static_cast<float>(r0 >> 9) * 0x1p-23f;      // exact
-  float k = static_cast<float>(e);
+  const float v = static_cast<float>(a | 1u);                     // in [1, 2^32], rounded to nearest even
+  const uint32_t bits = __float_as_uint(v);
+  float f = __uint_as_float((bits & 0x007FFFFFu) | 0x3F800000u);   // mantissa in [1, 2)
+  float k = static_cast<float>(static_cast<int>(bits >> 23) - 127 - 32);
   if (f > kGenSqrt2) {
     f = f * 0.5f;
-    k = k - 1.0f;
+    k = k + 1.0f;
   }
   const float s = (f - 1.0f) / (f + 1.0f);
   const float w = s * s;
@@ -78,7 +80,7 @@ __device__ __forceinline__ float gen_log_u(uint32_t r0, uint32_t r1) {
   P = __builtin_fmaf(P, w, 1.0f / 3.0f);
   P = __builtin_fmaf(P, w, 1.0f);
   const float lnf = (2.0f * s) * P;
-  return __builtin_fmaf(-k, kGenLn2Hi, __builtin_fmaf(-k, kGenLn2Lo, lnf));
+  return __builtin_fmaf(k, kGenLn2Hi, __builtin_fmaf(k, kGenLn2Lo, lnf));
 }
 
 // sin and cos of phi = t pi/2, t = (2T + 1) 2^-24 <= 1/2, by Taylor polynomials in
@@ -105,11 +107,11 @@ __device__ __forceinline__ void gen_sincos_quarter(uint32_t T, float* s_out, flo
   *c_out = C;
 }
 
-__device__ __forceinline__ void gen_normal_pair(const Philox4& r, float* z0, float* z1) {
+__device__ __forceinline__ void gen_normal_pair(uint32_t a, uint32_t b, float* z0, float* z1) {
 #pragma clang fp contract(off)
-  const float R = __builtin_sqrtf(-2.0f * gen_log_u(r.w[0], r.w[1]));
-  const uint32_t q = r.w[2] >> 30;
-  const uint32_t T = (r.w[2] >> 7) & 0x7FFFFFu;
+  const float R = __builtin_sqrtf(-2.0f * gen_log_u(a));
+  const uint32_t q = b >> 30;
+  const uint32_t T = (b >> 7) & 0x7FFFFFu;
   const bool upper = T >= (1u << 22);
   float sq, cq;
   gen_sincos_quarter(upper ? ((1u << 23) - 1u - T) : T, &sq, &cq);
@@ -126,24 +128,43 @@ __device__ __forceinline__ void gen_normal_pair(const Philox4& r, float* z0, flo
   *z1 = R * st;
 }
 
-
-// Channel use n (global index g = offset + n): transmitted index and the D received values.
+// Channel use g (counter words g_lo, g_hi): the Philox blocks (g_lo, g_hi, j, 1), j = 0, 1, ...
+// give one stream of words w_{4j+i} = r_i.  Word w_0 gives the transmitted index
+// u = w_0 >> (32 - m); pair p takes the radius word w_{2p+1} and the angle word w_{2p+2}
+// and gives dimensions 2p and 2p + 1 (the last pair of an odd D uses only its first
+// value).  Each received value is y_d = fl32(x_d + sigma z_d), one double fma.  So 8D
+// takes three blocks and 2D one.
 __device__ __forceinline__ uint32_t channel_symbol(const float* __restrict__ X, int m, int D, uint32_t k0,
                                                    uint32_t k1, uint64_t g, double sigma, float* yout) {
 #pragma clang fp contract(off)
   const uint32_t glo = static_cast<uint32_t>(g), ghi = static_cast<uint32_t>(g >> 32);
-  const Philox4 rt = philox10(glo, ghi, 0u, 1u, k0, k1);
-  const uint32_t u = rt.w[0] >> (32 - m);
-  const float* xu = X + static_cast<int64_t>(u) * D;
   const int npairs = (D + 1) >> 1;
-  for (int p = 0; p < npairs; ++p) {
-    const Philox4 r = philox10(glo, ghi, static_cast<uint32_t>(p), 2u, k0, k1);
-    float z0, z1;
-    gen_normal_pair(r, &z0, &z1);
-    const int d0 = 2 * p;
-    yout[d0] = static_cast<float>(__builtin_fma(sigma, static_cast<double>(z0), static_cast<double>(xu[d0])));
-    if (d0 + 1 < D)
-      yout[d0 + 1] = static_cast<float>(__builtin_fma(sigma, static_cast<double>(z1), static_cast<double>(xu[d0 + 1])));
+  uint32_t u = 0, radius = 0;
+  const float* xu = X;
+  int p = 0;
+  for (uint32_t j = 0; p < npairs; ++j) {
+    const Philox4 r = philox10(glo, ghi, j, 1u, k0, k1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if ((i & 1) != 0) {            // odd word: the radius word of the next pair
+        radius = r.w[i];
+        continue;
+      }
+      if (j == 0 && i == 0) {        // word 0: the transmitted index
+        u = r.w[0] >> (32 - m);
+        xu = X + static_cast<int64_t>(u) * D;
+        continue;
+      }
+      if (p >= npairs) break;
+      float z0, z1;
+      gen_normal_pair(radius, r.w[i], &z0, &z1);
+      const int d0 = 2 * p;
+      yout[d0] = static_cast<float>(__builtin_fma(sigma, static_cast<double>(z0), static_cast<double>(xu[d0])));
+      if (d0 + 1 < D)
+        yout[d0 + 1] =
+            static_cast<float>(__builtin_fma(sigma, static_cast<double>(z1), static_cast<double>(xu[d0 + 1])));
+      ++p;
+    }
   }
   return u;
 }

@@ -11,7 +11,7 @@
 // together.  For every item a block draws
 // the channel uses itself (the awgn_sample definition at offset = noise index * N), forms
 // the scores and subset sums with the same tile loop as llr_exact, and adds the item's
-// GMI loss sum_n sum_k log2(1 + S_other / S_sent) to a per-item FP64 slot -- LLRs and
+// GMI loss sum_n sum_k log2(S_all / S_sent) to a per-item FP64 slot -- LLRs and
 // received symbols never touch HBM.  Symbols whose subset sums leave FP32 range are
 // queued with their received vector and label and re-evaluated in FP64 by a second kernel,
 // which adds its losses as 2^-40 fixed-point integers (order independent).  A final kernel
@@ -208,12 +208,14 @@ __device__ void process_item(const Problem& P, const Item& I, int it, uint4* lds
             smax = fmaxf(smax, fmaxf(S0[b], S1[b]));
           }
         if (smin >= 0x1p-96f && smax <= 0x1p+126f) {
+          // S0 + S1 is the sum over all points for every bit: one logarithm serves all
+          const float l2tot = fastk::log2_normal(S0[0] + S1[0]);
           float T = 0.0f;
 #pragma unroll
           for (int b = 0; b < MB; ++b)
             if (b < m) {
               const float sent = ((lab >> b) & 1u) ? S1[b] : S0[b];
-              T += fastk::log2_normal(S0[b] + S1[b]) - fastk::log2_normal(sent);
+              T += l2tot - fastk::log2_normal(sent);
             }
           acc_loss += T;
         } else {

@@ -83,6 +83,21 @@ def test_awgn_bit_exact_against_cpu_twin(M, D, seed, offset, N):
     assert np.array_equal(yd.cpu().numpy().view(np.uint32), y_ref.view(np.uint32))
 
 
+@pytest.mark.parametrize("D,N", [(3, 1000), (8, 130), (5, 64)])
+def test_awgn_into_unaligned_output(D, N):
+    """y starting one float into its buffer (not 16-byte aligned): the kernel's 4-byte store
+    path, bit-exact like the aligned one; the float after y stays untouched."""
+    X, _ = synth.gaussian_constellation(64, D, 40 + D)
+    buf = torch.full((N * D + 2,), -7.0, dtype=torch.float32, device="cuda")
+    y = buf[1:1 + N * D].view(N, D)
+    txd, yd = md().awgn_sample(to_dev(X), 11, 5, N, 0.3, y=y)
+    tx_ref, y_ref = oracle.awgn(X, 11, 5, N, 0.3)
+    assert np.array_equal(txd.cpu().numpy().astype(np.uint32), tx_ref)
+    assert np.array_equal(yd.cpu().numpy().view(np.uint32), y_ref.view(np.uint32))
+    b = buf.cpu().numpy()
+    assert b[0] == -7.0 and b[-1] == -7.0
+
+
 def test_awgn_window_consistency():
     X, _ = synth.gaussian_constellation(256, 4, 3)
     Xd = to_dev(X)
@@ -107,7 +122,13 @@ def _parity(X, labels, snr_db, N, seed, maxlog=False, prec="fp32"):
     g, gb, se = md().gmi_reduce(L, tx, ld)
     g_ref, gb_ref, se_ref = oracle.gmi(ref, txh, labels)
     g = float(g.item())
-    assert abs(g - g_ref) <= 1e-4, (g, g_ref)
+    if prec == "fp32":
+        assert abs(g - g_ref) <= 1e-4, (g, g_ref)
+    else:
+        # a reduced-precision variant is held to its LLR bound above; softplus is
+        # 1-Lipschitz, so the GMI (bits) moves by at most the mean of sum_k |dL_nk| / ln 2
+        bound = float(np.mean(np.abs(Lh.astype(np.float64) - ref).sum(axis=1))) / math.log(2.0)
+        assert abs(g - g_ref) <= bound + 1e-6, (g, g_ref, bound)
     # the reduction alone: GPU gmi_reduce vs FP64 GMI of the very same float32 LLRs
     g_same, gb_same, se_same = oracle.gmi(Lh.astype(np.float64), txh, labels)
     assert abs(g - g_same) <= 1e-6 * max(1.0, abs(g_same))

@@ -324,28 +324,66 @@ def test_philox_known_answers():
         assert list(oracle.philox4x32_10(ctr, key)) == out
 
 
+def _round_to_float32(v: int) -> float:
+    """Positive integer v rounded to 24 significant bits, ties to even (exact integer
+    arithmetic, independent of any float conversion)."""
+    shift = max(v.bit_length() - 24, 0)
+    q, r = divmod(v, 1 << shift)
+    half = 1 << shift >> 1
+    if shift and (r > half or (r == half and q & 1)):
+        q += 1
+    return float(q << shift)
+
+
 def test_box_muller_transform_against_libm():
     """The twin's FP32 normal pair against libm in FP64 on the same words: radius
-    sqrt(-2 ln U1) and angle 2 pi U2 with U1 = f 2^-e (f = 1 + (w0 >> 9) 2^-23,
-    e = 1 + clz(w1)) and U2 = (q + (2T + 1) 2^-24) / 4 (q = w2 >> 30, T = (w2 >> 7) mod
-    2^23).  FP32 bounds: a few units of 2^-24 relative; a wrong series coefficient or
-    constant moves them by 1e-4 or more."""
+    sqrt(-2 ln U1) with U1 = round24(a | 1) 2^-32 (a the radius word), angle 2 pi U2 with
+    U2 = (q + (2T + 1) 2^-24) / 4 (q = b >> 30, T = (b >> 7) mod 2^23, b the angle word).
+    FP32 bounds: a few units of 2^-24 relative; a wrong series coefficient, constant or
+    exponent offset moves them by 1e-4 or more."""
     rng = np.random.default_rng(21)
-    words = rng.integers(0, 2 ** 32, size=(3000, 4), dtype=np.uint64).astype(np.uint32)
-    words[:4, 1] = [0, 1, 2 ** 31, 2 ** 32 - 1]       # the shortest and longest radii
-    words[4:8, 2] = [0, 2 ** 30 - 1, 2 ** 30, 2 ** 32 - 1]   # quadrant edges
-    for w in words:
-        z0, z1 = oracle.box_muller(w)
-        e = 33 if int(w[1]) == 0 else 1 + (32 - int(w[1]).bit_length())
-        U1 = (1.0 + (int(w[0]) >> 9) * 2.0 ** -23) * 2.0 ** -e
-        q, T = int(w[2]) >> 30, (int(w[2]) >> 7) & 0x7FFFFF
+    words = rng.integers(0, 2 ** 32, size=(3000, 2), dtype=np.uint64).astype(np.uint32)
+    # the longest radius, a radius word rounding up to U1 = 1, binade and sqrt2 edges
+    words[:8, 0] = [0, 1, 2 ** 32 - 1, 2 ** 32 - 200, 2 ** 31, 2 ** 31 - 1, 0xB504F300, 0xB504F400]
+    words[8:12, 1] = [0, 2 ** 30 - 1, 2 ** 30, 2 ** 32 - 1]   # quadrant edges
+    for a, b in words:
+        z0, z1 = oracle.box_muller([a, b])
+        U1 = _round_to_float32(int(a) | 1) * 2.0 ** -32
+        q, T = int(b) >> 30, (int(b) >> 7) & 0x7FFFFF
         U2 = (q + (2 * T + 1) * 2.0 ** -24) / 4.0
         R = math.sqrt(-2.0 * math.log(U1))
-        assert abs(math.hypot(z0, z1) - R) <= 1e-6 * max(R, 1.0), (w, R, math.hypot(z0, z1))
+        assert abs(math.hypot(z0, z1) - R) <= 1e-6 * max(R, 1.0), (a, b, R, math.hypot(z0, z1))
+        if R == 0.0:
+            assert z0 == 0.0 and z1 == 0.0
+            continue
         ang = math.atan2(z1, z0) % (2 * math.pi)
         diff = abs(ang - 2 * math.pi * U2)
         diff = min(diff, 2 * math.pi - diff)
-        assert diff <= 1e-6, (w, diff)
+        assert diff <= 1e-6, (a, b, diff)
+    # U1 = 2^-32 gives the largest radius, sqrt(64 ln 2)
+    assert abs(math.hypot(*oracle.box_muller([0, 12345])) - math.sqrt(64 * math.log(2))) < 1e-5
+
+
+def test_awgn_word_stream_layout():
+    """The channel's use of the Philox stream, checked through the KAT-pinned Philox and
+    the libm-pinned pair: block j of channel use g is counter (g_lo, g_hi, j, 1); word 0
+    gives the index, words 2p + 1 and 2p + 2 the pair p (dimensions 2p, 2p + 1); the
+    received value is fl32(x + sigma z) in one double fma (checked to one FP32 ulp)."""
+    X, _ = synth.gaussian_constellation(64, 7, 3)
+    seed, offset, N, sigma = (5 << 32) | 99, (1 << 32) - 3, 6, 0.7
+    tx, y = oracle.awgn(X, seed, offset, N, sigma)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for n in range(N):
+        g = offset + n
+        words = np.concatenate([oracle.philox4x32_10([g & 0xFFFFFFFF, g >> 32, j, 1], key) for j in range(3)])
+        assert tx[n] == int(words[0]) >> (32 - 6)
+        for p in range(4):
+            z = oracle.box_muller([words[2 * p + 1], words[2 * p + 2]])
+            for h in range(2):
+                d = 2 * p + h
+                if d < 7:
+                    want = float(X[tx[n], d]) + sigma * z[h]
+                    assert abs(float(y[n, d]) - want) <= 2.0 ** -23 * max(abs(want), 1e-30), (n, d)
 
 
 def test_awgn_twin_statistics_and_offsets():
