@@ -300,8 +300,12 @@ int mlp_load(const char* path, void** out);
  * storing received symbols or LLRs.  The GMI equals gmi_reduce(llr_exact(...)) of the
  * same channel draw up to FP32 rounding.  Every class has its own launch shape
  * (wavefronts per block, 32-symbol blocks per wavefront, symbol groups per work item):
- * 0 (8, 2, 1), 1 (8, 2, 4), 2 (16, 1, 1), 3 (16, 1, 4).  variant 0..3 fixes one shape for
- * all classes; variant = -1 autotunes: the plan is run once under each shape with its
+ * 0 (8, 2, 1), 1 (8, 2, 4), 2 (16, 1, 1), 3 (16, 1, 4) for the matrix-core kernel, and
+ * for classes with M <= 64 also 4, a vector kernel with one thread per symbol (squared
+ * distances from differences; each wavefront claims work items of 512 symbols; reported
+ * as (4, 1, 4)).  variant 0..3 fixes one shape for all classes, variant 4 gives the classes
+ * with M <= 64 the vector kernel and the others shape 0; variant = -1 autotunes: the plan
+ * is run once under each shape with its
  * class kernels timed by events, and each class keeps the shape its kernel ran fastest
  * under; the choices are cached per (device, K steps, label bits) for the process, so a
  * later plan whose classes are all known is built without measuring (sweep_tuning_clear
@@ -322,7 +326,7 @@ int sweep_plan_create(const md_sweep_instance* inst, int n_inst, const double* s
                       void** out);
 /* The launch shape of the plan's first (most expensive) class and the number of work items. */
 int sweep_plan_info(const void* plan, int* waves, int* blocks_per_wave, int* groups_per_item, int* n_items);
-/* Class i of the plan (0 = most expensive): K steps, label bits, launch shape (0..3), work
+/* Class i of the plan (0 = most expensive): K steps, label bits, launch shape (0..4), work
  * items, and the kernel time the autotuner measured for the class under that shape (ms;
  * -1 when this plan measured nothing: fixed variant or cached choice); any output may be
  * NULL.  MD_EINVAL when i is not a class index (classes are numbered from 0). */

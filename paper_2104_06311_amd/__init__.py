@@ -542,7 +542,7 @@ class SweepPlan:
         return out
 
     def classes(self, with_times: bool = False):
-        """[(K steps, label bits, launch shape 0..3, work items)] of the plan's classes, plus
+        """[(K steps, label bits, launch shape 0..4, work items)] of the plan's classes, plus
         the autotuner's measured class time in ms (-1 if none) when with_times."""
         import ctypes
         out = []

@@ -276,6 +276,124 @@ __global__ void __launch_bounds__(WAVES * 64) sweep_kernel(const Problem* __rest
   }
 }
 
+// ------------------------------------------------------------------ small constellations
+// For M <= 64 the matrix-core path spends most of its time around the tile loop (operand
+// staging, subset combine, and for M = 16 half of every 32-point tile is padding).  The
+// vector path gives each thread whole symbols: the channel draw, all M squared distances
+// ||y - x_j||^2 from differences (the constellation's label-order copy is read at uniform
+// addresses, so through the scalar cache), one exponential per point with the same fixed
+// bias as the tile loop, e_j = 2^(kExpBias - c ||y - x_j||^2), and the 2m subset sums by
+// one pass per label bit over block sums (about 2.3 adds per point).  Range check, FP64
+// fallback queue and loss term are those of the matrix-core kernel.
+constexpr int kSmallThreads = 256;
+
+template <int MB, int D>
+__device__ __forceinline__ float small_item(const Problem& P, const Item& I, int lane, int* __restrict__ counters,
+                                            FbRecord* __restrict__ fb) {
+  constexpr int M = 1 << MB;
+  const float cexp = static_cast<float>(static_cast<double>(P.cn) * static_cast<double>(P.alpha));
+  // the label-order points, read-only during the kernel and at uniform addresses: through the
+  // constant address space, so that they arrive by scalar loads into scalar registers
+  typedef const __attribute__((address_space(4))) float ConstFloat;
+  ConstFloat* xl = (ConstFloat*)P.xl;
+  float acc = 0.0f;
+  for (int local = lane; local < I.count; local += 64) {
+    const uint64_t g = P.offset + static_cast<uint64_t>(I.start + local);
+    float yv[8];
+#pragma unroll
+    for (int d = 0; d < 8; ++d) yv[d] = 0.0f;
+    const uint32_t u = rng::channel_symbol(P.X, MB, D, P.k0, P.k1, g, P.sigma, yv);
+    const uint32_t lab = P.labels[u];
+    float v[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      float d2 = 0.0f;
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const float df = yv[d] - xl[j * D + d];
+        d2 = fmaf(df, df, d2);
+      }
+      v[j] = __builtin_amdgcn_exp2f(fmaf(-cexp, d2, fastk::kExpBias));
+    }
+    // level b: v[k] is the sum over the 2^b consecutive labels of block k, so bit b of a
+    // label is the parity of its block index
+    float S0[MB], S1[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      const int n = M >> b;
+      float a0 = v[0], a1 = v[1];
+#pragma unroll
+      for (int k = 2; k < n; k += 2) {
+        a0 += v[k];
+        a1 += v[k + 1];
+      }
+      S0[b] = a0;
+      S1[b] = a1;
+#pragma unroll
+      for (int k = 0; k < n / 2; ++k) v[k] = v[2 * k] + v[2 * k + 1];
+    }
+    float smin = INFINITY, smax = 0.0f;
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      smin = fminf(smin, fminf(S0[b], S1[b]));
+      smax = fmaxf(smax, fmaxf(S0[b], S1[b]));
+    }
+    if (smin >= 0x1p-96f && smax <= 0x1p+126f) {
+      const float l2tot = fastk::log2_normal(S0[0] + S1[0]);
+      float T = 0.0f;
+#pragma unroll
+      for (int b = 0; b < MB; ++b) T += l2tot - fastk::log2_normal(((lab >> b) & 1u) ? S1[b] : S0[b]);
+      acc += T;
+    } else {
+      const int idx = atomicAdd(&counters[1], 1);
+      if (idx < kFbCap) {
+        FbRecord& r = fb[idx];
+        r.prob = I.prob;
+        r.label = lab;
+#pragma unroll
+        for (int d = 0; d < 8; ++d) r.y[d] = yv[d];
+      } else {
+        atomicOr(&counters[2], 1);
+      }
+    }
+  }
+  return acc;
+}
+
+// Every wavefront claims work items on its own: no LDS, no block barriers, and no branch
+// on the lane index around the claim (all lanes take part in one atomic that only lane 0
+// increments, and all lanes store the item's sum).
+template <int MB>
+__global__ void __launch_bounds__(kSmallThreads) sweep_small_kernel(const Problem* __restrict__ probs,
+                                                                    const Item* __restrict__ items, int item_begin,
+                                                                    int item_end, int* __restrict__ claim,
+                                                                    int* __restrict__ counters,
+                                                                    double* __restrict__ item_sum,
+                                                                    FbRecord* __restrict__ fb) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    const int c = atomicAdd(claim, lane == 0 ? 1 : 0);
+    const int it = item_begin + __builtin_amdgcn_readfirstlane(c);
+    if (it >= item_end) break;
+    const Item I = items[it];
+    const Problem P = probs[I.prob];
+    float acc = 0.0f;
+    switch (P.D) {
+      case 1: acc = small_item<MB, 1>(P, I, lane, counters, fb); break;
+      case 2: acc = small_item<MB, 2>(P, I, lane, counters, fb); break;
+      case 3: acc = small_item<MB, 3>(P, I, lane, counters, fb); break;
+      case 4: acc = small_item<MB, 4>(P, I, lane, counters, fb); break;
+      case 5: acc = small_item<MB, 5>(P, I, lane, counters, fb); break;
+      case 6: acc = small_item<MB, 6>(P, I, lane, counters, fb); break;
+      case 7: acc = small_item<MB, 7>(P, I, lane, counters, fb); break;
+      default: acc = small_item<MB, 8>(P, I, lane, counters, fb); break;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    item_sum[it] = static_cast<double>(acc);
+  }
+}
+
 // Re-evaluates queued symbols in FP64 (one wavefront per record): per-subset maxima and
 // log-sum-exp, then the loss sum_k log2(1 + e^{L_other - L_sent}) added to the problem's
 // fixed-point accumulator.
@@ -400,11 +518,19 @@ struct SweepPlan {
 };
 
 // Launch shapes: wavefronts per block, 32-symbol blocks per wavefront, symbol groups per
-// work item.
+// work item.  Shape 4 is the vector kernel of the small classes (M <= 64): blocks of four
+// wavefronts, each claiming work items of 512 symbols on its own.
 struct Shape {
   int waves, sb, gpi;
 };
-constexpr Shape kShapes[4] = {{8, 2, 1}, {8, 2, 4}, {16, 1, 1}, {16, 1, 4}};
+constexpr int kNumShapes = 5;
+constexpr int kValuShape = 4;
+constexpr int kValuMaxBits = 6;
+constexpr Shape kShapes[kNumShapes] = {{8, 2, 1}, {8, 2, 4}, {16, 1, 1}, {16, 1, 4}, {4, 1, 4}};
+
+// The shape a class of label bits m gets under plan variant v: the vector kernel only for
+// small constellations (shape 0 elsewhere).
+inline int class_shape(int v, int m) { return (v == kValuShape && m > kValuMaxBits) ? 0 : v; }
 
 // Autotuner choices, per device and constellation class (K steps, label bits): measured
 // once per process, reused by every later plan with the same classes.
@@ -475,6 +601,31 @@ int launch_class_shape(SweepPlan* p, const SweepPlan::Class& c, int ci, hipStrea
   }
 }
 
+template <int MB>
+int launch_small_class(SweepPlan* p, const SweepPlan::Class& c, int ci, hipStream_t s) {
+  auto kern = sweep_small_kernel<MB>;
+  int ncu = 0, occ = 0;
+  MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device));
+  MD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kern), kSmallThreads,
+                                                           0));
+  if (occ < 1) occ = 1;
+  int64_t grid = static_cast<int64_t>(ncu) * occ;
+  if (grid > c.end - c.begin) grid = c.end - c.begin;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(kSmallThreads), 0, s, p->d_probs, p->d_items,
+                     c.begin, c.end, p->d_counters + kCounterBase + ci, p->d_counters, p->d_item_sum, p->d_fb);
+  MD_LAUNCH_CHECK("sweep_small_kernel launch");
+  return MD_OK;
+}
+
+int launch_small(SweepPlan* p, const SweepPlan::Class& c, int ci, hipStream_t s) {
+  switch (c.m) {
+    case 4: return launch_small_class<4>(p, c, ci, s);
+    case 5: return launch_small_class<5>(p, c, ci, s);
+    case 6: return launch_small_class<6>(p, c, ci, s);
+    default: return fail(MD_EUNSUPPORTED, "no vector sweep kernel for this constellation class");
+  }
+}
+
 // ev: NULL, or two events per class recorded around that class's kernel (autotuning).
 int enqueue(SweepPlan* p, hipStream_t s, const std::vector<hipEvent_t>* ev = nullptr) {
   const int ncounters = kCounterBase + static_cast<int>(p->classes.size());
@@ -484,8 +635,9 @@ int enqueue(SweepPlan* p, hipStream_t s, const std::vector<hipEvent_t>* ev = nul
   for (size_t ci = 0; ci < p->classes.size(); ++ci) {
     const SweepPlan::Class& c = p->classes[ci];
     if (ev) MD_HIP_TRY(hipEventRecord((*ev)[2 * ci], s));
-    const int st = kShapes[c.v].waves == 16 ? launch_class_shape<16, 1>(p, c, static_cast<int>(ci), s)
-                                            : launch_class_shape<8, 2>(p, c, static_cast<int>(ci), s);
+    const int st = c.v == kValuShape            ? launch_small(p, c, static_cast<int>(ci), s)
+                   : kShapes[c.v].waves == 16 ? launch_class_shape<16, 1>(p, c, static_cast<int>(ci), s)
+                                              : launch_class_shape<8, 2>(p, c, static_cast<int>(ci), s);
     if (st != MD_OK) return st;
     if (ev) MD_HIP_TRY(hipEventRecord((*ev)[2 * ci + 1], s));
   }
@@ -532,9 +684,11 @@ int build_items(SweepPlan* p) {
     ct -= ct % 8;
     P.chunk_tiles = std::min(ct, P.ntiles);
     // the tile loop's prefetch reads up to two tiles past a chunk's end (into the staging
-    // rows that follow it), so the staging rows must span at least two tiles
-    const size_t need = static_cast<size_t>(P.chunk_tiles) * P.ks * 64 * 16 +
-                        std::max<size_t>(bstage, static_cast<size_t>(2) * P.ks * 64 * 16);
+    // rows that follow it), so the staging rows must span at least two tiles; the vector
+    // kernel has no dynamic LDS
+    const size_t need = v == kValuShape ? 0
+                                        : static_cast<size_t>(P.chunk_tiles) * P.ks * 64 * 16 +
+                                              std::max<size_t>(bstage, static_cast<size_t>(2) * P.ks * 64 * 16);
     p->classes.back().lds = std::max(p->classes.back().lds, need);
     const int per_item = sh.waves * 32 * sh.sb * sh.gpi;
     P.item_begin = static_cast<int>(items.size());
@@ -597,7 +751,7 @@ int sweep_plan_create(const md_sweep_instance* inst, int n_inst, const double* s
   *out = nullptr;
   if (n_inst < 1 || n_snr < 1 || static_cast<int64_t>(n_inst) * n_snr > (1 << 20))
     return md::fail(MD_EINVAL, "need 1 <= instances x noise levels <= 2^20");
-  if (variant < -1 || variant > 3) return md::fail(MD_EINVAL, "variant outside [-1, 3]");
+  if (variant < -1 || variant > 4) return md::fail(MD_EINVAL, "variant outside [-1, 4]");
   int dev = 0;
   int st = md::current_device(&dev);
   if (st != MD_OK) return st;
@@ -708,13 +862,18 @@ int sweep_plan_create(const md_sweep_instance* inst, int n_inst, const double* s
     }
   }
   if (variant >= 0) {
-    for (const auto& k : keys) p->class_var[k] = variant;
+    for (const auto& k : keys) p->class_var[k] = md::class_shape(variant, k.second);
   } else if (!cached) {
     // run the whole plan once per shape, timing every class's kernel with events, and give
     // each class the shape under which its own kernel was fastest
     std::map<std::pair<int, int>, float> best;
-    for (int v = 0; v < 4; ++v) {
-      for (const auto& k : keys) p->class_var[k] = v;
+    for (int v = 0; v < md::kNumShapes; ++v) {
+      bool any = false;
+      for (const auto& k : keys) {
+        p->class_var[k] = md::class_shape(v, k.second);
+        any |= p->class_var[k] == v;
+      }
+      if (!any) continue;
       if ((st = md::build_items(p))) return bail(st);
       const size_t nc = p->classes.size();
       std::vector<hipEvent_t> ev(2 * nc, nullptr);
@@ -730,6 +889,7 @@ int sweep_plan_create(const md_sweep_instance* inst, int n_inst, const double* s
           break;
         }
         const std::pair<int, int> k{p->classes[ci].ks, p->classes[ci].m};
+        if (p->classes[ci].v != v) continue;        // a class measured under another pass
         const auto b = best.find(k);
         if (b == best.end() || ms < b->second) {
           best[k] = ms;

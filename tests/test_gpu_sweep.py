@@ -56,7 +56,7 @@ def sigma2_grid(host, snrs):
     return np.array([[synth.sigma2_from_snr_db(X, s) for s in snrs] for X, _ in host])
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 def test_sweep_matches_per_instance_path(variant):
     inst, host = make_instances(SPECS)
     s2 = sigma2_grid(host, [2.0, 7.0, 12.0])
@@ -98,7 +98,7 @@ def test_autotuned_plan_and_limits():
     inst, host = make_instances(SPECS[:4], seed=4)
     s2 = sigma2_grid(host, [5.0])
     plan = md().SweepPlan(inst, s2, variant=-1)
-    assert plan.shape in [(8, 2, 1), (8, 2, 4), (16, 1, 1), (16, 1, 4)]
+    assert plan.shape in [(8, 2, 1), (8, 2, 4), (16, 1, 1), (16, 1, 4), (4, 1, 4)]
     ref = per_instance_gmi(inst, s2)
     np.testing.assert_allclose(plan.run().cpu().numpy(), ref, atol=1e-4, rtol=0)
     X, labels = synth.gaussian_constellation(8, 2, 1)
@@ -126,7 +126,7 @@ def test_every_class_of_the_mixed_sweep_against_oracle():
         [(M, D) for M in (16, 64, 256, 1024, 4096) for D in (2, 4, 8)])]
     inst, host = make_instances(specs, seed=21)
     s2 = sigma2_grid(host, [2.0, 7.0, 12.0])
-    for variant in (0, 3):
+    for variant in (0, 3, 4):
         plan = md().SweepPlan(inst, s2, variant=variant)
         g = plan.run().cpu().numpy()
         n_fb, overflow = plan.stats()
@@ -159,6 +159,24 @@ def test_fp64_fallback_at_high_snr_against_oracle():
     plan.close()
 
 
+def test_vector_kernel_fallback_at_high_snr_against_oracle():
+    """The small-constellation vector kernel (shape 4) at 28 and 34 dB: symbols whose
+    other-label subsets leave the FP32 range go to the FP64 fallback, and every GMI still
+    matches the oracle."""
+    inst, host = make_instances([(16, 2, 3000), (64, 4, 2000), (16, 8, 1500), (32, 3, 1200)], seed=44)
+    s2 = sigma2_grid(host, [28.0, 34.0])
+    plan = md().SweepPlan(inst, s2, variant=4)
+    assert all(c[2] == 4 for c in plan.classes())
+    g = plan.run().cpu().numpy()
+    n_fb, overflow = plan.stats()
+    assert n_fb > 0 and not overflow, (n_fb, overflow)
+    for i in range(len(inst)):
+        for s in range(2):
+            gr = oracle_gmi(host, inst, s2, i, s)
+            assert abs(g[i, s] - gr) <= 1e-4, (i, s, g[i, s], gr)
+    plan.close()
+
+
 def test_autotuner_per_class_shapes_and_cache():
     """With variant -1 every class gets its own measured launch shape; a second plan with
     the same classes takes them from the cache; variant 2 fixes one shape for all."""
@@ -168,7 +186,9 @@ def test_autotuner_per_class_shapes_and_cache():
     plan = md().SweepPlan(inst, s2, variant=-1)
     cls = plan.classes()
     assert len(cls) >= 3
-    assert all(0 <= c[2] <= 3 for c in cls)
+    assert all(0 <= c[2] <= 4 for c in cls)
+    # the vector kernel (shape 4) only for classes of at most 6 label bits
+    assert all(c[2] != 4 or c[1] <= 6 for c in cls)
     assert sum(c[3] for c in cls) == plan.n_items
     ref = per_instance_gmi(inst, s2)
     np.testing.assert_allclose(plan.run().cpu().numpy(), ref, atol=1e-4, rtol=0)
@@ -178,5 +198,8 @@ def test_autotuner_per_class_shapes_and_cache():
     fixed = md().SweepPlan(inst, s2, variant=2)
     assert all(c[2] == 2 for c in fixed.classes())
     np.testing.assert_allclose(fixed.run().cpu().numpy(), ref, atol=1e-4, rtol=0)
-    for p in (plan, plan2, fixed):
+    small = md().SweepPlan(inst, s2, variant=4)
+    assert all(c[2] == (4 if c[1] <= 6 else 0) for c in small.classes())
+    np.testing.assert_allclose(small.run().cpu().numpy(), ref, atol=1e-4, rtol=0)
+    for p in (plan, plan2, fixed, small):
         p.close()
