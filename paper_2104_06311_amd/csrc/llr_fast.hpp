@@ -465,6 +465,136 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
   }
 }
 
+// ------------------------------------------------------------------ streamed fragments
+// Constellations whose fragments exceed LDS (the 16D M = 65536 workload: 2048 tiles, 8 MiB
+// at four K steps) stream them through two LDS buffers of C tiles.  Before the tile loop
+// over one buffer the wavefronts issue the direct global-to-LDS loads
+// (global_load_lds_dwordx4, 1 KiB per wavefront instruction) of the next chunk into the
+// other, so that the loads' latency hides behind a whole chunk of work and each chunk costs
+// one barrier instead of a synchronous copy between two.  The buffers are two distinct
+// arrays, used in a fixed alternation (the chunk loop is unrolled by two), so that the
+// compiler can tell the reads of one buffer from the loads into the other and does not make
+// them wait for each other.  Each buffer carries two spare tiles for the tile loop's
+// prefetch past a chunk's end.  After the last chunk of a symbol group the first chunk of
+// the block's next group is already on its way.  Same arithmetic and epilogue as
+// llr_fast_kernel (no fused GMI: that path needs one or two K steps).  Used for max-log.
+constexpr int kStreamTiles = 8;
+
+template <int KS, int WAVES, int MB, int SB, bool MAXLOG>
+__global__ void __launch_bounds__(WAVES * 64) llr_stream_kernel(const uint4* __restrict__ frag, int ntiles,
+                                                                int ctiles, int D,
+                                                                const float* __restrict__ y, int64_t N, float cb,
+                                                                float cn, float alpha, float* __restrict__ llr,
+                                                                int* __restrict__ flags,
+                                                                unsigned* __restrict__ fb_list) {
+  constexpr int C = kStreamTiles;
+  constexpr int FPT = KS * 64;                      // uint4 per tile
+  constexpr int S = 16 * KS;                        // K slots per symbol
+  __shared__ uint4 bufA[(C + 2) * FPT];
+  __shared__ uint4 bufB[(C + 2) * FPT];
+  __shared__ _Float16 stage[WAVES * SB * 32 * S];
+  constexpr int m = MB;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const bool invalid = flags[0] != 0;
+  const bool range_bad = flags[2] != 0;
+  const int64_t per_group = static_cast<int64_t>(WAVES) * 32 * SB;
+  const int64_t ngroups = (N + per_group - 1) / per_group;
+  const int nchunks = ntiles / C;                   // even (checked by the launcher)
+  _Float16* bst = stage + wave * SB * 32 * S;
+  // wavefront w loads the 1 KiB blocks w, w + WAVES, ... of a chunk's C KS blocks: a
+  // wave-uniform base (scalar registers) plus the lane's 16 bytes, so that the loads need
+  // no address registers of their own
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  auto issue = [&](int c, uint4* dst) {
+    const uint4* src = frag + static_cast<int64_t>(c) * (C * FPT) + wave_u * 64;
+    uint4* d = dst + wave_u * 64;
+#pragma unroll
+    for (int k = 0; k < (C * KS + WAVES - 1) / WAVES; ++k)
+      if (wave_u + k * WAVES < C * KS)
+        __builtin_amdgcn_global_load_lds(src + k * WAVES * 64 + lane, d + k * WAVES * 64, 16, 0, 0);
+  };
+  if (static_cast<int64_t>(blockIdx.x) < ngroups) {
+    issue(0, bufA);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const bool next_group = g + gridDim.x < ngroups;
+    half8 bf[SB][KS];
+    SymAcc<MB> ac[SB];
+    bool bad[SB];
+    int64_t nsym[SB];
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const int64_t n = g * per_group + (static_cast<int64_t>(wave) * SB + sb) * 32 + (lane & 31);
+      nsym[sb] = n;
+      const bool b = build_symbol_operand<KS, 0>(bst + (sb * 32 + (lane & 31)) * S, y, n, n < N, D, cb, cn, alpha,
+                                                 MAXLOG ? 0.0f : kExpBias, bf[sb]);
+      bad[sb] = b || range_bad;
+    }
+    acc_init<MB, SB, MAXLOG>(ac);
+    for (int c = 0; c < nchunks; c += 2) {
+      // bufA holds chunk c; chunk c + 1 goes to bufB meanwhile
+      issue(c + 1, bufB);
+      // ctiles = C, passed at run time: a compile-time trip count lets the compiler unroll
+      // the whole chunk and hoist every tile's products, which spills
+      tile_loop<KS, MB, SB, MAXLOG, 0>(bufA, c * C, ctiles, lane, bf, ac);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      // bufB holds chunk c + 1; chunk c + 2 (or the next group's first) goes to bufA
+      if (c + 2 < nchunks || next_group) issue(c + 2 < nchunks ? c + 2 : 0, bufA);
+      tile_loop<KS, MB, SB, MAXLOG, 0>(bufB, (c + 1) * C, ctiles, lane, bf, ac);
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int sb = 0; sb < SB; ++sb) {
+      const int64_t n = nsym[sb];
+      float S0[MB], S1[MB];
+      combine_subsets<MB, MAXLOG>(ac[sb], false, S0, S1);
+      const bool badp = __shfl_xor(static_cast<int>(bad[sb]), 32, 64) != 0;
+      if (h == 0 && n < N) {
+        if (invalid) {
+          for (int k = 0; k < m; ++k) llr[n * m + k] = __builtin_nanf("");
+        } else if (bad[sb] || badp || (!MAXLOG && !sums_in_range<MB>(S0, S1))) {
+          const int idx = atomicAdd(&flags[1], 1);
+          fb_list[idx] = static_cast<unsigned>(n);
+        } else {
+#pragma unroll
+          for (int k = 0; k < m; ++k) {
+            const int b = m - 1 - k;
+            llr[n * m + k] = MAXLOG ? kLn2 * (S0[b] - S1[b]) : kLn2 * (log2_normal(S0[b]) - log2_normal(S1[b]));
+          }
+        }
+      }
+    }
+  }
+}
+
+template <int KS, int WAVES, int MB, int SB, bool MAXLOG>
+int launch_stream_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr, hipStream_t stream) {
+  const int ntiles = M / 32;
+  auto kern = llr_stream_kernel<KS, WAVES, MB, SB, MAXLOG>;
+  int dev = 0, ncu = 0, occ = 0;
+  MD_HIP_TRY(hipGetDevice(&dev));
+  MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  MD_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(kern), WAVES * 64, 0));
+  if (occ < 1) occ = 1;
+  const int64_t per_group = static_cast<int64_t>(WAVES) * 32 * SB;
+  const int64_t ngroups = (N + per_group - 1) / per_group;
+  int64_t grid = static_cast<int64_t>(ncu) * occ;
+  if (grid > ngroups) grid = ngroups;
+  const double c = P.c_over_alpha * static_cast<double>(P.alpha);
+  const float cb = static_cast<float>(2.0 * c / P.alpha);
+  const float cn = P.c_over_alpha;
+  hipLaunchKernelGGL(kern, dim3(static_cast<unsigned>(grid)), dim3(WAVES * 64), 0, stream, P.frag, ntiles,
+                     kStreamTiles, D, d_y, N, cb, cn, P.alpha, d_llr, P.flags, P.fb_list);
+  MD_LAUNCH_CHECK("llr_stream_kernel launch");
+  return MD_OK;
+}
+
 template <int KS, int WAVES, int MB, int SB, bool MAXLOG, int SC = 0, bool GMI = false>
 int launch_fast_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
                   hipStream_t stream) {
@@ -478,6 +608,14 @@ int launch_fast_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
   if (chunk_tiles > ntiles) chunk_tiles = ntiles;
   if (chunk_tiles < G) return fail(MD_EUNSUPPORTED, "constellation fragments do not fit in LDS");
   const size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
+  if constexpr (KS == 4 && WAVES == 16 && SB == 1 && SC == 0 && !GMI && MAXLOG && MB >= 10) {
+    // max-log with fragments beyond LDS: stream them through two buffers (an even number of
+    // chunks) with twelve wavefronts per block.  The exact path keeps the synchronous
+    // chunks: its tile loop needs all 128 registers of four wavefronts per SIMD, and the
+    // three of the streamed kernel cost it more than the hidden copies gain
+    if (chunk_tiles < ntiles && ntiles % (2 * kStreamTiles) == 0)
+      return launch_stream_t<KS, 12, MB, SB, MAXLOG>(P, M, D, d_y, N, d_llr, stream);
+  }
   auto kern = llr_fast_kernel<KS, WAVES, MB, SB, MAXLOG, SC, GMI>;
   {
     const int st_attr = set_lds_limit(reinterpret_cast<const void*>(kern), 160 * 1024);

@@ -66,3 +66,29 @@ def test_16d_65536_exact_and_maxlog(constellation, snr_db):
     check_close(Lm[:N_ORACLE].cpu().numpy(), oracle.llr_maxlog(X, labels, yh, s2), f"max-log {snr_db} dB")
     g_sub = md().gmi_reduce(L[:N_ORACLE].contiguous(), tx[:N_ORACLE].contiguous(), ld)[0].item()
     assert abs(g_sub - oracle.gmi(ref, txh, labels)[0]) <= 1e-4
+    # rows that blocks reach after their first symbol group (fragments streamed across
+    # groups), and the ragged end of the draw
+    for a in (500_000, N_FULL - 200):
+        yh = y[a:a + 200].cpu().numpy()
+        check_close(L[a:a + 200].cpu().numpy(), oracle.llr_exact(X, labels, yh, s2), f"exact {snr_db} dB rows {a}+")
+        check_close(Lm[a:a + 200].cpu().numpy(), oracle.llr_maxlog(X, labels, yh, s2), f"max-log {snr_db} dB rows {a}+")
+
+
+@pytest.mark.parametrize("maxlog", [False, True])
+def test_streamed_fragments_against_oracle(maxlog):
+    """M = 1024, D = 16: four K steps, 128 KiB of fragments, more than LDS holds next to the
+    symbol staging: max-log streams them through two LDS buffers in four chunks, the exact
+    path copies them chunk by chunk.  N = 110,000 symbols: every block also takes a later
+    symbol group (for max-log its first chunk is loaded during the previous group's last
+    one).  Every row against the oracle."""
+    X, labels = synth.gaussian_constellation(1024, 16, 77)
+    labels = synth.random_labels(1024, 16)
+    Xd, ld = torch.from_numpy(X).cuda(), torch.from_numpy(labels.astype(np.int32)).cuda()
+    s2 = synth.sigma2_from_snr_db(X, 11.0)
+    N = 110_000
+    print(f"M=1024 D=16 N={N} maxlog={maxlog}", flush=True)
+    tx, y = md().awgn_sample(Xd, 91, 0, N, math.sqrt(s2))
+    L = (md().llr_maxlog if maxlog else md().llr_exact)(Xd, ld, y, s2).cpu().numpy()
+    yh = y.cpu().numpy()
+    ref = (oracle.llr_maxlog if maxlog else oracle.llr_exact)(X, labels, yh, s2)
+    check_close(L, ref, f"M=1024 D=16 {'max-log' if maxlog else 'exact'}")
