@@ -117,22 +117,36 @@ __global__ void __launch_bounds__(kBlock) gmi_terms_partial_kernel(const float* 
   Kahan sT{0.f, 0.f}, sT2{0.f, 0.f};
   int nonfinite = 0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  for (int64_t n = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; n < N; n += stride) {
-    float T = terms[n];
-    if (isnan(T)) {
-      const uint32_t u = tx[n];
-      const bool ok = u < (1u << MB);
-      const uint32_t lab = labels[ok ? u : 0u];
-      T = ok ? 0.0f : __builtin_nanf("");
+  // four coalesced loads in flight per thread before any of them is used: the pass reads
+  // 4 bytes per symbol, so it is bound by load latency, not by bandwidth, one at a time
+  constexpr int U = 4;
+  for (int64_t n0 = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; n0 < N; n0 += U * stride) {
+    float Tu[U];
 #pragma unroll
-      for (int k = 0; k < MB; ++k) {
-        const float s = ((lab >> (MB - 1 - k)) & 1u) ? 1.0f : -1.0f;
-        T += softplus_bits(s * llr[n * MB + k]);
-      }
+    for (int j = 0; j < U; ++j) {
+      const int64_t n = n0 + j * stride;
+      Tu[j] = n < N ? terms[n] : 0.0f;
     }
-    nonfinite += !isfinite(T);
-    sT.add(T);
-    sT2.add(T * T);
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int64_t n = n0 + j * stride;
+      if (n >= N) break;
+      float T = Tu[j];
+      if (isnan(T)) {
+        const uint32_t u = tx[n];
+        const bool ok = u < (1u << MB);
+        const uint32_t lab = labels[ok ? u : 0u];
+        T = ok ? 0.0f : __builtin_nanf("");
+#pragma unroll
+        for (int k = 0; k < MB; ++k) {
+          const float s = ((lab >> (MB - 1 - k)) & 1u) ? 1.0f : -1.0f;
+          T += softplus_bits(s * llr[n * MB + k]);
+        }
+      }
+      nonfinite += !isfinite(T);
+      sT.add(T);
+      sT2.add(T * T);
+    }
   }
   const int64_t nb = gridDim.x;
   double v = block_sum(sT.get(), sh);

@@ -154,6 +154,40 @@ __device__ __forceinline__ void acc_init(SymAcc<MB> (&ac)[SB]) {
   }
 }
 
+// Copies `total` uint4 of fragments from global memory to LDS with all NT threads of the
+// block, four loads in flight per thread before the first store (named registers, not an
+// array, which the compiler would place in scratch): a plain copy loop waits for each
+// load before its store, one memory latency per uint4.
+template <int NT>
+__device__ __forceinline__ void stage_chunk(uint4* __restrict__ dst, const uint4* __restrict__ src, int total) {
+  for (int i0 = static_cast<int>(threadIdx.x); i0 < total; i0 += 4 * NT) {
+    const int i1 = i0 + NT, i2 = i0 + 2 * NT, i3 = i0 + 3 * NT;
+    const uint4 a0 = src[i0];
+    uint4 a1, a2, a3;
+    if (i1 < total) a1 = src[i1];
+    if (i2 < total) a2 = src[i2];
+    if (i3 < total) a3 = src[i3];
+    dst[i0] = a0;
+    if (i1 < total) dst[i1] = a1;
+    if (i2 < total) dst[i2] = a2;
+    if (i3 < total) dst[i3] = a3;
+  }
+}
+
+// Stages one fragment chunk: a constellation whose fragments all fit in LDS beside the NB
+// staging bytes is copied once per block by the plain loop; larger ones are re-copied for
+// every symbol group, with the batched loads of stage_chunk.  The choice is made at compile
+// time, so that the resident kernels keep their register allocation.
+template <int KS, int MB, int NT, int NB>
+__device__ __forceinline__ void copy_chunk(uint4* __restrict__ dst, const uint4* __restrict__ src, int total) {
+  constexpr bool kResident = (MB >= 5) && ((1 << MB) / 32) * KS * 1024 + NB <= 160 * 1024;
+  if constexpr (kResident) {
+    for (int i = threadIdx.x; i < total; i += NT) dst[i] = src[i];
+  } else {
+    stage_chunk<NT>(dst, src, total);
+  }
+}
+
 // Accumulates the tiles [t0, t0 + tn) of one LDS-resident chunk (tile t of the chunk is at
 // lds[t * KS * 64 ...]; tn is a multiple of G) into the SB symbol blocks' partial sums.
 template <int KS, int MB, int SB, bool MAXLOG, int SC = 0>
@@ -418,7 +452,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
         __syncthreads();
         const int total = tn * frag_per_tile;
         const uint4* src = frag + static_cast<int64_t>(t0) * frag_per_tile;
-        for (int i = threadIdx.x; i < total; i += WAVES * 64) lds[i] = src[i];
+        copy_chunk<KS, MB, WAVES * 64, WAVES * SB * bstage_bytes<KS>()>(lds, src, total);
         __syncthreads();
         staged = true;
       }
@@ -714,7 +748,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_wide_kernel(const uint4* __res
         __syncthreads();
         const int total = tn * frag_per_tile;
         const uint4* src = frag + static_cast<int64_t>(t0) * frag_per_tile;
-        for (int i = threadIdx.x; i < total; i += WAVES * 64) lds[i] = src[i];
+        copy_chunk<KS, MB, WAVES * 64, WAVES * NW * bstage_bytes<KS>()>(lds, src, total);
         __syncthreads();
         staged = true;
       }
@@ -1010,7 +1044,7 @@ __global__ void __launch_bounds__(WAVES * 64) llr_bf16_kernel(const uint4* __res
         __syncthreads();
         const int total = tn * frag_per_tile;
         const uint4* src = frag + static_cast<int64_t>(t0) * frag_per_tile;
-        for (int i = threadIdx.x; i < total; i += WAVES * 64) lds[i] = src[i];
+        copy_chunk<KS, MB, WAVES * 64, WAVES * SB * bstage_bytes<KS>()>(lds, src, total);
         __syncthreads();
         staged = true;
       }
