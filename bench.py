@@ -3,9 +3,11 @@
 Workload (the metric's configuration): 8D constellation with M = 2048 Gaussian
 points (unit energy per 2D, binary-index labels), N = 1e7 received symbols per SNR
 point, 11 SNR points 4..14 dB.  One step is one pass of the whole path over that
-sweep: for every SNR point awgn_sample (channel draw into resident HBM buffers),
-llr_exact (label-order prep + fused score/exp/subset-sum kernel + fallback) and
-gmi_reduce.  value = 11 * N received symbols per step / step time.
+sweep: for every SNR point awgn_sample (channel draw into resident HBM buffers) and
+llr_exact_gmi (label-order prep, the fused score/exp/subset-sum kernel that writes the
+LLRs and each symbol's GMI loss term, the wide-range and FP64 fallback passes, the
+deterministic loss-term reduction); --unfused runs llr_exact then gmi_reduce instead.
+value = 11 * N received symbols per step / step time.
 
 Prints one JSON line.  Extra objects:
   roofline      the dominant kernel (the fast pass of llr_exact) against the
@@ -494,6 +496,41 @@ def extra_rx(md, seconds):
                      "q_db_min": min(q) if q else None, "q_db_mean": float(np.mean(q)) if q else None,
                      "gmi_mean": float(np.mean(r["bin_gmi"]))}
         del y_h, tx_h, out_h
+    # dependent buffers: the equaliser stage, taps carried from buffer to buffer through
+    # events across the streams (4096 channels of 16-QAM at 2 samples per symbol, 25 dB)
+    P, n = 4096, 256
+    Nr = 16 * n
+    x, txq, C, labq = synth.equaliser_input(P, Nr, M=16)
+    Xq = np.stack([C.real, C.imag], axis=1).astype(np.float32)
+    Xd = torch.from_numpy(Xq).cuda()
+    Ld = torch.from_numpy(labq.astype(np.int32)).cuda()
+    y_h = torch.from_numpy(x.view(np.float32).reshape(2 * Nr + 2, 2 * P)).pin_memory()
+    tx_h = torch.from_numpy(np.ascontiguousarray(txq[:Nr].reshape(-1)).astype(np.int32)).pin_memory()
+    del x, txq
+    ring = Nr * P
+    out_h = torch.empty(ring, dtype=torch.int32).pin_memory()
+    s2 = synth.sigma2_from_snr_db(Xq, 25.0)
+    eq = {"instances": P, "mu": 0.01, "h0": [1, 0, 0, 0], "g0": [0, 0, 0, 0]}
+    rx = md.RxStream(Xd, Ld, s2, mode="hard", n_streams=4, buf_symbols=n * P, bin_symbols=21 * B, equaliser=eq)
+    rx.run(y_h, tx_h, total=4 * n * P, out=out_h)                    # warm-up
+    probe = rx.run(y_h, tx_h, total=ring, out=out_h)
+    total = max(ring, int(probe["symbols_per_s"] * seconds) // ring * ring)
+    r = rx.run(y_h, tx_h, total=total, out=out_h)
+    one = rx.run(y_h, tx_h, total=ring, out=out_h)                    # the ring once: converged BER
+    rx.close()
+    m = 4
+    res["2d_qam16_ddlms_chain_hard_25dB"] = {
+        "mode": "hard, equaliser stage", "M": 16, "D": 2, "channels": P, "symbols_per_channel_per_buffer": n,
+        "symbols": total, "seconds": r["seconds"], "symbols_per_s": r["symbols_per_s"],
+        "vs_1_gbaud": r["symbols_per_s"] / 1e9,
+        "pcie_gb_per_s": r["symbols_per_s"] * (16 + 4 + 4) / 1e9,
+        "bytes_per_symbol_h2d_d2h": [20, 4],
+        "latency_ms_mean": r["latency_ms_mean"], "latency_ms_max": r["latency_ms_max"],
+        "ber_ring_once": float(sum(int(e) for e in one["bin_errors"]) / (ring * m)),
+        "ber_last_bin_ring_once": float(int(one["bin_errors"][-1]) / (min(21 * B, ring - (len(one["bin_errors"]) - 1) * 21 * B) * m)),
+        "note": "each buffer's equaliser waits for the previous buffer's (taps carried); when the ring repeats, "
+                "the equaliser runs on across the wrap"}
+    del y_h, tx_h, out_h
     return {"buffers": "16 x 2^20 symbols, 4 streams, pinned host ring", "per_case": res}
 
 

@@ -384,7 +384,24 @@ typedef struct {
   int n_streams;          /* 1 .. 8 */
   int64_t buf_symbols;    /* symbols per buffer, 1 .. 2^24 */
   int64_t bin_symbols;    /* symbols per statistics bin, >= buf_symbols */
+  int eq_instances;       /* 0: the ring holds received symbols; P > 0: equaliser stage below */
+  double eq_mu;           /* equaliser step size (finite, >= 0) */
+  double eq_h0[8];        /* starting taps h_j, g_j (re, im), shared by the P instances */
+  double eq_g0[8];
 } md_rx_config;
+
+/* Equaliser stage (eq_instances = P > 0; D = 2, M <= 1024, the constellation's rows are also
+ * the equaliser's reference points): the ring holds complex samples at two per symbol of P
+ * parallel channels, TIME-MAJOR as in ddlms_equalize: h_y is (2 N/P + 2) rows of P complex
+ * float32 (re, im), stream symbol i is symbol i / P of channel i mod P.  buf_symbols, N and
+ * total must be multiples of P.  Each buffer (n = buf_symbols / P symbols per channel) is
+ * copied in with its two overlapping samples, equalised by ddlms_equalize_chain on its lane
+ * after an event from the previous buffer's equaliser (the taps are carried from buffer to
+ * buffer, so the equaliser stages run in stream order while copies and demapping of other
+ * buffers overlap them), and the equaliser outputs z are demapped in place of received
+ * symbols.  The decisions, outputs and taps equal one ddlms_equalize call over the whole
+ * stream; every rx_run starts from eq_h0, eq_g0.  When a ring is read more than once, the
+ * equaliser continues across the wrap with the ring's first samples. */
 
 /* Copies the constellation (M x D float32, device) and its labels (M uint32 permutation,
  * device) and allocates every device buffer of the pipeline (synchronous).  sigma2 is the
@@ -392,7 +409,8 @@ typedef struct {
 int rx_create(const float* d_X, const uint32_t* d_labels, int M, int D, double sigma2, const md_rx_config* cfg,
               void** out);
 /* Runs `total` stream symbols through the pipeline and returns when all are done.
- *   h_y            N x D float32 received symbols (pinned host ring)
+ *   h_y            N x D float32 received symbols (pinned host ring), or with the
+ *                  equaliser stage (2 N/P + 2) x P complex float32 samples
  *   h_tx           N uint32 sent point indices (pinned host ring), or NULL: no statistics
  *   h_out          N uint32 decisions (MD_RX_HARD) or N x m float32 LLRs (MD_RX_EXACT)
  *                  (pinned host ring), or NULL: nothing copied back
@@ -401,7 +419,8 @@ int rx_create(const float* d_X, const uint32_t* d_labels, int M, int D, double s
  *   h_stats        4 doubles, or NULL: wall seconds, symbols per second, mean and maximum
  *                  buffer latency in milliseconds
  * h_bin_errors and h_bin_gmi need h_tx.  Returns MD_OK, MD_EINVAL (NULL or unpinned
- * array, total < 0, N < 1, ring length not a multiple of buf_symbols), MD_ENOMEM, MD_EHIP. */
+ * array, total < 0, N < 1, ring length not a multiple of buf_symbols, equaliser sizes not
+ * multiples of P), MD_ENOMEM, MD_EHIP. */
 int rx_run(void* rx, const float* h_y, const uint32_t* h_tx, int64_t N, int64_t total, void* h_out,
            uint64_t* h_bin_errors, double* h_bin_gmi, double* h_stats);
 int rx_destroy(void* rx);
@@ -435,6 +454,17 @@ int rx_destroy(void* rx);
 int ddlms_equalize(const float* d_x, int64_t B, int64_t N, const float* d_C, int M, const double* h_h0,
                    const double* h_g0, double mu, uint32_t* d_dec, float* d_z, double* d_h, double* d_g,
                    void* stream);
+/* ddlms_equalize_chain -- the same recursion, continued across consecutive buffers of one
+ * stream (the paper's receiver orders such dependent buffers with events): every instance
+ * starts from its own taps in d_h, d_g (B x 8 doubles each, device, in/out) and leaves its
+ * final taps there.  A call over samples [2S, 2S + 2N + 2) of each instance continues one
+ * over [2S - 2N', 2S + 2) exactly (consecutive windows overlap by two samples): chained
+ * calls give the decisions, outputs and taps of a single call over the whole window, bit
+ * for bit.  The other arguments are those of ddlms_equalize; taps that are not finite
+ * propagate.  Returns MD_OK (B = 0 enqueues nothing; N = 0 leaves the taps unchanged),
+ * MD_EINVAL, MD_EHIP. */
+int ddlms_equalize_chain(const float* d_x, int64_t B, int64_t N, const float* d_C, int M, double mu,
+                         uint32_t* d_dec, float* d_z, double* d_h, double* d_g, void* stream);
 
 /* ------------------------------------------------------------------ Kramers-Kronig front end */
 /* kk_frontend -- the receiver's first step (section "Experimental setup": square root and

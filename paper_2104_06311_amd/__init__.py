@@ -14,7 +14,7 @@ from ._lib import MdemapError, PREC, check, lib
 
 __all__ = ["awgn_sample", "llr_exact", "llr_exact_noalloc", "llr_exact_gmi", "gmi_status", "alloc_fault_inject", "alloc_stats",
            "llr_maxlog", "llr_path_counts", "gmi_reduce", "ber_count", "q_factor_db", "llr_learned", "MLP", "SweepPlan", "RxStream", "release_cache",
-           "ddlms_equalize", "kk_frontend", "ubench", "UBENCH_KINDS", "kernel_timing", "kernel_timing_read", "MdemapError",
+           "ddlms_equalize", "ddlms_equalize_chain", "kk_frontend", "ubench", "UBENCH_KINDS", "kernel_timing", "kernel_timing_read", "MdemapError",
            "log2_exact"]
 
 
@@ -267,6 +267,32 @@ def ddlms_equalize(x, C, h0, g0, mu: float, want_z: bool = True, want_taps: bool
     return dec, z, h, g
 
 
+def ddlms_equalize_chain(x, C, h, g, mu: float, want_z: bool = True):
+    """ddlms_equalize continued from each instance's own taps (ddlms_equalize_chain in
+    mdemap.h): h, g (B, 4) complex128 device tensors, updated in place to the final taps.
+    x (2N + 2, B) complex64 time-major, C (M,) complex64.  Returns (dec (N, B) int32, z (N, B)
+    complex64 or None)."""
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.complex64 or x.dim() != 2 or not x.is_cuda:
+        raise ValueError("x must be a 2-D complex64 device tensor")
+    if not isinstance(C, torch.Tensor) or C.dtype != torch.complex64 or C.dim() != 1 or not C.is_cuda:
+        raise ValueError("C must be a 1-D complex64 device tensor")
+    T, B = x.shape
+    for name, t in (("h", h), ("g", g)):
+        if (not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or tuple(t.shape) != (B, 4)
+                or not t.is_cuda or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous (B, 4) complex128 device tensor")
+    if T < 2 or T % 2:
+        raise ValueError("x must hold 2 N + 2 samples per instance")
+    x = x.contiguous()
+    C = C.contiguous()
+    N = (T - 2) // 2
+    dec = torch.empty((N, B), dtype=torch.int32, device=x.device)
+    z = torch.empty((N, B), dtype=torch.complex64, device=x.device) if want_z else None
+    check("ddlms_equalize_chain", lib().ddlms_equalize_chain(_ptr(x), B, N, _ptr(C), C.shape[0], float(mu), _ptr(dec),
+                                                             _ptr(z), _ptr(h), _ptr(g), _stream()))
+    return dec, z
+
+
 def kk_frontend(x, A: float, nu: float, out=None):
     """Kramers-Kronig front end (see kk_frontend in mdemap.h): x is a 1-D float32 device
     tensor of T intensity samples (T a multiple of 512); returns T complex64 samples."""
@@ -442,8 +468,12 @@ class RxStream:
     point decisions) or "exact" (exact LLRs)."""
 
     def __init__(self, X, labels, sigma2: float, mode: str = "hard", n_streams: int = 4,
-                 buf_symbols: int = 1 << 20, bin_symbols: int | None = None):
+                 buf_symbols: int = 1 << 20, bin_symbols: int | None = None, equaliser: dict | None = None):
+        """equaliser: None, or {"instances": P, "mu": step, "h0": 4 complex, "g0": 4 complex}:
+        the ring then holds complex samples (see run) that pass the DD-LMS equaliser, taps
+        carried from buffer to buffer, before demapping."""
         import ctypes
+        import numpy as np
         from ._lib import RX_MODE, RxConfig
         _dev(X, "X", torch.float32, 2)
         _dev(labels, "labels", torch.int32, 1)
@@ -454,7 +484,17 @@ class RxStream:
         self.mode = mode
         self.buf_symbols = int(buf_symbols)
         self.bin_symbols = int(bin_symbols if bin_symbols is not None else buf_symbols)
+        self.P = 0
         cfg = RxConfig(RX_MODE[mode], int(n_streams), self.buf_symbols, self.bin_symbols)
+        if equaliser is not None:
+            self.P = int(equaliser["instances"])
+            cfg.eq_instances = self.P
+            cfg.eq_mu = float(equaliser["mu"])
+            h0 = np.ascontiguousarray(np.asarray(equaliser["h0"], dtype=np.complex128).reshape(4)).view(np.float64)
+            g0 = np.ascontiguousarray(np.asarray(equaliser["g0"], dtype=np.complex128).reshape(4)).view(np.float64)
+            for i in range(8):
+                cfg.eq_h0[i] = float(h0[i])
+                cfg.eq_g0[i] = float(g0[i])
         h = ctypes.c_void_p()
         check("rx_create", lib().rx_create(_ptr(X), _ptr(labels), self.M, self.D, float(sigma2), ctypes.byref(cfg),
                                            ctypes.byref(h)))
@@ -462,16 +502,25 @@ class RxStream:
 
     def run(self, y, tx=None, total: int | None = None, out=None, stats: bool = True):
         """Runs `total` stream symbols (default: the ring once) from the pinned host ring y
-        float32 [N, D] (and tx int32 [N]); decisions (hard, int32 [N]) or LLRs (exact,
-        float32 [N, m]) go to the pinned host ring `out` if given.  Returns a dict with the
-        per-bin bit errors and GMI (when tx is given) and the run's timing."""
+        float32 [N, D] (with the equaliser: complex samples float32 [2 N/P + 2, 2 P], stream
+        symbol i being symbol i // P of channel i % P) and tx int32 [N] (stream order);
+        decisions (hard, int32 [N]) or LLRs (exact, float32 [N, m]) go to the pinned host ring
+        `out` if given.  Returns a dict with the per-bin bit errors and GMI (when tx is given)
+        and the run's timing."""
         import numpy as np
         for name, t in (("y", y), ("tx", tx), ("out", out)):
             if t is not None and (t.is_cuda or not t.is_pinned() or not t.is_contiguous()):
                 raise ValueError(f"{name} must be a contiguous pinned host tensor")
-        if y.dtype != torch.float32 or y.dim() != 2 or y.shape[1] != self.D:
-            raise ValueError("y must be float32 [N, D]")
-        N = y.shape[0]
+        if self.P:
+            # complex samples, time-major: (2 N/P + 2) rows of P (re, im) pairs
+            if (y.dtype != torch.float32 or y.dim() != 2 or y.shape[1] != 2 * self.P or y.shape[0] < 4
+                    or y.shape[0] % 2):
+                raise ValueError("with the equaliser y must be float32 [2 N/P + 2, 2 P]")
+            N = (y.shape[0] - 2) // 2 * self.P
+        else:
+            if y.dtype != torch.float32 or y.dim() != 2 or y.shape[1] != self.D:
+                raise ValueError("y must be float32 [N, D]")
+            N = y.shape[0]
         if tx is not None and (tx.dtype != torch.int32 or tx.shape != (N,)):
             raise ValueError("tx must be int32 [N]")
         if out is not None:

@@ -69,6 +69,7 @@ SIGNATURES = {
     "release_cache": (_I, []),
     "last_error": (ctypes.c_char_p, []),
     "ddlms_equalize": (_I, [_P, _I64, _I64, _P, _I, _P, _P, _D, _P, _P, _P, _P, _P]),
+    "ddlms_equalize_chain": (_I, [_P, _I64, _I64, _P, _I, _D, _P, _P, _P, _P, _P]),
     "kk_frontend": (_I, [_P, _I64, _F, _D, _P, _P]),
     "ubench": (_I, [_I, _I64, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _P]),
     "mdemap_version": (_I, []),
@@ -84,7 +85,8 @@ class SweepInstance(ctypes.Structure):
 class RxConfig(ctypes.Structure):
     """md_rx_config of mdemap.h."""
     _fields_ = [("mode", ctypes.c_int), ("n_streams", ctypes.c_int), ("buf_symbols", ctypes.c_int64),
-                ("bin_symbols", ctypes.c_int64)]
+                ("bin_symbols", ctypes.c_int64), ("eq_instances", ctypes.c_int), ("eq_mu", ctypes.c_double),
+                ("eq_h0", ctypes.c_double * 8), ("eq_g0", ctypes.c_double * 8)]
 
 
 RX_MODE = {"hard": 0, "exact": 1}

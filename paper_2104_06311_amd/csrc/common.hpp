@@ -89,6 +89,13 @@ int set_lds_limit(const void* kern, int bytes);
 // switched on by kernel_timing(): timing_begin records the first event of a pair before
 // the launch and returns its slot (or -1 when timing is off or the stream is capturing),
 // timing_end records the second after it.
+// The DD-LMS equaliser's launcher (ddlms.hip): every instance starts from the taps t0_h /
+// t0_g (host, 8 doubles each) or, when d_h_in / d_g_in are given, from its own B x 8 device
+// taps (which may be d_h / d_g themselves).
+int launch_ddlms(const float* d_x, int64_t B, int64_t N, const float* d_C, int M, const double* t0_h,
+                 const double* t0_g, const double* d_h_in, const double* d_g_in, double mu, uint32_t* d_dec,
+                 float* d_z, double* d_h, double* d_g, hipStream_t stream);
+
 int timing_begin(hipStream_t stream);
 void timing_end(hipStream_t stream, int slot);
 

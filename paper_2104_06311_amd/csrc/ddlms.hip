@@ -22,10 +22,14 @@ struct Taps {
   double v[16];   // h re/im for j = 0..3, then g re/im for j = 0..3
 };
 
+// h_in, g_in: NULL (every instance starts from t0) or B x 8 doubles, each instance's own
+// starting taps; they may be the same arrays as h_out, g_out (each thread reads its
+// instance's taps before it writes them).
 __global__ void __launch_bounds__(kEqThreads) ddlms_kernel(const float2* __restrict__ x, int64_t B, int64_t N,
                                                           const float2* __restrict__ C, int M, Taps t0, double mu,
                                                           uint32_t* __restrict__ dec, float2* __restrict__ z,
-                                                          double* __restrict__ h_out, double* __restrict__ g_out) {
+                                                          const double* h_in, const double* g_in, double* h_out,
+                                                          double* g_out) {
   __shared__ float2 pts[kEqMaxPoints];
   for (int i = threadIdx.x; i < M; i += blockDim.x) pts[i] = C[i];
   __syncthreads();
@@ -35,10 +39,10 @@ __global__ void __launch_bounds__(kEqThreads) ddlms_kernel(const float2* __restr
   double hr[4], hi[4], gr[4], gi[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    hr[j] = t0.v[2 * j];
-    hi[j] = t0.v[2 * j + 1];
-    gr[j] = t0.v[8 + 2 * j];
-    gi[j] = t0.v[8 + 2 * j + 1];
+    hr[j] = h_in ? h_in[8 * b + 2 * j] : t0.v[2 * j];
+    hi[j] = h_in ? h_in[8 * b + 2 * j + 1] : t0.v[2 * j + 1];
+    gr[j] = g_in ? g_in[8 * b + 2 * j] : t0.v[8 + 2 * j];
+    gi[j] = g_in ? g_in[8 * b + 2 * j + 1] : t0.v[8 + 2 * j + 1];
   }
   // window w_j = u_{2n+j}; samples 2n and 2n+1 carry over from the previous symbol
   double wr[4] = {0.0, 0.0, 0.0, 0.0}, wi[4] = {0.0, 0.0, 0.0, 0.0};
@@ -121,6 +125,25 @@ bool finite_taps(const double* t) {
 }
 
 }  // namespace
+
+int launch_ddlms(const float* d_x, int64_t B, int64_t N, const float* d_C, int M, const double* t0_h,
+                 const double* t0_g, const double* d_h_in, const double* d_g_in, double mu, uint32_t* d_dec,
+                 float* d_z, double* d_h, double* d_g, hipStream_t stream) {
+  if (B == 0) return MD_OK;
+  Taps t0;
+  for (int i = 0; i < 8; ++i) {
+    t0.v[i] = t0_h ? t0_h[i] : 0.0;
+    t0.v[8 + i] = t0_g ? t0_g[i] : 0.0;
+  }
+  const int64_t blocks = (B + kEqThreads - 1) / kEqThreads;
+  if (blocks > 0x7fffffff) return fail(MD_EINVAL, "ddlms: B too large");
+  hipLaunchKernelGGL(ddlms_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kEqThreads), 0, stream,
+                     reinterpret_cast<const float2*>(d_x), B, N, reinterpret_cast<const float2*>(d_C), M, t0, mu,
+                     d_dec, reinterpret_cast<float2*>(d_z), d_h_in, d_g_in, d_h, d_g);
+  MD_LAUNCH_CHECK("ddlms_kernel launch");
+  return MD_OK;
+}
+
 }  // namespace md
 
 extern "C" {
@@ -137,20 +160,22 @@ int ddlms_equalize(const float* d_x, int64_t B, int64_t N, const float* d_C, int
   if (d_x == nullptr || d_C == nullptr) return fail(MD_EINVAL, "ddlms_equalize: d_x and d_C are required");
   if (N > 0 && d_dec == nullptr) return fail(MD_EINVAL, "ddlms_equalize: d_dec is required");
   if (N > (int64_t(1) << 40) / (B > 0 ? B : 1)) return fail(MD_EINVAL, "ddlms_equalize: (2N + 2) B too large");
-  if (B == 0) return MD_OK;
-  Taps t0;
-  for (int i = 0; i < 8; ++i) {
-    t0.v[i] = h_h0[i];
-    t0.v[8 + i] = h_g0[i];
-  }
-  const int64_t blocks = (B + kEqThreads - 1) / kEqThreads;
-  if (blocks > 0x7fffffff) return fail(MD_EINVAL, "ddlms_equalize: B too large");
-  hipLaunchKernelGGL(ddlms_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kEqThreads), 0,
-                     static_cast<hipStream_t>(stream), reinterpret_cast<const float2*>(d_x), B, N,
-                     reinterpret_cast<const float2*>(d_C), M, t0, mu, d_dec, reinterpret_cast<float2*>(d_z), d_h,
-                     d_g);
-  MD_LAUNCH_CHECK("ddlms_kernel launch");
-  return MD_OK;
+  return launch_ddlms(d_x, B, N, d_C, M, h_h0, h_g0, nullptr, nullptr, mu, d_dec, d_z, d_h, d_g,
+                      static_cast<hipStream_t>(stream));
+}
+
+int ddlms_equalize_chain(const float* d_x, int64_t B, int64_t N, const float* d_C, int M, double mu,
+                         uint32_t* d_dec, float* d_z, double* d_h, double* d_g, void* stream) {
+  using namespace md;
+  if (B < 0 || N < 0) return fail(MD_EINVAL, "ddlms_equalize_chain: B and N must be >= 0");
+  if (M < 1 || M > kEqMaxPoints) return fail(MD_EINVAL, "ddlms_equalize_chain: M must be in [1, 1024]");
+  if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(MD_EINVAL, "ddlms_equalize_chain: mu must be finite and >= 0");
+  if (d_x == nullptr || d_C == nullptr) return fail(MD_EINVAL, "ddlms_equalize_chain: d_x and d_C are required");
+  if (d_h == nullptr || d_g == nullptr) return fail(MD_EINVAL, "ddlms_equalize_chain: d_h and d_g are required");
+  if (N > 0 && d_dec == nullptr) return fail(MD_EINVAL, "ddlms_equalize_chain: d_dec is required");
+  if (N > (int64_t(1) << 40) / (B > 0 ? B : 1)) return fail(MD_EINVAL, "ddlms_equalize_chain: (2N + 2) B too large");
+  return launch_ddlms(d_x, B, N, d_C, M, nullptr, nullptr, d_h, d_g, mu, d_dec, d_z, d_h, d_g,
+                      static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

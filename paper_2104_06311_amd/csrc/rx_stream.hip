@@ -3,6 +3,10 @@
 // symbols in, demaps them with the library's own entry points, reduces the statistics of
 // the bins the buffer touches and copies the results out; an event at the end of each
 // buffer lets the host retire it, fold its statistics in stream order and reuse the lane.
+// With the equaliser stage a buffer's samples pass the DD-LMS equaliser first; its taps
+// carry over from buffer to buffer, so each lane's equaliser waits for an event that the
+// previous buffer's lane records after its own (a dependency chain through the lanes),
+// while the copies and demapping of neighbouring buffers run beside it.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -37,6 +41,8 @@ struct PieceResult {
 struct Lane {
   hipStream_t s = nullptr;
   hipEvent_t beg = nullptr, end = nullptr;
+  hipEvent_t eq = nullptr;           // after the buffer's equaliser (equaliser stage only)
+  float* x = nullptr;                // the buffer's samples (equaliser stage only)
   float* y = nullptr;
   uint32_t* tx = nullptr;
   float* llr = nullptr;
@@ -58,6 +64,11 @@ struct RxStream {
   float* X = nullptr;
   uint32_t* labels = nullptr;
   std::vector<Lane> lanes;
+  // equaliser stage: P channels, their taps (P x 8 doubles each, carried across buffers)
+  int64_t P = 0;
+  double mu = 0.0, h0[8] = {}, g0[8] = {};
+  double* th = nullptr;
+  double* tg = nullptr;
 };
 
 namespace {
@@ -106,6 +117,7 @@ void free_lane(Lane& L) {
     (void)hipStreamSynchronize(L.s);
     (void)release_stream_resources(L.s);
   }
+  if (L.x) (void)md::dev_free(L.x);
   if (L.y) (void)md::dev_free(L.y);
   if (L.tx) (void)md::dev_free(L.tx);
   if (L.llr) (void)md::dev_free(L.llr);
@@ -114,12 +126,15 @@ void free_lane(Lane& L) {
   if (L.h_res) (void)hipHostFree(L.h_res);
   if (L.beg) (void)hipEventDestroy(L.beg);
   if (L.end) (void)hipEventDestroy(L.end);
+  if (L.eq) (void)hipEventDestroy(L.eq);
   if (L.s) (void)hipStreamDestroy(L.s);
   L = Lane{};
 }
 
 void destroy(RxStream* r) {
   for (Lane& L : r->lanes) free_lane(L);
+  if (r->th) (void)md::dev_free(r->th);
+  if (r->tg) (void)md::dev_free(r->tg);
   if (r->X) (void)md::dev_free(r->X);
   if (r->labels) (void)md::dev_free(r->labels);
   (void)hipGetLastError();
@@ -157,6 +172,17 @@ int rx_create(const float* d_X, const uint32_t* d_labels, int M, int D, double s
   if (cfg->buf_symbols < 1 || cfg->buf_symbols > (int64_t(1) << 24))
     return md::fail(MD_EINVAL, "buf_symbols must be in [1, 2^24]");
   if (cfg->bin_symbols < cfg->buf_symbols) return md::fail(MD_EINVAL, "bin_symbols must be >= buf_symbols");
+  if (cfg->eq_instances < 0) return md::fail(MD_EINVAL, "eq_instances must be >= 0");
+  if (cfg->eq_instances > 0) {
+    if (D != 2) return md::fail(MD_EINVAL, "the equaliser stage needs a 2D (complex) constellation");
+    if (M > 1024) return md::fail(MD_EINVAL, "the equaliser stage takes M <= 1024 reference points");
+    if (cfg->buf_symbols % cfg->eq_instances != 0)
+      return md::fail(MD_EINVAL, "buf_symbols must be a multiple of eq_instances");
+    if (!(cfg->eq_mu >= 0.0) || !std::isfinite(cfg->eq_mu)) return md::fail(MD_EINVAL, "eq_mu must be finite and >= 0");
+    for (int i = 0; i < 8; ++i)
+      if (!std::isfinite(cfg->eq_h0[i]) || !std::isfinite(cfg->eq_g0[i]))
+        return md::fail(MD_EINVAL, "the equaliser's starting taps must be finite");
+  }
   int dev = 0;
   int st = md::current_device(&dev);
   if (st != MD_OK) return st;
@@ -170,6 +196,12 @@ int rx_create(const float* d_X, const uint32_t* d_labels, int M, int D, double s
   r->bin = cfg->bin_symbols;
   r->sigma2 = sigma2;
   r->device = dev;
+  r->P = cfg->eq_instances;
+  r->mu = cfg->eq_mu;
+  for (int i = 0; i < 8; ++i) {
+    r->h0[i] = cfg->eq_h0[i];
+    r->g0[i] = cfg->eq_g0[i];
+  }
   auto bail = [&](int status) {
     md::destroy(r);
     return status;
@@ -180,12 +212,22 @@ int rx_create(const float* d_X, const uint32_t* d_labels, int M, int D, double s
   if (e == hipSuccess) e = hipMemcpy(r->labels, d_labels, sizeof(uint32_t) * M, hipMemcpyDeviceToDevice);
   if (e != hipSuccess) return bail(md::hip_fail(e, "copy of the constellation"));
   const size_t B = static_cast<size_t>(r->B);
+  if (r->P > 0) {
+    if ((st = md::dev_alloc(&r->th, static_cast<size_t>(r->P) * 8)) != MD_OK) return bail(st);
+    if ((st = md::dev_alloc(&r->tg, static_cast<size_t>(r->P) * 8)) != MD_OK) return bail(st);
+  }
   r->lanes.resize(static_cast<size_t>(r->S));
   for (md::Lane& L : r->lanes) {
     e = hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreate(&L.beg);
     if (e == hipSuccess) e = hipEventCreate(&L.end);
+    if (e == hipSuccess && r->P > 0) e = hipEventCreateWithFlags(&L.eq, hipEventDisableTiming);
     if (e != hipSuccess) return bail(md::hip_fail(e, "stream or event creation"));
+    if (r->P > 0) {
+      // (2n + 2) rows of P complex samples
+      const size_t rows = 2 * (B / static_cast<size_t>(r->P)) + 2;
+      if ((st = md::dev_alloc(&L.x, rows * static_cast<size_t>(r->P) * 2)) != MD_OK) return bail(st);
+    }
     if ((st = md::dev_alloc(&L.y, B * D)) != MD_OK) return bail(st);
     if ((st = md::dev_alloc(&L.tx, B)) != MD_OK) return bail(st);
     if ((st = md::dev_alloc(&L.llr, B * r->m)) != MD_OK) return bail(st);
@@ -201,7 +243,13 @@ int rx_create(const float* d_X, const uint32_t* d_labels, int M, int D, double s
     // stream is sized (and the labels are checked) before the first timed run
     e = hipMemsetAsync(L.y, 0, sizeof(float) * B * D, L.s);
     if (e == hipSuccess) e = hipMemsetAsync(L.tx, 0, sizeof(uint32_t) * B, L.s);
+    if (e == hipSuccess && r->P > 0)
+      e = hipMemsetAsync(L.x, 0, sizeof(float) * 2 * (2 * (B / r->P) + 2) * r->P, L.s);
     if (e != hipSuccess) return bail(md::hip_fail(e, "hipMemsetAsync"));
+    if (r->P > 0 &&
+        (st = md::launch_ddlms(L.x, r->P, r->B / r->P, r->X, M, r->h0, r->g0, nullptr, nullptr, r->mu, L.dec, L.y,
+                               nullptr, nullptr, L.s)) != MD_OK)
+      return bail(st);
     if ((st = md::lane_demap(r, L, r->B)) != MD_OK) return bail(st);
     if ((st = gmi_reduce(L.llr, r->B, r->m, L.tx, r->labels, &L.d_res->gmi[0], nullptr, nullptr, L.s)) != MD_OK)
       return bail(st);
@@ -226,6 +274,8 @@ int rx_run(void* rx, const float* h_y, const uint32_t* h_tx, int64_t N, int64_t 
   if (total > N && N % r->B != 0)
     return md::fail(MD_EINVAL, "a ring that is read more than once must hold a multiple of buf_symbols symbols");
   if ((h_bin_errors || h_bin_gmi) && !h_tx) return md::fail(MD_EINVAL, "bin statistics need h_tx");
+  if (r->P > 0 && (N % r->P != 0 || total % r->P != 0))
+    return md::fail(MD_EINVAL, "with the equaliser stage N and total must be multiples of eq_instances");
   if (!md::is_pinned(h_y) || (h_tx && !md::is_pinned(h_tx)) || (h_out && !md::is_pinned(h_out)))
     return md::fail(MD_EINVAL, "host arrays must be pinned (hipHostMalloc or pin_memory)");
   int dev = 0;
@@ -243,6 +293,18 @@ int rx_run(void* rx, const float* h_y, const uint32_t* h_tx, int64_t N, int64_t 
   int64_t n_lat = 0;
   const int m = r->m, D = r->D;
   const bool stats = h_tx != nullptr;
+  if (r->P > 0) {
+    // every run starts the equaliser from the configured taps
+    std::vector<double> th(static_cast<size_t>(r->P) * 8), tg(static_cast<size_t>(r->P) * 8);
+    for (int64_t b = 0; b < r->P; ++b)
+      for (int i = 0; i < 8; ++i) {
+        th[static_cast<size_t>(b * 8 + i)] = r->h0[i];
+        tg[static_cast<size_t>(b * 8 + i)] = r->g0[i];
+      }
+    MD_HIP_TRY(hipMemcpy(r->th, th.data(), sizeof(double) * th.size(), hipMemcpyHostToDevice));
+    MD_HIP_TRY(hipMemcpy(r->tg, tg.data(), sizeof(double) * tg.size(), hipMemcpyHostToDevice));
+  }
+  const md::Lane* prev = nullptr;   // the lane of the previous buffer (equaliser order)
   const auto t0 = std::chrono::steady_clock::now();
   int64_t k = 0;
   for (int64_t i0 = 0; i0 < total; i0 += r->B, ++k) {
@@ -251,7 +313,21 @@ int rx_run(void* rx, const float* h_y, const uint32_t* h_tx, int64_t N, int64_t 
     const int64_t nb = std::min(r->B, total - i0);
     const int64_t r0 = i0 % N;          // no buffer wraps: N % B == 0 whenever total > N
     MD_HIP_TRY(hipEventRecord(L.beg, L.s));
-    MD_HIP_TRY(hipMemcpyAsync(L.y, h_y + r0 * D, sizeof(float) * nb * D, hipMemcpyHostToDevice, L.s));
+    if (r->P > 0) {
+      // samples of channel rows [2 t0, 2 t0 + 2 nr + 2): the buffer's symbols and the two
+      // samples it shares with the next buffer; the equaliser waits for the previous one
+      const int64_t t0 = r0 / r->P, nr = nb / r->P;
+      MD_HIP_TRY(hipMemcpyAsync(L.x, h_y + 2 * (2 * t0) * r->P, sizeof(float) * 2 * (2 * nr + 2) * r->P,
+                                hipMemcpyHostToDevice, L.s));
+      if (prev) MD_HIP_TRY(hipStreamWaitEvent(L.s, prev->eq, 0));
+      if ((st = md::launch_ddlms(L.x, r->P, nr, r->X, r->M, nullptr, nullptr, r->th, r->tg, r->mu, L.dec, L.y, r->th,
+                                 r->tg, L.s)) != MD_OK)
+        return st;
+      MD_HIP_TRY(hipEventRecord(L.eq, L.s));
+      prev = &L;
+    } else {
+      MD_HIP_TRY(hipMemcpyAsync(L.y, h_y + r0 * D, sizeof(float) * nb * D, hipMemcpyHostToDevice, L.s));
+    }
     if (stats) MD_HIP_TRY(hipMemcpyAsync(L.tx, h_tx + r0, sizeof(uint32_t) * nb, hipMemcpyHostToDevice, L.s));
     if ((st = md::lane_demap(r, L, nb)) != MD_OK) return st;
     L.n_pieces = 0;

@@ -100,6 +100,20 @@ def test_receiver_arguments_are_checked_before_device_work():
     assert create(buf=0) == -1 and create(buf=(1 << 24) + 1, binsz=1 << 25) == -1
     assert create(buf=1000, binsz=999) == -1
     assert b"bin_symbols" in L.last_error()
+
+    def create_eq(M=16, D=2, P=100, buf=1000, mu=0.01, h0=0.0):
+        c = RxConfig(0, 2, buf, buf)
+        c.eq_instances = P
+        c.eq_mu = mu
+        c.eq_h0[0] = h0
+        return L.rx_create(fake, fake, M, D, 0.1, ctypes.byref(c), ctypes.byref(h))
+
+    assert create_eq(P=-1) == -1
+    assert create_eq(D=4) == -1 and b"2D" in L.last_error()
+    assert create_eq(M=2048) == -1
+    assert create_eq(P=300) == -1 and b"multiple" in L.last_error()     # 1000 % 300 != 0
+    assert create_eq(mu=-1.0) == -1 and create_eq(mu=float("nan")) == -1
+    assert create_eq(h0=float("inf")) == -1
     assert L.rx_run(None, fake, None, 10, 10, None, None, None, None) == -1
     assert L.rx_destroy(None) == 0
 
@@ -153,6 +167,15 @@ def test_equaliser_argument_validation_before_device_work():
     assert L.ddlms_equalize(*args(10, 1 << 40, 16, 0.01)) == -1
     assert b"ddlms_equalize" in L.last_error()
     assert L.ddlms_equalize(*args(0, 10, 16, 0.01)) == 0          # no instances: nothing to do
+    chain = lambda B, N, M, mu, x=fake, dec=fake, hh=fake, gg=fake: (x, B, N, fake, M, mu, dec, None, hh, gg, None)
+    assert L.ddlms_equalize_chain(*chain(-1, 10, 16, 0.01)) == -1
+    assert L.ddlms_equalize_chain(*chain(10, 10, 1025, 0.01)) == -1
+    assert L.ddlms_equalize_chain(*chain(10, 10, 16, float("nan"))) == -1
+    assert L.ddlms_equalize_chain(*chain(10, 10, 16, 0.01, hh=None)) == -1
+    assert L.ddlms_equalize_chain(*chain(10, 10, 16, 0.01, gg=None)) == -1
+    assert L.ddlms_equalize_chain(*chain(10, 10, 16, 0.01, dec=None)) == -1
+    assert b"ddlms_equalize_chain" in L.last_error()
+    assert L.ddlms_equalize_chain(*chain(0, 10, 16, 0.01)) == 0
 
 
 def test_kk_argument_validation_before_device_work():
