@@ -169,5 +169,36 @@ __device__ __forceinline__ uint32_t channel_symbol(const float* __restrict__ X, 
   return u;
 }
 
+// The same channel use for a compile-time D: every word index, block and output dimension
+// is a constant, so the D values stay in registers without the selects that a run-time
+// index into a register array costs.  Identical results to channel_symbol.
+template <int D>
+__device__ __forceinline__ uint32_t channel_symbol_d(const float* __restrict__ X, int m, uint32_t k0, uint32_t k1,
+                                                     uint64_t g, double sigma, float (&yout)[8]) {
+#pragma clang fp contract(off)
+  constexpr int NP = (D + 1) / 2;          // normal pairs
+  constexpr int NB = (1 + 2 * NP + 3) / 4;  // Philox blocks of the word stream
+  const uint32_t glo = static_cast<uint32_t>(g), ghi = static_cast<uint32_t>(g >> 32);
+  uint32_t w[4 * NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const Philox4 r = philox10(glo, ghi, static_cast<uint32_t>(j), 1u, k0, k1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w[4 * j + i] = r.w[i];
+  }
+  const uint32_t u = w[0] >> (32 - m);
+  const float* xu = X + static_cast<int64_t>(u) * D;
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    float z0, z1;
+    gen_normal_pair(w[2 * p + 1], w[2 * p + 2], &z0, &z1);
+    yout[2 * p] = static_cast<float>(__builtin_fma(sigma, static_cast<double>(z0), static_cast<double>(xu[2 * p])));
+    if (2 * p + 1 < D)
+      yout[2 * p + 1] =
+          static_cast<float>(__builtin_fma(sigma, static_cast<double>(z1), static_cast<double>(xu[2 * p + 1])));
+  }
+  return u;
+}
+
 }  // namespace rng
 }  // namespace md

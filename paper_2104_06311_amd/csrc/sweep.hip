@@ -133,7 +133,17 @@ __device__ void process_item(const Problem& P, const Item& I, int it, uint4* lds
       float (&yv)[8] = yv_own;
       if (live_own) {
         const uint64_t g = P.offset + static_cast<uint64_t>(I.start + local);
-        const uint32_t u = rng::channel_symbol(P.X, P.m, P.D, P.k0, P.k1, g, P.sigma, yv);
+        uint32_t u = 0;
+        switch (P.D) {      // compile-time D: the received vector stays in registers
+          case 1: u = rng::channel_symbol_d<1>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
+          case 2: u = rng::channel_symbol_d<2>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
+          case 3: u = rng::channel_symbol_d<3>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
+          case 4: u = rng::channel_symbol_d<4>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
+          case 5: u = rng::channel_symbol_d<5>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
+          case 6: u = rng::channel_symbol_d<6>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
+          case 7: u = rng::channel_symbol_d<7>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
+          default: u = rng::channel_symbol_d<8>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
+        }
         lab_own = P.labels[u];
       }
       _Float16* row = bst + (owner_sb * 32 + (lane & 31)) * S;
@@ -302,7 +312,7 @@ __device__ __forceinline__ float small_item(const Problem& P, const Item& I, int
     float yv[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) yv[d] = 0.0f;
-    const uint32_t u = rng::channel_symbol(P.X, MB, D, P.k0, P.k1, g, P.sigma, yv);
+    const uint32_t u = rng::channel_symbol_d<D>(P.X, MB, P.k0, P.k1, g, P.sigma, yv);
     const uint32_t lab = P.labels[u];
     float v[M];
 #pragma unroll
