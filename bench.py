@@ -310,11 +310,12 @@ def extra_learned_capacity(md, steps=10000, pairs=1 << 22, N=1_000_000):
 
 def measured_peaks(md):
     """Rates measured on this device by the library's calibration kernels (ubench): the
-    exponential unit, non-packed FP32 adds, the matrix cores and a 256 MiB device copy."""
+    exponential unit, non-packed FP32 adds, the exp + 2 add mix, the exact kernel's whole
+    per-tile mix with its matrix products, the matrix cores and a 256 MiB device copy."""
     import torch
     res = {}
     for kind, key in (("exp", "exp_per_s"), ("add_f32", "add_f32_per_s"), ("exp_add2", "exp_add2_per_s"),
-                      ("mfma_f16", "mfma_f16_flop_per_s"),
+                      ("tile_mix", "tile_mix_exp_per_s"), ("mfma_f16", "mfma_f16_flop_per_s"),
                       ("mfma_bf16", "mfma_bf16_flop_per_s"), ("mfma_f32", "mfma_f32_flop_per_s")):
         res[key] = md.ubench(kind)[0]
     nbytes = 1 << 28
@@ -733,9 +734,13 @@ def main():
     roofline["measured_peaks"] = peaks
     roofline["frac_measured_exp"] = exps / peaks["exp_per_s"]
     roofline["pair_issue"]["frac_measured_mix"] = exps / peaks["exp_add2_per_s"]
+    roofline["pair_issue"]["frac_tile_mix"] = exps / peaks["tile_mix_exp_per_s"]
     roofline["measured_basis"] = ("exp_per_s: v_exp_f32 alone; exp_add2_per_s: one exponential and two independent "
-                                  "adds per step (the kernel's mix), both from the library's ubench kernels on "
-                                  "this device after the timed steps")
+                                  "adds per step; tile_mix_exp_per_s: the kernel's whole per-tile instruction mix "
+                                  "(two dependent matrix products per 32 x 32 tile from LDS operands, 16 "
+                                  "exponentials per lane of the previous tile's products, position adds, tile-sum "
+                                  "tree, group routing) without its HBM traffic, prologue and epilogue; all from "
+                                  "the library's ubench kernels on this device after the timed steps")
 
     if args.copy_probe:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)   # 256 MiB

@@ -514,6 +514,12 @@ int kk_frontend(const float* d_x, int64_t T, float A, double nu, float* d_out, v
  *   MD_UB_EXP_ADD2   one v_exp_f32 and two independent v_add_f32 of its result per step
  *                    (the exact demapper's work per (symbol, point) pair)
  *                                                               -> steps/s
+ *   MD_UB_TILE_MIX   the exact demapper's whole per-tile instruction mix at two K steps
+ *                    and 11 label bits, without memory traffic: two dependent
+ *                    v_mfma_f32_32x32x16_f16 per 32 x 32 tile (A operands from LDS),
+ *                    16 exponentials per lane of the previous tile's products, their
+ *                    position adds and tile-sum tree, group routing every 8 tiles
+ *                                                               -> exponentials/s
  * Returns MD_OK, MD_EINVAL (unknown kind, work < 0, a copy without buffers, with work not a
  * positive multiple of 16 or with unaligned buffers), MD_ENOMEM, MD_EHIP. */
 #define MD_UB_EXP       0
@@ -523,6 +529,7 @@ int kk_frontend(const float* d_x, int64_t T, float A, double nu, float* d_out, v
 #define MD_UB_MFMA_F32  4
 #define MD_UB_COPY      5
 #define MD_UB_EXP_ADD2  6
+#define MD_UB_TILE_MIX  7
 int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rate, double* h_ms, void* stream);
 
 /* ------------------------------------------------------------------ kernel timing */

@@ -17,7 +17,8 @@ def md():
 # vector peak, which needs packed instructions; non-packed adds measure about 2.8
 # cycles), FP16/BF16 matrix 2.5e15 flop/s, FP32 matrix 1.57e14 flop/s, HBM 8e12 B/s.
 BANDS = {"exp": (4e12, 2.6e13), "add_f32": (8e12, 8.2e13), "mfma_f16": (8e14, 2.8e15),
-         "mfma_bf16": (8e14, 2.8e15), "mfma_f32": (4e13, 1.8e14), "exp_add2": (3e12, 2.0e13)}
+         "mfma_bf16": (8e14, 2.8e15), "mfma_f32": (4e13, 1.8e14), "exp_add2": (3e12, 2.0e13),
+         "tile_mix": (2e12, 2.0e13)}
 
 
 @pytest.mark.parametrize("kind", sorted(BANDS))
@@ -28,7 +29,7 @@ def test_compute_rates_are_plausible(kind):
     assert 0.05 < ms < 200.0, (kind, ms)
     # twice the iterations take about twice as long
     doubled = {"exp": 16384, "add_f32": 16384, "mfma_f16": 8192, "mfma_bf16": 8192, "mfma_f32": 4096,
-               "exp_add2": 16384}
+               "exp_add2": 16384, "tile_mix": 2048}
     rate2, ms2 = md().ubench(kind, work=doubled[kind])
     assert 1.5 < ms2 / ms < 2.6, (kind, ms, ms2)
 
@@ -57,3 +58,17 @@ def test_exp_add2_mix_is_slower_than_exp_alone():
     assert r_mix < r_exp, (r_mix, r_exp)
     serial = 1.0 / (1.0 / r_exp + 2.0 / r_add)
     assert r_mix > 0.8 * serial, (r_mix, serial)
+
+
+def test_tile_mix_is_bounded_by_its_parts():
+    """The demapper's per-tile mix issues the exp + 2 add work of every pair and the two
+    matrix products of every tile: it cannot beat the exp + 2 add mix alone, and it cannot
+    be slower than that mix and the products issued one after the other."""
+    r_mix = md().ubench("exp_add2")[0]
+    r_tile = md().ubench("tile_mix")[0]
+    r_mfma = md().ubench("mfma_f16")[0]
+    assert r_tile < 1.05 * r_mix, (r_tile, r_mix)
+    # per exponential: 2 x 32 x 32 x 16 x 2 flop of products per 1024 exponentials
+    flop_per_exp = 2.0 * 2 * 32 * 32 * 16 / 1024
+    serial = 1.0 / (1.0 / r_mix + flop_per_exp / r_mfma)
+    assert r_tile > 0.7 * serial, (r_tile, serial)
