@@ -446,7 +446,15 @@ def extra_16d(md, steps, pairs):
                            "learned_ms": t_ln, "gmi_learned": g_ln, "learned_gap_bits": g_ex - g_ln,
                            "learned_speedup_vs_exact": t_ex / t_ln, "train_steps": steps, "train_pairs": pairs,
                            "train_s": train_s}
-    return {"workload": "16d_m65536_gauss", "N_per_snr": N, "per_snr": res}
+    # the exact kernel's own instruction-mix ceiling at four K steps and 16 label bits
+    mix4 = md.ubench("tile_mix4")[0]
+    for v in res.values():
+        v["exact_frac_tile_mix4"] = v["exact_pairs_per_s"] / mix4
+    return {"workload": "16d_m65536_gauss", "N_per_snr": N, "per_snr": res, "tile_mix4_exp_per_s": mix4,
+            "tile_mix4_basis": "ubench tile_mix4: four dependent FP16 MFMAs per 32 x 32 tile from LDS operands, "
+                               "16 exponentials per lane of the previous tile's products, position adds, tile-sum "
+                               "tree, 8 routed bits per 8 tiles, without memory traffic (N M / this rate is the "
+                               "least time this instruction mix allows)"}
 
 
 def extra_rx(md, seconds):

@@ -520,6 +520,8 @@ int kk_frontend(const float* d_x, int64_t T, float A, double nu, float* d_out, v
  *                    16 exponentials per lane of the previous tile's products, their
  *                    position adds and tile-sum tree, group routing every 8 tiles
  *                                                               -> exponentials/s
+ *   MD_UB_TILE_MIX4  the same at four K steps and 16 label bits (four MFMAs per tile,
+ *                    8 routed bits)                             -> exponentials/s
  * Returns MD_OK, MD_EINVAL (unknown kind, work < 0, a copy without buffers, with work not a
  * positive multiple of 16 or with unaligned buffers), MD_ENOMEM, MD_EHIP. */
 #define MD_UB_EXP       0
@@ -530,6 +532,7 @@ int kk_frontend(const float* d_x, int64_t T, float A, double nu, float* d_out, v
 #define MD_UB_COPY      5
 #define MD_UB_EXP_ADD2  6
 #define MD_UB_TILE_MIX  7
+#define MD_UB_TILE_MIX4 8
 int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rate, double* h_ms, void* stream);
 
 /* ------------------------------------------------------------------ kernel timing */

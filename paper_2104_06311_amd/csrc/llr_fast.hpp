@@ -174,17 +174,38 @@ __device__ __forceinline__ void stage_chunk(uint4* __restrict__ dst, const uint4
   }
 }
 
+// Copies `total` uint4 (a multiple of 64: whole 1 KiB blocks) from global memory straight
+// into LDS: wavefront w issues the direct loads (global_load_lds_dwordx4, 16 bytes per
+// lane) of blocks w, w + NT/64, ... with a wave-uniform LDS base, and waits for them, so
+// that the whole chunk is in flight at once without passing through registers.  The
+// caller's barrier then publishes it to the block.
+template <int NT>
+__device__ __forceinline__ void stage_chunk_direct(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                   int total) {
+  constexpr int NW = NT / 64;
+  const int lane = threadIdx.x & 63;
+  const int wave_u = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+  const int nblk = total >> 6;
+  for (int b = wave_u; b < nblk; b += NW)
+    __builtin_amdgcn_global_load_lds(src + b * 64 + lane, dst + b * 64, 16, 0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+}
+
 // Stages one fragment chunk: a constellation whose fragments all fit in LDS beside the NB
 // staging bytes is copied once per block by the plain loop; larger ones are re-copied for
-// every symbol group, with the batched loads of stage_chunk.  The choice is made at compile
-// time, so that the resident kernels keep their register allocation.
+// every symbol group by direct global-to-LDS loads.  The choice is made at compile time, so
+// that the resident kernels keep their register allocation.
+template <int KS, int MB, int NB>
+constexpr bool fragments_resident() {
+  return (MB >= 5) && ((1 << MB) / 32) * KS * 1024 + NB <= 160 * 1024;
+}
+
 template <int KS, int MB, int NT, int NB>
 __device__ __forceinline__ void copy_chunk(uint4* __restrict__ dst, const uint4* __restrict__ src, int total) {
-  constexpr bool kResident = (MB >= 5) && ((1 << MB) / 32) * KS * 1024 + NB <= 160 * 1024;
-  if constexpr (kResident) {
+  if constexpr (fragments_resident<KS, MB, NB>()) {
     for (int i = threadIdx.x; i < total; i += NT) dst[i] = src[i];
   } else {
-    stage_chunk<NT>(dst, src, total);
+    stage_chunk_direct<NT>(dst, src, total);
   }
 }
 
@@ -420,11 +441,18 @@ __global__ void __launch_bounds__(WAVES * 64) llr_fast_kernel(const uint4* __res
   const int64_t ngroups = (N + per_group - 1) / per_group;
   const int nchunks = (ntiles + chunk_tiles - 1) / chunk_tiles;
   const int frag_per_tile = KS * 64;
-  // per-wave staging rows for the B operand, after the fragment chunk
-  _Float16* bst = reinterpret_cast<_Float16*>(lds + chunk_tiles * frag_per_tile) + wave * SB * 32 * S;
+  // per-wave staging rows for the B operand: after the fragment chunk, or, when the
+  // fragments pass through LDS in several chunks, over the chunk buffer's start (the rows
+  // are read once per group, before its first chunk is copied), so that the chunks can be
+  // larger; the launcher sizes the buffer for either layout
+  constexpr bool kMayOverlay = !fragments_resident<KS, MB, WAVES * SB * bstage_bytes<KS>()>();
+  const bool overlay = kMayOverlay && nchunks > 1;
+  _Float16* bst = reinterpret_cast<_Float16*>(overlay ? lds : lds + chunk_tiles * frag_per_tile) + wave * SB * 32 * S;
   bool staged = false;
 
   for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    // overlaid rows: every wavefront has left the previous group's last chunk
+    if (overlay) __syncthreads();
     half8 bf[SB][KS];
     SymAcc<MB> ac[SB];
     bool bad[SB];
@@ -641,7 +669,17 @@ int launch_fast_t(const Prepared& P, int M, int D, const float* d_y, int64_t N, 
   chunk_tiles -= chunk_tiles % G;
   if (chunk_tiles > ntiles) chunk_tiles = ntiles;
   if (chunk_tiles < G) return fail(MD_EUNSUPPORTED, "constellation fragments do not fit in LDS");
-  const size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
+  size_t lds_bytes = static_cast<size_t>(chunk_tiles) * frag_tile_bytes + bstage;
+  if constexpr (!fragments_resident<KS, MB, WAVES * SB * bstage_bytes<KS>()>()) {
+    // several chunks: the staging rows go over the chunk buffer's start (see the kernel)
+    // and the buffer keeps two spare tiles for the tile loop's prefetch past its end
+    int ov = (160 * 1024) / frag_tile_bytes - 2;
+    ov -= ov % G;
+    if (chunk_tiles < ntiles && ov < ntiles && ov > chunk_tiles && ov * frag_tile_bytes >= bstage) {
+      chunk_tiles = ov;
+      lds_bytes = static_cast<size_t>(ov + 2) * frag_tile_bytes;
+    }
+  }
   if constexpr (KS == 4 && WAVES == 16 && SB == 1 && SC == 0 && !GMI && MAXLOG && MB >= 10) {
     // max-log with fragments beyond LDS: stream them through two buffers (an even number of
     // chunks) with twelve wavefronts per block.  The exact path keeps the synchronous

@@ -73,52 +73,54 @@ __global__ void __launch_bounds__(kThreads) ub_exp_add2_kernel(int64_t iters, fl
   if (r == kNever) sink[0] = r;
 }
 
-// The exact demapper's per-tile instruction mix at two K steps (D <= 9) and 11 label
-// bits, without its memory traffic: per 32 x 32 tile, two dependent
-// v_mfma_f32_32x32x16_f16 score the next tile from A operands read from LDS (a ring of
-// kMixTiles tiles), then each lane takes 16 exponentials of the current tile's products,
-// adds each into its position sum and reduces them by a 15-add tree into the tile's
-// group sum; every 8 tiles the group sum is routed by 3 bits.  Hard scheduling fences
-// keep the matrix products of tile t + 1 ahead of the exponentials of tile t, as in the
-// demapper, so its rate is the ceiling that instruction mix allows on this device.  Blocks
-// of 16 wavefronts, like the demapper's, leave 128 registers per lane, so the products
-// stay in ordinary vector registers as they do there.
+// The exact demapper's per-tile instruction mix at KS K steps and 5 + 3 + NH label bits,
+// without its memory traffic: per 32 x 32 tile, KS dependent v_mfma_f32_32x32x16_f16
+// score the next tile from A operands read from LDS (a ring of kMixTiles tiles), then
+// each lane takes 16 exponentials of the current tile's products, adds each into its
+// position sum and reduces them by a 15-add tree into the tile's group sum; every 8 tiles
+// the group sum is routed by NH bits.  Hard scheduling fences keep the matrix products of
+// tile t + 1 ahead of the exponentials of tile t, as in the demapper, so its rate is the
+// ceiling that instruction mix allows on this device (KS = 2, NH = 3: the 8D M = 2048
+// kernel; KS = 4, NH = 8: the 16D M = 65536 one).  Blocks of 16 wavefronts, like the
+// demapper's, leave 128 registers per lane, so the products stay in ordinary vector
+// registers as they do there.
 constexpr int kMixTiles = 8;
 constexpr int kMixGroup = 8;
 constexpr int kMixThreads = 1024;
 
+template <int KS, int NH>
 __global__ void __launch_bounds__(kMixThreads) ub_tile_mix_kernel(int64_t iters, float seed, float* sink) {
-  __shared__ uint4 frag[kMixTiles * 2 * 64];
+  __shared__ uint4 frag[kMixTiles * KS * 64];
   const int lane = threadIdx.x & 63;
-  for (int i = threadIdx.x; i < kMixTiles * 2 * 64; i += kMixThreads) {
+  for (int i = threadIdx.x; i < kMixTiles * KS * 64; i += kMixThreads) {
     half8 h;
 #pragma unroll
     for (int v = 0; v < 8; ++v) h[v] = static_cast<_Float16>(seed * static_cast<float>((i + v) & 15) - 0.004f);
     __builtin_memcpy(&frag[i], &h, 16);
   }
   __syncthreads();
-  half8 bf[2], ah[2];
+  half8 bf[KS], ah[KS];
 #pragma unroll
-  for (int ks = 0; ks < 2; ++ks)
+  for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
     for (int v = 0; v < 8; ++v) bf[ks][v] = static_cast<_Float16>(seed * static_cast<float>((lane + v + ks) & 31));
-  float pos[16], tg[kMixGroup], h0[3], h1[3], gt = 0.0f;
+  float pos[16], tg[kMixGroup], h0[NH], h1[NH], gt = 0.0f;
 #pragma unroll
   for (int r = 0; r < 16; ++r) pos[r] = 0.0f;
 #pragma unroll
   for (int i = 0; i < kMixGroup; ++i) tg[i] = 0.0f;
 #pragma unroll
-  for (int q = 0; q < 3; ++q) h0[q] = h1[q] = 0.0f;
+  for (int q = 0; q < NH; ++q) h0[q] = h1[q] = 0.0f;
   floatx16 cur;
 #pragma unroll
   for (int r = 0; r < 16; ++r) cur[r] = 0.0f;
 #pragma unroll
-  for (int ks = 0; ks < 2; ++ks) {
+  for (int ks = 0; ks < KS; ++ks) {
     __builtin_memcpy(&ah[ks], &frag[ks * 64 + lane], 16);
     cur = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[ks], cur, 0, 0, 0);
   }
 #pragma unroll
-  for (int ks = 0; ks < 2; ++ks) __builtin_memcpy(&ah[ks], &frag[(2 + ks) * 64 + lane], 16);
+  for (int ks = 0; ks < KS; ++ks) __builtin_memcpy(&ah[ks], &frag[(KS + ks) * 64 + lane], 16);
   for (int64_t it = 0; it < iters; ++it) {
 #pragma unroll
     for (int i = 0; i < kMixGroup; ++i) {
@@ -126,10 +128,10 @@ __global__ void __launch_bounds__(kMixThreads) ub_tile_mix_kernel(int64_t iters,
 #pragma unroll
       for (int r = 0; r < 16; ++r) nxt[r] = 0.0f;
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) nxt = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[ks], nxt, 0, 0, 0);
+      for (int ks = 0; ks < KS; ++ks) nxt = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[ks], bf[ks], nxt, 0, 0, 0);
       const int t = (i + 2) & (kMixTiles - 1);
 #pragma unroll
-      for (int ks = 0; ks < 2; ++ks) __builtin_memcpy(&ah[ks], &frag[(t * 2 + ks) * 64 + lane], 16);
+      for (int ks = 0; ks < KS; ++ks) __builtin_memcpy(&ah[ks], &frag[(t * KS + ks) * 64 + lane], 16);
       __builtin_amdgcn_sched_barrier(0);
       float v[16];
 #pragma unroll
@@ -148,7 +150,7 @@ __global__ void __launch_bounds__(kMixThreads) ub_tile_mix_kernel(int64_t iters,
     }
     const int grp = static_cast<int>(it);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < NH; ++q) {
       const bool bit = (grp >> q) & 1;
       h1[q] += bit ? gt : 0.0f;
       h0[q] += bit ? 0.0f : gt;
@@ -160,7 +162,7 @@ __global__ void __launch_bounds__(kMixThreads) ub_tile_mix_kernel(int64_t iters,
 #pragma unroll
   for (int i = 0; i < kMixGroup; ++i) r += tg[i];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) r += h0[q] * h1[q];
+  for (int q = 0; q < NH; ++q) r += h0[q] * h1[q];
   if (r == kNever) sink[0] = r;
 }
 
@@ -205,7 +207,7 @@ __global__ void __launch_bounds__(kThreads) ub_copy_kernel(const uint4* __restri
 }
 
 constexpr double kMfmaFlop[3] = {2.0 * 32 * 32 * 16, 2.0 * 32 * 32 * 16, 2.0 * 32 * 32 * 2};
-constexpr int64_t kDefaultIters[8] = {8192, 8192, 4096, 4096, 2048, 0, 8192, 1024};
+constexpr int64_t kDefaultIters[9] = {8192, 8192, 4096, 4096, 2048, 0, 8192, 1024, 512};
 
 int launch_kind(int kind, int64_t work, int blocks, const void* d_src, void* d_dst, float* sink, hipStream_t s) {
   const int64_t iters = work > 0 ? work : kDefaultIters[kind];
@@ -225,7 +227,10 @@ int launch_kind(int kind, int64_t work, int blocks, const void* d_src, void* d_d
       hipLaunchKernelGGL(ub_exp_add2_kernel, dim3(blocks), dim3(kThreads), 0, s, iters, 1e-3f, sink);
       break;
     case MD_UB_TILE_MIX:
-      hipLaunchKernelGGL(ub_tile_mix_kernel, dim3(blocks / 4), dim3(kMixThreads), 0, s, iters, 1e-3f, sink);
+      hipLaunchKernelGGL((ub_tile_mix_kernel<2, 3>), dim3(blocks / 4), dim3(kMixThreads), 0, s, iters, 1e-3f, sink);
+      break;
+    case MD_UB_TILE_MIX4:
+      hipLaunchKernelGGL((ub_tile_mix_kernel<4, 8>), dim3(blocks / 4), dim3(kMixThreads), 0, s, iters, 1e-3f, sink);
       break;
     default: {
       const int64_t n = work / 16;
@@ -247,7 +252,7 @@ extern "C" {
 
 int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rate, double* h_ms, void* stream) {
   using namespace md;
-  if (kind < MD_UB_EXP || kind > MD_UB_TILE_MIX) return fail(MD_EINVAL, "ubench: unknown kind");
+  if (kind < MD_UB_EXP || kind > MD_UB_TILE_MIX4) return fail(MD_EINVAL, "ubench: unknown kind");
   if (work < 0) return fail(MD_EINVAL, "ubench: work must be >= 0");
   if (kind == MD_UB_COPY) {
     if (d_src == nullptr || d_dst == nullptr) return fail(MD_EINVAL, "ubench: the copy needs d_src and d_dst");
@@ -290,7 +295,8 @@ int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rat
     case MD_UB_EXP:
     case MD_UB_EXP_ADD2:
     case MD_UB_ADD_F32: amount = lanes * static_cast<double>(iters) * kChains; break;
-    case MD_UB_TILE_MIX: amount = lanes * static_cast<double>(iters) * kMixGroup * 16; break;
+    case MD_UB_TILE_MIX:
+    case MD_UB_TILE_MIX4: amount = lanes * static_cast<double>(iters) * kMixGroup * 16; break;
     case MD_UB_MFMA_F16:
     case MD_UB_MFMA_BF16:
     case MD_UB_MFMA_F32:
