@@ -192,7 +192,7 @@ __device__ void process_item(const Problem& P, const Item& I, int it, uint4* lds
         __syncthreads();
         const int total = tn * frag_per_tile;
         const uint4* src = P.frag + static_cast<int64_t>(t0) * frag_per_tile;
-        fastk::stage_chunk<WAVES * 64>(lds, src, total);
+        fastk::stage_chunk_direct<WAVES * 64>(lds, src, total);
         __syncthreads();
         staged_prob = (nchunks > 1) ? -1 : I.prob;
       }
