@@ -164,6 +164,20 @@ def test_parity_random_problems(M, D, N, snr, perm):
     _parity(X, labels, snr, N, 31 + M)
 
 
+@pytest.mark.parametrize("M,D,N,snr,maxlog", [
+    (4096, 8, 2000, 13.0, False), (8192, 8, 1500, 10.0, False), (8192, 8, 1500, 10.0, True),
+    (16384, 5, 700, 18.0, False),
+])
+def test_parity_streamed_fragments(M, D, N, snr, maxlog):
+    """Constellations whose fragments exceed LDS (two K steps: 128, 256 and 512 tiles of
+    2 KiB): the exact and max-log kernels copy them chunk by chunk for every symbol group,
+    with a partial last chunk (72-tile chunks), the staging rows over the chunk buffer, and
+    high SNR sending symbols through the wide-range passes."""
+    X, labels = synth.gaussian_constellation(M, D, 5000 + M + D)
+    labels = synth.random_labels(M, M + 3 * D)
+    _parity(X, labels, snr, N, 61 + M, maxlog=maxlog)
+
+
 @pytest.mark.parametrize("M,D,N,snr", [(2048, 8, 20_000, 4.0), (2048, 8, 20_000, 14.0), (64, 4, 30_001, 8.0),
                                        (32, 2, 3000, 10.0), (4096, 8, 2000, 12.0), (256, 16, 1500, 9.0),
                                        (128, 30, 700, 15.0)])
