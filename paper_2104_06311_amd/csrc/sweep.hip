@@ -105,6 +105,37 @@ __device__ __forceinline__ bool write_symbol_row(_Float16* row, const float (&yv
   return bad;
 }
 
+// The channel use of symbol `local` of item I: its received vector (yv[d] for d < D, zeros
+// after) and its point index.
+__device__ __forceinline__ uint32_t draw_symbol(const Problem& P, const Item& I, int64_t local, float (&yv)[8]) {
+  const uint64_t g = P.offset + static_cast<uint64_t>(I.start + local);
+  switch (P.D) {      // compile-time D: the received vector stays in registers
+    case 1: return rng::channel_symbol_d<1>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv);
+    case 2: return rng::channel_symbol_d<2>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv);
+    case 3: return rng::channel_symbol_d<3>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv);
+    case 4: return rng::channel_symbol_d<4>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv);
+    case 5: return rng::channel_symbol_d<5>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv);
+    case 6: return rng::channel_symbol_d<6>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv);
+    case 7: return rng::channel_symbol_d<7>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv);
+    default: return rng::channel_symbol_d<8>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv);
+  }
+}
+
+// Queues a symbol for the FP64 fallback kernel.
+__device__ __forceinline__ void queue_fallback(const Item& I, uint32_t lab, const float (&yv)[8],
+                                               int* __restrict__ counters, FbRecord* __restrict__ fb) {
+  const int idx = atomicAdd(&counters[1], 1);
+  if (idx < kFbCap) {
+    FbRecord& r = fb[idx];
+    r.prob = I.prob;
+    r.label = lab;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) r.y[d] = yv[d];
+  } else {
+    atomicOr(&counters[2], 1);
+  }
+}
+
 template <int WAVES, int SB, int KS, int MB>
 __device__ void process_item(const Problem& P, const Item& I, int it, uint4* lds, int& staged_prob,
                              double* __restrict__ item_sum, FbRecord* __restrict__ fb, int* __restrict__ counters,
@@ -118,48 +149,30 @@ __device__ void process_item(const Problem& P, const Item& I, int it, uint4* lds
   _Float16* bst = reinterpret_cast<_Float16*>(lds + P.chunk_tiles * frag_per_tile) + wave * SB * 32 * S;
   const bool half_tile = P.M < 32;
   float acc_loss = 0.0f;
+  // Channel draw.  SB = 2: lane half h draws symbol block h of every group.  SB = 1: both
+  // halves draw every other group, half 0 the symbols of group gi and half 1 those of group
+  // gi + 1, whose staging rows it writes once the operands of group gi are read; the
+  // (label, live, out-of-range) state of a symbol stays with the half that drew it.
+  uint32_t lab_own = 0;
+  bool live_own = false, bad_own = false;
   for (int gi = 0; gi < ngroups; ++gi) {
-    // ---- channel draw by the owning lanes, symbol rows into LDS
-    const int owner_sb = (SB == 2) ? h : 0;
-    const bool owner = (SB == 2) || h == 0;
-    const int64_t local = static_cast<int64_t>(gi) * per_group + (wave * SB + owner_sb) * 32 + (lane & 31);
-    const bool live_own = owner && local < I.count;
-    uint32_t lab_own = 0;
-    bool bad_own = false;
+    const bool draw_now = SB == 2 || (gi & 1) == 0;
+    // the lane half that holds this group's symbols (SB = 1) or block sb's (SB = 2: half sb)
+    const int cur_half = SB == 2 ? 0 : (gi & 1);
     float yv_own[8];
 #pragma unroll
     for (int d = 0; d < 8; ++d) yv_own[d] = 0.0f;
-    if (owner) {
-      float (&yv)[8] = yv_own;
-      if (live_own) {
-        const uint64_t g = P.offset + static_cast<uint64_t>(I.start + local);
-        uint32_t u = 0;
-        switch (P.D) {      // compile-time D: the received vector stays in registers
-          case 1: u = rng::channel_symbol_d<1>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
-          case 2: u = rng::channel_symbol_d<2>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
-          case 3: u = rng::channel_symbol_d<3>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
-          case 4: u = rng::channel_symbol_d<4>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
-          case 5: u = rng::channel_symbol_d<5>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
-          case 6: u = rng::channel_symbol_d<6>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
-          case 7: u = rng::channel_symbol_d<7>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
-          default: u = rng::channel_symbol_d<8>(P.X, P.m, P.k0, P.k1, g, P.sigma, yv); break;
-        }
-        lab_own = P.labels[u];
-      }
-      _Float16* row = bst + (owner_sb * 32 + (lane & 31)) * S;
-      bad_own = write_symbol_row<KS>(row, yv, P.D, P.cb, P.cn, P.alpha, fastk::kExpBias);
-      if (live_own && bad_own) {
+    if (draw_now) {
+      const int64_t local = SB == 2 ? static_cast<int64_t>(gi) * per_group + (wave * SB + h) * 32 + (lane & 31)
+                                    : static_cast<int64_t>(gi + h) * per_group + wave * 32 + (lane & 31);
+      live_own = local < I.count;
+      lab_own = 0;
+      if (live_own) lab_own = P.labels[draw_symbol(P, I, local, yv_own)];
+      if (SB == 2 || h == 0) {
+        _Float16* row = bst + ((SB == 2 ? h : 0) * 32 + (lane & 31)) * S;
+        bad_own = write_symbol_row<KS>(row, yv_own, P.D, P.cb, P.cn, P.alpha, fastk::kExpBias);
         // operands outside the FP16 split range: straight to the FP64 fallback
-        const int idx = atomicAdd(&counters[1], 1);
-        if (idx < kFbCap) {
-          FbRecord& r = fb[idx];
-          r.prob = I.prob;
-          r.label = lab_own;
-#pragma unroll
-          for (int d = 0; d < 8; ++d) r.y[d] = yv[d];
-        } else {
-          atomicOr(&counters[2], 1);
-        }
+        if (live_own && bad_own) queue_fallback(I, lab_own, yv_own, counters, fb);
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -173,13 +186,20 @@ __device__ void process_item(const Problem& P, const Item& I, int it, uint4* lds
         const uint4 v = *reinterpret_cast<const uint4*>(bst + (sb * 32 + (lane & 31)) * S + 16 * ks + 8 * h);
         __builtin_memcpy(&bf[sb][ks], &v, 16);
       }
-    // the rows are consumed: the owners park their received vectors there (8 floats <= 32 KS
-    // bytes) for the rare symbol that needs the FP64 fallback after the tile loop
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (owner) {
-      float* yrow = reinterpret_cast<float*>(bst + (owner_sb * 32 + (lane & 31)) * S);
+    if constexpr (SB == 1) {
+      // the rows are consumed: half 1 stages the next group's symbols in them
+      if (draw_now && h == 1) {
+        _Float16* row = bst + (lane & 31) * S;
+        bad_own = write_symbol_row<KS>(row, yv_own, P.D, P.cb, P.cn, P.alpha, fastk::kExpBias);
+        if (live_own && bad_own) queue_fallback(I, lab_own, yv_own, counters, fb);
+      }
+    } else {
+      // the owners park their received vectors there (8 floats <= 32 KS bytes) for the
+      // rare symbol that needs the FP64 fallback after the tile loop
+      float* yrow = reinterpret_cast<float*>(bst + (h * 32 + (lane & 31)) * S);
 #pragma unroll
       for (int d = 0; d < 8; ++d) yrow[d] = yv_own[d];
     }
@@ -203,8 +223,8 @@ __device__ void process_item(const Problem& P, const Item& I, int it, uint4* lds
     for (int sb = 0; sb < SB; ++sb) {
       float S0[MB], S1[MB];
       fastk::combine_subsets<MB, false>(ac[sb], half_tile, S0, S1);
-      // the owner of block sb is lane half sb (SB = 2) or half 0 (SB = 1)
-      const int src = (SB == 2 && sb == 1) ? 32 : 0;
+      // the owner of block sb is lane half sb (SB = 2) or the half that drew the group (SB = 1)
+      const int src = 32 * (SB == 2 ? sb : cur_half);
       const uint32_t lab = __shfl(lab_own, src + (lane & 31), 64);
       const bool live = __shfl(static_cast<int>(live_own), src + (lane & 31), 64) != 0;
       const bool bad = __shfl(static_cast<int>(bad_own), src + (lane & 31), 64) != 0;
@@ -229,21 +249,19 @@ __device__ void process_item(const Problem& P, const Item& I, int it, uint4* lds
             }
           acc_loss += T;
         } else {
-          // the owner parked the received vector in the symbol's staging row
-          const float* yrow = reinterpret_cast<const float*>(bst + (sb * 32 + (lane & 31)) * S);
           float yv[8];
 #pragma unroll
-          for (int d = 0; d < 8; ++d) yv[d] = yrow[d];
-          const int idx = atomicAdd(&counters[1], 1);
-          if (idx < kFbCap) {
-            FbRecord& r = fb[idx];
-            r.prob = I.prob;
-            r.label = lab;
+          for (int d = 0; d < 8; ++d) yv[d] = 0.0f;
+          if constexpr (SB == 2) {
+            // the owner parked the received vector in the symbol's staging row
+            const float* yrow = reinterpret_cast<const float*>(bst + (sb * 32 + (lane & 31)) * S);
 #pragma unroll
-            for (int d = 0; d < 8; ++d) r.y[d] = yv[d];
+            for (int d = 0; d < 8; ++d) yv[d] = yrow[d];
           } else {
-            atomicOr(&counters[2], 1);
+            // the rows hold the next group's operands: draw the channel use again
+            (void)draw_symbol(P, I, static_cast<int64_t>(gi) * per_group + wave * 32 + (lane & 31), yv);
           }
+          queue_fallback(I, lab, yv, counters, fb);
         }
       }
     }

@@ -138,13 +138,17 @@ def test_every_class_of_the_mixed_sweep_against_oracle():
                 assert abs(g[i, s] - gr) <= 1e-4, (variant, specs[i], s, g[i, s], gr)
 
 
-def test_fp64_fallback_at_high_snr_against_oracle():
+@pytest.mark.parametrize("variant", [0, 3])
+def test_fp64_fallback_at_high_snr_against_oracle(variant):
     """At 20 and 24 dB the label-1 or label-0 subset of many symbols lies beyond the FP32
     range of the fast pass: those symbols take the FP64 fallback kernel, whose 2^-40
-    fixed-point losses must still give the oracle's GMI."""
+    fixed-point losses must still give the oracle's GMI.  Variant 0 runs two symbol blocks
+    per wavefront (the received vectors parked in the staging rows for the fallback),
+    variant 3 one block per wavefront (both lane halves draw, every other group, and a
+    fallback symbol's received vector is drawn again)."""
     inst, host = make_instances([(2048, 8, 3000), (4096, 8, 2000), (1024, 4, 2500)], seed=33)
     s2 = sigma2_grid(host, [20.0, 24.0])
-    plan = md().SweepPlan(inst, s2, variant=0)
+    plan = md().SweepPlan(inst, s2, variant=variant)
     g = plan.run().cpu().numpy()
     n_fb, overflow = plan.stats()
     assert n_fb > 0 and not overflow, (n_fb, overflow)
