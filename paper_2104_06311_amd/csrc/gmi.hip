@@ -103,10 +103,13 @@ __global__ void __launch_bounds__(kBlock) gmi_partial_kernel(const float* __rest
   if (threadIdx.x == 0) partials[(2 + MB) * nb + blockIdx.x] = v;
 }
 
-// The same partials from the per-symbol loss terms T_n that the fused demapping pass
-// wrote; a NaN term marks a symbol the fast pass left to the later passes (or a bad
-// index), whose term is formed here from its final LLRs like gmi_partial_kernel does.
-// No per-bit columns.
+// Block partials of the per-symbol loss terms T_n that the fused demapping pass wrote,
+// three columns [sum T, sum T^2, count of non-finite T] (column c of block b at
+// partials[c * nblocks + b]); a NaN term marks a symbol the fast pass left to the later
+// passes (or a bad index), whose term is formed here from its final LLRs like
+// gmi_partial_kernel does.
+constexpr int kTermsMaxBlocks = 1024;
+
 template <int MB>
 __global__ void __launch_bounds__(kBlock) gmi_terms_partial_kernel(const float* __restrict__ terms,
                                                                    const float* __restrict__ llr, int64_t N,
@@ -117,9 +120,9 @@ __global__ void __launch_bounds__(kBlock) gmi_terms_partial_kernel(const float* 
   Kahan sT{0.f, 0.f}, sT2{0.f, 0.f};
   int nonfinite = 0;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * kBlock;
-  // four coalesced loads in flight per thread before any of them is used: the pass reads
+  // eight coalesced loads in flight per thread before any of them is used: the pass reads
   // 4 bytes per symbol, so it is bound by load latency, not by bandwidth, one at a time
-  constexpr int U = 4;
+  constexpr int U = 8;
   for (int64_t n0 = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; n0 < N; n0 += U * stride) {
     float Tu[U];
 #pragma unroll
@@ -153,11 +156,34 @@ __global__ void __launch_bounds__(kBlock) gmi_terms_partial_kernel(const float* 
   if (threadIdx.x == 0) partials[0 * nb + blockIdx.x] = v;
   v = block_sum(sT2.get(), sh);
   if (threadIdx.x == 0) partials[1 * nb + blockIdx.x] = v;
-#pragma unroll
-  for (int k = 0; k < MB; ++k)
-    if (threadIdx.x == 0) partials[(2 + k) * nb + blockIdx.x] = 0.0;
   v = block_sum(static_cast<double>(nonfinite), sh);
-  if (threadIdx.x == 0) partials[(2 + MB) * nb + blockIdx.x] = v;
+  if (threadIdx.x == 0) partials[2 * nb + blockIdx.x] = v;
+}
+
+// One block: the three columns of gmi_terms_partial_kernel summed in a fixed order, then
+// GMI = m - sum T / N, its standard error, and the count of non-finite terms.
+__global__ void __launch_bounds__(kBlock) gmi_terms_tail_kernel(const double* __restrict__ partials, int nblocks,
+                                                                int64_t N, int m, double* __restrict__ gmi,
+                                                                double* __restrict__ se,
+                                                                long long* __restrict__ status) {
+  __shared__ double sh[kBlock];
+  double tot[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) a += partials[static_cast<int64_t>(c) * nblocks + b];
+    tot[c] = block_sum(a, sh);
+  }
+  if (threadIdx.x == 0) {
+    const double Nd = static_cast<double>(N);
+    status[0] = static_cast<long long>(tot[2]);
+    const double mean = tot[0] / Nd;
+    gmi[0] = static_cast<double>(m) - mean;
+    if (se) {
+      const double var = N > 1 ? (tot[1] - tot[0] * mean) / (Nd - 1.0) : 0.0;
+      se[0] = var > 0.0 ? sqrt(var) / sqrt(Nd) : 0.0;
+    }
+  }
 }
 
 // One block per column: the block partials of column c summed in a fixed order.
@@ -304,7 +330,12 @@ int launch_gmi_tail(double* partials, int nb, int64_t N, int m, double* d_gmi, d
 int launch_gmi_terms(const float* d_terms, const float* d_llr, int64_t N, int m, const uint32_t* d_tx,
                      const uint32_t* d_labels, double* d_gmi, double* d_se, char* ws, long long* status,
                      hipStream_t stream) {
-  const int nb = gmi_blocks(N);
+  // about 16 terms per thread, at most kTermsMaxBlocks blocks (3 partials each: within the
+  // gmi_workspace_bytes of the per-bit reduction)
+  int64_t nb64 = (N + 16 * kBlock - 1) / (16 * kBlock);
+  if (nb64 > kTermsMaxBlocks) nb64 = kTermsMaxBlocks;
+  if (nb64 < 1) nb64 = 1;
+  const int nb = static_cast<int>(nb64);
   double* partials = reinterpret_cast<double*>(ws);
   switch (m) {
 #define MD_GMI_CASE(MB_)                                                                                    \
@@ -318,7 +349,10 @@ int launch_gmi_terms(const float* d_terms, const float* d_llr, int64_t N, int m,
 #undef MD_GMI_CASE
   }
   MD_LAUNCH_CHECK("gmi_terms_partial_kernel launch");
-  return launch_gmi_tail(partials, nb, N, m, d_gmi, nullptr, d_se, status, stream);
+  hipLaunchKernelGGL(gmi_terms_tail_kernel, dim3(1), dim3(kBlock), 0, stream, partials, nb, N, m, d_gmi, d_se,
+                     status);
+  MD_LAUNCH_CHECK("gmi_terms_tail_kernel launch");
+  return MD_OK;
 }
 
 int launch_gmi(const float* d_llr, int64_t N, int m, const uint32_t* d_tx, const uint32_t* d_labels, double* d_gmi,
