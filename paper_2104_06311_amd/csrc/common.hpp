@@ -120,6 +120,9 @@ struct Prepared {
   const uint32_t* gmi_tx = nullptr;
   const uint32_t* gmi_labels = nullptr;
   float* gmi_terms = nullptr;
+  // per-point score terms of the one-thread-per-symbol demapper (label order, D + 1 floats
+  // per point: 2c x_j, then -c ||x_j||^2); null for the shapes it does not take
+  const float* vx = nullptr;
 };
 
 // Builds the label-ordered copy, fragments and flags for one call.  `ws` must point

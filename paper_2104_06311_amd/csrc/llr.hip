@@ -350,7 +350,11 @@ int launch_llr(const Prepared& P, int M, int D, const float* d_y, int64_t N, dou
     return launch_careful_t<false>(P, M, D, d_y, N, sigma2, d_llr, P.fb_list, 1, stream);
   }
   const int slot = timing_begin(stream);
-  int st = P.gmi_terms ? launch_fast_gmi(P, M, D, d_y, N, sigma2, d_llr, stream)
+  // M = 32 and 64 (D <= 8): one thread per symbol, for llr_exact and llr_exact_gmi alike,
+  // so that both give the same LLRs
+  const bool vec = prec != MD_PREC_BF16 && vec_exact_supported(M, D) && P.vx;
+  int st = vec ? launch_vec_exact(P, M, D, d_y, N, d_llr, stream)
+           : P.gmi_terms ? launch_fast_gmi(P, M, D, d_y, N, sigma2, d_llr, stream)
            : prec == MD_PREC_BF16 ? launch_fast_bf16(P, M, D, d_y, N, d_llr, stream)
                                   : launch_fast_exact(P, M, D, d_y, N, sigma2, d_llr, stream);
   timing_end(stream, slot);

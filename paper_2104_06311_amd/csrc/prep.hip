@@ -30,6 +30,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "llr_kernels.hpp"
 
 namespace md {
 namespace {
@@ -74,9 +75,22 @@ __device__ __forceinline__ void split_bf16(float v, _Float16* hi, _Float16* lo) 
 __global__ void prep_build_kernel(const float* __restrict__ X, const uint32_t* __restrict__ labels,
                                   const uint32_t* __restrict__ inv, int M, int Mpad, int D, int KS, int sc,
                                   float alpha, float c_over_alpha, float* __restrict__ xl,
-                                  uint4* __restrict__ frag, int* __restrict__ flags) {
+                                  uint4* __restrict__ frag, int* __restrict__ flags, float* __restrict__ vx) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= Mpad) return;
+  if (vx && s < M) {
+    // the vector demapper's terms: 2c x (D floats) and -c ||x||^2, FP32 as it computes
+    const uint32_t jv = inv[s];
+    const bool okv = jv < static_cast<uint32_t>(M) && labels[jv] == static_cast<uint32_t>(s);
+    const float c = c_over_alpha * alpha;
+    float n32 = 0.0f;
+    for (int d = 0; d < D; ++d) {
+      const float v = okv ? X[static_cast<int64_t>(jv) * D + d] : 0.0f;
+      vx[static_cast<int64_t>(s) * (D + 1) + d] = 2.0f * c * v;
+      n32 = fmaf(v, v, n32);
+    }
+    vx[static_cast<int64_t>(s) * (D + 1) + D] = -c * n32;
+  }
   _Float16 row[kMaxSlots];
 #pragma unroll
   for (int k = 0; k < kMaxSlots; ++k) row[k] = static_cast<_Float16>(0.0f);
@@ -148,6 +162,7 @@ size_t prep_bytes(int M, int D, int64_t N) {
   b += carve_size(sizeof(uint32_t) * M);                                       // inv
   b += carve_size(sizeof(int) * 8);                                            // flags
   b += 2 * carve_size(sizeof(unsigned) * static_cast<size_t>(N > 0 ? N : 1)); // fallback lists
+  if (vec_exact_supported(M, D)) b += carve_size(sizeof(float) * static_cast<size_t>(M) * (D + 1));   // vx
   return b;
 }
 
@@ -163,19 +178,21 @@ int prepare(const float* d_X, const uint32_t* d_labels, int M, int D, int64_t N,
   int* flags = flags_given ? flags_given : flags_carved;
   unsigned* fb = cv.take<unsigned>(static_cast<size_t>(N > 0 ? N : 1));
   unsigned* fb2 = cv.take<unsigned>(static_cast<size_t>(N > 0 ? N : 1));
+  float* vx = (sc == 0 && vec_exact_supported(M, D)) ? cv.take<float>(static_cast<size_t>(M) * (D + 1)) : nullptr;
   const int bs = 256;
   hipLaunchKernelGGL(prep_init_kernel, dim3((M + bs - 1) / bs), dim3(bs), 0, stream, inv, M, flags);
   MD_LAUNCH_CHECK("prep_init_kernel launch");
   hipLaunchKernelGGL(prep_scatter_kernel, dim3((M + bs - 1) / bs), dim3(bs), 0, stream, d_labels, M, inv, flags);
   MD_LAUNCH_CHECK("prep_scatter_kernel launch");
   hipLaunchKernelGGL(prep_build_kernel, dim3((Mpad + bs - 1) / bs), dim3(bs), 0, stream, d_X, d_labels, inv, M,
-                     Mpad, D, KS, sc, alpha, c_over_alpha, xl, frag, flags);
+                     Mpad, D, KS, sc, alpha, c_over_alpha, xl, frag, flags, vx);
   MD_LAUNCH_CHECK("prep_build_kernel launch");
   out->xl = xl;
   out->frag = frag;
   out->flags = flags;
   out->fb_list = fb;
   out->fb_list2 = fb2;
+  out->vx = vx;
   out->ks = KS;
   out->sc = sc;
   out->alpha = alpha;

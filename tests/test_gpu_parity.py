@@ -164,6 +164,18 @@ def test_parity_random_problems(M, D, N, snr, perm):
     _parity(X, labels, snr, N, 31 + M)
 
 
+@pytest.mark.parametrize("M,D,N,snr", [
+    (64, 4, 3000, 30.0), (32, 8, 2000, 24.0), (64, 1, 2000, 20.0), (32, 3, 4097, 2.0), (64, 8, 1500, 14.0),
+])
+def test_parity_one_thread_per_symbol(M, D, N, snr):
+    """M = 32 and 64 with D <= 8 take the one-thread-per-symbol exact kernel (FP32 scores
+    from per-point terms); at 20-30 dB part of the symbols leave its FP32 range and are
+    finished by the wide-range and FP64 passes through the same fallback list."""
+    X, labels = synth.gaussian_constellation(M, D, 7000 + M + D)
+    labels = synth.random_labels(M, 5 * M + D)
+    _parity(X, labels, snr, N, 71 + M + D)
+
+
 @pytest.mark.parametrize("M,D,N,snr,maxlog", [
     (4096, 8, 2000, 13.0, False), (8192, 8, 1500, 10.0, False), (8192, 8, 1500, 10.0, True),
     (16384, 5, 700, 18.0, False),
