@@ -46,6 +46,7 @@ constexpr int kDynLds = 159 * 1024;  // dynamic LDS of the persistent kernel
 struct Problem {
   const uint4* frag;
   const float* xl;         // label order
+  const float* vx;         // per-point score terms (M = 32, 64: 2c x_j, -c ||x_j||^2), or null
   const float* X;          // index order (for the channel)
   const uint32_t* labels;  // label of each index
   int M, m, D, ks, ntiles, chunk_tiles;
@@ -324,6 +325,10 @@ __device__ __forceinline__ float small_item(const Problem& P, const Item& I, int
   // constant address space, so that they arrive by scalar loads into scalar registers
   typedef const __attribute__((address_space(4))) float ConstFloat;
   ConstFloat* xl = (ConstFloat*)P.xl;
+  // M = 32 and 64: the score from the per-point terms, sum_d y_d (2c x_jd) - c ||x_j||^2 +
+  // (bias - c ||y||^2), D + 1 operations per point as in llr_exact's one-thread-per-symbol
+  // kernel; M = 16 from the differences y - x_j
+  constexpr bool kTerms = MB == 5 || MB == 6;
   float acc = 0.0f;
   for (int local = lane; local < I.count; local += 64) {
     const uint64_t g = P.offset + static_cast<uint64_t>(I.start + local);
@@ -333,15 +338,34 @@ __device__ __forceinline__ float small_item(const Problem& P, const Item& I, int
     const uint32_t u = rng::channel_symbol_d<D>(P.X, MB, P.k0, P.k1, g, P.sigma, yv);
     const uint32_t lab = P.labels[u];
     float v[M];
+    if constexpr (kTerms) {
+      // the table's address passes through an empty asm statement on every symbol, so that
+      // its M (D + 1) terms are loaded as they are used rather than all hoisted
+      uint64_t vaddr = reinterpret_cast<uint64_t>(P.vx);
+      asm volatile("" : "+s"(vaddr));
+      ConstFloat* vx = reinterpret_cast<ConstFloat*>(vaddr);
+      float ysq = 0.0f;
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      float d2 = 0.0f;
+      for (int d = 0; d < D; ++d) ysq = fmaf(yv[d], yv[d], ysq);
+      const float r = fmaf(-cexp, ysq, fastk::kExpBias);
 #pragma unroll
-      for (int d = 0; d < D; ++d) {
-        const float df = yv[d] - xl[j * D + d];
-        d2 = fmaf(df, df, d2);
+      for (int j = 0; j < M; ++j) {
+        float t = vx[j * (D + 1) + D] + r;
+#pragma unroll
+        for (int d = 0; d < D; ++d) t = fmaf(yv[d], vx[j * (D + 1) + d], t);
+        v[j] = __builtin_amdgcn_exp2f(t);
       }
-      v[j] = __builtin_amdgcn_exp2f(fmaf(-cexp, d2, fastk::kExpBias));
+    } else {
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        float d2 = 0.0f;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const float df = yv[d] - xl[j * D + d];
+          d2 = fmaf(df, df, d2);
+        }
+        v[j] = __builtin_amdgcn_exp2f(fmaf(-cexp, d2, fastk::kExpBias));
+      }
     }
     // level b: v[k] is the sum over the 2^b consecutive labels of block k, so bit b of a
     // label is the parity of its block index
@@ -844,6 +868,7 @@ int sweep_plan_create(const md_sweep_instance* inst, int n_inst, const double* s
       md::Problem& P = p->h_probs[static_cast<size_t>(pi)];
       P.frag = prep.frag;
       P.xl = prep.xl;
+      P.vx = prep.vx;
       P.X = I.d_X;
       P.labels = I.d_labels;
       P.M = I.M;
