@@ -318,7 +318,8 @@ def measured_peaks(md):
     import torch
     res = {}
     for kind, key in (("exp", "exp_per_s"), ("add_f32", "add_f32_per_s"), ("exp_add2", "exp_add2_per_s"),
-                      ("tile_mix", "tile_mix_exp_per_s"), ("mfma_f16", "mfma_f16_flop_per_s"),
+                      ("tile_mix", "tile_mix_exp_per_s"), ("tile_mix1", "tile_mix1_exp_per_s"),
+                      ("mfma_f16", "mfma_f16_flop_per_s"),
                       ("mfma_bf16", "mfma_bf16_flop_per_s"), ("mfma_f32", "mfma_f32_flop_per_s")):
         res[key] = md.ubench(kind)[0]
     nbytes = 1 << 28
@@ -770,7 +771,8 @@ def main():
                                   "adds per step; tile_mix_exp_per_s: the kernel's whole per-tile instruction mix "
                                   "(two dependent matrix products per 32 x 32 tile from LDS operands, 16 "
                                   "exponentials per lane of the previous tile's products, position adds, tile-sum "
-                                  "tree, group routing) without its HBM traffic, prologue and epilogue; all from "
+                                  "tree, group routing) without its HBM traffic, prologue and epilogue; "
+                                  "tile_mix1_exp_per_s: the same loop with one matrix product per tile; all from "
                                   "the library's ubench kernels on this device after the timed steps")
 
     if args.copy_probe:

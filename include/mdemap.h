@@ -522,6 +522,8 @@ int kk_frontend(const float* d_x, int64_t T, float A, double nu, float* d_out, v
  *                                                               -> exponentials/s
  *   MD_UB_TILE_MIX4  the same at four K steps and 16 label bits (four MFMAs per tile,
  *                    8 routed bits)                             -> exponentials/s
+ *   MD_UB_TILE_MIX1  the same as MD_UB_TILE_MIX with one K step (one MFMA per tile)
+ *                                                               -> exponentials/s
  * Returns MD_OK, MD_EINVAL (unknown kind, work < 0, a copy without buffers, with work not a
  * positive multiple of 16 or with unaligned buffers), MD_ENOMEM, MD_EHIP. */
 #define MD_UB_EXP       0
@@ -533,6 +535,7 @@ int kk_frontend(const float* d_x, int64_t T, float A, double nu, float* d_out, v
 #define MD_UB_EXP_ADD2  6
 #define MD_UB_TILE_MIX  7
 #define MD_UB_TILE_MIX4 8
+#define MD_UB_TILE_MIX1 9
 int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rate, double* h_ms, void* stream);
 
 /* ------------------------------------------------------------------ kernel timing */

@@ -323,7 +323,7 @@ def kernel_timing_read():
     return ms.value, n.value
 
 
-UBENCH_KINDS = {"exp": 0, "add_f32": 1, "mfma_f16": 2, "mfma_bf16": 3, "mfma_f32": 4, "copy": 5, "exp_add2": 6, "tile_mix": 7, "tile_mix4": 8}
+UBENCH_KINDS = {"exp": 0, "add_f32": 1, "mfma_f16": 2, "mfma_bf16": 3, "mfma_f32": 4, "copy": 5, "exp_add2": 6, "tile_mix": 7, "tile_mix4": 8, "tile_mix1": 9}
 
 
 def ubench(kind: str, work: int = 0, src=None, dst=None):

@@ -81,7 +81,8 @@ __global__ void __launch_bounds__(kThreads) ub_exp_add2_kernel(int64_t iters, fl
 // the group sum is routed by NH bits.  Hard scheduling fences keep the matrix products of
 // tile t + 1 ahead of the exponentials of tile t, as in the demapper, so its rate is the
 // ceiling that instruction mix allows on this device (KS = 2, NH = 3: the 8D M = 2048
-// kernel; KS = 4, NH = 8: the 16D M = 65536 one).  Blocks of 16 wavefronts, like the
+// kernel; KS = 4, NH = 8: the 16D M = 65536 one; KS = 1, NH = 3: the 8D loop with one
+// matrix product per tile, which shows what the second one costs).  Blocks of 16 wavefronts, like the
 // demapper's, leave 128 registers per lane, so the products stay in ordinary vector
 // registers as they do there.
 constexpr int kMixTiles = 8;
@@ -207,7 +208,7 @@ __global__ void __launch_bounds__(kThreads) ub_copy_kernel(const uint4* __restri
 }
 
 constexpr double kMfmaFlop[3] = {2.0 * 32 * 32 * 16, 2.0 * 32 * 32 * 16, 2.0 * 32 * 32 * 2};
-constexpr int64_t kDefaultIters[9] = {8192, 8192, 4096, 4096, 2048, 0, 8192, 1024, 512};
+constexpr int64_t kDefaultIters[10] = {8192, 8192, 4096, 4096, 2048, 0, 8192, 1024, 512, 1024};
 
 int launch_kind(int kind, int64_t work, int blocks, const void* d_src, void* d_dst, float* sink, hipStream_t s) {
   const int64_t iters = work > 0 ? work : kDefaultIters[kind];
@@ -232,6 +233,9 @@ int launch_kind(int kind, int64_t work, int blocks, const void* d_src, void* d_d
     case MD_UB_TILE_MIX4:
       hipLaunchKernelGGL((ub_tile_mix_kernel<4, 8>), dim3(blocks / 4), dim3(kMixThreads), 0, s, iters, 1e-3f, sink);
       break;
+    case MD_UB_TILE_MIX1:
+      hipLaunchKernelGGL((ub_tile_mix_kernel<1, 3>), dim3(blocks / 4), dim3(kMixThreads), 0, s, iters, 1e-3f, sink);
+      break;
     default: {
       const int64_t n = work / 16;
       int64_t g = (n + kThreads - 1) / kThreads;
@@ -252,7 +256,7 @@ extern "C" {
 
 int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rate, double* h_ms, void* stream) {
   using namespace md;
-  if (kind < MD_UB_EXP || kind > MD_UB_TILE_MIX4) return fail(MD_EINVAL, "ubench: unknown kind");
+  if (kind < MD_UB_EXP || kind > MD_UB_TILE_MIX1) return fail(MD_EINVAL, "ubench: unknown kind");
   if (work < 0) return fail(MD_EINVAL, "ubench: work must be >= 0");
   if (kind == MD_UB_COPY) {
     if (d_src == nullptr || d_dst == nullptr) return fail(MD_EINVAL, "ubench: the copy needs d_src and d_dst");
@@ -296,7 +300,8 @@ int ubench(int kind, int64_t work, const void* d_src, void* d_dst, double* h_rat
     case MD_UB_EXP_ADD2:
     case MD_UB_ADD_F32: amount = lanes * static_cast<double>(iters) * kChains; break;
     case MD_UB_TILE_MIX:
-    case MD_UB_TILE_MIX4: amount = lanes * static_cast<double>(iters) * kMixGroup * 16; break;
+    case MD_UB_TILE_MIX4:
+    case MD_UB_TILE_MIX1: amount = lanes * static_cast<double>(iters) * kMixGroup * 16; break;
     case MD_UB_MFMA_F16:
     case MD_UB_MFMA_BF16:
     case MD_UB_MFMA_F32:

@@ -137,7 +137,7 @@ def test_ubench_argument_validation_before_device_work():
     L = lib()
     fake = ctypes.c_void_p(0x1000)      # never dereferenced: validation fails first
     assert L.ubench(-1, 0, None, None, None, None, None) == -1
-    assert L.ubench(9, 0, None, None, None, None, None) == -1
+    assert L.ubench(10, 0, None, None, None, None, None) == -1
     assert L.ubench(0, -5, None, None, None, None, None) == -1
     assert L.ubench(5, 1 << 20, None, fake, None, None, None) == -1      # copy without a source
     assert L.ubench(5, 0, fake, fake, None, None, None) == -1            # copy of zero bytes

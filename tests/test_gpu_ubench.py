@@ -18,7 +18,8 @@ def md():
 # cycles), FP16/BF16 matrix 2.5e15 flop/s, FP32 matrix 1.57e14 flop/s, HBM 8e12 B/s.
 BANDS = {"exp": (4e12, 2.6e13), "add_f32": (8e12, 8.2e13), "mfma_f16": (8e14, 2.8e15),
          "mfma_bf16": (8e14, 2.8e15), "mfma_f32": (4e13, 1.8e14), "exp_add2": (3e12, 2.0e13),
-         "tile_mix": (2e12, 2.0e13), "tile_mix4": (1.5e12, 2.0e13)}
+         "tile_mix": (2e12, 2.0e13), "tile_mix4": (1.5e12, 2.0e13),
+         "tile_mix1": (2e12, 2.0e13)}
 
 
 @pytest.mark.parametrize("kind", sorted(BANDS))
@@ -29,7 +30,7 @@ def test_compute_rates_are_plausible(kind):
     assert 0.05 < ms < 200.0, (kind, ms)
     # twice the iterations take about twice as long
     doubled = {"exp": 16384, "add_f32": 16384, "mfma_f16": 8192, "mfma_bf16": 8192, "mfma_f32": 4096,
-               "exp_add2": 16384, "tile_mix": 2048, "tile_mix4": 1024}
+               "exp_add2": 16384, "tile_mix": 2048, "tile_mix4": 1024, "tile_mix1": 2048}
     rate2, ms2 = md().ubench(kind, work=doubled[kind])
     assert 1.5 < ms2 / ms < 2.6, (kind, ms, ms2)
 
