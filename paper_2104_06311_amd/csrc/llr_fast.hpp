@@ -895,36 +895,17 @@ int launch_wide(const Prepared& P, int M, int D, const float* d_y, float* d_llr,
 }
 
 // Launch shapes of the fast kernel: (wavefronts per block, 32-symbol blocks per wavefront)
-// for one or two K steps: 2 (default): (16, 1), four wavefronts per SIMD at <= 128
-// registers, which hides latency better than 0: (8, 2) (measured 6 % faster at 8D
-// M = 2048).  More K steps use (8, 1).  MDEMAP_FAST_VARIANT selects one for timing.
-inline int fast_variant() {
-  static int g_fast_variant = -1;
-  if (g_fast_variant < 0) {
-    const char* e = std::getenv("MDEMAP_FAST_VARIANT");
-    g_fast_variant = e ? std::atoi(e) : 2;
-    if (g_fast_variant != 0 && g_fast_variant != 2) g_fast_variant = 2;
-  }
-  return g_fast_variant;
-}
-
+// = (16, 1) for one to four K steps: four wavefronts per SIMD at <= 128 registers, which
+// hides latency better than (8, 2) (measured 6 % faster at 8D M = 2048); more K steps use
+// (8, 1).
 template <bool MAXLOG>
 int launch_fast(const Prepared& P, int M, int D, const float* d_y, int64_t N, double sigma2, float* d_llr,
                 hipStream_t stream) {
-  const int v = fast_variant();
   switch (P.ks) {
-    case 1:
-      if (v == 2) return launch_fast_m<1, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-      return launch_fast_m<1, 8, 2, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 2:
-      if (v == 2) return launch_fast_m<2, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-      return launch_fast_m<2, 8, 2, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 3:
-      if (v == 2) return launch_fast_m<3, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-      return launch_fast_m<3, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-    case 4:
-      if (v == 2) return launch_fast_m<4, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
-      return launch_fast_m<4, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 1: return launch_fast_m<1, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 2: return launch_fast_m<2, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 3: return launch_fast_m<3, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
+    case 4: return launch_fast_m<4, 16, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
     case 5: return launch_fast_m<5, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
     default: return launch_fast_m<6, 8, 1, MAXLOG>(P, M, D, d_y, N, sigma2, d_llr, stream);
   }
