@@ -154,26 +154,6 @@ __device__ __forceinline__ void acc_init(SymAcc<MB> (&ac)[SB]) {
   }
 }
 
-// Copies `total` uint4 of fragments from global memory to LDS with all NT threads of the
-// block, four loads in flight per thread before the first store (named registers, not an
-// array, which the compiler would place in scratch): a plain copy loop waits for each
-// load before its store, one memory latency per uint4.
-template <int NT>
-__device__ __forceinline__ void stage_chunk(uint4* __restrict__ dst, const uint4* __restrict__ src, int total) {
-  for (int i0 = static_cast<int>(threadIdx.x); i0 < total; i0 += 4 * NT) {
-    const int i1 = i0 + NT, i2 = i0 + 2 * NT, i3 = i0 + 3 * NT;
-    const uint4 a0 = src[i0];
-    uint4 a1, a2, a3;
-    if (i1 < total) a1 = src[i1];
-    if (i2 < total) a2 = src[i2];
-    if (i3 < total) a3 = src[i3];
-    dst[i0] = a0;
-    if (i1 < total) dst[i1] = a1;
-    if (i2 < total) dst[i2] = a2;
-    if (i3 < total) dst[i3] = a3;
-  }
-}
-
 // Copies `total` uint4 (a multiple of 64: whole 1 KiB blocks) from global memory straight
 // into LDS: wavefront w issues the direct loads (global_load_lds_dwordx4, 16 bytes per
 // lane) of blocks w, w + NT/64, ... with a wave-uniform LDS base, and waits for them, so
