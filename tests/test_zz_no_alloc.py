@@ -2,8 +2,9 @@
 ABI: on the same inputs it gives llr_exact's LLRs bit for bit, on two calls in a row (the
 second smaller, so that stale scratch contents of the first would show), across the
 paths the exact demapper has (fast pass with the wide-range fallback at high SNR, the
-M <= 16 kernel, a constellation streamed through LDS in chunks), and it rejects sizes
-beyond its limit before touching the device."""
+M <= 16 kernel, a constellation streamed through LDS in chunks), it rejects sizes
+beyond its limit before touching the device, and captured into a graph it replays like
+the eager call."""
 import ctypes
 import math
 
@@ -80,3 +81,49 @@ def test_noalloc_limits_are_rejected_before_device_work():
     assert L.llr_exact_noalloc(fake, fake, 2048, 8, fake, (1 << 20) + 1, 0.1, 0, fake, None) == -1
     assert b"2^20" in L.last_error()
     assert L.llr_exact_noalloc(fake, fake, 48, 8, fake, 10, 0.1, 0, fake, None) == -2
+
+
+@pytest.mark.parametrize("which", ["8d", "4d"])
+def test_noalloc_in_a_captured_graph_replays_like_eager(which):
+    """Captured into a graph (the callers it is for run under stream capture), the call
+    replays several times, with other eager work and synchronisations between the
+    replays, and every replay gives llr_exact's LLRs bit for bit: 8D M = 2048 through the
+    matrix-core kernel with wide-range symbols at 14 dB, 4D M = 64 through the
+    one-thread-per-symbol kernel."""
+    import paper_2104_06311_amd as md
+    if which == "8d":
+        X, labels = synth.gaussian_constellation(2048, 8, synth.SEED_BASE + 1)
+        snr, N = 14.0, 6000
+    else:
+        X, labels = synth.product_4d_8psk()
+        snr, N = 8.0, 5000
+    M, D = X.shape
+    m = M.bit_length() - 1
+    Xd = torch.from_numpy(X).cuda()
+    ld = torch.from_numpy(labels.astype(np.int32)).cuda()
+    s2 = synth.sigma2_from_snr_db(X, snr)
+    tx, y = md.awgn_sample(Xd, 77, 0, N, math.sqrt(s2))
+    ref = md.llr_exact(Xd, ld, y, s2)
+    L = lib()
+    out = torch.full((N, m), float("nan"), device="cuda")
+    # one eager call first (the host label check and the scratch address lookup happen here)
+    assert L.llr_exact_noalloc(Xd.data_ptr(), ld.data_ptr(), M, D, y.data_ptr(), N, s2, 0, out.data_ptr(),
+                               stream()) == 0, L.last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    with torch.cuda.stream(cap):
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=cap):
+            rc = L.llr_exact_noalloc(Xd.data_ptr(), ld.data_ptr(), M, D, y.data_ptr(), N, s2, 0, out.data_ptr(),
+                                     ctypes.c_void_p(cap.cuda_stream))
+    assert rc == 0, L.last_error()
+    for r in range(4):
+        out.fill_(float("nan"))
+        junk = torch.randn(1 << 20, device="cuda").sum()      # eager work between the replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), (which, r)
+        del junk
