@@ -301,8 +301,9 @@ int mlp_load(const char* path, void** out);
  * same channel draw up to FP32 rounding.  Every class has its own launch shape
  * (wavefronts per block, 32-symbol blocks per wavefront, symbol groups per work item):
  * 0 (8, 2, 1), 1 (8, 2, 4), 2 (16, 1, 1), 3 (16, 1, 4) for the matrix-core kernel, and
- * for classes with M <= 64 also 4, a vector kernel with one thread per symbol (squared
- * distances from differences; each wavefront claims work items of 512 symbols; reported
+ * for classes with M <= 64 also 4, a vector kernel with one thread per symbol (scores
+ * from coordinate differences at M = 16 and from the per-point terms of prep at M = 32
+ * and 64; each wavefront claims work items of 512 symbols; reported
  * as (4, 1, 4)).  variant 0..3 fixes one shape for all classes, variant 4 gives the classes
  * with M <= 64 the vector kernel and the others shape 0; variant = -1 autotunes: the plan
  * is run once under each shape with its

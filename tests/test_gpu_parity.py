@@ -166,6 +166,7 @@ def test_parity_random_problems(M, D, N, snr, perm):
 
 @pytest.mark.parametrize("M,D,N,snr", [
     (64, 4, 3000, 30.0), (32, 8, 2000, 24.0), (64, 1, 2000, 20.0), (32, 3, 4097, 2.0), (64, 8, 1500, 14.0),
+    (64, 6, 1500, 12.0), (32, 7, 1200, 18.0), (64, 2, 2500, 9.0), (32, 5, 1000, 6.0),
 ])
 def test_parity_one_thread_per_symbol(M, D, N, snr):
     """M = 32 and 64 with D <= 8 take the one-thread-per-symbol exact kernel (FP32 scores

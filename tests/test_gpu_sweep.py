@@ -68,6 +68,25 @@ def test_sweep_matches_per_instance_path(variant):
     plan.close()
 
 
+@pytest.mark.parametrize("variant", [0, 3, 4])
+def test_every_channel_dimension_matches_the_per_instance_path(variant):
+    """The sweep kernels draw the channel with the dimension fixed at compile time (one
+    instantiation per D), the per-instance path with awgn_sample's run-time D: every
+    dimension the sweep takes besides 2, 4 and 8 (1, 3, 5, 6, 7), through the matrix-core
+    kernel (variant 0: two symbol blocks per wavefront; 3: one block, both lane halves
+    drawing) and the vector kernel (variant 4, M <= 64), gives the per-instance GMI."""
+    specs = [(64, 1, 1500), (256, 3, 1200), (1024, 5, 700), (32, 6, 1100), (128, 7, 900), (64, 5, 1300),
+             (16, 7, 1000), (512, 6, 800)]
+    inst, host = make_instances(specs, seed=71)
+    s2 = sigma2_grid(host, [3.0, 11.0])
+    plan = md().SweepPlan(inst, s2, variant=variant)
+    g = plan.run().cpu().numpy()
+    ref = per_instance_gmi(inst, s2)
+    assert np.all(np.isfinite(g))
+    np.testing.assert_allclose(g, ref, atol=1e-4, rtol=0)
+    plan.close()
+
+
 def test_sweep_against_oracle():
     inst, host = make_instances([(64, 4, 20000), (256, 2, 8000)], seed=9)
     s2 = sigma2_grid(host, [4.0, 10.0])
