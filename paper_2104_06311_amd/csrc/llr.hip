@@ -334,7 +334,8 @@ int launch_llr(const Prepared& P, int M, int D, const float* d_y, int64_t N, dou
   if (maxlog) {
     // max-log never loses range; its list holds only operands outside the FP16 split range
     const int slot = timing_begin(stream);
-    int st = launch_fast_maxlog(P, M, D, d_y, N, sigma2, d_llr, stream);
+    int st = (vec_exact_supported(M, D) && P.vx) ? launch_vec_exact(P, M, D, d_y, N, d_llr, stream, true)
+                                                 : launch_fast_maxlog(P, M, D, d_y, N, sigma2, d_llr, stream);
     timing_end(stream, slot);
     if (st != MD_OK) return st;
     return launch_careful_t<true>(P, M, D, d_y, N, sigma2, d_llr, P.fb_list, 1, stream);

@@ -32,10 +32,11 @@ int launch_fast_gmi(const Prepared& P, int M, int D, const float* d_y, int64_t N
 bool fused_gmi_supported(int sc, int ks);
 // Exact LLRs with one thread per symbol (FP32 scores from per-point terms in LDS), for
 // M = 32 or 64 and D <= 8, where the matrix-core kernel's per-symbol work outweighs its
-// two tiles; out-of-range symbols join the first fallback list like the fast pass's.
+// two tiles; out-of-range symbols join the first fallback list like the fast pass's (the
+// max-log form, from the same scores, never does).
 bool vec_exact_supported(int M, int D);
 int launch_vec_exact(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr,
-                     hipStream_t stream);
+                     hipStream_t stream, bool maxlog = false);
 // Fragment layout (Prepared::sc) that llr_exact's precision `prec` needs.
 inline int score_layout(int prec) {
   return prec == MD_PREC_FP16 ? 1 : (prec == MD_PREC_BF16_SCORES ? 2 : 0);

@@ -1,4 +1,5 @@
-// Exact LLRs of small constellations (M = 32 or 64, D <= 8) with one thread per symbol.
+// Exact (and max-log) LLRs of small constellations (M = 32 or 64, D <= 8) with one thread
+// per symbol.
 //
 // With 64 points per symbol the matrix-core kernel does two tiles per 32-symbol block, so
 // its per-symbol prologue and epilogue (operand staging, subset combine) cost more than its
@@ -24,7 +25,10 @@ constexpr int kVecThreads = 256;
 // GMI: also the loss term T_n = sum_k log2((S0_k + S1_k) / S_sent,k) of every finished
 // symbol (NaN for the symbols left to the later passes), as the fast kernel's fused
 // epilogue writes it.
-template <int MB, int D, bool GMI>
+// MAXLOG: max-log LLRs instead, ln 2 (max_{bit 0} t_j - max_{bit 1} t_j), from the same
+// per-point terms with maxima in place of the exponentials and sums (scores never leave
+// the FP32 range, so no symbol goes to the fallback list).
+template <int MB, int D, bool GMI, bool MAXLOG = false>
 __global__ void __launch_bounds__(kVecThreads) llr_vec_kernel(const float* __restrict__ vx_g,
                                                               const float* __restrict__ y, int64_t N, float c,
                                                               float* __restrict__ llr, int* __restrict__ flags,
@@ -51,14 +55,16 @@ __global__ void __launch_bounds__(kVecThreads) llr_vec_kernel(const float* __res
       yv[d] = y[n * D + d];
       ysq = fmaf(yv[d], yv[d], ysq);
     }
-    const float r = fmaf(-c, ysq, fastk::kExpBias);
+    // max-log takes differences of scores only: the terms common to all points (the bias
+    // and -c ||y||^2) drop out, and leaving them out keeps the scores' magnitude small
+    const float r = MAXLOG ? 0.0f : fmaf(-c, ysq, fastk::kExpBias);
     float v[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) {
       float t = vx[j * (D + 1) + D] + r;
 #pragma unroll
       for (int d = 0; d < D; ++d) t = fmaf(yv[d], vx[j * (D + 1) + d], t);
-      v[j] = __builtin_amdgcn_exp2f(t);
+      v[j] = MAXLOG ? t : __builtin_amdgcn_exp2f(t);
     }
     // level b: v[k] is the sum over the 2^b consecutive labels of block k, so bit b of a
     // label is the parity of its block index
@@ -69,13 +75,21 @@ __global__ void __launch_bounds__(kVecThreads) llr_vec_kernel(const float* __res
       float a0 = v[0], a1 = v[1];
 #pragma unroll
       for (int k = 2; k < cnt; k += 2) {
-        a0 += v[k];
-        a1 += v[k + 1];
+        a0 = MAXLOG ? fmaxf(a0, v[k]) : a0 + v[k];
+        a1 = MAXLOG ? fmaxf(a1, v[k + 1]) : a1 + v[k + 1];
       }
       S0[b] = a0;
       S1[b] = a1;
 #pragma unroll
-      for (int k = 0; k < cnt / 2; ++k) v[k] = v[2 * k] + v[2 * k + 1];
+      for (int k = 0; k < cnt / 2; ++k) v[k] = MAXLOG ? fmaxf(v[2 * k], v[2 * k + 1]) : v[2 * k] + v[2 * k + 1];
+    }
+    if constexpr (MAXLOG) {
+#pragma unroll
+      for (int k = 0; k < m; ++k) {
+        const int b = m - 1 - k;
+        llr[n * m + k] = invalid ? __builtin_nanf("") : fastk::kLn2 * (S0[b] - S1[b]);
+      }
+      continue;
     }
     if (invalid) {
 #pragma unroll
@@ -108,9 +122,9 @@ __global__ void __launch_bounds__(kVecThreads) llr_vec_kernel(const float* __res
   }
 }
 
-template <int MB, int D, bool GMI>
+template <int MB, int D, bool GMI, bool MAXLOG = false>
 int launch_vec_g(const Prepared& P, const float* d_y, int64_t N, float* d_llr, hipStream_t stream) {
-  auto kern = llr_vec_kernel<MB, D, GMI>;
+  auto kern = llr_vec_kernel<MB, D, GMI, MAXLOG>;
   int dev = 0, ncu = 0, occ = 0;
   MD_HIP_TRY(hipGetDevice(&dev));
   MD_HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -127,22 +141,24 @@ int launch_vec_g(const Prepared& P, const float* d_y, int64_t N, float* d_llr, h
 }
 
 template <int MB, int D>
-int launch_vec_t(const Prepared& P, const float* d_y, int64_t N, float* d_llr, hipStream_t stream) {
+int launch_vec_t(const Prepared& P, const float* d_y, int64_t N, bool maxlog, float* d_llr, hipStream_t stream) {
+  if (maxlog) return launch_vec_g<MB, D, false, true>(P, d_y, N, d_llr, stream);
   return P.gmi_terms ? launch_vec_g<MB, D, true>(P, d_y, N, d_llr, stream)
                      : launch_vec_g<MB, D, false>(P, d_y, N, d_llr, stream);
 }
 
 template <int MB>
-int launch_vec_m(const Prepared& P, int D, const float* d_y, int64_t N, float* d_llr, hipStream_t stream) {
+int launch_vec_m(const Prepared& P, int D, const float* d_y, int64_t N, bool maxlog, float* d_llr,
+                 hipStream_t stream) {
   switch (D) {
-    case 1: return launch_vec_t<MB, 1>(P, d_y, N, d_llr, stream);
-    case 2: return launch_vec_t<MB, 2>(P, d_y, N, d_llr, stream);
-    case 3: return launch_vec_t<MB, 3>(P, d_y, N, d_llr, stream);
-    case 4: return launch_vec_t<MB, 4>(P, d_y, N, d_llr, stream);
-    case 5: return launch_vec_t<MB, 5>(P, d_y, N, d_llr, stream);
-    case 6: return launch_vec_t<MB, 6>(P, d_y, N, d_llr, stream);
-    case 7: return launch_vec_t<MB, 7>(P, d_y, N, d_llr, stream);
-    default: return launch_vec_t<MB, 8>(P, d_y, N, d_llr, stream);
+    case 1: return launch_vec_t<MB, 1>(P, d_y, N, maxlog, d_llr, stream);
+    case 2: return launch_vec_t<MB, 2>(P, d_y, N, maxlog, d_llr, stream);
+    case 3: return launch_vec_t<MB, 3>(P, d_y, N, maxlog, d_llr, stream);
+    case 4: return launch_vec_t<MB, 4>(P, d_y, N, maxlog, d_llr, stream);
+    case 5: return launch_vec_t<MB, 5>(P, d_y, N, maxlog, d_llr, stream);
+    case 6: return launch_vec_t<MB, 6>(P, d_y, N, maxlog, d_llr, stream);
+    case 7: return launch_vec_t<MB, 7>(P, d_y, N, maxlog, d_llr, stream);
+    default: return launch_vec_t<MB, 8>(P, d_y, N, maxlog, d_llr, stream);
   }
 }
 
@@ -151,9 +167,10 @@ int launch_vec_m(const Prepared& P, int D, const float* d_y, int64_t N, float* d
 bool vec_exact_supported(int M, int D) { return (M == 32 || M == 64) && D >= 1 && D <= 8; }
 
 int launch_vec_exact(const Prepared& P, int M, int D, const float* d_y, int64_t N, float* d_llr,
-                     hipStream_t stream) {
+                     hipStream_t stream, bool maxlog) {
   if (!vec_exact_supported(M, D) || !P.vx) return fail(MD_EUNSUPPORTED, "vector demapper: M 32 or 64 and D <= 8");
-  return M == 32 ? launch_vec_m<5>(P, D, d_y, N, d_llr, stream) : launch_vec_m<6>(P, D, d_y, N, d_llr, stream);
+  return M == 32 ? launch_vec_m<5>(P, D, d_y, N, maxlog, d_llr, stream)
+                 : launch_vec_m<6>(P, D, d_y, N, maxlog, d_llr, stream);
 }
 
 }  // namespace md

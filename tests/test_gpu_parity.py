@@ -169,12 +169,14 @@ def test_parity_random_problems(M, D, N, snr, perm):
     (64, 6, 1500, 12.0), (32, 7, 1200, 18.0), (64, 2, 2500, 9.0), (32, 5, 1000, 6.0),
 ])
 def test_parity_one_thread_per_symbol(M, D, N, snr):
-    """M = 32 and 64 with D <= 8 take the one-thread-per-symbol exact kernel (FP32 scores
-    from per-point terms); at 20-30 dB part of the symbols leave its FP32 range and are
-    finished by the wide-range and FP64 passes through the same fallback list."""
+    """M = 32 and 64 with D <= 8 take the one-thread-per-symbol kernel (FP32 scores from
+    per-point terms), exact and max-log; at 20-30 dB part of the symbols leave the exact
+    form's FP32 range and are finished by the wide-range and FP64 passes through the same
+    fallback list (max-log takes score differences only and never leaves the range)."""
     X, labels = synth.gaussian_constellation(M, D, 7000 + M + D)
     labels = synth.random_labels(M, 5 * M + D)
     _parity(X, labels, snr, N, 71 + M + D)
+    _parity(X, labels, snr, N, 72 + M + D, maxlog=True)
 
 
 @pytest.mark.parametrize("M,D,N,snr,maxlog", [
