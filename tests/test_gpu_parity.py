@@ -397,6 +397,7 @@ def test_labels_rewritten_in_place_are_caught_on_the_device():
     ld[5] = ld[6]                        # now a duplicate label, same address
     L = md().llr_exact(Xd, ld, y, s2)
     assert torch.isnan(L).all()
+    assert torch.isnan(md().llr_maxlog(Xd, ld, y, s2)).all()     # the max-log form of the same kernel
     md().release_cache()
     with pytest.raises(md().MdemapError) as e:
         md().llr_exact(Xd, ld, y, s2)
